@@ -1,0 +1,269 @@
+"""FP64 CPU oracle of the pose-graph optimisation (Sec. IV-D, Eqs. 1-3 and the
+Gauss-Newton step).  TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke
+check and the CPU-baseline leg of the benchmark, never by the GPU library.
+
+The numerics live in ``oracle.c`` (plain C, FP64); this module builds it with
+gcc and marshals NumPy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+OK, ERR_ARG, ERR_SINGULAR = 0, -1, -5
+MAX_ITERS = 64
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
+               "-Wno-unused-parameter", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True, cwd=_HERE)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("n_frames", C.c_int), ("width", C.c_int), ("height", C.c_int),
+        ("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+        ("depth", C.POINTER(C.c_float)), ("mask", C.POINTER(C.c_ubyte)), ("fixed", C.POINTER(C.c_int)),
+        ("n_match_sets", C.c_int),
+        ("match_i", C.POINTER(C.c_int)), ("match_j", C.POINTER(C.c_int)),
+        ("match_n", C.POINTER(C.c_int)), ("match_off", C.POINTER(C.c_int)),
+        ("uv_i", C.POINTER(C.c_float)), ("uv_j", C.POINTER(C.c_float)),
+        ("lambda_f", C.c_double), ("lambda_g", C.c_double),
+        ("huber_f", C.c_double), ("huber_g", C.c_double),
+        ("gate_dist", C.c_double), ("gate_angle", C.c_double),
+    ]
+
+
+class LinStats(C.Structure):
+    _fields_ = [("energy_f", C.c_double), ("energy_g", C.c_double),
+                ("n_valid_g", C.c_longlong), ("n_valid_f", C.c_longlong)]
+
+
+class OptStats(C.Structure):
+    _fields_ = [("iters_done", C.c_int),
+                ("energy_f", C.c_double * MAX_ITERS), ("energy_g", C.c_double * MAX_ITERS),
+                ("n_valid_g", C.c_longlong * MAX_ITERS), ("n_valid_f", C.c_longlong * MAX_ITERS)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = C.CDLL(_SO)
+        P = C.POINTER
+        dp = P(C.c_double)
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
+        L.orc_preprocess_frame.argtypes = [P(Problem), C.c_int, dp, dp, P(C.c_ubyte)]
+        L.orc_linearize.argtypes = [P(Problem), dp, dp, dp, dp, dp, P(LinStats)]
+        L.orc_optimize.argtypes = [P(Problem), dp, C.c_int, P(OptStats)]
+        L.orc_associate.argtypes = [P(Problem), dp, C.c_int, C.c_int, P(C.c_int), dp, dp, dp]
+        L.orc_dense_frozen.argtypes = [P(Problem), dp, C.c_int, C.c_int, C.c_int, P(C.c_int), P(C.c_int), dp, dp]
+        L.orc_feature_eval.argtypes = [P(Problem), dp, C.c_int, C.c_int, dp, dp]
+        L.orc_se3_exp.argtypes = [dp, dp]
+        L.orc_huber_rho.argtypes = [C.c_double, C.c_double]
+        L.orc_huber_rho.restype = C.c_double
+        L.orc_huber_weight.argtypes = [C.c_double, C.c_double]
+        L.orc_huber_weight.restype = C.c_double
+        L.orc_cholesky_solve.argtypes = [C.c_int, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+@dataclass
+class Params:
+    """The method's constants (readings of Sec. IV-B/IV-D, see the design notes):
+    lambda_1 = lambda_2 = 1 (Eq. 1 weights as used in the paper's experiments);
+    Huber thresholds 5 mm (the paper's inlier distance scale, RANSAC delta);
+    dense gates 1 cm / 30 degrees."""
+    lambda_f: float = 1.0
+    lambda_g: float = 1.0
+    huber_f: float = 0.005
+    huber_g: float = 0.005
+    gate_dist: float = 0.01
+    gate_angle: float = float(np.deg2rad(30.0))
+
+
+class OracleProblem:
+    """Owns the contiguous arrays an orc_problem borrows."""
+
+    def __init__(self, depth, mask, fx, fy, cx, cy, fixed=None, matches: Sequence = (),
+                 params: Optional[Params] = None):
+        self.depth = np.ascontiguousarray(depth, dtype=np.float32)
+        self.mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        N, H, W = self.depth.shape
+        self.fixed = np.ascontiguousarray(
+            np.zeros(N, np.int32) if fixed is None else np.asarray(fixed, np.int32))
+        self.params = params or Params()
+        mi, mj, mn, mo, ui, uj = [], [], [], [], [], []
+        off = 0
+        for m in matches:
+            a, b = np.asarray(m.uv_i, np.float32).reshape(-1, 2), np.asarray(m.uv_j, np.float32).reshape(-1, 2)
+            mi.append(m.i), mj.append(m.j), mn.append(len(a)), mo.append(off)
+            ui.append(a), uj.append(b)
+            off += len(a)
+        self.match_i = np.asarray(mi, np.int32)
+        self.match_j = np.asarray(mj, np.int32)
+        self.match_n = np.asarray(mn, np.int32)
+        self.match_off = np.asarray(mo, np.int32)
+        self.uv_i = np.ascontiguousarray(np.concatenate(ui) if ui else np.zeros((1, 2), np.float32))
+        self.uv_j = np.ascontiguousarray(np.concatenate(uj) if uj else np.zeros((1, 2), np.float32))
+        self.n_frames, self.height, self.width = N, H, W
+        self.fx, self.fy, self.cx, self.cy = float(fx), float(fy), float(cx), float(cy)
+        self.c = Problem()
+        self._fill()
+
+    def _fill(self):
+        c, p = self.c, self.params
+        c.n_frames, c.width, c.height = self.n_frames, self.width, self.height
+        c.fx, c.fy, c.cx, c.cy = self.fx, self.fy, self.cx, self.cy
+        c.depth = _ptr(self.depth, C.c_float)
+        c.mask = _ptr(self.mask, C.c_ubyte)
+        c.fixed = _ptr(self.fixed, C.c_int)
+        c.n_match_sets = len(self.match_i)
+        c.match_i = _ptr(self.match_i, C.c_int) if len(self.match_i) else None
+        c.match_j = _ptr(self.match_j, C.c_int) if len(self.match_j) else None
+        c.match_n = _ptr(self.match_n, C.c_int) if len(self.match_n) else None
+        c.match_off = _ptr(self.match_off, C.c_int) if len(self.match_off) else None
+        c.uv_i = _ptr(self.uv_i, C.c_float)
+        c.uv_j = _ptr(self.uv_j, C.c_float)
+        c.lambda_f, c.lambda_g = p.lambda_f, p.lambda_g
+        c.huber_f, c.huber_g = p.huber_f, p.huber_g
+        c.gate_dist, c.gate_angle = p.gate_dist, p.gate_angle
+
+    def set_params(self, **kw):
+        for k, v in kw.items():
+            setattr(self.params, k, v)
+        self._fill()
+
+    @classmethod
+    def from_synth(cls, g, params: Optional[Params] = None, clean: bool = False, matches=True):
+        return cls(g.depth_clean if clean else g.depth, g.mask, g.fx, g.fy, g.cx, g.cy, g.fixed,
+                   g.matches if matches else (), params)
+
+    # ---------------------------------------------------------- entry points
+    def preprocess(self, f):
+        hw = self.width * self.height
+        V = np.zeros(3 * hw)
+        Nn = np.zeros(3 * hw)
+        code = np.zeros(hw, np.uint8)
+        rc = lib().orc_preprocess_frame(C.byref(self.c), f, _ptr(V, C.c_double), _ptr(Nn, C.c_double),
+                                        _ptr(code, C.c_ubyte))
+        assert rc == OK
+        return (V.reshape(self.height, self.width, 3), Nn.reshape(self.height, self.width, 3),
+                code.reshape(self.height, self.width))
+
+    def linearize(self, poses):
+        poses = np.ascontiguousarray(poses, np.float64)
+        n6 = 6 * self.n_frames
+        H = np.zeros((n6, n6))
+        g = np.zeros(n6)
+        Ha = np.zeros((n6, n6))
+        ga = np.zeros(n6)
+        st = LinStats()
+        rc = lib().orc_linearize(C.byref(self.c), _ptr(poses, C.c_double), _ptr(H, C.c_double), _ptr(g, C.c_double),
+                                 _ptr(Ha, C.c_double), _ptr(ga, C.c_double), C.byref(st))
+        assert rc == OK, rc
+        return dict(H=H, g=g, H_abs=Ha, g_abs=ga, energy_f=st.energy_f, energy_g=st.energy_g,
+                    n_valid_g=st.n_valid_g, n_valid_f=st.n_valid_f)
+
+    def optimize(self, poses, iters=7):
+        P = np.ascontiguousarray(np.array(poses, np.float64, copy=True))
+        st = OptStats()
+        rc = lib().orc_optimize(C.byref(self.c), _ptr(P, C.c_double), int(iters), C.byref(st))
+        k = st.iters_done
+        return P, dict(status=rc, iters_done=k, energy_f=np.array(st.energy_f[:iters]),
+                       energy_g=np.array(st.energy_g[:iters]), n_valid_g=np.array(st.n_valid_g[:iters]),
+                       n_valid_f=np.array(st.n_valid_f[:iters]))
+
+    def associate(self, poses, i, j):
+        poses = np.ascontiguousarray(poses, np.float64)
+        hw = self.width * self.height
+        tgt = np.zeros(hw, np.int32)
+        r = np.zeros(hw)
+        proj = np.zeros(2 * hw)
+        gate = np.zeros(2 * hw)
+        rc = lib().orc_associate(C.byref(self.c), _ptr(poses, C.c_double), i, j, _ptr(tgt, C.c_int),
+                                 _ptr(r, C.c_double), _ptr(proj, C.c_double), _ptr(gate, C.c_double))
+        assert rc == OK
+        return tgt, r, proj.reshape(hw, 2), gate.reshape(hw, 2)
+
+    def dense_frozen(self, poses, i, j, src, tgt):
+        poses = np.ascontiguousarray(poses, np.float64)
+        src = np.ascontiguousarray(src, np.int32)
+        tgt = np.ascontiguousarray(tgt, np.int32)
+        n = len(src)
+        r = np.zeros(n)
+        J = np.zeros((n, 12))
+        rc = lib().orc_dense_frozen(C.byref(self.c), _ptr(poses, C.c_double), i, j, n, _ptr(src, C.c_int),
+                                    _ptr(tgt, C.c_int), _ptr(r, C.c_double), _ptr(J, C.c_double))
+        assert rc == OK
+        return r, J
+
+    def feature_eval(self, poses, s, k):
+        poses = np.ascontiguousarray(poses, np.float64)
+        e = np.zeros(3)
+        J = np.zeros((3, 12))
+        ok = lib().orc_feature_eval(C.byref(self.c), _ptr(poses, C.c_double), s, k, _ptr(e, C.c_double),
+                                    _ptr(J, C.c_double))
+        return bool(ok), e, J
+
+
+def se3_exp(xi) -> np.ndarray:
+    xi = np.ascontiguousarray(xi, np.float64)
+    T = np.zeros(16)
+    lib().orc_se3_exp(_ptr(xi, C.c_double), _ptr(T, C.c_double))
+    return T.reshape(4, 4)
+
+
+def huber_rho(s, delta):
+    return lib().orc_huber_rho(float(s), float(delta))
+
+
+def huber_weight(s, delta):
+    return lib().orc_huber_weight(float(s), float(delta))
+
+
+def cholesky_solve(A, b):
+    A = np.ascontiguousarray(A, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    x = np.zeros_like(b)
+    rc = lib().orc_cholesky_solve(len(b), _ptr(A, C.c_double), _ptr(b, C.c_double), _ptr(x, C.c_double))
+    return rc, x
+
+
+def set_threads(n: int):
+    lib().orc_set_threads(int(n))
+
+
+def pose_error(Ta, Tb):
+    """(rotation angle in rad, translation distance in m) between two poses;
+    the angle from atan2 of the skew and trace parts (accurate near zero)."""
+    Ra, Rb = np.asarray(Ta)[:3, :3], np.asarray(Tb)[:3, :3]
+    M = Ra @ Rb.T
+    sk = np.array([M[2, 1] - M[1, 2], M[0, 2] - M[2, 0], M[1, 0] - M[0, 1]])
+    ang = np.arctan2(np.linalg.norm(sk) / 2.0, (np.trace(M) - 1.0) / 2.0)
+    return float(ang), float(np.linalg.norm(np.asarray(Ta)[:3, 3] - np.asarray(Tb)[:3, 3]))

@@ -1,0 +1,724 @@
+/*
+ * FP64 CPU oracle for BundleTrack's online pose-graph optimisation
+ * (Wen & Bekris, IROS 2021, Sec. IV-D).  TEST INFRASTRUCTURE ONLY: the plain,
+ * slow, obviously-correct reference the GPU library is checked against.  It
+ * shares no code with the GPU library.
+ *
+ * What it computes, in the paper's order:
+ *   S0  per frame: validity (mask, finite positive depth), back-projected
+ *       vertex map p = pi_D^-1 (Sec. IV-D, after Eq. 3), normal map n_i(.)
+ *       (central differences; the paper does not say how normals are made);
+ *   S1  per ordered pair (i, j), j != i (the double sum of Eq. 1):
+ *       A = T_i T_j^-1 and B = T_j T_i^-1 (the two transforms of Eq. 3);
+ *   S2  dense projective association of every valid pixel of frame i into
+ *       frame j, gated by point distance and normal angle (text after Eq. 3);
+ *   S3  point-to-plane residual of Eq. 3, its Jacobian, Huber IRLS weight
+ *       (rho of Eq. 2/3 is the Huber loss; W in the Gauss-Newton step);
+ *   S4  feature residual of Eq. 2 and its Jacobian for every match;
+ *   S5  normal equations J^T W J and J^T W r summed in a fixed order;
+ *   S6  the first keyframe's pose held constant (the gauge of Sec. IV-D),
+ *       Gauss-Newton step solved by Cholesky (the converged PCG solution);
+ *   S7  update in the tangent space, T <- Exp(delta) T.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ utils */
+
+static int g_threads = 1;
+
+void orc_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
+int orc_get_threads(void) { return g_threads; }
+
+/* nearest pixel, ties to the upper pixel: floor(x + 1/2) computed exactly */
+static double round_half_up(double x)
+{
+    double f = floor(x);
+    return (x - f >= 0.5) ? f + 1.0 : f;
+}
+
+static void rigid_inverse(const double *T, double *Ti)
+{
+    /* [R t; 0 1]^-1 = [R^T  -R^T t; 0 1] */
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            Ti[4 * r + c] = T[4 * c + r];
+    for (int r = 0; r < 3; ++r)
+        Ti[4 * r + 3] = -(Ti[4 * r + 0] * T[3] + Ti[4 * r + 1] * T[7] + Ti[4 * r + 2] * T[11]);
+    Ti[12] = Ti[13] = Ti[14] = 0.0;
+    Ti[15] = 1.0;
+}
+
+static void mat4_mul(const double *A, const double *B, double *C)
+{
+    double tmp[16];
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 4; ++k)
+                s += A[4 * r + k] * B[4 * k + c];
+            tmp[4 * r + c] = s;
+        }
+    memcpy(C, tmp, sizeof(tmp));
+}
+
+static void apply_T(const double *T, const double *x, double *y)
+{
+    for (int r = 0; r < 3; ++r)
+        y[r] = T[4 * r] * x[0] + T[4 * r + 1] * x[1] + T[4 * r + 2] * x[2] + T[4 * r + 3];
+}
+
+static void apply_R(const double *T, const double *x, double *y)
+{
+    for (int r = 0; r < 3; ++r)
+        y[r] = T[4 * r] * x[0] + T[4 * r + 1] * x[1] + T[4 * r + 2] * x[2];
+}
+
+static void apply_Rt(const double *T, const double *x, double *y)
+{
+    for (int r = 0; r < 3; ++r)
+        y[r] = T[r] * x[0] + T[4 + r] * x[1] + T[8 + r] * x[2];
+}
+
+static void cross3(const double *a, const double *b, double *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* ------------------------------------------------------------------ Huber */
+
+double orc_huber_rho(double s, double delta)
+{
+    return (s <= delta) ? 0.5 * s * s : delta * (s - 0.5 * delta);
+}
+
+double orc_huber_weight(double s, double delta)
+{
+    /* rho'(s)/s: the IRLS weight of the diagonal matrix W */
+    return (s <= delta) ? 1.0 : delta / s;
+}
+
+/* ------------------------------------------------------------------ SE(3) */
+
+void orc_se3_exp(const double *xi, double *T)
+{
+    const double *v = xi, *w = xi + 3;
+    double th2 = dot3(w, w), th = sqrt(th2);
+    double A, B, C; /* sin(t)/t, (1-cos t)/t^2, (t - sin t)/t^3 */
+    if (th < 1e-6) {
+        A = 1.0 - th2 / 6.0;
+        B = 0.5 - th2 / 24.0;
+        C = 1.0 / 6.0 - th2 / 120.0;
+    } else {
+        A = sin(th) / th;
+        B = (1.0 - cos(th)) / th2;
+        C = (th - sin(th)) / (th2 * th);
+    }
+    double K[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+    double K2[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0;
+            for (int k = 0; k < 3; ++k)
+                s += K[3 * r + k] * K[3 * k + c];
+            K2[3 * r + c] = s;
+        }
+    double R[9], V[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double I = (r == c) ? 1.0 : 0.0;
+            R[3 * r + c] = I + A * K[3 * r + c] + B * K2[3 * r + c];
+            V[3 * r + c] = I + B * K[3 * r + c] + C * K2[3 * r + c];
+        }
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c)
+            T[4 * r + c] = R[3 * r + c];
+        T[4 * r + 3] = V[3 * r] * v[0] + V[3 * r + 1] * v[1] + V[3 * r + 2] * v[2];
+    }
+    T[12] = T[13] = T[14] = 0.0;
+    T[15] = 1.0;
+}
+
+/* --------------------------------------------------------- S0: per frame */
+
+int orc_preprocess_frame(const orc_problem *pb, int f, double *vertex, double *normal,
+                         unsigned char *valid)
+{
+    if (!pb || f < 0 || f >= pb->n_frames)
+        return ORC_ERR_ARG;
+    const int W = pb->width, H = pb->height;
+    const float *D = pb->depth + (size_t)f * W * H;
+    const unsigned char *M = pb->mask + (size_t)f * W * H;
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            size_t x = (size_t)v * W + u;
+            double z = (double)D[x];
+            int ok = (M[x] != 0) && isfinite(z) && z > 0.0;
+            valid[x] = ok ? 1 : 0;
+            /* pi_D^-1: back-projection through the pinhole at the pixel centre */
+            vertex[3 * x + 0] = ok ? z * ((double)u - pb->cx) / pb->fx : 0.0;
+            vertex[3 * x + 1] = ok ? z * ((double)v - pb->cy) / pb->fy : 0.0;
+            vertex[3 * x + 2] = ok ? z : 0.0;
+        }
+    for (int v = 0; v < H; ++v)
+        for (int u = 0; u < W; ++u) {
+            size_t x = (size_t)v * W + u;
+            normal[3 * x] = normal[3 * x + 1] = normal[3 * x + 2] = 0.0;
+            if (!valid[x] || u == 0 || v == 0 || u == W - 1 || v == H - 1)
+                continue;
+            size_t xl = x - 1, xr = x + 1, xu = x - W, xd = x + W;
+            if (!valid[xl] || !valid[xr] || !valid[xu] || !valid[xd])
+                continue;
+            double du[3], dv[3], n[3];
+            for (int k = 0; k < 3; ++k) {
+                du[k] = vertex[3 * xr + k] - vertex[3 * xl + k];
+                dv[k] = vertex[3 * xd + k] - vertex[3 * xu + k];
+            }
+            cross3(du, dv, n);
+            double len = sqrt(dot3(n, n));
+            if (!(len > 0.0))
+                continue;
+            for (int k = 0; k < 3; ++k)
+                n[k] /= len;
+            if (dot3(n, vertex + 3 * x) > 0.0) /* face the camera */
+                for (int k = 0; k < 3; ++k)
+                    n[k] = -n[k];
+            for (int k = 0; k < 3; ++k)
+                normal[3 * x + k] = n[k];
+            valid[x] |= 2;
+        }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------- frame cache */
+
+typedef struct {
+    double *vertex, *normal;
+    unsigned char *valid;
+} frame_maps;
+
+static frame_maps *build_frames(const orc_problem *pb)
+{
+    size_t hw = (size_t)pb->width * pb->height;
+    frame_maps *fm = (frame_maps *)calloc((size_t)pb->n_frames, sizeof(frame_maps));
+    if (!fm)
+        return NULL;
+    for (int f = 0; f < pb->n_frames; ++f) {
+        fm[f].vertex = (double *)malloc(3 * hw * sizeof(double));
+        fm[f].normal = (double *)malloc(3 * hw * sizeof(double));
+        fm[f].valid = (unsigned char *)malloc(hw);
+        orc_preprocess_frame(pb, f, fm[f].vertex, fm[f].normal, fm[f].valid);
+    }
+    return fm;
+}
+
+static void free_frames(const orc_problem *pb, frame_maps *fm)
+{
+    if (!fm)
+        return;
+    for (int f = 0; f < pb->n_frames; ++f) {
+        free(fm[f].vertex);
+        free(fm[f].normal);
+        free(fm[f].valid);
+    }
+    free(fm);
+}
+
+/* --------------------------------------------- per-pair partial normal eqs */
+
+typedef struct {
+    int i, j;                 /* node ids of the 12 columns: [i (6) | j (6)] */
+    double H[144], g[12];
+    double Habs[144], gabs[12];
+    double energy;
+    long long count;
+} pair_part;
+
+static void add_row(pair_part *pp, const double *row, double w, double res)
+{
+    /* H += w row row^T, g += w res row */
+    for (int a = 0; a < 12; ++a) {
+        for (int b = 0; b < 12; ++b) {
+            double c = w * (row[a] * row[b]); /* symmetric in a, b */
+            pp->H[12 * a + b] += c;
+            pp->Habs[12 * a + b] += fabs(c);
+        }
+        double c = w * res * row[a];
+        pp->g[a] += c;
+        pp->gabs[a] += fabs(c);
+    }
+}
+
+/* One dense association step (S2) of source pixel x of frame i into frame j.
+ * Returns the target pixel index (>= 0) or a negative rejection code, and the
+ * quantities the decision used. */
+static int associate_pixel(const orc_problem *pb, const frame_maps *fm, int i, int j,
+                           const double *A, const double *B, size_t x, double *s_out,
+                           double *r_out, double *proj, double *gate)
+{
+    const int W = pb->width, H = pb->height;
+    if ((fm[i].valid[x] & 3) != 3)
+        return -1;
+    const double *p = fm[i].vertex + 3 * x;
+    const double *n = fm[i].normal + 3 * x;
+    double pp[3];
+    apply_T(B, p, pp);              /* T_j T_i^-1 p */
+    if (!(pp[2] > 0.0))
+        return -2;
+    double uf = pb->fx * pp[0] / pp[2] + pb->cx; /* pi(.) */
+    double vf = pb->fy * pp[1] / pp[2] + pb->cy;
+    if (proj) {
+        proj[0] = uf;
+        proj[1] = vf;
+    }
+    double ui = round_half_up(uf), vi = round_half_up(vf);
+    if (!(ui >= 0.0 && ui < (double)W && vi >= 0.0 && vi < (double)H))
+        return -3;
+    size_t y = (size_t)vi * W + (size_t)ui;
+    if ((fm[j].valid[y] & 3) != 3)
+        return -4;
+    const double *q = fm[j].vertex + 3 * y;     /* pi_D^-1 of frame j */
+    const double *nq = fm[j].normal + 3 * y;
+    double s[3], d[3], Rnq[3];
+    apply_T(A, q, s);                /* T_i T_j^-1 pi_D^-1(.) */
+    for (int k = 0; k < 3; ++k)
+        d[k] = s[k] - p[k];
+    double dist = sqrt(dot3(d, d));
+    apply_R(A, nq, Rnq);
+    double cosang = dot3(n, Rnq);
+    if (gate) {
+        gate[0] = dist;
+        gate[1] = cosang;
+    }
+    if (!(dist < pb->gate_dist))
+        return -5;
+    if (!(cosang > cos(pb->gate_angle)))
+        return -6;
+    if (s_out)
+        memcpy(s_out, s, sizeof(s));
+    if (r_out)
+        *r_out = dot3(n, d);         /* n_i(x) . (s - p) */
+    return (int)y;
+}
+
+/* Jacobian row of r = n.(A q - p) w.r.t. left perturbations of T_i and T_j. */
+static void dense_jacobian(const double *A, const double *n, const double *s, const double *q,
+                           double *row)
+{
+    double sxn[3], Rtn[3], qxRtn[3];
+    cross3(s, n, sxn);
+    apply_Rt(A, n, Rtn);
+    cross3(q, Rtn, qxRtn);
+    for (int k = 0; k < 3; ++k) {
+        row[k] = n[k];            /* d r / d v_i */
+        row[3 + k] = sxn[k];      /* d r / d w_i */
+        row[6 + k] = -Rtn[k];     /* d r / d v_j */
+        row[9 + k] = -qxRtn[k];   /* d r / d w_j */
+    }
+}
+
+static void pair_transforms(const double *poses, int i, int j, double *A, double *B)
+{
+    double Ti_inv[16], Tj_inv[16];
+    rigid_inverse(poses + 16 * i, Ti_inv);
+    rigid_inverse(poses + 16 * j, Tj_inv);
+    mat4_mul(poses + 16 * i, Tj_inv, A);   /* frame-j camera -> frame-i camera */
+    mat4_mul(poses + 16 * j, Ti_inv, B);   /* frame-i camera -> frame-j camera */
+}
+
+static void dense_pair(const orc_problem *pb, const frame_maps *fm, const double *poses,
+                       pair_part *pp)
+{
+    const int i = pp->i, j = pp->j;
+    double A[16], B[16];
+    pair_transforms(poses, i, j, A, B);
+    const size_t hw = (size_t)pb->width * pb->height;
+    for (size_t x = 0; x < hw; ++x) {   /* row-major source order */
+        double s[3], r;
+        int y = associate_pixel(pb, fm, i, j, A, B, x, s, &r, NULL, NULL);
+        if (y < 0)
+            continue;
+        const double *n = fm[i].normal + 3 * x;
+        const double *q = fm[j].vertex + 3 * (size_t)y;
+        double row[12];
+        dense_jacobian(A, n, s, q, row);
+        double ar = fabs(r);
+        double w = pb->lambda_g * orc_huber_weight(ar, pb->huber_g);
+        add_row(pp, row, w, r);
+        pp->energy += pb->lambda_g * orc_huber_rho(ar, pb->huber_g);
+        pp->count += 1;
+    }
+}
+
+/* Match endpoint: back-projection of the nearest pixel, if it has depth. */
+static int match_point(const orc_problem *pb, const frame_maps *fm, int f, const float *uv,
+                       double *p)
+{
+    double u = round_half_up((double)uv[0]), v = round_half_up((double)uv[1]);
+    if (!(u >= 0.0 && u < pb->width && v >= 0.0 && v < pb->height))
+        return 0;
+    size_t x = (size_t)v * pb->width + (size_t)u;
+    if (!(fm[f].valid[x] & 1))
+        return 0;
+    memcpy(p, fm[f].vertex + 3 * x, 3 * sizeof(double));
+    return 1;
+}
+
+/* e = T_i^-1 p_m - T_j^-1 p_n (Eq. 2) and its 3x12 Jacobian. */
+static void feature_eval(const double *Ti, const double *Tj, const double *pm, const double *pn,
+                         double *e, double *J)
+{
+    double Ti_inv[16], Tj_inv[16], a[3], b[3];
+    rigid_inverse(Ti, Ti_inv);
+    rigid_inverse(Tj, Tj_inv);
+    apply_T(Ti_inv, pm, a);
+    apply_T(Tj_inv, pn, b);
+    for (int k = 0; k < 3; ++k)
+        e[k] = a[k] - b[k];
+    /* de/dv_i = -R_i^T, de/dw_i = R_i^T [p_m]x ; de/dv_j = R_j^T, de/dw_j = -R_j^T [p_n]x */
+    double Pm[9] = {0, -pm[2], pm[1], pm[2], 0, -pm[0], -pm[1], pm[0], 0};
+    double Pn[9] = {0, -pn[2], pn[1], pn[2], 0, -pn[0], -pn[1], pn[0], 0};
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) {
+            double Rti = Ti[4 * c + r], Rtj = Tj[4 * c + r]; /* (R^T)_{rc} */
+            double RtPm = 0.0, RtPn = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                RtPm += Ti[4 * k + r] * Pm[3 * k + c];
+                RtPn += Tj[4 * k + r] * Pn[3 * k + c];
+            }
+            J[12 * r + c] = -Rti;
+            J[12 * r + 3 + c] = RtPm;
+            J[12 * r + 6 + c] = Rtj;
+            J[12 * r + 9 + c] = -RtPn;
+        }
+    }
+}
+
+static void feature_set(const orc_problem *pb, const frame_maps *fm, const double *poses, int s,
+                        pair_part *pp)
+{
+    const int i = pb->match_i[s], j = pb->match_j[s];
+    for (int k = 0; k < pb->match_n[s]; ++k) {
+        size_t m = (size_t)pb->match_off[s] + k;
+        double pm[3], pn[3];
+        if (!match_point(pb, fm, i, pb->uv_i + 2 * m, pm) || !match_point(pb, fm, j, pb->uv_j + 2 * m, pn))
+            continue;
+        double e[3], J[36];
+        feature_eval(poses + 16 * i, poses + 16 * j, pm, pn, e, J);
+        double ne = sqrt(dot3(e, e));
+        /* E_f(i,j) and E_f(j,i) are the same sum: each match counts twice in Eq. 1 */
+        double w = 2.0 * pb->lambda_f * orc_huber_weight(ne, pb->huber_f);
+        for (int c = 0; c < 3; ++c)
+            add_row(pp, J + 12 * c, w, e[c]);
+        pp->energy += 2.0 * pb->lambda_f * orc_huber_rho(ne, pb->huber_f);
+        pp->count += 1;
+    }
+}
+
+static int check_problem(const orc_problem *pb)
+{
+    if (!pb || pb->n_frames < 1 || pb->width < 3 || pb->height < 3 || !pb->depth || !pb->mask)
+        return ORC_ERR_ARG;
+    if (!(pb->fx > 0 && pb->fy > 0))
+        return ORC_ERR_ARG;
+    for (int s = 0; s < pb->n_match_sets; ++s) {
+        int i = pb->match_i[s], j = pb->match_j[s];
+        if (i < 0 || j < 0 || i >= pb->n_frames || j >= pb->n_frames || i == j)
+            return ORC_ERR_ARG;
+    }
+    return ORC_OK;
+}
+
+static int linearize_with(const orc_problem *pb, const frame_maps *fm, const double *poses,
+                          double *H, double *g, double *H_abs, double *g_abs, orc_lin_stats *st)
+{
+    const int N = pb->n_frames, n6 = 6 * N;
+    const int n_dense = (pb->lambda_g != 0.0) ? N * (N - 1) : 0;
+    const int n_feat = (pb->lambda_f != 0.0) ? pb->n_match_sets : 0;
+    pair_part *parts = (pair_part *)calloc((size_t)(n_dense + n_feat) + 1, sizeof(pair_part));
+    if (!parts)
+        return ORC_ERR_ARG;
+    /* S1: ordered pairs in lexicographic order, then the match sets in order */
+    int k = 0;
+    for (int i = 0; i < N && n_dense; ++i)
+        for (int j = 0; j < N; ++j)
+            if (j != i) {
+                parts[k].i = i;
+                parts[k].j = j;
+                ++k;
+            }
+    for (int s = 0; s < n_feat; ++s) {
+        parts[n_dense + s].i = pb->match_i[s];
+        parts[n_dense + s].j = pb->match_j[s];
+    }
+    const int total = n_dense + n_feat;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
+    for (int t = 0; t < total; ++t) {
+        if (t < n_dense)
+            dense_pair(pb, fm, poses, &parts[t]);          /* S2 + S3 */
+        else
+            feature_set(pb, fm, poses, t - n_dense, &parts[t]); /* S4 */
+    }
+    /* S5: fixed-order sum of the per-pair partial systems */
+    memset(H, 0, sizeof(double) * n6 * n6);
+    memset(g, 0, sizeof(double) * n6);
+    if (H_abs)
+        memset(H_abs, 0, sizeof(double) * n6 * n6);
+    if (g_abs)
+        memset(g_abs, 0, sizeof(double) * n6);
+    double Ef = 0.0, Eg = 0.0;
+    long long cf = 0, cg = 0;
+    for (int t = 0; t < total; ++t) {
+        const pair_part *pp = &parts[t];
+        int node[2] = {pp->i, pp->j};
+        for (int a = 0; a < 12; ++a) {
+            int ra = 6 * node[a / 6] + a % 6;
+            for (int b = 0; b < 12; ++b) {
+                int cb = 6 * node[b / 6] + b % 6;
+                H[(size_t)ra * n6 + cb] += pp->H[12 * a + b];
+                if (H_abs)
+                    H_abs[(size_t)ra * n6 + cb] += pp->Habs[12 * a + b];
+            }
+            g[ra] += pp->g[a];
+            if (g_abs)
+                g_abs[ra] += pp->gabs[a];
+        }
+        if (t < n_dense) {
+            Eg += pp->energy;
+            cg += pp->count;
+        } else {
+            Ef += pp->energy;
+            cf += pp->count;
+        }
+    }
+    if (st) {
+        st->energy_f = Ef;
+        st->energy_g = Eg;
+        st->n_valid_f = cf;
+        st->n_valid_g = cg;
+    }
+    free(parts);
+    return ORC_OK;
+}
+
+int orc_linearize(const orc_problem *pb, const double *poses, double *H, double *g,
+                  double *H_abs, double *g_abs, orc_lin_stats *st)
+{
+    int rc = check_problem(pb);
+    if (rc != ORC_OK || !poses || !H || !g)
+        return ORC_ERR_ARG;
+    frame_maps *fm = build_frames(pb);
+    if (!fm)
+        return ORC_ERR_ARG;
+    rc = linearize_with(pb, fm, poses, H, g, H_abs, g_abs, st);
+    free_frames(pb, fm);
+    return rc;
+}
+
+/* ------------------------------------------------------------ S6: solve */
+
+int orc_cholesky_solve(int n, const double *A, const double *b, double *x)
+{
+    if (n <= 0)
+        return ORC_OK;
+    double *L = (double *)calloc((size_t)n * n, sizeof(double));
+    double *y = (double *)malloc((size_t)n * sizeof(double));
+    if (!L || !y) {
+        free(L);
+        free(y);
+        return ORC_ERR_ARG;
+    }
+    double maxdiag = 0.0;
+    for (int i = 0; i < n; ++i)
+        if (A[(size_t)i * n + i] > maxdiag)
+            maxdiag = A[(size_t)i * n + i];
+    int rc = ORC_OK;
+    if (!(maxdiag > 0.0))
+        rc = ORC_ERR_SINGULAR;
+    for (int j = 0; j < n && rc == ORC_OK; ++j) {
+        double s = A[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k)
+            s -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(s > 1e-12 * maxdiag)) {
+            rc = ORC_ERR_SINGULAR;
+            break;
+        }
+        double d = sqrt(s);
+        L[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double t = A[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k)
+                t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = t / d;
+        }
+    }
+    if (rc == ORC_OK) {
+        for (int i = 0; i < n; ++i) { /* L y = b */
+            double t = b[i];
+            for (int k = 0; k < i; ++k)
+                t -= L[(size_t)i * n + k] * y[k];
+            y[i] = t / L[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) { /* L^T x = y */
+            double t = y[i];
+            for (int k = i + 1; k < n; ++k)
+                t -= L[(size_t)k * n + i] * x[k];
+            x[i] = t / L[(size_t)i * n + i];
+        }
+    }
+    free(L);
+    free(y);
+    return rc;
+}
+
+/* ------------------------------------------------------ S1..S7 iterated */
+
+int orc_optimize(const orc_problem *pb, double *poses, int iters, orc_opt_stats *st)
+{
+    int rc = check_problem(pb);
+    if (rc != ORC_OK || !poses || iters < 0 || iters > ORC_MAX_ITERS)
+        return ORC_ERR_ARG;
+    const int N = pb->n_frames, n6 = 6 * N;
+    int *free_ids = (int *)malloc(sizeof(int) * N);
+    int nfree = 0;
+    for (int f = 0; f < N; ++f)
+        if (!(pb->fixed && pb->fixed[f]))
+            free_ids[nfree++] = f;
+    const int nf = 6 * nfree;
+    double *H = (double *)malloc(sizeof(double) * n6 * n6);
+    double *g = (double *)malloc(sizeof(double) * n6);
+    double *Hff = (double *)malloc(sizeof(double) * (nf ? nf * nf : 1));
+    double *bf = (double *)malloc(sizeof(double) * (nf ? nf : 1));
+    double *dx = (double *)malloc(sizeof(double) * (nf ? nf : 1));
+    frame_maps *fm = build_frames(pb);
+    if (st)
+        memset(st, 0, sizeof(*st));
+    rc = ORC_OK;
+    for (int it = 0; it < iters; ++it) {
+        orc_lin_stats ls;
+        linearize_with(pb, fm, poses, H, g, NULL, NULL, &ls);
+        if (st) {
+            st->energy_f[it] = ls.energy_f;
+            st->energy_g[it] = ls.energy_g;
+            st->n_valid_f[it] = ls.n_valid_f;
+            st->n_valid_g[it] = ls.n_valid_g;
+        }
+        if (nfree) {
+            /* S6: drop the fixed nodes, solve H_ff delta = -g_f */
+            for (int a = 0; a < nf; ++a) {
+                int ra = 6 * free_ids[a / 6] + a % 6;
+                for (int b = 0; b < nf; ++b) {
+                    int cb = 6 * free_ids[b / 6] + b % 6;
+                    Hff[(size_t)a * nf + b] = H[(size_t)ra * n6 + cb];
+                }
+                bf[a] = -g[ra];
+            }
+            if (orc_cholesky_solve(nf, Hff, bf, dx) != ORC_OK) {
+                rc = ORC_ERR_SINGULAR;
+                break;
+            }
+            /* S7: T_i <- Exp(delta_i) T_i */
+            for (int a = 0; a < nfree; ++a) {
+                double E[16];
+                orc_se3_exp(dx + 6 * a, E);
+                mat4_mul(E, poses + 16 * free_ids[a], poses + 16 * free_ids[a]);
+            }
+        }
+        if (st)
+            st->iters_done = it + 1;
+    }
+    free_frames(pb, fm);
+    free(free_ids);
+    free(H);
+    free(g);
+    free(Hff);
+    free(bf);
+    free(dx);
+    return rc;
+}
+
+/* ------------------------------------------------ inspection entry points */
+
+int orc_associate(const orc_problem *pb, const double *poses, int i, int j, int *target,
+                  double *r, double *proj, double *gate)
+{
+    if (check_problem(pb) != ORC_OK || !poses || i < 0 || j < 0 || i >= pb->n_frames ||
+        j >= pb->n_frames || i == j)
+        return ORC_ERR_ARG;
+    frame_maps *fm = build_frames(pb);
+    double A[16], B[16];
+    pair_transforms(poses, i, j, A, B);
+    const size_t hw = (size_t)pb->width * pb->height;
+    for (size_t x = 0; x < hw; ++x) {
+        double rr = 0.0, pr[2] = {NAN, NAN}, gt[2] = {NAN, NAN};
+        int y = associate_pixel(pb, fm, i, j, A, B, x, NULL, &rr, pr, gt);
+        if (target)
+            target[x] = y;
+        if (r)
+            r[x] = (y >= 0) ? rr : 0.0;
+        if (proj) {
+            proj[2 * x] = pr[0];
+            proj[2 * x + 1] = pr[1];
+        }
+        if (gate) {
+            gate[2 * x] = gt[0];
+            gate[2 * x + 1] = gt[1];
+        }
+    }
+    free_frames(pb, fm);
+    return ORC_OK;
+}
+
+int orc_dense_frozen(const orc_problem *pb, const double *poses, int i, int j, int n,
+                     const int *src, const int *tgt, double *r, double *J)
+{
+    if (check_problem(pb) != ORC_OK || !poses || i == j)
+        return ORC_ERR_ARG;
+    frame_maps *fm = build_frames(pb);
+    double A[16], B[16];
+    pair_transforms(poses, i, j, A, B);
+    for (int k = 0; k < n; ++k) {
+        const double *p = fm[i].vertex + 3 * (size_t)src[k];
+        const double *nn = fm[i].normal + 3 * (size_t)src[k];
+        const double *q = fm[j].vertex + 3 * (size_t)tgt[k];
+        double s[3], d[3];
+        apply_T(A, q, s);
+        for (int c = 0; c < 3; ++c)
+            d[c] = s[c] - p[c];
+        r[k] = dot3(nn, d);
+        if (J)
+            dense_jacobian(A, nn, s, q, J + 12 * (size_t)k);
+    }
+    free_frames(pb, fm);
+    return ORC_OK;
+}
+
+int orc_feature_eval(const orc_problem *pb, const double *poses, int s, int k, double *e,
+                     double *J)
+{
+    if (check_problem(pb) != ORC_OK || s < 0 || s >= pb->n_match_sets || k < 0 ||
+        k >= pb->match_n[s])
+        return ORC_ERR_ARG;
+    frame_maps *fm = build_frames(pb);
+    const int i = pb->match_i[s], j = pb->match_j[s];
+    size_t m = (size_t)pb->match_off[s] + k;
+    double pm[3], pn[3], Jl[36];
+    int ok = match_point(pb, fm, i, pb->uv_i + 2 * m, pm) && match_point(pb, fm, j, pb->uv_j + 2 * m, pn);
+    if (ok) {
+        feature_eval(poses + 16 * i, poses + 16 * j, pm, pn, e, Jl);
+        if (J)
+            memcpy(J, Jl, sizeof(Jl));
+    }
+    free_frames(pb, fm);
+    return ok;
+}

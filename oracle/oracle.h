@@ -1,0 +1,115 @@
+/*
+ * FP64 CPU oracle for the online pose-graph optimisation of BundleTrack
+ * (Wen & Bekris, IROS 2021), Sec. IV-D: the total energy of Eq. (1), the
+ * feature term of Eq. (2), the dense point-to-plane term of Eq. (3), and the
+ * IRLS Gauss-Newton iteration with the first keyframe held fixed.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the slow, plain reference that the
+ * GPU library is checked against.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the GPU library never does,
+ * and the two share no source.
+ *
+ * Conventions (the readings of the paper this oracle fixes):
+ *   pose T maps object to camera, x_cam = R x_obj + t, 4x4 row-major doubles;
+ *   twist xi = [v; w] (translation first), update T <- Exp(delta) T;
+ *   Gauss-Newton step delta = -(J^T W J)^-1 J^T W r over the free nodes.
+ */
+#ifndef BT_ORACLE_H
+#define BT_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_SINGULAR = -5 };
+
+/* One keyframe window and the method's parameters.  All arrays are borrowed. */
+typedef struct {
+    int n_frames, width, height;
+    double fx, fy, cx, cy;
+    const float *depth;          /* n_frames*H*W, metres; 0 or non-finite = no depth */
+    const unsigned char *mask;   /* n_frames*H*W, nonzero = object                   */
+    const int *fixed;            /* n_frames, nonzero = pose held constant           */
+    int n_match_sets;            /* sets of sparse matches, one per node pair        */
+    const int *match_i, *match_j;/* n_match_sets node ids, i != j                    */
+    const int *match_n;          /* n_match_sets match counts                        */
+    const int *match_off;        /* n_match_sets offsets into uv_i/uv_j (in matches) */
+    const float *uv_i, *uv_j;    /* 2 floats (u,v) per match, pixel coordinates      */
+    double lambda_f, lambda_g;   /* Eq. (1) weights; 0 disables a term               */
+    double huber_f, huber_g;     /* Huber thresholds (metres)                        */
+    double gate_dist;            /* dense association distance gate (metres)         */
+    double gate_angle;           /* dense association normal-angle gate (radians)    */
+} orc_problem;
+
+/* Per-call statistics. */
+typedef struct {
+    double energy_f, energy_g;   /* lambda-weighted Huber energies at the given poses */
+    long long n_valid_g;         /* gated-in dense residuals (ordered pairs)          */
+    long long n_valid_f;         /* valid matches, each counted once                   */
+} orc_lin_stats;
+
+#define ORC_MAX_ITERS 64
+typedef struct {
+    int iters_done;
+    double energy_f[ORC_MAX_ITERS], energy_g[ORC_MAX_ITERS];
+    long long n_valid_g[ORC_MAX_ITERS], n_valid_f[ORC_MAX_ITERS];
+} orc_opt_stats;
+
+/* Threads used by the ordered-pair loop (1 = sequential).  Results do not
+ * depend on it: per-pair sums are added in a fixed order. */
+void orc_set_threads(int n);
+int  orc_get_threads(void);
+
+/* Per-frame preprocessing: vertex map (3*H*W), normal map (3*H*W) and a
+ * per-pixel code: bit0 = depth/mask valid, bit1 = normal valid. */
+int orc_preprocess_frame(const orc_problem *pb, int f, double *vertex, double *normal,
+                         unsigned char *valid);
+
+/* Normal equations at the given poses (n_frames*16 doubles): H (6N x 6N,
+ * row-major), g (6N), and per entry the sum of |contributions| to H and g
+ * (scales of the rounding a different summation order may introduce).
+ * Any of H_abs/g_abs/st may be NULL. */
+int orc_linearize(const orc_problem *pb, const double *poses, double *H, double *g,
+                  double *H_abs, double *g_abs, orc_lin_stats *st);
+
+/* Fixed number of IRLS Gauss-Newton iterations; poses updated in place.  On a
+ * singular system the poses of the last completed iteration are kept and
+ * ORC_ERR_SINGULAR is returned. */
+int orc_optimize(const orc_problem *pb, double *poses, int iters, orc_opt_stats *st);
+
+/* Dense association of the ordered pair (i, j) at the given poses.  For every
+ * pixel of frame i: target[x] = target pixel index, or a negative code
+ *   -1 not a valid source, -2 behind camera, -3 outside image,
+ *   -4 invalid target, -5 distance gate, -6 normal gate;
+ * r[x] = point-to-plane residual (0 where rejected); proj[2x..2x+1] = the
+ * continuous projection (u', v') where computed (NaN otherwise); gate[2x..] =
+ * (|s-p|, cosine of the normal angle) where computed. */
+int orc_associate(const orc_problem *pb, const double *poses, int i, int j,
+                  int *target, double *r, double *proj, double *gate);
+
+/* Residuals and Jacobian rows of frozen associations, without gating: for the
+ * n source pixels src[k] of frame i associated with target pixels tgt[k] of
+ * frame j, r[k] and J[12k..12k+11] = [dr/d(xi_i), dr/d(xi_j)] at the poses. */
+int orc_dense_frozen(const orc_problem *pb, const double *poses, int i, int j, int n,
+                     const int *src, const int *tgt, double *r, double *J);
+
+/* Feature residual e (3) and Jacobian (3x12, [de/dxi_i | de/dxi_j], row-major)
+ * of match k of set s at the given poses.  Returns 1 if the match is valid. */
+int orc_feature_eval(const orc_problem *pb, const double *poses, int s, int k,
+                     double *e, double *J);
+
+/* SE(3) exponential of xi = [v; w] as a 4x4 row-major matrix. */
+void orc_se3_exp(const double *xi, double *T);
+
+/* Huber loss and IRLS weight at s >= 0 with threshold delta. */
+double orc_huber_rho(double s, double delta);
+double orc_huber_weight(double s, double delta);
+
+/* Dense Cholesky solve of the SPD system A x = b (n x n row-major).
+ * Returns ORC_ERR_SINGULAR when a pivot is <= 1e-12 * max diagonal. */
+int orc_cholesky_solve(int n, const double *A, const double *b, double *x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
