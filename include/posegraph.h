@@ -1,0 +1,189 @@
+/*
+ * posegraph.h - C ABI of the MI355X pose-graph optimiser.
+ *
+ * The library implements the online pose-graph optimisation of BundleTrack
+ * (Wen & Bekris, IROS 2021), Sec. IV-D: the nodes are the object poses of a
+ * window of RGB-D keyframes (current frame plus selected keyframes); the
+ * total energy of Eq. (1) sums, over every ordered node pair, a sparse
+ * feature term (Eq. 2) and a dense point-to-plane term with projective data
+ * association (Eq. 3), both under the Huber M-estimator; it is minimised by
+ * iteratively re-weighted Gauss-Newton with the first keyframe's pose held
+ * constant and updates applied in the tangent space.
+ *
+ * Conventions shared by every entry point:
+ *  - Pose T maps object to camera coordinates (the object pose in the camera
+ *    frame, Sec. III): x_cam = R x_obj + t; passed as 16 doubles, 4x4
+ *    row-major, bottom row (0,0,0,1), R orthonormal within 1e-6.
+ *  - Twist xi = [v; w] (3 translation then 3 rotation parameters, Sec. IV-D);
+ *    an update is T <- Exp(delta) T.
+ *  - Depth is metres (float); 0, negative or non-finite means no depth.
+ *    Mask is uint8, nonzero = object pixel (the binary mask of Sec. IV-A).
+ *  - Pixel (u, v) has its centre at integer coordinates; u is the column.
+ *  - Every input pointer may be host or device memory (detected); inputs are
+ *    always copied, so the caller keeps ownership and may free them on return.
+ *    Output pointers are host memory unless stated.
+ *  - All GPU work is ordered on the stream given at creation (a hipStream_t,
+ *    NULL = the null stream).  Calls that return results synchronise it.
+ *  - Every call returns a pg_status; no exception or abort crosses the ABI.
+ *    pose_graph_last_error() gives a message for the last failed call.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef POSEGRAPH_H
+#define POSEGRAPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pg_graph pg_graph; /* opaque, library-owned */
+
+typedef enum {
+    PG_OK = 0,
+    PG_ERR_INVALID_ARG = -1,   /* bad pointer, size, id, intrinsics or pose       */
+    PG_ERR_NO_DEVICE = -2,     /* no usable GPU                                    */
+    PG_ERR_OUT_OF_MEMORY = -3, /* device allocation failed                         */
+    PG_ERR_CAPACITY = -4,      /* more frames than max_frames, or too many to solve */
+    PG_ERR_SINGULAR = -5,      /* normal equations not positive definite           */
+    PG_ERR_NONFINITE = -6,     /* non-finite update                                 */
+    PG_ERR_HIP = -7            /* a HIP runtime call failed                         */
+} pg_status;
+
+enum { PG_SOLVER_CHOLESKY = 0, PG_SOLVER_PCG = 1 };
+enum { PG_WEIGHT_HUBER = 0, PG_WEIGHT_LEARNED = 1 };
+enum { PG_PREC_FP32 = 0, PG_PREC_BF16X3 = 1 };
+
+#define PG_MAX_FRAMES_LIMIT 32 /* upper bound of pg_config.max_frames */
+#define PG_MAX_ITERS 32        /* upper bound of pg_config.gn_iters   */
+
+/* One pinhole camera per graph (pi and pi_D^-1 of Eq. 3). */
+typedef struct {
+    int width, height;          /* pixels, 3..8192 each                 */
+    double fx, fy, cx, cy;      /* focal lengths > 0 and principal point */
+} pg_camera;
+
+/* Method parameters and execution options.  Fill with pg_config_default(). */
+typedef struct {
+    int max_frames;             /* node capacity, 2..PG_MAX_FRAMES_LIMIT (default 16)       */
+    int gn_iters;               /* Gauss-Newton iterations per optimize (default 7)          */
+    double lambda_f, lambda_g;  /* Eq. (1) weights of the feature / dense terms (1, 1)       */
+    double huber_f_m;           /* Huber threshold of the feature term, metres (0.005)      */
+    double huber_g_m;           /* Huber threshold of the dense term, metres (0.005)        */
+    double gate_dist_m;         /* dense association distance gate, metres (0.01)           */
+    double gate_normal_rad;     /* dense association normal-angle gate, radians (30 deg)    */
+    int solver;                 /* PG_SOLVER_CHOLESKY (default) or PG_SOLVER_PCG             */
+    int pcg_max_iters;          /* PCG iteration cap (default 500)                           */
+    double pcg_rel_tol;         /* PCG stop: |r| <= tol |b| (default 1e-12)                  */
+    int weighting;              /* PG_WEIGHT_HUBER (default) or PG_WEIGHT_LEARNED            */
+    int precision;              /* PG_PREC_FP32 (default) or PG_PREC_BF16X3                  */
+    int use_graph;              /* 1 = replay the iteration loop as a captured hipGraph (1)  */
+    int timing;                 /* 1 = record HIP events around each kernel (0)              */
+    int tile_pixels;            /* source pixels per association work item, 0 = library pick */
+    double prune_frac;          /* learned weighting: fraction of source pixels dropped (0.25) */
+} pg_config;
+
+/* Per-optimize statistics. */
+typedef struct {
+    int iters_done;                          /* completed Gauss-Newton iterations          */
+    double energy_f[PG_MAX_ITERS];           /* lambda_f * sum of Eq. (2) over ordered pairs */
+    double energy_g[PG_MAX_ITERS];           /* lambda_g * sum of Eq. (3) over ordered pairs */
+    long long n_valid_g[PG_MAX_ITERS];       /* gated-in dense residuals                   */
+    long long n_valid_f[PG_MAX_ITERS];       /* valid feature matches (each counted once)  */
+    int status_bits;                         /* bit0 singular, bit1 non-finite             */
+    long long src_pixels;                    /* sum over ordered pairs of valid source pixels */
+    int n_assoc_launches;                    /* association kernel launches (timing = 1)   */
+    float ms_assoc, ms_feature, ms_reduce, ms_solve, ms_total; /* kernel time (timing = 1) */
+} pg_stats;
+
+/* Defaults listed in pg_config. */
+void pg_config_default(pg_config *cfg);
+
+/* Create a graph on the current HIP device.  hip_stream: a hipStream_t or NULL.
+ * Errors: PG_ERR_INVALID_ARG (cfg/camera out of range), PG_ERR_NO_DEVICE,
+ * PG_ERR_OUT_OF_MEMORY, PG_ERR_CAPACITY (max_frames too large to solve in one
+ * workgroup on this device).  *out is NULL on error. */
+pg_status pose_graph_create(const pg_config *cfg, const pg_camera *cam, void *hip_stream,
+                            pg_graph **out);
+
+/* Add a node: depth (H*W floats, metres) and mask (H*W bytes) of one frame,
+ * row-major; its initial pose; fixed != 0 holds the pose constant (the first
+ * keyframe I_0 is the fixed reference of Sec. IV-D).  Preprocesses the frame
+ * on the GPU (validity, back-projection, normals, packed layout and the list
+ * of valid source pixels).  *out_id receives the node id 0, 1, ...
+ * Errors: PG_ERR_INVALID_ARG, PG_ERR_CAPACITY (max_frames reached). */
+pg_status pose_graph_add_frame(pg_graph *g, const float *depth_m, const uint8_t *mask,
+                               const double T_obj_to_cam[16], int fixed, int *out_id);
+
+/* Feature correspondences C_ij between nodes i and j (Eq. 2): n pixel pairs,
+ * uv_i and uv_j hold 2n floats (u, v).  Stored once per unordered pair (i and j
+ * are swapped when i > j); a later call for the same pair replaces the set,
+ * which is otherwise reused by every optimize (Sec. IV-D).  n = 0 removes it.
+ * Each match's 3-D points are the back-projections of the nearest pixels; a
+ * match whose pixel is outside the image or has no depth/mask is skipped.
+ * Errors: PG_ERR_INVALID_ARG. */
+pg_status pose_graph_add_matches(pg_graph *g, int id_i, int id_j, const float *uv_i,
+                                 const float *uv_j, int n);
+
+/* Set / read a node pose (host memory, 16 doubles). */
+pg_status pose_graph_set_pose(pg_graph *g, int id, const double T[16]);
+pg_status pose_graph_get_pose(const pg_graph *g, int id, double T_out[16]);
+
+/* Run cfg.gn_iters iterations: per iteration, dense association and
+ * residuals of every ordered pair, feature residuals, the fused reduction into
+ * the 6N x 6N normal equations (J^T W J) delta = -J^T W r, the solve over the
+ * free nodes and the update T <- Exp(delta) T.  Poses stay in the graph (the
+ * memory-pool write-back of Sec. IV-D) and are readable with get_pose.
+ * Synchronous.  On PG_ERR_SINGULAR / PG_ERR_NONFINITE the poses are those of
+ * the last completed iteration and stats->iters_done says which.
+ * stats may be NULL. */
+pg_status pose_graph_optimize(pg_graph *g, pg_stats *stats);
+
+/* Optimise n_graphs independent graphs in one batched schedule (one launch per
+ * phase for all graphs; uneven node counts and resolutions allowed).  All
+ * graphs must share one device and one stream.  stats: NULL or n_graphs
+ * entries.  Returns the first non-OK per-graph status. */
+pg_status pose_graph_optimize_batch(pg_graph *const *graphs, int n_graphs, pg_stats *stats);
+
+/* Normal equations at the current poses without updating them: H (6N*6N,
+ * row-major, all nodes including fixed ones) and g = J^T W r (6N), as doubles
+ * in host memory.  stats (nullable) receives energies and counts in entry 0.
+ * The same kernels as optimize. */
+pg_status pose_graph_linearize(pg_graph *g, double *H, double *grad, pg_stats *stats);
+
+/* Test inspection of the dense association of ordered pair (i, j) at the
+ * current poses: for every pixel x of frame i (H*W entries, host memory),
+ * target[x] = associated pixel of frame j, or a negative code (-1 not a valid
+ * source, -2 behind the camera, -3 outside the image, -4 invalid target,
+ * -5 distance gate, -6 normal gate); r[x] = point-to-plane residual (0 where
+ * rejected); uv[2x..2x+1] = continuous projection (NaN where not computed).
+ * Any output may be NULL. */
+pg_status pose_graph_associate(pg_graph *g, int i, int j, int32_t *target, float *r,
+                               float *uv);
+
+/* Test inspection of a preprocessed frame: packed map (4*H*W floats, host:
+ * nx, ny, nz, z per pixel, z = 0 where the pixel is not a valid source/target)
+ * and the number of valid source pixels.  Either output may be NULL. */
+pg_status pose_graph_frame_info(pg_graph *g, int id, float *map, int *n_valid);
+
+/* Learned correspondence weighting: parameters of the 6-32-32-1 MLP as fp16,
+ * layout W1[32x6] b1[32] W2[32x32] b2[32] W3[1x32] b3[1] (row-major, 1313
+ * values).  Used when cfg.weighting == PG_WEIGHT_LEARNED.  Errors:
+ * PG_ERR_INVALID_ARG when n_bytes != 2626. */
+pg_status pose_graph_set_mlp(pg_graph *g, const void *fp16_params, size_t n_bytes);
+
+/* Number of nodes. */
+int pose_graph_num_frames(const pg_graph *g);
+
+/* Message of the last failed call on g (or of the last failed create when g
+ * is NULL).  Valid until the next call on the same handle. */
+const char *pose_graph_last_error(const pg_graph *g);
+
+/* Release the graph and its device memory.  NULL-safe. */
+void pose_graph_destroy(pg_graph *g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POSEGRAPH_H */

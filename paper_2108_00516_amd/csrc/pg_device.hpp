@@ -1,0 +1,76 @@
+// Internal layout shared by the kernels and the host library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace pg {
+
+constexpr int kMaxFrames = 32;       // hard cap of nodes per graph
+constexpr int kMaxIters = 32;
+constexpr int kDenseFields = 29;     // per pixel-pair sums: 21 (J^T W J upper) + 6 (J^T W r) + E + count
+constexpr int kDenseStride = 32;     // floats per dense partial record
+constexpr int kFeatFields = 92;      // 78 (12x12 upper) + 12 + E + count
+constexpr int kFeatStride = 96;
+constexpr int kAssocThreads = 256;   // threads per association work item
+constexpr int kTileMaxPixels = 8 * kAssocThreads;  // largest association tile
+constexpr int kNodeStats = 4;        // per node: E_g, E_f, n_g, n_f (doubles)
+constexpr int kIterRecord = 8;       // per iteration: E_f, E_g, n_g, n_f, ...
+
+// status bits (sticky, per graph)
+constexpr int kStatusSingular = 1;
+constexpr int kStatusNonFinite = 2;
+
+// One association work item: source frame i, target frame j, a contiguous
+// range of frame i's valid-pixel list.  'slot' is the index of its partial
+// record within its graph.
+struct WorkItem {
+    int gij;    // i | (j << 8) | (graph << 16)
+    int start;
+    int count;
+    int slot;
+};
+
+// Device view of one graph (one entry per graph of a batch).
+struct GraphDev {
+    int W, H, HW, n_frames;
+    float fx, fy, cx, cy;
+    float ifx, ify;
+    float lambda_f, lambda_g, huber_f, huber_g, gate_d2, gate_cos;
+    int n_sets;       // feature match sets
+    int n_free;
+    int precision;
+    int weighting;
+    int solver;
+    int pcg_max_iters;
+    double pcg_rel_tol;
+
+    const float4* maps;       // n_frames * HW packed {nx, ny, nz, z}; z = 0 invalid
+    const float4* src_nz;     // frame f list at f*HW: {nx, ny, nz, z}
+    const uint32_t* src_uv;   // frame f list at f*HW: u | v << 16
+    const int* n_src;         // valid source pixels per frame
+    const int* item_base;     // per frame: index of its first work item (global)
+    const int* n_tiles;       // per frame: tiles of its source list
+    float* partials;          // dense partial records (global item index)
+    float* fpartials;         // feature partial records per set
+    const float4* fpts;       // per match: p_m then p_n (w = 1 valid)
+    const int4* fsets;        // per set: {i, j, first match, count}
+    const int* set_of;        // N*N: feature set of node pair, or -1
+    float* xf32;              // per ordered pair: A (12) then B (12), rows of [R|t]
+    double* xf64;             // per ordered pair: A (12)
+    float* tinv32;            // per node: T^-1 (12)
+    double* poses;            // N * 16
+    double* Hm;               // 6N * 6N normal matrix, row-major
+    double* grad;             // 6N
+    double* node_stats;       // N * kNodeStats
+    const int* free_ids;      // n_free node ids
+    int* status;              // sticky status bits
+    int* iters_done;
+    double* iter_stats;       // kMaxIters * kIterRecord
+    const __half* mlp;        // learned weighting parameters (fp16)
+};
+
+__host__ __device__ inline int pair_index(int i, int j, int n) { return i * (n - 1) + (j < i ? j : j - 1); }
+
+}  // namespace pg

@@ -1,0 +1,1024 @@
+// Host side of the C ABI declared in include/posegraph.h: argument checking,
+// device buffers, the per-graph work tables, the Gauss-Newton schedule (plain
+// launches or a captured hipGraph) and the batched path.
+#include "pg_device.hpp"
+#include "posegraph.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace pg {
+void launch_preprocess(const float* depth, const uint8_t* mask, int W, int H, float cx, float cy, float ifx,
+                       float ify, float4* map, uint8_t* flag, int* row_cnt, int* total, float4* src_nz,
+                       uint32_t* src_uv, hipStream_t st);
+void launch_match_points(const float* di, const uint8_t* mi, const float* dj, const uint8_t* mj, int W, int H,
+                         float cx, float cy, float ifx, float ify, const float* uvi, const float* uvj, int n,
+                         float4* out, hipStream_t st);
+int assoc_ppt_supported(int ppt);
+void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, hipStream_t st);
+void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int* target, float* r, float* uv,
+                        hipStream_t st);
+void launch_feature(const GraphDev* gds, const int2* fitems, int n, hipStream_t st);
+void launch_assemble(const GraphDev* gds, const int2* nbs, int n, hipStream_t st);
+size_t solve_lds_bytes(int n_free, int n_frames);
+hipError_t solve_set_max_lds(size_t bytes);
+void launch_solve(const GraphDev* gds, int n_graphs, size_t lds, int mode, hipStream_t st);
+}  // namespace pg
+
+using namespace pg;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// RAII device buffer
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p)
+            (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n)
+    {
+        if (n <= bytes && p)
+            return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n ? n : 16);
+        if (e == hipSuccess)
+            bytes = n ? n : 16;
+        return e;
+    }
+    template <class T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+struct MatchSetHost {
+    int i = 0, j = 0, n = 0;
+    DevBuf pts;   // 2n float4
+};
+
+// Tables and buffers of one schedule (a single graph or a batch).
+struct Schedule {
+    std::vector<pg_graph*> graphs;
+    std::vector<unsigned long long> versions;
+    DevBuf gds, items, fitems, nbs;
+    int n_items = 0, n_fitems = 0, n_nbs = 0;
+    size_t lds = 0;
+    int ppt = 4;
+    int iters = 0;
+    hipGraphExec_t exec = nullptr;
+    ~Schedule()
+    {
+        if (exec)
+            (void)hipGraphExecDestroy(exec);
+    }
+};
+
+}  // namespace
+
+struct pg_graph {
+    pg_config cfg;
+    pg_camera cam;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int device = 0;
+    int HW = 0;
+    std::string err;
+    unsigned long long version = 1;   // bumped whenever the schedule must be rebuilt
+
+    int n_frames = 0;
+    std::vector<int> fixed;
+    std::vector<int> n_src;
+    std::vector<double> poses;        // host mirror, 16 per node
+
+    // per-frame device data (max_frames slots)
+    DevBuf depth, mask, maps, src_nz, src_uv, flag, rowcnt, total;
+    std::map<std::pair<int, int>, MatchSetHost> msets;
+
+    // per-optimize device state
+    DevBuf d_poses, d_partials, d_fpartials, d_fpts, d_fsets, d_set_of, d_xf32, d_xf64, d_tinv, d_H, d_grad,
+        d_node_stats, d_free_ids, d_status, d_iters, d_iter_stats, d_n_src, d_item_base, d_n_tiles, d_mlp;
+    bool poses_dirty = true;          // host mirror newer than d_poses
+    int n_sets = 0, n_free = 0, n_items = 0, tile = 0;
+    unsigned long long tables_version = 0;   // version the tables were built for
+    std::vector<int> item_base, n_tiles;
+    std::vector<WorkItem> items;      // local items (graph field 0)
+    std::vector<int4> fsets;
+    bool has_mlp = false;
+
+    std::unique_ptr<Schedule> sched;  // single-graph schedule cache
+    // pinned readback
+    int* h_status = nullptr;
+    int* h_iters = nullptr;
+    double* h_iter_stats = nullptr;
+    double* h_poses = nullptr;
+};
+
+namespace {
+
+std::mutex g_batch_mutex;
+std::vector<std::unique_ptr<Schedule>> g_batch_cache;
+
+pg_status fail(pg_graph* g, pg_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (g)
+        g->err = buf;
+    else
+        g_create_error = buf;
+    return s;
+}
+
+#define HIP_OR_FAIL(g, call)                                                                             \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess)                                                                            \
+            return fail((g), e_ == hipErrorOutOfMemory ? PG_ERR_OUT_OF_MEMORY : PG_ERR_HIP, "%s: %s",   \
+                        #call, hipGetErrorString(e_));                                                   \
+    } while (0)
+
+bool finite_pose(const double* T)
+{
+    for (int k = 0; k < 16; ++k)
+        if (!isfinite(T[k]))
+            return false;
+    if (T[12] != 0.0 || T[13] != 0.0 || T[14] != 0.0 || T[15] != 1.0)
+        return false;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k)
+                s += T[4 * k + a] * T[4 * k + b];
+            if (fabs(s - (a == b ? 1.0 : 0.0)) > 1e-6)
+                return false;
+        }
+    const double det = T[0] * (T[5] * T[10] - T[6] * T[9]) - T[1] * (T[4] * T[10] - T[6] * T[8]) +
+                       T[2] * (T[4] * T[9] - T[5] * T[8]);
+    return det > 0.0;
+}
+
+bool is_device_ptr(const void* p)
+{
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice;
+}
+
+// copy 'bytes' from a host or device pointer into device memory on the stream
+hipError_t copy_in(void* dst, const void* src, size_t bytes, hipStream_t st)
+{
+    return hipMemcpyAsync(dst, src, bytes, is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          st);
+}
+
+int pick_tile(const pg_graph* g, int* ppt)
+{
+    int t = g->cfg.tile_pixels;
+    if (t <= 0)
+        t = 1024;
+    // tile = 256 threads x PPT pixels
+    int p = t / kAssocThreads;
+    if (p < 1)
+        p = 1;
+    if (!assoc_ppt_supported(p))
+        p = (p >= 8) ? 8 : (p >= 4) ? 4 : (p >= 2) ? 2 : 1;
+    *ppt = p;
+    return p * kAssocThreads;
+}
+
+// (Re)build the graph's tables and device state for the current frames/matches.
+pg_status prepare_graph(pg_graph* g)
+{
+    const int N = g->n_frames;
+    if (N < 1)
+        return fail(g, PG_ERR_INVALID_ARG, "graph has no frames");
+    int ppt;
+    const int tile = pick_tile(g, &ppt);
+    if (g->tables_version == g->version && g->tile == tile)
+        return PG_OK;
+    g->tile = tile;
+    // free nodes
+    std::vector<int> free_ids;
+    for (int f = 0; f < N; ++f)
+        if (!g->fixed[f])
+            free_ids.push_back(f);
+    g->n_free = (int)free_ids.size();
+    // dense work items, ordered (source frame, tile, target frame)
+    g->items.clear();
+    g->item_base.assign(N, 0);
+    g->n_tiles.assign(N, 0);
+    int slot = 0;
+    for (int i = 0; i < N && N > 1; ++i) {
+        const int nt = (g->n_src[i] + tile - 1) / tile;
+        g->item_base[i] = slot;
+        g->n_tiles[i] = nt;
+        for (int t = 0; t < nt; ++t)
+            for (int j = 0; j < N; ++j) {
+                if (j == i)
+                    continue;
+                WorkItem w;
+                w.gij = i | (j << 8);
+                w.start = t * tile;
+                w.count = std::min(tile, g->n_src[i] - t * tile);
+                w.slot = slot++;
+                g->items.push_back(w);
+            }
+    }
+    g->n_items = slot;
+    // feature sets, in (i, j) order
+    g->fsets.clear();
+    std::vector<int> set_of(N * N, -1);
+    size_t total_m = 0;
+    for (auto& kv : g->msets)
+        total_m += kv.second.n;
+    HIP_OR_FAIL(g, g->d_fpts.ensure(sizeof(float4) * 2 * std::max<size_t>(total_m, 1)));
+    size_t off = 0;
+    for (auto& kv : g->msets) {
+        MatchSetHost& m = kv.second;
+        if (m.n <= 0)
+            continue;
+        set_of[m.i * N + m.j] = set_of[m.j * N + m.i] = (int)g->fsets.size();
+        g->fsets.push_back(make_int4(m.i, m.j, (int)off, m.n));
+        HIP_OR_FAIL(g, hipMemcpyAsync(g->d_fpts.as<float4>() + 2 * off, m.pts.p, sizeof(float4) * 2 * m.n,
+                                      hipMemcpyDeviceToDevice, g->stream));
+        off += m.n;
+    }
+    g->n_sets = (int)g->fsets.size();
+    const int P = N * (N - 1);
+    HIP_OR_FAIL(g, g->d_partials.ensure(sizeof(float) * kDenseStride * std::max(g->n_items, 1)));
+    HIP_OR_FAIL(g, g->d_fpartials.ensure(sizeof(float) * kFeatStride * std::max(g->n_sets, 1)));
+    HIP_OR_FAIL(g, g->d_fsets.ensure(sizeof(int4) * std::max(g->n_sets, 1)));
+    HIP_OR_FAIL(g, g->d_set_of.ensure(sizeof(int) * N * N));
+    HIP_OR_FAIL(g, g->d_xf32.ensure(sizeof(float) * 24 * std::max(P, 1)));
+    HIP_OR_FAIL(g, g->d_xf64.ensure(sizeof(double) * 12 * std::max(P, 1)));
+    HIP_OR_FAIL(g, g->d_tinv.ensure(sizeof(float) * 12 * N));
+    HIP_OR_FAIL(g, g->d_H.ensure(sizeof(double) * 36 * N * N));
+    HIP_OR_FAIL(g, g->d_grad.ensure(sizeof(double) * 6 * N));
+    HIP_OR_FAIL(g, g->d_node_stats.ensure(sizeof(double) * kNodeStats * N));
+    HIP_OR_FAIL(g, g->d_free_ids.ensure(sizeof(int) * std::max(g->n_free, 1)));
+    HIP_OR_FAIL(g, g->d_n_src.ensure(sizeof(int) * N));
+    HIP_OR_FAIL(g, g->d_item_base.ensure(sizeof(int) * N));
+    HIP_OR_FAIL(g, g->d_n_tiles.ensure(sizeof(int) * N));
+    if (g->n_sets)
+        HIP_OR_FAIL(g, hipMemcpyAsync(g->d_fsets.p, g->fsets.data(), sizeof(int4) * g->n_sets,
+                                      hipMemcpyHostToDevice, g->stream));
+    HIP_OR_FAIL(g, hipMemcpyAsync(g->d_set_of.p, set_of.data(), sizeof(int) * N * N, hipMemcpyHostToDevice,
+                                  g->stream));
+    if (g->n_free)
+        HIP_OR_FAIL(g, hipMemcpyAsync(g->d_free_ids.p, free_ids.data(), sizeof(int) * g->n_free,
+                                      hipMemcpyHostToDevice, g->stream));
+    HIP_OR_FAIL(g, hipMemcpyAsync(g->d_n_src.p, g->n_src.data(), sizeof(int) * N, hipMemcpyHostToDevice,
+                                  g->stream));
+    HIP_OR_FAIL(g, hipMemcpyAsync(g->d_item_base.p, g->item_base.data(), sizeof(int) * N, hipMemcpyHostToDevice,
+                                  g->stream));
+    HIP_OR_FAIL(g, hipMemcpyAsync(g->d_n_tiles.p, g->n_tiles.data(), sizeof(int) * N, hipMemcpyHostToDevice,
+                                  g->stream));
+    // the host copies above read pageable host vectors that stay alive; make
+    // sure they completed before the vectors may change
+    HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    g->tables_version = g->version;
+    return PG_OK;
+}
+
+GraphDev make_dev(pg_graph* g)
+{
+    GraphDev d;
+    memset(&d, 0, sizeof(d));
+    d.W = g->cam.width;
+    d.H = g->cam.height;
+    d.HW = g->HW;
+    d.n_frames = g->n_frames;
+    d.fx = (float)g->cam.fx;
+    d.fy = (float)g->cam.fy;
+    d.cx = (float)g->cam.cx;
+    d.cy = (float)g->cam.cy;
+    d.ifx = (float)(1.0 / g->cam.fx);
+    d.ify = (float)(1.0 / g->cam.fy);
+    d.lambda_f = (float)g->cfg.lambda_f;
+    d.lambda_g = (float)g->cfg.lambda_g;
+    d.huber_f = (float)g->cfg.huber_f_m;
+    d.huber_g = (float)g->cfg.huber_g_m;
+    d.gate_d2 = (float)(g->cfg.gate_dist_m * g->cfg.gate_dist_m);
+    d.gate_cos = (float)cos(g->cfg.gate_normal_rad);
+    d.n_sets = g->n_sets;
+    d.n_free = g->n_free;
+    d.precision = g->cfg.precision;
+    d.weighting = g->cfg.weighting;
+    d.solver = g->cfg.solver;
+    d.pcg_max_iters = g->cfg.pcg_max_iters;
+    d.pcg_rel_tol = g->cfg.pcg_rel_tol;
+    d.maps = g->maps.as<float4>();
+    d.src_nz = g->src_nz.as<float4>();
+    d.src_uv = g->src_uv.as<uint32_t>();
+    d.n_src = g->d_n_src.as<int>();
+    d.item_base = g->d_item_base.as<int>();
+    d.n_tiles = g->d_n_tiles.as<int>();
+    d.partials = g->d_partials.as<float>();
+    d.fpartials = g->d_fpartials.as<float>();
+    d.fpts = g->d_fpts.as<float4>();
+    d.fsets = g->d_fsets.as<int4>();
+    d.set_of = g->d_set_of.as<int>();
+    d.xf32 = g->d_xf32.as<float>();
+    d.xf64 = g->d_xf64.as<double>();
+    d.tinv32 = g->d_tinv.as<float>();
+    d.poses = g->d_poses.as<double>();
+    d.Hm = g->d_H.as<double>();
+    d.grad = g->d_grad.as<double>();
+    d.node_stats = g->d_node_stats.as<double>();
+    d.free_ids = g->d_free_ids.as<int>();
+    d.status = g->d_status.as<int>();
+    d.iters_done = g->d_iters.as<int>();
+    d.iter_stats = g->d_iter_stats.as<double>();
+    d.mlp = g->d_mlp.as<__half>();
+    return d;
+}
+
+pg_status upload_poses(pg_graph* g)
+{
+    if (!g->poses_dirty)
+        return PG_OK;
+    HIP_OR_FAIL(g, hipMemcpyAsync(g->d_poses.p, g->poses.data(), sizeof(double) * 16 * g->n_frames,
+                                  hipMemcpyHostToDevice, g->stream));
+    HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    g->poses_dirty = false;
+    return PG_OK;
+}
+
+// Build a schedule (device tables of all graphs) for one graph or a batch.
+pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
+{
+    pg_graph* g0 = gs[0];
+    s.graphs = gs;
+    s.versions.clear();
+    std::vector<GraphDev> devs;
+    std::vector<WorkItem> items;
+    std::vector<int2> fitems, nbs;
+    size_t lds = 0;
+    int ppt = 4;
+    for (size_t k = 0; k < gs.size(); ++k) {
+        pg_graph* g = gs[k];
+        pg_status st = prepare_graph(g);
+        if (st != PG_OK)
+            return st;
+        s.versions.push_back(g->version);
+        int p;
+        pick_tile(g, &p);
+        if (k == 0)
+            ppt = p;
+        else if (p != ppt)
+            return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must use one tile size");
+        devs.push_back(make_dev(g));
+        for (const WorkItem& w : g->items) {
+            WorkItem v = w;
+            v.gij |= (int)k << 16;
+            items.push_back(v);
+        }
+        for (int t = 0; t < g->n_sets; ++t)
+            fitems.push_back(make_int2((int)k, t));
+        for (int I = 0; I < g->n_frames; ++I)
+            for (int J = 0; J <= I; ++J)
+                nbs.push_back(make_int2((int)k, I | (J << 8)));
+        lds = std::max(lds, solve_lds_bytes(g->n_free, g->n_frames));
+    }
+    // items of all graphs are concatenated; the XCD mapping of the association
+    // kernel hands each XCD a contiguous run of them
+    s.n_items = (int)items.size();
+    s.n_fitems = (int)fitems.size();
+    s.n_nbs = (int)nbs.size();
+    s.lds = lds;
+    s.ppt = ppt;
+    HIP_OR_FAIL(g0, s.gds.ensure(sizeof(GraphDev) * devs.size()));
+    HIP_OR_FAIL(g0, s.items.ensure(sizeof(WorkItem) * std::max<size_t>(items.size(), 1)));
+    HIP_OR_FAIL(g0, s.fitems.ensure(sizeof(int2) * std::max<size_t>(fitems.size(), 1)));
+    HIP_OR_FAIL(g0, s.nbs.ensure(sizeof(int2) * std::max<size_t>(nbs.size(), 1)));
+    hipStream_t st = g0->stream;
+    HIP_OR_FAIL(g0, hipMemcpyAsync(s.gds.p, devs.data(), sizeof(GraphDev) * devs.size(), hipMemcpyHostToDevice, st));
+    if (!items.empty())
+        HIP_OR_FAIL(g0, hipMemcpyAsync(s.items.p, items.data(), sizeof(WorkItem) * items.size(),
+                                       hipMemcpyHostToDevice, st));
+    if (!fitems.empty())
+        HIP_OR_FAIL(g0, hipMemcpyAsync(s.fitems.p, fitems.data(), sizeof(int2) * fitems.size(),
+                                       hipMemcpyHostToDevice, st));
+    if (!nbs.empty())
+        HIP_OR_FAIL(g0, hipMemcpyAsync(s.nbs.p, nbs.data(), sizeof(int2) * nbs.size(), hipMemcpyHostToDevice, st));
+    HIP_OR_FAIL(g0, hipStreamSynchronize(st));
+    if (s.exec) {
+        (void)hipGraphExecDestroy(s.exec);
+        s.exec = nullptr;
+    }
+    return PG_OK;
+}
+
+// Enqueue the whole optimisation: prepare, then per iteration the four phases.
+void enqueue_iters(const Schedule& s, int iters, hipStream_t st)
+{
+    const GraphDev* gds = s.gds.as<GraphDev>();
+    const int ng = (int)s.graphs.size();
+    launch_solve(gds, ng, s.lds, 1, st);
+    for (int it = 0; it < iters; ++it) {
+        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, st);
+        launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
+        launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
+        launch_solve(gds, ng, s.lds, 0, st);
+    }
+}
+
+struct Timers {
+    std::vector<hipEvent_t> ev;
+    ~Timers()
+    {
+        for (auto e : ev)
+            (void)hipEventDestroy(e);
+    }
+    hipEvent_t make()
+    {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        ev.push_back(e);
+        return e;
+    }
+};
+
+pg_status run_schedule(Schedule& s, int iters, bool use_graph, bool timing, std::vector<pg_stats*>& stats)
+{
+    pg_graph* g0 = s.graphs[0];
+    hipStream_t st = g0->stream;
+    for (pg_graph* g : s.graphs) {
+        pg_status r = upload_poses(g);
+        if (r != PG_OK)
+            return r;
+    }
+    float ms[5] = {0, 0, 0, 0, 0};
+    int n_assoc = 0;
+    if (timing) {
+        // events around every launch, on the launch stream
+        Timers T;
+        const GraphDev* gds = s.gds.as<GraphDev>();
+        const int ng = (int)s.graphs.size();
+        hipEvent_t e0 = T.make();
+        HIP_OR_FAIL(g0, hipEventRecord(e0, st));
+        launch_solve(gds, ng, s.lds, 1, st);
+        std::vector<hipEvent_t> marks;
+        for (int it = 0; it < iters; ++it) {
+            hipEvent_t a = T.make(), b = T.make(), c = T.make(), d = T.make(), e = T.make();
+            HIP_OR_FAIL(g0, hipEventRecord(a, st));
+            launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, st);
+            HIP_OR_FAIL(g0, hipEventRecord(b, st));
+            launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
+            HIP_OR_FAIL(g0, hipEventRecord(c, st));
+            launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
+            HIP_OR_FAIL(g0, hipEventRecord(d, st));
+            launch_solve(gds, ng, s.lds, 0, st);
+            HIP_OR_FAIL(g0, hipEventRecord(e, st));
+            marks.insert(marks.end(), {a, b, c, d, e});
+        }
+        HIP_OR_FAIL(g0, hipGetLastError());
+        HIP_OR_FAIL(g0, hipStreamSynchronize(st));
+        for (int it = 0; it < iters; ++it) {
+            float t;
+            for (int k = 0; k < 4; ++k) {
+                HIP_OR_FAIL(g0, hipEventElapsedTime(&t, marks[5 * it + k], marks[5 * it + k + 1]));
+                ms[k] += t;
+            }
+        }
+        float tot;
+        HIP_OR_FAIL(g0, hipEventElapsedTime(&tot, e0, marks.empty() ? e0 : marks.back()));
+        ms[4] = tot;
+        n_assoc = s.n_items > 0 ? iters : 0;
+    } else if (use_graph) {
+        if (!s.exec || s.iters != iters) {
+            if (s.exec) {
+                (void)hipGraphExecDestroy(s.exec);
+                s.exec = nullptr;
+            }
+            hipStream_t cs = g0->capture_stream;
+            HIP_OR_FAIL(g0, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            enqueue_iters(s, iters, cs);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(cs, &graph);
+            if (e != hipSuccess)
+                return fail(g0, PG_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&s.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                s.exec = nullptr;
+                return fail(g0, PG_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+            }
+            s.iters = iters;
+        }
+        HIP_OR_FAIL(g0, hipGraphLaunch(s.exec, st));
+    } else {
+        enqueue_iters(s, iters, st);
+        HIP_OR_FAIL(g0, hipGetLastError());
+    }
+    // read back poses and statistics of every graph
+    for (pg_graph* g : s.graphs) {
+        HIP_OR_FAIL(g0, hipMemcpyAsync(g->h_poses, g->d_poses.p, sizeof(double) * 16 * g->n_frames,
+                                       hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(g0, hipMemcpyAsync(g->h_status, g->d_status.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(g0, hipMemcpyAsync(g->h_iters, g->d_iters.p, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(g0, hipMemcpyAsync(g->h_iter_stats, g->d_iter_stats.p, sizeof(double) * kIterRecord * iters,
+                                       hipMemcpyDeviceToHost, st));
+    }
+    HIP_OR_FAIL(g0, hipStreamSynchronize(st));
+    pg_status ret = PG_OK;
+    for (size_t k = 0; k < s.graphs.size(); ++k) {
+        pg_graph* g = s.graphs[k];
+        memcpy(g->poses.data(), g->h_poses, sizeof(double) * 16 * g->n_frames);
+        pg_status r = PG_OK;
+        if (*g->h_status & kStatusSingular)
+            r = fail(g, PG_ERR_SINGULAR, "normal equations not positive definite at iteration %d", *g->h_iters);
+        else if (*g->h_status & kStatusNonFinite)
+            r = fail(g, PG_ERR_NONFINITE, "non-finite update at iteration %d", *g->h_iters);
+        if (ret == PG_OK)
+            ret = r;
+        pg_stats* out = stats[k];
+        if (out) {
+            memset(out, 0, sizeof(*out));
+            out->iters_done = *g->h_iters;
+            const int rec = std::min(iters, *g->h_iters + (r != PG_OK ? 1 : 0));
+            for (int it = 0; it < rec && it < PG_MAX_ITERS; ++it) {
+                out->energy_f[it] = g->h_iter_stats[kIterRecord * it + 0];
+                out->energy_g[it] = g->h_iter_stats[kIterRecord * it + 1];
+                out->n_valid_g[it] = (long long)g->h_iter_stats[kIterRecord * it + 2];
+                out->n_valid_f[it] = (long long)g->h_iter_stats[kIterRecord * it + 3];
+            }
+            out->status_bits = *g->h_status;
+            long long sp = 0;
+            for (int f = 0; f < g->n_frames; ++f)
+                sp += (long long)g->n_src[f] * (g->n_frames - 1);
+            out->src_pixels = sp;
+            out->n_assoc_launches = n_assoc;
+            out->ms_assoc = ms[0];
+            out->ms_feature = ms[1];
+            out->ms_reduce = ms[2];
+            out->ms_solve = ms[3];
+            out->ms_total = ms[4];
+        }
+    }
+    return ret;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+void pg_config_default(pg_config* c)
+{
+    if (!c)
+        return;
+    memset(c, 0, sizeof(*c));
+    c->max_frames = 16;
+    c->gn_iters = 7;
+    c->lambda_f = 1.0;
+    c->lambda_g = 1.0;
+    c->huber_f_m = 0.005;
+    c->huber_g_m = 0.005;
+    c->gate_dist_m = 0.01;
+    c->gate_normal_rad = 30.0 * M_PI / 180.0;
+    c->solver = PG_SOLVER_CHOLESKY;
+    c->pcg_max_iters = 500;
+    c->pcg_rel_tol = 1e-12;
+    c->weighting = PG_WEIGHT_HUBER;
+    c->precision = PG_PREC_FP32;
+    c->use_graph = 1;
+    c->timing = 0;
+    c->tile_pixels = 0;
+    c->prune_frac = 0.25;
+}
+
+pg_status pose_graph_create(const pg_config* cfg, const pg_camera* cam, void* hip_stream, pg_graph** out)
+{
+    if (!out)
+        return fail(nullptr, PG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!cfg || !cam)
+        return fail(nullptr, PG_ERR_INVALID_ARG, "cfg and cam are required");
+    if (cam->width < 3 || cam->height < 3 || cam->width > 8192 || cam->height > 8192)
+        return fail(nullptr, PG_ERR_INVALID_ARG, "image size %dx%d out of range", cam->width, cam->height);
+    if (!(cam->fx > 0 && cam->fy > 0 && isfinite(cam->fx) && isfinite(cam->fy) && isfinite(cam->cx) &&
+          isfinite(cam->cy)))
+        return fail(nullptr, PG_ERR_INVALID_ARG, "bad intrinsics");
+    if (cfg->max_frames < 2 || cfg->max_frames > PG_MAX_FRAMES_LIMIT)
+        return fail(nullptr, PG_ERR_INVALID_ARG, "max_frames %d out of [2, %d]", cfg->max_frames,
+                    PG_MAX_FRAMES_LIMIT);
+    if (cfg->gn_iters < 0 || cfg->gn_iters > PG_MAX_ITERS)
+        return fail(nullptr, PG_ERR_INVALID_ARG, "gn_iters %d out of [0, %d]", cfg->gn_iters, PG_MAX_ITERS);
+    if (!(cfg->huber_f_m > 0 && cfg->huber_g_m > 0 && cfg->gate_dist_m > 0 && cfg->gate_normal_rad > 0 &&
+          cfg->gate_normal_rad <= M_PI && cfg->lambda_f >= 0 && cfg->lambda_g >= 0))
+        return fail(nullptr, PG_ERR_INVALID_ARG, "bad method parameters");
+    if (cfg->solver != PG_SOLVER_CHOLESKY && cfg->solver != PG_SOLVER_PCG)
+        return fail(nullptr, PG_ERR_INVALID_ARG, "unknown solver");
+    if (cfg->weighting != PG_WEIGHT_HUBER && cfg->weighting != PG_WEIGHT_LEARNED)
+        return fail(nullptr, PG_ERR_INVALID_ARG, "unknown weighting");
+    if (cfg->precision != PG_PREC_FP32 && cfg->precision != PG_PREC_BF16X3)
+        return fail(nullptr, PG_ERR_INVALID_ARG, "unknown precision");
+    if (cfg->tile_pixels < 0 || cfg->tile_pixels > kTileMaxPixels)
+        return fail(nullptr, PG_ERR_INVALID_ARG, "tile_pixels out of range");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(nullptr, PG_ERR_NO_DEVICE, "no HIP device");
+    }
+    pg_graph* g = new (std::nothrow) pg_graph();
+    if (!g)
+        return fail(nullptr, PG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    g->cfg = *cfg;
+    g->cam = *cam;
+    g->stream = (hipStream_t)hip_stream;
+    g->HW = cam->width * cam->height;
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return fail(nullptr, PG_ERR_NO_DEVICE, "hipGetDevice failed");
+    }
+    // LDS of the solve for a window of max_frames nodes with one fixed
+    int lds_max = 0;
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device);
+    const size_t need = solve_lds_bytes(cfg->max_frames - 1, cfg->max_frames) + 4096;
+    if (need > (size_t)lds_max) {
+        delete g;
+        return fail(nullptr, PG_ERR_CAPACITY, "max_frames %d needs %zu B of LDS for the solve, device has %d",
+                    cfg->max_frames, need, lds_max);
+    }
+    if (need > 65536 && solve_set_max_lds(need) != hipSuccess) {
+        (void)hipGetLastError();
+        delete g;
+        return fail(nullptr, PG_ERR_CAPACITY, "cannot raise the solve kernel's LDS limit to %zu B", need);
+    }
+    const size_t M = cfg->max_frames, HW = g->HW;
+    hipError_t e = hipSuccess;
+    if ((e = g->depth.ensure(sizeof(float) * M * HW)) != hipSuccess ||
+        (e = g->mask.ensure(M * HW)) != hipSuccess || (e = g->maps.ensure(sizeof(float4) * M * HW)) != hipSuccess ||
+        (e = g->src_nz.ensure(sizeof(float4) * M * HW)) != hipSuccess ||
+        (e = g->src_uv.ensure(sizeof(uint32_t) * M * HW)) != hipSuccess || (e = g->flag.ensure(HW)) != hipSuccess ||
+        (e = g->rowcnt.ensure(sizeof(int) * cam->height)) != hipSuccess ||
+        (e = g->total.ensure(sizeof(int))) != hipSuccess ||
+        (e = g->d_poses.ensure(sizeof(double) * 16 * M)) != hipSuccess ||
+        (e = g->d_status.ensure(sizeof(int))) != hipSuccess || (e = g->d_iters.ensure(sizeof(int))) != hipSuccess ||
+        (e = g->d_iter_stats.ensure(sizeof(double) * kIterRecord * kMaxIters)) != hipSuccess ||
+        (e = g->d_mlp.ensure(2 * 1320)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&g->h_status, sizeof(int) * 2 + sizeof(double) * (kIterRecord * kMaxIters + 16 * M))) !=
+            hipSuccess) {
+        pose_graph_destroy(g);
+        return fail(nullptr, e == hipErrorOutOfMemory ? PG_ERR_OUT_OF_MEMORY : PG_ERR_HIP, "allocation: %s",
+                    hipGetErrorString(e));
+    }
+    g->h_iters = g->h_status + 1;
+    g->h_iter_stats = (double*)(g->h_status + 2);
+    g->h_poses = g->h_iter_stats + kIterRecord * kMaxIters;
+    if ((e = hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
+        pose_graph_destroy(g);
+        return fail(nullptr, PG_ERR_HIP, "stream: %s", hipGetErrorString(e));
+    }
+    if ((e = hipMemsetAsync(g->d_status.p, 0, sizeof(int), g->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(g->d_iters.p, 0, sizeof(int), g->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(g->stream)) != hipSuccess) {
+        pose_graph_destroy(g);
+        return fail(nullptr, PG_ERR_HIP, "init: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return PG_OK;
+}
+
+pg_status pose_graph_add_frame(pg_graph* g, const float* depth_m, const uint8_t* mask, const double T[16], int fixed,
+                               int* out_id)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (!depth_m || !mask || !T)
+        return fail(g, PG_ERR_INVALID_ARG, "depth, mask and pose are required");
+    if (!finite_pose(T))
+        return fail(g, PG_ERR_INVALID_ARG, "pose is not a rigid transform");
+    if (g->n_frames >= g->cfg.max_frames)
+        return fail(g, PG_ERR_CAPACITY, "graph holds max_frames = %d frames", g->cfg.max_frames);
+    const int f = g->n_frames;
+    const size_t HW = g->HW;
+    float* d = g->depth.as<float>() + f * HW;
+    uint8_t* m = g->mask.as<uint8_t>() + f * HW;
+    HIP_OR_FAIL(g, copy_in(d, depth_m, sizeof(float) * HW, g->stream));
+    HIP_OR_FAIL(g, copy_in(m, mask, HW, g->stream));
+    launch_preprocess(d, m, g->cam.width, g->cam.height, (float)g->cam.cx, (float)g->cam.cy, (float)(1.0 / g->cam.fx),
+                      (float)(1.0 / g->cam.fy), g->maps.as<float4>() + f * HW, g->flag.as<uint8_t>(),
+                      g->rowcnt.as<int>(), g->total.as<int>(), g->src_nz.as<float4>() + f * HW,
+                      g->src_uv.as<uint32_t>() + f * HW, g->stream);
+    HIP_OR_FAIL(g, hipGetLastError());
+    int nv = 0;
+    HIP_OR_FAIL(g, hipMemcpyAsync(&nv, g->total.p, sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    g->n_frames = f + 1;
+    g->fixed.push_back(fixed ? 1 : 0);
+    g->n_src.push_back(nv);
+    g->poses.insert(g->poses.end(), T, T + 16);
+    g->poses_dirty = true;
+    g->version++;
+    if (out_id)
+        *out_id = f;
+    return PG_OK;
+}
+
+pg_status pose_graph_add_matches(pg_graph* g, int id_i, int id_j, const float* uv_i, const float* uv_j, int n)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (id_i < 0 || id_j < 0 || id_i >= g->n_frames || id_j >= g->n_frames || id_i == id_j)
+        return fail(g, PG_ERR_INVALID_ARG, "bad node pair (%d, %d)", id_i, id_j);
+    if (n < 0 || (n > 0 && (!uv_i || !uv_j)))
+        return fail(g, PG_ERR_INVALID_ARG, "bad match arrays");
+    if (id_i > id_j) {
+        std::swap(id_i, id_j);
+        std::swap(uv_i, uv_j);
+    }
+    const auto key = std::make_pair(id_i, id_j);
+    g->version++;
+    if (n == 0) {
+        g->msets.erase(key);
+        return PG_OK;
+    }
+    MatchSetHost& ms = g->msets[key];
+    ms.i = id_i;
+    ms.j = id_j;
+    ms.n = n;
+    DevBuf uvbuf;
+    HIP_OR_FAIL(g, uvbuf.ensure(sizeof(float) * 4 * n));
+    HIP_OR_FAIL(g, ms.pts.ensure(sizeof(float4) * 2 * n));
+    float* ui = uvbuf.as<float>();
+    float* uj = ui + 2 * n;
+    HIP_OR_FAIL(g, copy_in(ui, uv_i, sizeof(float) * 2 * n, g->stream));
+    HIP_OR_FAIL(g, copy_in(uj, uv_j, sizeof(float) * 2 * n, g->stream));
+    const size_t HW = g->HW;
+    launch_match_points(g->depth.as<float>() + id_i * HW, g->mask.as<uint8_t>() + id_i * HW,
+                        g->depth.as<float>() + id_j * HW, g->mask.as<uint8_t>() + id_j * HW, g->cam.width,
+                        g->cam.height, (float)g->cam.cx, (float)g->cam.cy, (float)(1.0 / g->cam.fx),
+                        (float)(1.0 / g->cam.fy), ui, uj, n, ms.pts.as<float4>(), g->stream);
+    HIP_OR_FAIL(g, hipGetLastError());
+    HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    return PG_OK;
+}
+
+pg_status pose_graph_set_pose(pg_graph* g, int id, const double T[16])
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (id < 0 || id >= g->n_frames || !T)
+        return fail(g, PG_ERR_INVALID_ARG, "bad node id %d", id);
+    if (!finite_pose(T))
+        return fail(g, PG_ERR_INVALID_ARG, "pose is not a rigid transform");
+    memcpy(g->poses.data() + 16 * id, T, sizeof(double) * 16);
+    g->poses_dirty = true;
+    return PG_OK;
+}
+
+pg_status pose_graph_get_pose(const pg_graph* g, int id, double T[16])
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (id < 0 || id >= g->n_frames || !T)
+        return fail(const_cast<pg_graph*>(g), PG_ERR_INVALID_ARG, "bad node id %d", id);
+    memcpy(T, g->poses.data() + 16 * id, sizeof(double) * 16);
+    return PG_OK;
+}
+
+int pose_graph_num_frames(const pg_graph* g) { return g ? g->n_frames : 0; }
+
+pg_status pose_graph_optimize(pg_graph* g, pg_stats* stats)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (g->cfg.weighting == PG_WEIGHT_LEARNED || g->cfg.precision == PG_PREC_BF16X3)
+        return fail(g, PG_ERR_INVALID_ARG, "learned weighting / BF16x3 precision are not available in this build");
+    if (!g->sched)
+        g->sched.reset(new (std::nothrow) Schedule());
+    if (!g->sched)
+        return fail(g, PG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    pg_status r = prepare_graph(g);
+    if (r != PG_OK)
+        return r;
+    if (g->sched->versions.empty() || g->sched->versions[0] != g->version) {
+        r = build_schedule({g}, *g->sched);
+        if (r != PG_OK)
+            return r;
+    }
+    std::vector<pg_stats*> st{stats};
+    return run_schedule(*g->sched, g->cfg.gn_iters, g->cfg.use_graph != 0, g->cfg.timing != 0, st);
+}
+
+pg_status pose_graph_optimize_batch(pg_graph* const* graphs, int n_graphs, pg_stats* stats)
+{
+    if (!graphs || n_graphs < 1)
+        return fail(nullptr, PG_ERR_INVALID_ARG, "no graphs");
+    std::vector<pg_graph*> gs(graphs, graphs + n_graphs);
+    for (pg_graph* g : gs)
+        if (!g)
+            return fail(nullptr, PG_ERR_INVALID_ARG, "NULL graph in batch");
+    pg_graph* g0 = gs[0];
+    for (pg_graph* g : gs) {
+        if (g->stream != g0->stream || g->device != g0->device)
+            return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must share one device and stream");
+        if (g->cfg.gn_iters != g0->cfg.gn_iters)
+            return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must share gn_iters");
+        if (g->cfg.weighting == PG_WEIGHT_LEARNED || g->cfg.precision == PG_PREC_BF16X3)
+            return fail(g0, PG_ERR_INVALID_ARG, "learned weighting / BF16x3 precision are not available in this build");
+    }
+    std::lock_guard<std::mutex> lk(g_batch_mutex);
+    Schedule* s = nullptr;
+    for (auto& c : g_batch_cache)
+        if (c->graphs == gs) {
+            s = c.get();
+            break;
+        }
+    if (!s) {
+        g_batch_cache.emplace_back(new Schedule());
+        s = g_batch_cache.back().get();
+        s->graphs = gs;
+    }
+    bool stale = s->versions.size() != gs.size();
+    for (size_t k = 0; !stale && k < gs.size(); ++k)
+        stale = s->versions[k] != gs[k]->version;
+    if (stale) {
+        pg_status r = build_schedule(gs, *s);
+        if (r != PG_OK)
+            return r;
+    }
+    std::vector<pg_stats*> st(gs.size(), nullptr);
+    if (stats)
+        for (int k = 0; k < n_graphs; ++k)
+            st[k] = stats + k;
+    return run_schedule(*s, g0->cfg.gn_iters, g0->cfg.use_graph != 0, g0->cfg.timing != 0, st);
+}
+
+pg_status pose_graph_linearize(pg_graph* g, double* H, double* grad, pg_stats* stats)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (!g->sched)
+        g->sched.reset(new (std::nothrow) Schedule());
+    pg_status r = prepare_graph(g);
+    if (r != PG_OK)
+        return r;
+    if (g->sched->versions.empty() || g->sched->versions[0] != g->version) {
+        r = build_schedule({g}, *g->sched);
+        if (r != PG_OK)
+            return r;
+    }
+    r = upload_poses(g);
+    if (r != PG_OK)
+        return r;
+    Schedule& s = *g->sched;
+    const GraphDev* gds = s.gds.as<GraphDev>();
+    hipStream_t st = g->stream;
+    launch_solve(gds, 1, s.lds, 1, st);
+    launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, st);
+    launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
+    launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
+    HIP_OR_FAIL(g, hipGetLastError());
+    const int N = g->n_frames;
+    std::vector<double> ns(kNodeStats * N);
+    if (H)
+        HIP_OR_FAIL(g, hipMemcpyAsync(H, g->d_H.p, sizeof(double) * 36 * N * N, hipMemcpyDeviceToHost, st));
+    if (grad)
+        HIP_OR_FAIL(g, hipMemcpyAsync(grad, g->d_grad.p, sizeof(double) * 6 * N, hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(g, hipMemcpyAsync(ns.data(), g->d_node_stats.p, sizeof(double) * kNodeStats * N,
+                                  hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(g, hipStreamSynchronize(st));
+    if (stats) {
+        memset(stats, 0, sizeof(*stats));
+        double ef = 0, eg = 0, cf = 0, cg = 0;
+        for (int k = 0; k < N; ++k) {
+            eg += ns[kNodeStats * k + 0];
+            ef += ns[kNodeStats * k + 1];
+            cg += ns[kNodeStats * k + 2];
+            cf += ns[kNodeStats * k + 3];
+        }
+        stats->energy_f[0] = ef;
+        stats->energy_g[0] = eg;
+        stats->n_valid_g[0] = (long long)cg;
+        stats->n_valid_f[0] = (long long)cf;
+        long long sp = 0;
+        for (int f = 0; f < N; ++f)
+            sp += (long long)g->n_src[f] * (N - 1);
+        stats->src_pixels = sp;
+    }
+    return PG_OK;
+}
+
+pg_status pose_graph_associate(pg_graph* g, int i, int j, int32_t* target, float* r, float* uv)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (i < 0 || j < 0 || i >= g->n_frames || j >= g->n_frames || i == j)
+        return fail(g, PG_ERR_INVALID_ARG, "bad node pair (%d, %d)", i, j);
+    if (!g->sched)
+        g->sched.reset(new (std::nothrow) Schedule());
+    pg_status rc = prepare_graph(g);
+    if (rc != PG_OK)
+        return rc;
+    if (g->sched->versions.empty() || g->sched->versions[0] != g->version) {
+        rc = build_schedule({g}, *g->sched);
+        if (rc != PG_OK)
+            return rc;
+    }
+    rc = upload_poses(g);
+    if (rc != PG_OK)
+        return rc;
+    Schedule& s = *g->sched;
+    const size_t HW = g->HW;
+    DevBuf out;
+    HIP_OR_FAIL(g, out.ensure(HW * (sizeof(int) + 3 * sizeof(float))));
+    int* dt = out.as<int>();
+    float* dr = (float*)(dt + HW);
+    float* duv = dr + HW;
+    launch_solve(s.gds.as<GraphDev>(), 1, s.lds, 1, g->stream);
+    launch_assoc_debug(s.gds.as<GraphDev>(), (int)HW, i, j, dt, dr, duv, g->stream);
+    HIP_OR_FAIL(g, hipGetLastError());
+    if (target)
+        HIP_OR_FAIL(g, hipMemcpyAsync(target, dt, HW * sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    if (r)
+        HIP_OR_FAIL(g, hipMemcpyAsync(r, dr, HW * sizeof(float), hipMemcpyDeviceToHost, g->stream));
+    if (uv)
+        HIP_OR_FAIL(g, hipMemcpyAsync(uv, duv, 2 * HW * sizeof(float), hipMemcpyDeviceToHost, g->stream));
+    HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    return PG_OK;
+}
+
+pg_status pose_graph_frame_info(pg_graph* g, int id, float* map, int* n_valid)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (id < 0 || id >= g->n_frames)
+        return fail(g, PG_ERR_INVALID_ARG, "bad node id %d", id);
+    if (n_valid)
+        *n_valid = g->n_src[id];
+    if (map) {
+        HIP_OR_FAIL(g, hipMemcpyAsync(map, g->maps.as<float4>() + (size_t)id * g->HW, sizeof(float4) * g->HW,
+                                      hipMemcpyDeviceToHost, g->stream));
+        HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    }
+    return PG_OK;
+}
+
+pg_status pose_graph_set_mlp(pg_graph* g, const void* params, size_t n_bytes)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (!params || n_bytes != 2626)
+        return fail(g, PG_ERR_INVALID_ARG, "expected 1313 fp16 parameters (2626 bytes), got %zu bytes", n_bytes);
+    HIP_OR_FAIL(g, copy_in(g->d_mlp.p, params, n_bytes, g->stream));
+    HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    g->has_mlp = true;
+    return PG_OK;
+}
+
+const char* pose_graph_last_error(const pg_graph* g)
+{
+    return g ? g->err.c_str() : g_create_error.c_str();
+}
+
+void pose_graph_destroy(pg_graph* g)
+{
+    if (!g)
+        return;
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mutex);
+        g_batch_cache.erase(std::remove_if(g_batch_cache.begin(), g_batch_cache.end(),
+                                           [g](const std::unique_ptr<Schedule>& s) {
+                                               return std::find(s->graphs.begin(), s->graphs.end(), g) !=
+                                                      s->graphs.end();
+                                           }),
+                            g_batch_cache.end());
+    }
+    (void)hipStreamSynchronize(g->stream);
+    g->sched.reset();
+    if (g->capture_stream)
+        (void)hipStreamDestroy(g->capture_stream);
+    if (g->h_status)
+        (void)hipHostFree(g->h_status);
+    delete g;
+}
+
+}  // extern "C"

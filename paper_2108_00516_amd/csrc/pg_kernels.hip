@@ -1,0 +1,1079 @@
+// HIP kernels (gfx950) of the online pose-graph optimisation of BundleTrack
+// (Wen & Bekris, IROS 2021), Sec. IV-D.
+//
+// Per Gauss-Newton iteration:
+//   assoc_kernel     dense projective association, point-to-plane residual of
+//                    Eq. (3), Jacobian, Huber IRLS weight and the per-item sum of
+//                    w J_i^T J_i, w r J_i, energy and count (29 values);
+//   feature_kernel   feature residual of Eq. (2) with its 3x12 Jacobian;
+//   assemble_kernel  FP64 expansion of the per-pair sums into the 6x6 node
+//                    blocks of J^T W J and J^T W r, in a fixed order;
+//   solve_kernel     FP64 Cholesky (or Jacobi-PCG) solve over the free nodes,
+//                    T <- Exp(delta) T, and the next iteration's transforms.
+//
+// The dense residual depends on the two poses only through A = T_i T_j^-1, so
+// its Jacobian w.r.t. a left perturbation of T_j is minus the Jacobian w.r.t.
+// T_i times the adjoint of A.  Each pixel-pair therefore only accumulates the
+// 6x6 block w J_i^T J_i (21 unique values), w r J_i, rho and a count; the
+// (i,j), (j,i) and (j,j) blocks follow exactly from Ad_A in FP64.
+#include "pg_device.hpp"
+
+#include <math.h>
+
+namespace pg {
+
+// ------------------------------------------------------------------ helpers
+
+// nearest pixel with ties to the upper pixel, floor(x + 1/2) without the
+// rounding of the addition
+__device__ __forceinline__ float round_half_up(float x)
+{
+    const float f = floorf(x);
+    return (x - f >= 0.5f) ? f + 1.0f : f;
+}
+
+__device__ __forceinline__ bool depth_ok(float z, uint8_t m) { return m != 0 && isfinite(z) && z > 0.0f; }
+
+// upper-triangle index of (a, b), a <= b, in an n x n symmetric matrix
+__host__ __device__ constexpr int upper_index(int a, int b, int n) { return a * n - a * (a - 1) / 2 + (b - a); }
+
+// packed lower-triangle index of (i, j), i >= j
+__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// ---------------------------------------------------- per-frame preprocessing
+
+// Validity, back-projection pi_D^-1 at the pixel centre and the normal by
+// central differences of the vertex map, oriented towards the camera.  A pixel
+// is a source/target only with a valid normal (all four neighbours valid,
+// not on the border).  Output: packed {nx, ny, nz, z}, zero when invalid.
+__global__ void preprocess_map_kernel(const float* __restrict__ depth, const uint8_t* __restrict__ mask,
+                                      int W, int H, float cx, float cy, float ifx, float ify,
+                                      float4* __restrict__ map, uint8_t* __restrict__ flag)
+{
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y * blockDim.y + threadIdx.y;
+    if (u >= W || v >= H)
+        return;
+    const int x = v * W + u;
+    const float z = depth[x];
+    float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint8_t ok = 0;
+    if (depth_ok(z, mask[x]) && u > 0 && v > 0 && u < W - 1 && v < H - 1) {
+        const float zl = depth[x - 1], zr = depth[x + 1], zu = depth[x - W], zd = depth[x + W];
+        if (depth_ok(zl, mask[x - 1]) && depth_ok(zr, mask[x + 1]) && depth_ok(zu, mask[x - W]) &&
+            depth_ok(zd, mask[x + W])) {
+            const float xu = (u - cx) * ifx, yv = (v - cy) * ify;
+            const float xl = (u - 1 - cx) * ifx, xr = (u + 1 - cx) * ifx;
+            const float yu = (v - 1 - cy) * ify, yd = (v + 1 - cy) * ify;
+            // d/du: V(u+1,v) - V(u-1,v); d/dv: V(u,v+1) - V(u,v-1)
+            const float ax = zr * xr - zl * xl, ay = zr * yv - zl * yv, az = zr - zl;
+            const float bx = zd * xu - zu * xu, by = zd * yd - zu * yu, bz = zd - zu;
+            float nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+            const float len2 = nx * nx + ny * ny + nz * nz;
+            if (len2 > 0.0f) {
+                const float len = sqrtf(len2);
+                nx /= len;
+                ny /= len;
+                nz /= len;
+                if (nx * (z * xu) + ny * (z * yv) + nz * z > 0.0f) {
+                    nx = -nx;
+                    ny = -ny;
+                    nz = -nz;
+                }
+                out = make_float4(nx, ny, nz, z);
+                ok = 1;
+            }
+        }
+    }
+    map[x] = out;
+    flag[x] = ok;
+}
+
+__global__ void row_count_kernel(const uint8_t* __restrict__ flag, int W, int* __restrict__ row_cnt)
+{
+    __shared__ int part[4];
+    const int v = blockIdx.x;
+    int c = 0;
+    for (int u = threadIdx.x; u < W; u += blockDim.x)
+        c += flag[v * W + u];
+    for (int o = 32; o > 0; o >>= 1)
+        c += __shfl_xor(c, o);
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        row_cnt[v] = part[0] + part[1] + part[2] + part[3];
+}
+
+// exclusive scan of the row counts (single thread; rows <= 8192)
+__global__ void row_scan_kernel(int* __restrict__ row_cnt, int H, int* __restrict__ total)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int s = 0;
+        for (int v = 0; v < H; ++v) {
+            const int c = row_cnt[v];
+            row_cnt[v] = s;
+            s += c;
+        }
+        *total = s;
+    }
+}
+
+// row-major compaction of the valid pixels: the source list of a frame
+__global__ void row_scatter_kernel(const float4* __restrict__ map, const uint8_t* __restrict__ flag,
+                                   const int* __restrict__ row_off, int W, float4* __restrict__ src_nz,
+                                   uint32_t* __restrict__ src_uv)
+{
+    __shared__ int wave_cnt[4];
+    const int v = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int base = row_off[v];
+    for (int u0 = 0; u0 < W; u0 += 256) {
+        const int u = u0 + threadIdx.x;
+        const bool f = (u < W) && flag[v * W + u];
+        const unsigned long long bal = __ballot(f);
+        const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0)
+            wave_cnt[wv] = __popcll(bal);
+        __syncthreads();
+        int off = base, tot = 0;
+        for (int w = 0; w < 4; ++w) {
+            if (w < wv)
+                off += wave_cnt[w];
+            tot += wave_cnt[w];
+        }
+        if (f) {
+            src_nz[off + pre] = map[v * W + u];
+            src_uv[off + pre] = (uint32_t)u | ((uint32_t)v << 16);
+        }
+        __syncthreads();
+        base += tot;
+    }
+}
+
+// ------------------------------------------------------------ feature points
+
+__device__ __forceinline__ bool match_point(const float* __restrict__ depth, const uint8_t* __restrict__ mask,
+                                            int W, int H, float cx, float cy, float ifx, float ify, float u,
+                                            float v, float4& p)
+{
+    const float ui = round_half_up(u), vi = round_half_up(v);
+    p = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (!(ui >= 0.f && ui < (float)W && vi >= 0.f && vi < (float)H))
+        return false;
+    const int x = (int)vi * W + (int)ui;
+    const float z = depth[x];
+    if (!depth_ok(z, mask[x]))
+        return false;
+    p = make_float4(z * ((ui - cx) * ifx), z * ((vi - cy) * ify), z, 1.0f);
+    return true;
+}
+
+// 3-D endpoints of each match (back-projection of the nearest pixel); w = 1
+// when both endpoints have depth, else the match is inert.
+__global__ void match_points_kernel(const float* __restrict__ depth_i, const uint8_t* __restrict__ mask_i,
+                                    const float* __restrict__ depth_j, const uint8_t* __restrict__ mask_j,
+                                    int W, int H, float cx, float cy, float ifx, float ify,
+                                    const float* __restrict__ uv_i, const float* __restrict__ uv_j, int n,
+                                    float4* __restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n)
+        return;
+    float4 pm, pn;
+    const bool a = match_point(depth_i, mask_i, W, H, cx, cy, ifx, ify, uv_i[2 * k], uv_i[2 * k + 1], pm);
+    const bool b = match_point(depth_j, mask_j, W, H, cx, cy, ifx, ify, uv_j[2 * k], uv_j[2 * k + 1], pn);
+    const float ok = (a && b) ? 1.0f : 0.0f;
+    pm.w = ok;
+    pn.w = ok;
+    out[2 * k] = pm;
+    out[2 * k + 1] = pn;
+}
+
+// ------------------------------------------------------ dense association
+
+// Project source point p (frame-i camera) into frame j with B = T_j T_i^-1:
+// returns the nearest target pixel index, or -2 (behind the camera) / -3
+// (outside the image); (uf, vf) is the continuous projection.
+__device__ __forceinline__ int project_px(const float (&B)[12], float px, float py, float pz, const GraphDev& gd,
+                                          float& uf, float& vf)
+{
+    const float qx = fmaf(B[0], px, fmaf(B[1], py, fmaf(B[2], pz, B[3])));
+    const float qy = fmaf(B[4], px, fmaf(B[5], py, fmaf(B[6], pz, B[7])));
+    const float qz = fmaf(B[8], px, fmaf(B[9], py, fmaf(B[10], pz, B[11])));
+    uf = __builtin_nanf("");
+    vf = uf;
+    if (!(qz > 0.0f))
+        return -2;
+    const float iz = 1.0f / qz;
+    uf = fmaf(gd.fx * qx, iz, gd.cx);
+    vf = fmaf(gd.fy * qy, iz, gd.cy);
+    const float ui = round_half_up(uf), vi = round_half_up(vf);
+    if (!(ui >= 0.0f && ui < (float)gd.W && vi >= 0.0f && vi < (float)gd.H))
+        return -3;
+    return (int)vi * gd.W + (int)ui;
+}
+
+// Finish the association with the gathered target t = {n_q, z_q} of pixel y:
+// -4 invalid target, -5 distance gate, -6 normal gate; else returns y with the
+// residual r = n . (A q - p) and J_i = [n, s x n] (s = A q).
+__device__ __forceinline__ int finish_px(const float (&A)[12], float px, float py, float pz, float nx, float ny,
+                                         float nz, int y, float4 t, const GraphDev& gd, float& r,
+                                         float (&J)[6])
+{
+    if (!(t.w > 0.0f))
+        return -4;
+    const int ui = y % gd.W, vi = y / gd.W;
+    const float qz = t.w;
+    const float qx = qz * (((float)ui - gd.cx) * gd.ifx);
+    const float qy = qz * (((float)vi - gd.cy) * gd.ify);
+    const float sx = fmaf(A[0], qx, fmaf(A[1], qy, fmaf(A[2], qz, A[3])));
+    const float sy = fmaf(A[4], qx, fmaf(A[5], qy, fmaf(A[6], qz, A[7])));
+    const float sz = fmaf(A[8], qx, fmaf(A[9], qy, fmaf(A[10], qz, A[11])));
+    const float dx = sx - px, dy = sy - py, dz = sz - pz;
+    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    if (!(d2 < gd.gate_d2))
+        return -5;
+    const float rnx = fmaf(A[0], t.x, fmaf(A[1], t.y, A[2] * t.z));
+    const float rny = fmaf(A[4], t.x, fmaf(A[5], t.y, A[6] * t.z));
+    const float rnz = fmaf(A[8], t.x, fmaf(A[9], t.y, A[10] * t.z));
+    const float c = fmaf(nx, rnx, fmaf(ny, rny, nz * rnz));
+    if (!(c > gd.gate_cos))
+        return -6;
+    r = fmaf(nx, dx, fmaf(ny, dy, nz * dz));
+    J[0] = nx;
+    J[1] = ny;
+    J[2] = nz;
+    J[3] = sy * nz - sz * ny;
+    J[4] = sz * nx - sx * nz;
+    J[5] = sx * ny - sy * nx;
+    return y;
+}
+
+// recursive-halving step of the wave reduction: lanes differing in bit
+// log2(2*HALF) exchange half of their values, each keeping the half its bit
+// selects, so 32 values reduce with 31 shuffles
+template <int HALF>
+__device__ __forceinline__ void halve(float (&acc)[32], int lane)
+{
+    const bool up = (lane & (2 * HALF)) != 0;
+#pragma unroll
+    for (int q = 0; q < HALF; ++q) {
+        const float send = up ? acc[q] : acc[q + HALF];
+        const float keep = up ? acc[q + HALF] : acc[q];
+        acc[q] = keep + __shfl_xor(send, 2 * HALF);
+    }
+}
+
+// One work item per block: PPT source pixels per thread of one frame-i tile,
+// associated into frame j.  Blocks are mapped so that each XCD (blockIdx mod
+// 8) walks a contiguous run of the item list, which is ordered source tile
+// first: the items that re-read one source tile share an L2.
+template <int PPT>
+__global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __restrict__ gds,
+                                                              const WorkItem* __restrict__ items, int n_items,
+                                                              int per_xcd)
+{
+    const int b = blockIdx.x;
+    const int L = (b & 7) * per_xcd + (b >> 3);
+    if (L >= n_items)
+        return;
+    const WorkItem it = items[L];
+    const int gid = it.gij >> 16, i = it.gij & 0xff, j = (it.gij >> 8) & 0xff;
+    const GraphDev& gd = gds[gid];
+    if (*gd.status)
+        return;
+    const int p = pair_index(i, j, gd.n_frames);
+    float A[12], B[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        A[k] = gd.xf32[p * 24 + k];
+        B[k] = gd.xf32[p * 24 + 12 + k];
+    }
+    const float4* __restrict__ src_nz = gd.src_nz + (size_t)i * gd.HW;
+    const uint32_t* __restrict__ src_uv = gd.src_uv + (size_t)i * gd.HW;
+    const float4* __restrict__ tmap = gd.maps + (size_t)j * gd.HW;
+    const float huber = gd.huber_g;
+
+    float acc[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+        acc[k] = 0.0f;
+
+    // phase 1: source records; phase 2: projections and target gathers;
+    // phase 3: residuals and accumulation (loads of all PPT pixels in flight)
+    float4 s[PPT];
+    float px[PPT], py[PPT];
+    int y[PPT];
+    const int end = it.start + it.count;
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int k = it.start + threadIdx.x + m * kAssocThreads;
+        y[m] = -1;
+        s[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+        px[m] = py[m] = 0.f;
+        if (k < end) {
+            s[m] = src_nz[k];
+            const uint32_t uv = src_uv[k];
+            const float z = s[m].w;
+            px[m] = z * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
+            py[m] = z * (((float)(uv >> 16) - gd.cy) * gd.ify);
+            float uf, vf;
+            y[m] = project_px(B, px[m], py[m], z, gd, uf, vf);
+        }
+    }
+    float4 t[PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m)
+        t[m] = (y[m] >= 0) ? tmap[y[m]] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        if (y[m] < 0)
+            continue;
+        float r, J[6];
+        if (finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J) < 0)
+            continue;
+        const float ar = fabsf(r);
+        const float w = (ar <= huber) ? 1.0f : huber / ar;
+        const float e = (ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber);
+        float wJ[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+            wJ[a] = w * J[a];
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+#pragma unroll
+            for (int c = a; c < 6; ++c)
+                acc[q++] += wJ[a] * J[c];
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+            acc[21 + a] += wJ[a] * r;
+        acc[27] += e;
+        acc[28] += 1.0f;
+    }
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    halve<16>(acc, lane);
+    halve<8>(acc, lane);
+    halve<4>(acc, lane);
+    halve<2>(acc, lane);
+    halve<1>(acc, lane);
+    acc[0] += __shfl_xor(acc[0], 1);   // lane l now holds value (l >> 1)
+    __shared__ float red[kAssocThreads / 64][32];
+    if ((lane & 1) == 0)
+        red[wave][lane >> 1] = acc[0];
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float v = red[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < kAssocThreads / 64; ++w)
+            v += red[w][threadIdx.x];
+        gd.partials[(size_t)it.slot * kDenseStride + threadIdx.x] = v;
+    }
+}
+
+// Association decisions of one ordered pair for inspection: the same
+// projection and gating code as the association kernel, one thread per pixel.
+__global__ void assoc_debug_kernel(const GraphDev* __restrict__ gds, int i, int j, int* __restrict__ target,
+                                   float* __restrict__ res, float* __restrict__ uv)
+{
+    const GraphDev& gd = gds[0];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= gd.HW)
+        return;
+    const int p = pair_index(i, j, gd.n_frames);
+    float A[12], B[12];
+    for (int k = 0; k < 12; ++k) {
+        A[k] = gd.xf32[p * 24 + k];
+        B[k] = gd.xf32[p * 24 + 12 + k];
+    }
+    const float4 s = gd.maps[(size_t)i * gd.HW + x];
+    int code = -1;
+    float r = 0.f, uf = __builtin_nanf(""), vf = uf;
+    if (s.w > 0.f) {
+        const float px = s.w * (((float)(x % gd.W) - gd.cx) * gd.ifx);
+        const float py = s.w * (((float)(x / gd.W) - gd.cy) * gd.ify);
+        code = project_px(B, px, py, s.w, gd, uf, vf);
+        if (code >= 0) {
+            float J[6], rr;
+            const float4 t = gd.maps[(size_t)j * gd.HW + code];
+            code = finish_px(A, px, py, s.w, s.x, s.y, s.z, code, t, gd, rr, J);
+            if (code >= 0)
+                r = rr;
+        }
+    }
+    target[x] = code;
+    res[x] = r;
+    uv[2 * x] = uf;
+    uv[2 * x + 1] = vf;
+}
+
+// -------------------------------------------------------- feature residuals
+
+// One block per match set: e = T_i^-1 p_m - T_j^-1 p_n (Eq. 2), its Jacobian
+// [-R_i^T, R_i^T [p_m]x | R_j^T, -R_j^T [p_n]x], Huber weight; sums of
+// w J^T J (12x12 upper), w J^T e, rho and the count.
+constexpr int kFeatThreads = 128;
+
+__global__ __launch_bounds__(kFeatThreads) void feature_kernel(const GraphDev* __restrict__ gds,
+                                                               const int2* __restrict__ fitems)
+{
+    const int2 fi = fitems[blockIdx.x];
+    const GraphDev& gd = gds[fi.x];
+    if (*gd.status)
+        return;
+    const int4 S = gd.fsets[fi.y];
+    const float* Ti = gd.tinv32 + 12 * S.x;
+    const float* Tj = gd.tinv32 + 12 * S.y;
+    float acc[kFeatFields];
+#pragma unroll
+    for (int k = 0; k < kFeatFields; ++k)
+        acc[k] = 0.f;
+    const float huber = gd.huber_f;
+    for (int k = threadIdx.x; k < S.w; k += kFeatThreads) {
+        const float4 pm = gd.fpts[2 * (S.z + k)];
+        const float4 pn = gd.fpts[2 * (S.z + k) + 1];
+        if (!(pm.w > 0.f))
+            continue;
+        float e[3], J[3][12];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const float ai = Ti[4 * r], bi = Ti[4 * r + 1], ci = Ti[4 * r + 2];
+            const float aj = Tj[4 * r], bj = Tj[4 * r + 1], cj = Tj[4 * r + 2];
+            e[r] = (fmaf(ai, pm.x, fmaf(bi, pm.y, fmaf(ci, pm.z, Ti[4 * r + 3])))) -
+                   (fmaf(aj, pn.x, fmaf(bj, pn.y, fmaf(cj, pn.z, Tj[4 * r + 3]))));
+            J[r][0] = -ai;
+            J[r][1] = -bi;
+            J[r][2] = -ci;
+            J[r][3] = bi * pm.z - ci * pm.y;   // row r of R_i^T [p_m]x = (R_i^T)_r x p_m
+            J[r][4] = ci * pm.x - ai * pm.z;
+            J[r][5] = ai * pm.y - bi * pm.x;
+            J[r][6] = aj;
+            J[r][7] = bj;
+            J[r][8] = cj;
+            J[r][9] = -(bj * pn.z - cj * pn.y);
+            J[r][10] = -(cj * pn.x - aj * pn.z);
+            J[r][11] = -(aj * pn.y - bj * pn.x);
+        }
+        const float ne = sqrtf(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        const float w = (ne <= huber) ? 1.0f : huber / ne;
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < 12; ++a)
+#pragma unroll
+            for (int c = a; c < 12; ++c)
+                acc[q++] += w * (J[0][a] * J[0][c] + J[1][a] * J[1][c] + J[2][a] * J[2][c]);
+#pragma unroll
+        for (int a = 0; a < 12; ++a)
+            acc[78 + a] += w * (J[0][a] * e[0] + J[1][a] * e[1] + J[2][a] * e[2]);
+        acc[90] += (ne <= huber) ? 0.5f * ne * ne : huber * (ne - 0.5f * huber);
+        acc[91] += 1.0f;
+    }
+    __shared__ float red[kFeatThreads * (kFeatFields + 1)];
+#pragma unroll
+    for (int k = 0; k < kFeatFields; ++k)
+        red[threadIdx.x * (kFeatFields + 1) + k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < kFeatFields) {
+        float v = 0.f;
+        for (int t = 0; t < kFeatThreads; ++t)
+            v += red[t * (kFeatFields + 1) + threadIdx.x];
+        gd.fpartials[(size_t)fi.y * kFeatStride + threadIdx.x] = v;
+    }
+}
+
+// --------------------------------------------------- FP64 normal equations
+
+// 6x6 adjoint of A = [R t] for twists [v; w]: [[R, [t]x R], [0, R]]
+__device__ __forceinline__ double adj(const double* __restrict__ X, int r, int c)
+{
+    if (r >= 3 && c < 3)
+        return 0.0;
+    if (r < 3 && c >= 3) {
+        const int cc = c - 3;
+        const double t0 = X[3], t1 = X[7], t2 = X[11];
+        const double R0 = X[cc], R1 = X[4 + cc], R2 = X[8 + cc];
+        // ([t]x R)[r][cc] = (t x R_col)[r]
+        return (r == 0) ? (t1 * R2 - t2 * R1) : (r == 1) ? (t2 * R0 - t0 * R2) : (t0 * R1 - t1 * R0);
+    }
+    const int rr = r % 3, cc = c % 3;
+    return X[4 * rr + cc];
+}
+
+__device__ __forceinline__ double sym6(const double* M, int a, int b)
+{
+    return (a <= b) ? M[upper_index(a, b, 6)] : M[upper_index(b, a, 6)];
+}
+
+__device__ __forceinline__ double sym12(const float* F, int a, int b)
+{
+    return (double)((a <= b) ? F[upper_index(a, b, 12)] : F[upper_index(b, a, 12)]);
+}
+
+constexpr int kAsmThreads = 256;
+constexpr int kMaxPairsPerBlock = 2 * (kMaxFrames - 1);
+
+// One block per node block (I, J), I >= J, of the 6N x 6N system: reduces the
+// per-item partial records of the ordered pairs touching it in FP64 (tiles in
+// order), expands them with the adjoint, adds the feature blocks (each match
+// counted for both orderings of Eq. 1), and writes H (both triangles), the
+// gradient segment and the node's energy/count record (diagonal blocks).
+__global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* __restrict__ gds,
+                                                               const int2* __restrict__ nbs)
+{
+    const int2 nb = nbs[blockIdx.x];
+    const GraphDev& gd = gds[nb.x];
+    if (*gd.status)
+        return;
+    const int I = nb.y & 0xff, J = (nb.y >> 8) & 0xff;
+    const int N = gd.n_frames, n6 = 6 * N;
+    const bool diag = (I == J);
+    const int np = diag ? 2 * (N - 1) : 2;
+    __shared__ double S[kMaxPairsPerBlock][kDenseFields];
+    __shared__ double P[kMaxPairsPerBlock][36];
+    __shared__ double X[kMaxPairsPerBlock][42];
+
+    // pair k: for k < np/2 the pair has I as source, else I as target
+    auto pair_of = [&](int k, int& i, int& j) {
+        if (!diag) {
+            i = (k == 0) ? I : J;
+            j = (k == 0) ? J : I;
+        } else if (k < N - 1) {
+            i = I;
+            j = (k < I) ? k : k + 1;
+        } else {
+            const int kk = k - (N - 1);
+            i = (kk < I) ? kk : kk + 1;
+            j = I;
+        }
+    };
+
+    for (int task = threadIdx.x; task < np * kDenseFields; task += kAsmThreads) {
+        const int k = task / kDenseFields, f = task % kDenseFields;
+        int i, j;
+        pair_of(k, i, j);
+        const int jj = (j < i) ? j : j - 1;
+        const int nt = gd.n_tiles[i], base = gd.item_base[i];
+        double s = 0.0;
+        for (int t = 0; t < nt; ++t)
+            s += (double)gd.partials[(size_t)(base + t * (N - 1) + jj) * kDenseStride + f];
+        S[k][f] = s;
+    }
+    __syncthreads();
+    // P = M Ad (off-diagonal blocks and the target-role diagonal term)
+    for (int task = threadIdx.x; task < np * 36; task += kAsmThreads) {
+        const int k = task / 36, e = task % 36, a = e / 6, c = e % 6;
+        int i, j;
+        pair_of(k, i, j);
+        const double* Xa = gd.xf64 + 12 * pair_index(i, j, N);
+        double v = 0.0;
+        for (int l = 0; l < 6; ++l)
+            v += sym6(S[k], a, l) * adj(Xa, l, c);
+        P[k][e] = v;
+    }
+    __syncthreads();
+    for (int task = threadIdx.x; task < np * 42; task += kAsmThreads) {
+        const int k = task / 42, e = task % 42;
+        int i, j;
+        pair_of(k, i, j);
+        const bool src = (i == I) && (diag ? k < N - 1 : k == 0);
+        const double* Xa = gd.xf64 + 12 * pair_index(i, j, N);
+        double v;
+        if (e < 36) {
+            const int a = e / 6, c = e % 6;
+            if (!diag)
+                v = src ? -P[k][e] : -P[k][6 * c + a];       // -M Ad  |  -(M Ad)^T
+            else if (src)
+                v = sym6(S[k], a, c);                         // M
+            else {
+                v = 0.0;                                       // Ad^T M Ad
+                for (int l = 0; l < 6; ++l)
+                    v += adj(Xa, l, a) * P[k][6 * l + c];
+            }
+        } else {
+            const int a = e - 36;
+            if (src)
+                v = S[k][21 + a];                              // g_i = v
+            else {
+                v = 0.0;                                       // g_j = -Ad^T v
+                for (int l = 0; l < 6; ++l)
+                    v -= adj(Xa, l, a) * S[k][21 + l];
+            }
+        }
+        X[k][e] = v;
+    }
+    __syncthreads();
+    const double lg = (double)gd.lambda_g, lf2 = 2.0 * (double)gd.lambda_f;
+    if (!diag) {
+        if (threadIdx.x < 36) {
+            const int e = threadIdx.x, a = e / 6, c = e % 6;
+            double h = lg * (X[0][e] + X[1][e]);
+            const int s = gd.set_of[I * N + J];
+            if (s >= 0) {
+                const float* F = gd.fpartials + (size_t)s * kFeatStride;
+                const bool first = gd.fsets[s].x == I;
+                h += lf2 * (first ? sym12(F, a, 6 + c) : sym12(F, 6 + a, c));
+            }
+            gd.Hm[(size_t)(6 * I + a) * n6 + 6 * J + c] = h;
+            gd.Hm[(size_t)(6 * J + c) * n6 + 6 * I + a] = h;
+        }
+    } else {
+        if (threadIdx.x < 42) {
+            const int e = threadIdx.x;
+            double h = 0.0;
+            for (int k = 0; k < np; ++k)
+                h += X[k][e];
+            h *= lg;
+            for (int K = 0; K < N; ++K) {
+                const int s = (K == I) ? -1 : gd.set_of[I * N + K];
+                if (s < 0)
+                    continue;
+                const float* F = gd.fpartials + (size_t)s * kFeatStride;
+                const int o = (gd.fsets[s].x == I) ? 0 : 6;
+                if (e < 36)
+                    h += lf2 * sym12(F, o + e / 6, o + e % 6);
+                else
+                    h += lf2 * (double)F[78 + o + (e - 36)];
+            }
+            if (e < 36)
+                gd.Hm[(size_t)(6 * I + e / 6) * n6 + 6 * I + e % 6] = h;
+            else
+                gd.grad[6 * I + (e - 36)] = h;
+        } else if (threadIdx.x == 64) {
+            double Eg = 0.0, cg = 0.0, Ef = 0.0, cf = 0.0;
+            for (int k = 0; k < N - 1; ++k) {
+                Eg += S[k][27];
+                cg += S[k][28];
+            }
+            for (int K = 0; K < N; ++K) {
+                const int s = (K == I) ? -1 : gd.set_of[I * N + K];
+                if (s < 0 || gd.fsets[s].x != I)
+                    continue;
+                const float* F = gd.fpartials + (size_t)s * kFeatStride;
+                Ef += (double)F[90];
+                cf += (double)F[91];
+            }
+            gd.node_stats[kNodeStats * I + 0] = lg * Eg;
+            gd.node_stats[kNodeStats * I + 1] = lf2 * Ef;
+            gd.node_stats[kNodeStats * I + 2] = cg;
+            gd.node_stats[kNodeStats * I + 3] = cf;
+        }
+    }
+}
+
+// ------------------------------------------------------------ FP64 solve
+
+constexpr int kSolveThreads = 512;
+
+// SE(3) exponential of [v; w] (Rodrigues and the left Jacobian V), 4x4 row-major
+__device__ void se3_exp(const double* xi, double* T)
+{
+    const double w0 = xi[3], w1 = xi[4], w2 = xi[5];
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
+    double a, b, c;
+    if (th < 1e-6) {
+        a = 1.0 - th2 / 6.0;
+        b = 0.5 - th2 / 24.0;
+        c = 1.0 / 6.0 - th2 / 120.0;
+    } else {
+        const double sn = sin(th), cs = cos(th);
+        a = sn / th;
+        b = (1.0 - cs) / th2;
+        c = (th - sn) / (th2 * th);
+    }
+    const double K[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
+    double K2[9];
+    for (int r = 0; r < 3; ++r)
+        for (int s = 0; s < 3; ++s)
+            K2[3 * r + s] = K[3 * r] * K[s] + K[3 * r + 1] * K[3 + s] + K[3 * r + 2] * K[6 + s];
+    for (int r = 0; r < 3; ++r) {
+        double t = 0.0;
+        for (int s = 0; s < 3; ++s) {
+            const double I = (r == s) ? 1.0 : 0.0;
+            T[4 * r + s] = I + a * K[3 * r + s] + b * K2[3 * r + s];
+            t += (I + b * K[3 * r + s] + c * K2[3 * r + s]) * xi[s];
+        }
+        T[4 * r + 3] = t;
+    }
+    T[12] = T[13] = T[14] = 0.0;
+    T[15] = 1.0;
+}
+
+__device__ void mat4_mul(const double* A, const double* B, double* C)
+{
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c)
+            C[4 * r + c] = A[4 * r] * B[c] + A[4 * r + 1] * B[4 + c] + A[4 * r + 2] * B[8 + c] + A[4 * r + 3] * B[12 + c];
+}
+
+// A = T_i T_j^-1, B = T_j T_i^-1 per ordered pair (FP64, stored FP32 and
+// FP64), T^-1 per node (FP32), from the poses in LDS.
+__device__ void compute_transforms(const GraphDev& gd, const double* __restrict__ Ts)
+{
+    const int N = gd.n_frames;
+    for (int p = threadIdx.x; p < N * (N - 1); p += blockDim.x) {
+        const int i = p / (N - 1), jj = p % (N - 1), j = (jj < i) ? jj : jj + 1;
+        const double* Ti = Ts + 16 * i;
+        const double* Tj = Ts + 16 * j;
+        double A[12], B[12];
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) {
+                A[4 * r + c] = Ti[4 * r] * Tj[4 * c] + Ti[4 * r + 1] * Tj[4 * c + 1] + Ti[4 * r + 2] * Tj[4 * c + 2];
+                B[4 * r + c] = Tj[4 * r] * Ti[4 * c] + Tj[4 * r + 1] * Ti[4 * c + 1] + Tj[4 * r + 2] * Ti[4 * c + 2];
+            }
+        }
+        for (int r = 0; r < 3; ++r) {
+            A[4 * r + 3] = Ti[4 * r + 3] - (A[4 * r] * Tj[3] + A[4 * r + 1] * Tj[7] + A[4 * r + 2] * Tj[11]);
+            B[4 * r + 3] = Tj[4 * r + 3] - (B[4 * r] * Ti[3] + B[4 * r + 1] * Ti[7] + B[4 * r + 2] * Ti[11]);
+        }
+        for (int k = 0; k < 12; ++k) {
+            gd.xf32[p * 24 + k] = (float)A[k];
+            gd.xf32[p * 24 + 12 + k] = (float)B[k];
+            gd.xf64[p * 12 + k] = A[k];
+        }
+    }
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const double* T = Ts + 16 * n;
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c)
+                gd.tinv32[12 * n + 4 * r + c] = (float)T[4 * c + r];
+            gd.tinv32[12 * n + 4 * r + 3] = (float)(-(T[r] * T[3] + T[4 + r] * T[7] + T[8 + r] * T[11]));
+        }
+    }
+}
+
+__device__ double block_sum(double v, double* scratch)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        scratch[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w)
+        s += scratch[w];
+    return s;
+}
+
+__device__ double block_max(double v, double* scratch)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        scratch[wave] = v;
+    __syncthreads();
+    double s = scratch[0];
+    for (int w = 1; w < nw; ++w)
+        s = fmax(s, scratch[w]);
+    return s;
+}
+
+__device__ __forceinline__ double sym_tri(const double* L, int i, int j) { return (i >= j) ? L[tri(i, j)] : L[tri(j, i)]; }
+
+// mode 1: start of an optimize (clear status, iteration counter; transforms).
+// mode 0: one Gauss-Newton solve + update + transforms for the next iteration.
+// Dynamic LDS: packed lower triangle of H_ff, then 6 vectors of n, then 16N poses.
+__global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __restrict__ gds, int mode)
+{
+    const GraphDev& gd = gds[blockIdx.x];
+    const int N = gd.n_frames;
+    const int n = 6 * gd.n_free, n6 = 6 * N;
+    extern __shared__ double sm[];
+    double* Lm = sm;                               // n(n+1)/2
+    double* bv = Lm + n * (n + 1) / 2;              // rhs, then solution
+    double* dv = bv + n;                            // pivots / diagonal
+    double* xv = dv + n;                            // PCG vectors
+    double* rv = xv + n;
+    double* pv = rv + n;
+    double* qv = pv + n;
+    double* Ts = qv + n;                            // 16 N poses
+    __shared__ double scratch[kSolveThreads / 64];
+
+    for (int k = threadIdx.x; k < 16 * N; k += blockDim.x)
+        Ts[k] = gd.poses[k];
+    if (mode == 1) {
+        if (threadIdx.x == 0) {
+            *gd.status = 0;
+            *gd.iters_done = 0;
+        }
+        __syncthreads();
+        compute_transforms(gd, Ts);
+        return;
+    }
+    if (*gd.status)
+        return;
+    const int it = *gd.iters_done;
+    if (threadIdx.x == 0) {
+        double Ef = 0.0, Eg = 0.0, cf = 0.0, cg = 0.0;
+        for (int k = 0; k < N; ++k) {
+            Eg += gd.node_stats[kNodeStats * k + 0];
+            Ef += gd.node_stats[kNodeStats * k + 1];
+            cg += gd.node_stats[kNodeStats * k + 2];
+            cf += gd.node_stats[kNodeStats * k + 3];
+        }
+        double* rec = gd.iter_stats + kIterRecord * it;
+        rec[0] = Ef;
+        rec[1] = Eg;
+        rec[2] = cg;
+        rec[3] = cf;
+    }
+    if (n == 0) {                                   // every node fixed
+        __syncthreads();
+        if (threadIdx.x == 0)
+            *gd.iters_done = it + 1;
+        return;
+    }
+    // H_ff (lower, packed) and b = -g_f
+    for (int e = threadIdx.x; e < n * (n + 1) / 2; e += blockDim.x) {
+        int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+        while ((a + 1) * (a + 2) / 2 <= e)
+            ++a;
+        while (a * (a + 1) / 2 > e)
+            --a;
+        const int b = e - a * (a + 1) / 2;
+        const int ra = 6 * gd.free_ids[a / 6] + a % 6, rb = 6 * gd.free_ids[b / 6] + b % 6;
+        Lm[e] = gd.Hm[(size_t)ra * n6 + rb];
+    }
+    for (int a = threadIdx.x; a < n; a += blockDim.x)
+        bv[a] = -gd.grad[6 * gd.free_ids[a / 6] + a % 6];
+    __syncthreads();
+    double md = 0.0;
+    for (int a = threadIdx.x; a < n; a += blockDim.x)
+        md = fmax(md, Lm[tri(a, a)]);
+    const double maxdiag = block_max(md, scratch);
+    bool singular = !(maxdiag > 0.0);
+
+    if (!singular && gd.solver == 0) {
+        // right-looking Cholesky on the packed lower triangle, one barrier per
+        // column: after step k the trailing block holds the Schur complement
+        for (int k = 0; k < n && !singular; ++k) {
+            const double akk = Lm[tri(k, k)];
+            if (!(akk > 1e-12 * maxdiag)) {
+                singular = true;
+                break;
+            }
+            const double inv = 1.0 / akk;
+            const int m = n - k - 1, cnt = m * (m + 1) / 2;
+            for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+                int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+                while ((a + 1) * (a + 2) / 2 <= e)
+                    ++a;
+                while (a * (a + 1) / 2 > e)
+                    --a;
+                const int b = e - a * (a + 1) / 2;
+                const int ii = k + 1 + a, jj = k + 1 + b;
+                Lm[tri(ii, jj)] -= Lm[tri(ii, k)] * (Lm[tri(jj, k)] * inv);
+            }
+            __syncthreads();
+        }
+        if (!singular) {
+            for (int k = threadIdx.x; k < n; k += blockDim.x)
+                dv[k] = sqrt(Lm[tri(k, k)]);
+            __syncthreads();
+            for (int e = threadIdx.x; e < n * (n + 1) / 2; e += blockDim.x) {
+                int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+                while ((a + 1) * (a + 2) / 2 <= e)
+                    ++a;
+                while (a * (a + 1) / 2 > e)
+                    --a;
+                const int b = e - a * (a + 1) / 2;
+                Lm[e] = (a == b) ? dv[a] : Lm[e] / dv[b];
+            }
+            __syncthreads();
+            // triangular solves by one wave, rows lane + 64 m held in registers
+            if (threadIdx.x < 64) {
+                const int lane = threadIdx.x;
+                double r0 = (lane < n) ? bv[lane] : 0.0;
+                double r1 = (lane + 64 < n) ? bv[lane + 64] : 0.0;
+                double r2 = (lane + 128 < n) ? bv[lane + 128] : 0.0;
+                for (int k = 0; k < n; ++k) {               // L y = b
+                    const int mk = k >> 6, lk = k & 63;
+                    const double own = (mk == 0) ? r0 : (mk == 1) ? r1 : r2;
+                    const double yk = __shfl(own, lk) / Lm[tri(k, k)];
+                    if (lane + 0 > k && lane < n) r0 -= Lm[tri(lane, k)] * yk;
+                    if (lane + 64 > k && lane + 64 < n) r1 -= Lm[tri(lane + 64, k)] * yk;
+                    if (lane + 128 > k && lane + 128 < n) r2 -= Lm[tri(lane + 128, k)] * yk;
+                    if (lane == lk) {
+                        if (mk == 0) r0 = yk;
+                        else if (mk == 1) r1 = yk;
+                        else r2 = yk;
+                    }
+                }
+                for (int k = n - 1; k >= 0; --k) {          // L^T x = y
+                    const int mk = k >> 6, lk = k & 63;
+                    const double own = (mk == 0) ? r0 : (mk == 1) ? r1 : r2;
+                    const double xk = __shfl(own, lk) / Lm[tri(k, k)];
+                    if (lane < k) r0 -= Lm[tri(k, lane)] * xk;
+                    if (lane + 64 < k) r1 -= Lm[tri(k, lane + 64)] * xk;
+                    if (lane + 128 < k) r2 -= Lm[tri(k, lane + 128)] * xk;
+                    if (lane == lk) {
+                        if (mk == 0) r0 = xk;
+                        else if (mk == 1) r1 = xk;
+                        else r2 = xk;
+                    }
+                }
+                if (lane < n) xv[lane] = r0;
+                if (lane + 64 < n) xv[lane + 64] = r1;
+                if (lane + 128 < n) xv[lane + 128] = r2;
+            }
+            __syncthreads();
+        }
+    } else if (!singular) {
+        // Jacobi-preconditioned conjugate gradients (the solver the paper names)
+        for (int a = threadIdx.x; a < n; a += blockDim.x) {
+            dv[a] = Lm[tri(a, a)];
+            xv[a] = 0.0;
+            rv[a] = bv[a];
+            pv[a] = bv[a] / dv[a];
+        }
+        __syncthreads();
+        double rz = 0.0, bb = 0.0;
+        for (int a = threadIdx.x; a < n; a += blockDim.x) {
+            rz += rv[a] * rv[a] / dv[a];
+            bb += bv[a] * bv[a];
+        }
+        rz = block_sum(rz, scratch);
+        bb = block_sum(bb, scratch);
+        const double tol2 = gd.pcg_rel_tol * gd.pcg_rel_tol * bb;
+        for (int iter = 0; iter < gd.pcg_max_iters; ++iter) {
+            double pq = 0.0;
+            for (int a = threadIdx.x; a < n; a += blockDim.x) {
+                double s = 0.0;
+                for (int c = 0; c < n; ++c)
+                    s += sym_tri(Lm, a, c) * pv[c];
+                qv[a] = s;
+                pq += pv[a] * s;
+            }
+            pq = block_sum(pq, scratch);
+            if (!(pq > 0.0)) {
+                singular = true;
+                break;
+            }
+            const double alpha = rz / pq;
+            double rr = 0.0, rzn = 0.0;
+            for (int a = threadIdx.x; a < n; a += blockDim.x) {
+                xv[a] += alpha * pv[a];
+                rv[a] -= alpha * qv[a];
+                rr += rv[a] * rv[a];
+                rzn += rv[a] * rv[a] / dv[a];
+            }
+            rr = block_sum(rr, scratch);
+            rzn = block_sum(rzn, scratch);
+            if (rr <= tol2)
+                break;
+            const double beta = rzn / rz;
+            rz = rzn;
+            for (int a = threadIdx.x; a < n; a += blockDim.x)
+                pv[a] = rv[a] / dv[a] + beta * pv[a];
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+    if (singular) {
+        if (threadIdx.x == 0)
+            *gd.status |= kStatusSingular;
+        return;
+    }
+    bool bad = false;
+    for (int a = threadIdx.x; a < n; a += blockDim.x)
+        bad |= !isfinite(xv[a]);
+    if (__syncthreads_or(bad)) {
+        if (threadIdx.x == 0)
+            *gd.status |= kStatusNonFinite;
+        return;
+    }
+    // T <- Exp(delta) T for the free nodes
+    for (int a = threadIdx.x; a < gd.n_free; a += blockDim.x) {
+        const int node = gd.free_ids[a];
+        double E[16], Tn[16];
+        se3_exp(xv + 6 * a, E);
+        mat4_mul(E, Ts + 16 * node, Tn);
+        for (int k = 0; k < 16; ++k) {
+            Ts[16 * node + k] = Tn[k];
+            gd.poses[16 * node + k] = Tn[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        *gd.iters_done = it + 1;
+    compute_transforms(gd, Ts);
+}
+
+// ------------------------------------------------------------ launchers
+
+void launch_preprocess(const float* depth, const uint8_t* mask, int W, int H, float cx, float cy, float ifx,
+                       float ify, float4* map, uint8_t* flag, int* row_cnt, int* total, float4* src_nz,
+                       uint32_t* src_uv, hipStream_t st)
+{
+    dim3 blk(32, 8), grd((W + 31) / 32, (H + 7) / 8);
+    preprocess_map_kernel<<<grd, blk, 0, st>>>(depth, mask, W, H, cx, cy, ifx, ify, map, flag);
+    row_count_kernel<<<H, 256, 0, st>>>(flag, W, row_cnt);
+    row_scan_kernel<<<1, 64, 0, st>>>(row_cnt, H, total);
+    row_scatter_kernel<<<H, 256, 0, st>>>(map, flag, row_cnt, W, src_nz, src_uv);
+}
+
+void launch_match_points(const float* di, const uint8_t* mi, const float* dj, const uint8_t* mj, int W, int H,
+                         float cx, float cy, float ifx, float ify, const float* uvi, const float* uvj, int n,
+                         float4* out, hipStream_t st)
+{
+    if (n > 0)
+        match_points_kernel<<<(n + 255) / 256, 256, 0, st>>>(di, mi, dj, mj, W, H, cx, cy, ifx, ify, uvi, uvj, n,
+                                                             out);
+}
+
+int assoc_ppt_supported(int ppt) { return ppt == 1 || ppt == 2 || ppt == 4 || ppt == 8; }
+
+void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, hipStream_t st)
+{
+    if (n_items <= 0)
+        return;
+    const int per_xcd = (n_items + 7) / 8;
+    const int grid = 8 * per_xcd;
+    switch (ppt) {
+    case 1: assoc_kernel<1><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
+    case 2: assoc_kernel<2><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
+    case 8: assoc_kernel<8><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
+    default: assoc_kernel<4><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
+    }
+}
+
+void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int* target, float* r, float* uv,
+                        hipStream_t st)
+{
+    assoc_debug_kernel<<<(HW + 255) / 256, 256, 0, st>>>(gds, i, j, target, r, uv);
+}
+
+void launch_feature(const GraphDev* gds, const int2* fitems, int n, hipStream_t st)
+{
+    if (n > 0)
+        feature_kernel<<<n, kFeatThreads, 0, st>>>(gds, fitems);
+}
+
+void launch_assemble(const GraphDev* gds, const int2* nbs, int n, hipStream_t st)
+{
+    if (n > 0)
+        assemble_kernel<<<n, kAsmThreads, 0, st>>>(gds, nbs);
+}
+
+size_t solve_lds_bytes(int n_free, int n_frames)
+{
+    const size_t n = 6 * (size_t)n_free;
+    return sizeof(double) * (n * (n + 1) / 2 + 6 * n + 16 * (size_t)n_frames);
+}
+
+hipError_t solve_set_max_lds(size_t bytes)
+{
+    return hipFuncSetAttribute((const void*)solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+void launch_solve(const GraphDev* gds, int n_graphs, size_t lds, int mode, hipStream_t st)
+{
+    solve_kernel<<<n_graphs, kSolveThreads, lds, st>>>(gds, mode);
+}
+
+}  // namespace pg

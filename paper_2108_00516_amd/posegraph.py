@@ -1,0 +1,259 @@
+"""Python binding of the pose-graph library: argument marshalling only.
+
+Every step of the optimisation runs in the HIP kernels behind the C ABI.
+Frames may be given as NumPy arrays (host memory) or torch tensors (host or
+device); torch supplies device memory and the stream, nothing else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+
+class PoseGraphError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {message}")
+
+
+@dataclasses.dataclass
+class Config:
+    """Mirror of pg_config (defaults as pg_config_default)."""
+    max_frames: int = 16
+    gn_iters: int = 7
+    lambda_f: float = 1.0
+    lambda_g: float = 1.0
+    huber_f_m: float = 0.005
+    huber_g_m: float = 0.005
+    gate_dist_m: float = 0.01
+    gate_normal_rad: float = math.radians(30.0)
+    solver: int = L.PG_SOLVER_CHOLESKY
+    pcg_max_iters: int = 500
+    pcg_rel_tol: float = 1e-12
+    weighting: int = L.PG_WEIGHT_HUBER
+    precision: int = L.PG_PREC_FP32
+    use_graph: int = 1
+    timing: int = 0
+    tile_pixels: int = 0
+    prune_frac: float = 0.25
+
+    def to_c(self) -> L.pg_config:
+        c = L.pg_config()
+        for f in dataclasses.fields(self):
+            setattr(c, f.name, getattr(self, f.name))
+        return c
+
+
+@dataclasses.dataclass
+class Camera:
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+
+    def to_c(self) -> L.pg_camera:
+        return L.pg_camera(self.width, self.height, self.fx, self.fy, self.cx, self.cy)
+
+
+def stats_to_dict(s: L.pg_stats, iters: int) -> dict:
+    k = max(0, min(iters, L.PG_MAX_ITERS))
+    return dict(iters_done=s.iters_done, energy_f=np.array(s.energy_f[:k]), energy_g=np.array(s.energy_g[:k]),
+                n_valid_g=np.array(s.n_valid_g[:k]), n_valid_f=np.array(s.n_valid_f[:k]),
+                status_bits=s.status_bits, src_pixels=s.src_pixels, n_assoc_launches=s.n_assoc_launches,
+                ms_assoc=s.ms_assoc, ms_feature=s.ms_feature, ms_reduce=s.ms_reduce, ms_solve=s.ms_solve,
+                ms_total=s.ms_total)
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return C.c_void_p(None)
+
+
+def _pointer(a, dtype, shape):
+    """(pointer, keep-alive) of an array-like with the given dtype and shape:
+    torch tensors (host or device) are passed by their data pointer, anything
+    else through a contiguous NumPy copy in host memory."""
+    try:
+        import torch
+        if isinstance(a, torch.Tensor):
+            tdt = {np.float32: torch.float32, np.uint8: torch.uint8}[dtype]
+            t = a.detach().to(tdt).contiguous()
+            if tuple(t.shape) != tuple(shape):
+                raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+            return C.c_void_p(t.data_ptr()), t
+    except ImportError:
+        pass
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    if arr.shape != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {arr.shape}")
+    return C.c_void_p(arr.ctypes.data), arr
+
+
+class PoseGraph:
+    """One keyframe window on the GPU (pose_graph_* handle)."""
+
+    def __init__(self, camera: Camera, config: Optional[Config] = None, stream=None):
+        self.lib = L.load()
+        self.camera = camera
+        self.config = config or Config()
+        self._cfg = self.config.to_c()
+        self._cam = camera.to_c()
+        if stream is None:
+            st = _current_stream()
+        elif isinstance(stream, int):
+            st = C.c_void_p(stream)
+        else:
+            st = C.c_void_p(stream.cuda_stream)
+        self._stream = st
+        h = C.c_void_p()
+        rc = self.lib.pose_graph_create(C.byref(self._cfg), C.byref(self._cam), st, C.byref(h))
+        if rc != L.PG_OK:
+            raise PoseGraphError(rc, self.lib.pose_graph_last_error(None).decode())
+        self.h = h
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, rc):
+        if rc != L.PG_OK:
+            raise PoseGraphError(rc, self.lib.pose_graph_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.pose_graph_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def n_frames(self) -> int:
+        return self.lib.pose_graph_num_frames(self.h)
+
+    # -------------------------------------------------------- entry points
+    def add_frame(self, depth, mask, T, fixed: bool = False) -> int:
+        H, W = self.camera.height, self.camera.width
+        dp, keep_d = _pointer(depth, np.float32, (H, W))
+        mp, keep_m = _pointer(mask, np.uint8, (H, W))
+        Tm = np.ascontiguousarray(T, dtype=np.float64).reshape(16)
+        out = C.c_int()
+        self._check(self.lib.pose_graph_add_frame(self.h, dp, mp, Tm.ctypes.data_as(C.POINTER(C.c_double)),
+                                                  int(bool(fixed)), C.byref(out)))
+        return out.value
+
+    def add_matches(self, i: int, j: int, uv_i, uv_j):
+        n = int(np.asarray(uv_i.shape[0] if hasattr(uv_i, "shape") else len(uv_i)))
+        if n == 0:
+            self._check(self.lib.pose_graph_add_matches(self.h, i, j, None, None, 0))
+            return
+        a, ka = _pointer(uv_i, np.float32, (n, 2))
+        b, kb = _pointer(uv_j, np.float32, (n, 2))
+        self._check(self.lib.pose_graph_add_matches(self.h, i, j, a, b, n))
+
+    def set_pose(self, i: int, T):
+        Tm = np.ascontiguousarray(T, dtype=np.float64).reshape(16)
+        self._check(self.lib.pose_graph_set_pose(self.h, i, Tm.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def get_pose(self, i: int) -> np.ndarray:
+        T = np.zeros(16)
+        self._check(self.lib.pose_graph_get_pose(self.h, i, T.ctypes.data_as(C.POINTER(C.c_double))))
+        return T.reshape(4, 4)
+
+    @property
+    def poses(self) -> np.ndarray:
+        return np.stack([self.get_pose(i) for i in range(self.n_frames)]) if self.n_frames else np.zeros((0, 4, 4))
+
+    def set_poses(self, P):
+        for i, T in enumerate(np.asarray(P)):
+            self.set_pose(i, T)
+
+    def optimize(self, check: bool = True) -> dict:
+        s = L.pg_stats()
+        rc = self.lib.pose_graph_optimize(self.h, C.byref(s))
+        d = stats_to_dict(s, self.config.gn_iters)
+        d["status"] = rc
+        if check:
+            self._check(rc)
+        return d
+
+    def linearize(self):
+        N = self.n_frames
+        H = np.zeros((6 * N, 6 * N))
+        g = np.zeros(6 * N)
+        s = L.pg_stats()
+        self._check(self.lib.pose_graph_linearize(self.h, H.ctypes.data_as(C.POINTER(C.c_double)),
+                                                  g.ctypes.data_as(C.POINTER(C.c_double)), C.byref(s)))
+        return H, g, dict(energy_f=s.energy_f[0], energy_g=s.energy_g[0], n_valid_g=s.n_valid_g[0],
+                          n_valid_f=s.n_valid_f[0], src_pixels=s.src_pixels)
+
+    def associate(self, i: int, j: int):
+        hw = self.camera.width * self.camera.height
+        tgt = np.zeros(hw, np.int32)
+        r = np.zeros(hw, np.float32)
+        uv = np.zeros(2 * hw, np.float32)
+        self._check(self.lib.pose_graph_associate(self.h, i, j, tgt.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                  r.ctypes.data_as(C.POINTER(C.c_float)),
+                                                  uv.ctypes.data_as(C.POINTER(C.c_float))))
+        return tgt, r, uv.reshape(hw, 2)
+
+    def frame_info(self, i: int):
+        hw = self.camera.width * self.camera.height
+        m = np.zeros(4 * hw, np.float32)
+        n = C.c_int()
+        self._check(self.lib.pose_graph_frame_info(self.h, i, m.ctypes.data_as(C.POINTER(C.c_float)), C.byref(n)))
+        return m.reshape(self.camera.height, self.camera.width, 4), n.value
+
+    def set_mlp(self, params_fp16):
+        p = np.ascontiguousarray(params_fp16, dtype=np.float16)
+        self._check(self.lib.pose_graph_set_mlp(self.h, C.c_void_p(p.ctypes.data), p.nbytes))
+
+
+def optimize_batch(graphs: Sequence[PoseGraph], check: bool = True):
+    lib = L.load()
+    n = len(graphs)
+    arr = (C.c_void_p * n)(*[g.h.value for g in graphs])
+    stats = (L.pg_stats * n)()
+    rc = lib.pose_graph_optimize_batch(arr, n, stats)
+    if check and rc != L.PG_OK:
+        msg = lib.pose_graph_last_error(graphs[0].h).decode()
+        raise PoseGraphError(rc, msg)
+    out = [stats_to_dict(stats[k], graphs[k].config.gn_iters) for k in range(n)]
+    return rc, out
+
+
+def from_synth(g, config: Optional[Config] = None, stream=None, device_inputs: bool = False) -> PoseGraph:
+    """Fill a PoseGraph with a synthetic window (frames, poses, matches)."""
+    cfg = config or Config(max_frames=max(g.n_frames, 2))
+    pg = PoseGraph(Camera(g.width, g.height, g.fx, g.fy, g.cx, g.cy), cfg, stream)
+    conv = (lambda a: a)
+    if device_inputs:
+        import torch
+        conv = (lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda())
+    for k in range(g.n_frames):
+        pg.add_frame(conv(g.depth[k]), conv(g.mask[k]), g.poses_init[k], fixed=bool(g.fixed[k]))
+    for m in g.matches:
+        pg.add_matches(m.i, m.j, conv(m.uv_i), conv(m.uv_j))
+    if device_inputs:
+        import torch
+        torch.cuda.synchronize()
+    return pg

@@ -1,0 +1,310 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Sizes span several association tiles with ragged tails
+(tiny window: ~1.4k valid pixels per frame, 1024-pixel tiles; paper-scale
+window: ~22k per frame), plus the full 640x480 10- and 20-keyframe windows."""
+import functools
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_helpers import (G_REL_TOL, H_REL_TOL, POSE_TOL_M, POSE_TOL_RAD, check_normal_equations,
+                         max_pose_diff, near_half_integer)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    torch.zeros(1, device="cuda")
+    oracle.build(force=False)
+    oracle.set_threads(16)
+    return torch
+
+
+@functools.lru_cache(maxsize=None)
+def graph(name, **kw):
+    return synth.make_graph(name, **kw)
+
+
+def gpu_graph(g, **cfg):
+    from paper_2108_00516_amd import Config, from_synth
+    c = Config(max_frames=max(g.n_frames, 2), **cfg)
+    return from_synth(g, c, device_inputs=True)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("name", ["T", "P"])
+def test_preprocess_parity(name):
+    g = graph(name)
+    say(f"preprocess parity {name}")
+    pg = gpu_graph(g)
+    pb = oracle.OracleProblem.from_synth(g)
+    for f in range(g.n_frames):
+        m, nv = pg.frame_info(f)
+        V, Nn, code = pb.preprocess(f)
+        valid_o = code == 3
+        valid_g = m[..., 3] > 0
+        assert np.array_equal(valid_o, valid_g)
+        assert nv == valid_o.sum()
+        assert np.array_equal(m[..., 3][valid_g], g.depth[f][valid_g])
+        assert np.abs(m[..., :3][valid_g] - Nn[valid_g]).max() < 1e-5
+    pg.close()
+
+
+def certify_assoc(name, g, pg, pb, pairs):
+    """Every GPU/oracle decision difference must be a near-tie of FP32 vs FP64
+    rounding: a projection within 1e-3 px of a rounding boundary or the image
+    edge, a distance within 1e-6 m of the gate, a normal cosine within 1e-5 of
+    the gate."""
+    cos_gate = math.cos(pb.params.gate_angle)
+    total_diff = 0
+    for (i, j) in pairs:
+        tg, rg, uvg = pg.associate(i, j)
+        to, ro, proj, gate = pb.associate(g.poses_init, i, j)
+        diff = tg != to
+        total_diff += int(diff.sum())
+        for x in np.flatnonzero(diff):
+            u, v = proj[x]
+            ok = near_half_integer(u, 1e-3) or near_half_integer(v, 1e-3)
+            ok |= abs(gate[x, 0] - pb.params.gate_dist) <= 1e-6 if np.isfinite(gate[x, 0]) else False
+            ok |= abs(gate[x, 1] - cos_gate) <= 1e-5 if np.isfinite(gate[x, 1]) else False
+            assert ok, f"{name} pair {(i, j)} pixel {x}: gpu {tg[x]} oracle {to[x]} proj {proj[x]} gate {gate[x]}"
+        same = (tg >= 0) & (to >= 0) & ~diff
+        assert np.abs(rg[same] - ro[same]).max() < 2e-6
+        both = np.isfinite(uvg[:, 0]) & np.isfinite(proj[:, 0])
+        assert np.abs(uvg[both] - proj[both]).max() < 2e-3
+        assert (to >= 0).sum() > 0
+    return total_diff
+
+
+@pytest.mark.parametrize("name,pairs", [("T", [(0, 1), (1, 0), (3, 1)]), ("P", [(0, 1), (3, 7), (9, 2)])])
+def test_association_parity(name, pairs):
+    g = graph(name)
+    say(f"association parity {name} {pairs}")
+    pg = gpu_graph(g)
+    pb = oracle.OracleProblem.from_synth(g)
+    nd = certify_assoc(name, g, pg, pb, pairs)
+    say(f"  certified near-tie differences: {nd}")
+    pg.close()
+
+
+@pytest.mark.parametrize("name", ["T", "P"])
+def test_linearize_parity(name):
+    g = graph(name)
+    say(f"linearize parity {name}")
+    pg = gpu_graph(g)
+    H, gv, st = pg.linearize()
+    lin = oracle.OracleProblem.from_synth(g).linearize(g.poses_init)
+    rel = check_normal_equations(H, gv, lin)
+    say(f"  H rel Frobenius error {rel:.2e}")
+    assert np.array_equal(H, H.T)
+    assert st["n_valid_f"] == lin["n_valid_f"]
+    assert abs(st["n_valid_g"] - lin["n_valid_g"]) <= max(3, 1e-4 * lin["n_valid_g"])
+    assert st["energy_f"] == pytest.approx(lin["energy_f"], rel=1e-5)
+    assert st["energy_g"] == pytest.approx(lin["energy_g"], rel=1e-4)
+    pg.close()
+
+
+@pytest.mark.parametrize("name", ["T", "P", "X"])
+def test_optimize_parity(name):
+    g = graph(name)
+    say(f"optimize parity {name} ({g.n_frames} keyframes {g.width}x{g.height}, 7 iterations)")
+    pg = gpu_graph(g)
+    st = pg.optimize()
+    Pg = pg.poses
+    Po, so = oracle.OracleProblem.from_synth(g).optimize(g.poses_init, 7)
+    dr, dt = max_pose_diff(Pg, Po)
+    say(f"  max pose difference vs oracle: {dr:.2e} rad, {dt:.2e} m")
+    assert st["iters_done"] == 7 and so["iters_done"] == 7
+    assert dr <= POSE_TOL_RAD and dt <= POSE_TOL_M
+    assert np.allclose(st["energy_f"], so["energy_f"], rtol=1e-4)
+    assert np.allclose(st["energy_g"], so["energy_g"], rtol=1e-3)
+    assert np.array_equal(st["n_valid_f"], so["n_valid_f"])
+    pg.close()
+
+
+def test_determinism_and_graph_replay():
+    g = graph("T")
+    say("determinism / graph replay T")
+    import torch
+    pg_plain = gpu_graph(g, use_graph=0)
+    pg_graph = gpu_graph(g, use_graph=1)
+    pg_plain.optimize()
+    ref = pg_plain.poses
+    for rep in range(4):
+        pg_graph.set_poses(g.poses_init)
+        pg_graph.optimize()
+        assert np.array_equal(pg_graph.poses, ref), f"replay {rep}"
+        # eager work of the program between replays
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+        torch.cuda.synchronize()
+    pg_plain.set_poses(g.poses_init)
+    pg_plain.optimize()
+    assert np.array_equal(pg_plain.poses, ref)
+    pg_plain.close()
+    pg_graph.close()
+
+
+@pytest.mark.parametrize("tile", [256, 512, 2048])
+def test_tile_sizes(tile):
+    g = graph("T")
+    say(f"tile {tile} T")
+    pg = gpu_graph(g, tile_pixels=tile)
+    pg.optimize()
+    Po, _ = oracle.OracleProblem.from_synth(g).optimize(g.poses_init, 7)
+    dr, dt = max_pose_diff(pg.poses, Po)
+    assert dr <= POSE_TOL_RAD and dt <= POSE_TOL_M
+    pg.close()
+
+
+@pytest.mark.parametrize("lf,lg", [(1.0, 0.0), (0.0, 1.0), (0.5, 2.0)])
+def test_energy_term_weights(lf, lg):
+    g = graph("T")
+    say(f"lambda_f={lf} lambda_g={lg} T")
+    pg = gpu_graph(g, lambda_f=lf, lambda_g=lg)
+    pg.optimize()
+    Po, _ = oracle.OracleProblem.from_synth(g, oracle.Params(lambda_f=lf, lambda_g=lg)).optimize(g.poses_init, 7)
+    dr, dt = max_pose_diff(pg.poses, Po)
+    assert dr <= POSE_TOL_RAD and dt <= POSE_TOL_M
+    pg.close()
+
+
+def test_pcg_solver_matches():
+    from paper_2108_00516_amd import _lib
+    g = graph("T")
+    say("PCG solver T")
+    pg = gpu_graph(g, solver=_lib.PG_SOLVER_PCG)
+    pg.optimize()
+    Po, _ = oracle.OracleProblem.from_synth(g).optimize(g.poses_init, 7)
+    dr, dt = max_pose_diff(pg.poses, Po)
+    assert dr <= POSE_TOL_RAD and dt <= POSE_TOL_M
+    pg.close()
+
+
+def test_singular_window_keeps_poses():
+    from paper_2108_00516_amd import PoseGraphError, _lib
+    g0 = graph("T")
+    say("singular window T")
+    mask = g0.mask.copy()
+    mask[2] = 0
+    g = synth.SynthGraph(**{**g0.__dict__, "mask": mask,
+                            "matches": [m for m in g0.matches if 2 not in (m.i, m.j)]})
+    pg = gpu_graph(g)
+    st = pg.optimize(check=False)
+    assert st["status"] == _lib.PG_ERR_SINGULAR
+    assert st["iters_done"] == 0
+    assert np.array_equal(pg.poses, g.poses_init)
+    Po, so = oracle.OracleProblem.from_synth(g).optimize(g.poses_init, 7)
+    assert so["status"] == oracle.ERR_SINGULAR and so["iters_done"] == 0
+    with pytest.raises(PoseGraphError):
+        pg.optimize()
+    pg.close()
+
+
+def test_all_fixed_and_single_frame():
+    from paper_2108_00516_amd import Camera, Config, PoseGraph
+    g = graph("T")
+    say("all fixed / single frame T")
+    pg = PoseGraph(Camera(g.width, g.height, g.fx, g.fy, g.cx, g.cy), Config(max_frames=4))
+    for k in range(g.n_frames):
+        pg.add_frame(g.depth[k], g.mask[k], g.poses_init[k], fixed=True)
+    st = pg.optimize()
+    assert st["iters_done"] == 7 and np.array_equal(pg.poses, g.poses_init)
+    pg.close()
+    pg = PoseGraph(Camera(g.width, g.height, g.fx, g.fy, g.cx, g.cy), Config(max_frames=4))
+    pg.add_frame(g.depth[0], g.mask[0], g.poses_init[0], fixed=True)
+    st = pg.optimize()
+    assert st["iters_done"] == 7 and np.array_equal(pg.poses[0], g.poses_init[0])
+    pg.close()
+
+
+def test_host_and_device_inputs_agree():
+    from paper_2108_00516_amd import Config, from_synth
+    g = graph("T")
+    say("host vs device inputs T")
+    a = from_synth(g, Config(max_frames=4), device_inputs=False)
+    b = from_synth(g, Config(max_frames=4), device_inputs=True)
+    a.optimize()
+    b.optimize()
+    assert np.array_equal(a.poses, b.poses)
+    a.close()
+    b.close()
+
+
+def test_nonfinite_depth_is_invalid():
+    g0 = graph("T")
+    say("non-finite depth T")
+    depth = g0.depth.copy()
+    rng = np.random.default_rng(9)
+    for f in range(g0.n_frames):
+        vv, uu = np.nonzero(g0.mask[f])
+        sel = rng.choice(len(vv), 40, replace=False)
+        depth[f, vv[sel[:20]], uu[sel[:20]]] = np.nan
+        depth[f, vv[sel[20:30]], uu[sel[20:30]]] = np.inf
+        depth[f, vv[sel[30:]], uu[sel[30:]]] = -1.0
+    g = synth.SynthGraph(**{**g0.__dict__, "depth": depth})
+    pg = gpu_graph(g)
+    pg.optimize()
+    Po, _ = oracle.OracleProblem.from_synth(g).optimize(g.poses_init, 7)
+    dr, dt = max_pose_diff(pg.poses, Po)
+    assert dr <= POSE_TOL_RAD and dt <= POSE_TOL_M
+    pg.close()
+
+
+def test_matches_replace_and_remove():
+    g = graph("T")
+    say("match replacement T")
+    pg = gpu_graph(g)
+    m0 = g.matches[0]
+    # replace the first set by its first half, given in swapped order
+    half = len(m0.uv_i) // 2
+    pg.add_matches(m0.j, m0.i, m0.uv_j[:half], m0.uv_i[:half])
+    # remove the last set
+    ml = g.matches[-1]
+    pg.add_matches(ml.i, ml.j, np.zeros((0, 2), np.float32), np.zeros((0, 2), np.float32))
+    pg.optimize()
+    matches = [synth.MatchSet(m0.i, m0.j, m0.uv_i[:half], m0.uv_j[:half], m0.inlier[:half])] + \
+        list(g.matches[1:-1])
+    pb = oracle.OracleProblem(g.depth, g.mask, g.fx, g.fy, g.cx, g.cy, g.fixed, matches)
+    Po, so = pb.optimize(g.poses_init, 7)
+    dr, dt = max_pose_diff(pg.poses, Po)
+    assert dr <= POSE_TOL_RAD and dt <= POSE_TOL_M
+    pg.close()
+
+
+def test_abi_errors_on_gpu():
+    from paper_2108_00516_amd import Camera, Config, PoseGraph, PoseGraphError, _lib
+    g = graph("T")
+    say("ABI errors")
+    pg = PoseGraph(Camera(g.width, g.height, g.fx, g.fy, g.cx, g.cy), Config(max_frames=2))
+    pg.add_frame(g.depth[0], g.mask[0], g.poses_init[0], fixed=True)
+    bad = g.poses_init[1].copy()
+    bad[0, 0] += 0.1
+    with pytest.raises(PoseGraphError) as e:
+        pg.add_frame(g.depth[1], g.mask[1], bad)
+    assert e.value.status == _lib.PG_ERR_INVALID_ARG
+    pg.add_frame(g.depth[1], g.mask[1], g.poses_init[1])
+    with pytest.raises(PoseGraphError) as e:
+        pg.add_frame(g.depth[2], g.mask[2], g.poses_init[2])
+    assert e.value.status == _lib.PG_ERR_CAPACITY
+    with pytest.raises(PoseGraphError) as e:
+        pg.add_matches(0, 0, g.matches[0].uv_i, g.matches[0].uv_j)
+    assert e.value.status == _lib.PG_ERR_INVALID_ARG
+    with pytest.raises(PoseGraphError) as e:
+        pg.get_pose(5)
+    assert e.value.status == _lib.PG_ERR_INVALID_ARG
+    with pytest.raises(PoseGraphError) as e:
+        pg.set_mlp(np.zeros(10, np.float16))
+    assert e.value.status == _lib.PG_ERR_INVALID_ARG
+    pg.close()
+    pg.close()  # destroy is NULL-safe / idempotent in the binding
