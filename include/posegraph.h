@@ -51,7 +51,11 @@ typedef enum {
     PG_ERR_HIP = -7            /* a HIP runtime call failed                         */
 } pg_status;
 
-enum { PG_SOLVER_CHOLESKY = 0, PG_SOLVER_PCG = 1 };
+/* Solvers of the Gauss-Newton step (all exact up to rounding):
+ * AUTO picks Gauss-Jordan when the augmented system fits one workgroup's LDS
+ * (at most 21 free nodes), else Cholesky; PCG is the Jacobi-preconditioned
+ * conjugate gradient the paper names (Sec. IV-D). */
+enum { PG_SOLVER_AUTO = 0, PG_SOLVER_PCG = 1, PG_SOLVER_CHOLESKY = 2, PG_SOLVER_GAUSS_JORDAN = 3 };
 enum { PG_WEIGHT_HUBER = 0, PG_WEIGHT_LEARNED = 1 };
 enum { PG_PREC_FP32 = 0, PG_PREC_BF16X3 = 1 };
 
@@ -73,13 +77,13 @@ typedef struct {
     double huber_g_m;           /* Huber threshold of the dense term, metres (0.005)        */
     double gate_dist_m;         /* dense association distance gate, metres (0.01)           */
     double gate_normal_rad;     /* dense association normal-angle gate, radians (30 deg)    */
-    int solver;                 /* PG_SOLVER_CHOLESKY (default) or PG_SOLVER_PCG             */
+    int solver;                 /* PG_SOLVER_AUTO (default), _PCG, _CHOLESKY, _GAUSS_JORDAN */
     int pcg_max_iters;          /* PCG iteration cap (default 500)                           */
     double pcg_rel_tol;         /* PCG stop: |r| <= tol |b| (default 1e-12)                  */
     int weighting;              /* PG_WEIGHT_HUBER (default) or PG_WEIGHT_LEARNED            */
     int precision;              /* PG_PREC_FP32 (default) or PG_PREC_BF16X3                  */
     int use_graph;              /* 1 = replay the iteration loop as a captured hipGraph (1)  */
-    int timing;                 /* 1 = record HIP events around each kernel (0)              */
+    int timing;                 /* 1 = HIP events around each kernel, launched directly (0)  */
     int tile_pixels;            /* source pixels per association work item, 0 = library pick */
     double prune_frac;          /* learned weighting: fraction of source pixels dropped (0.25) */
 } pg_config;
@@ -95,6 +99,7 @@ typedef struct {
     long long src_pixels;                    /* sum over ordered pairs of valid source pixels */
     int n_assoc_launches;                    /* association kernel launches (timing = 1)   */
     float ms_assoc, ms_feature, ms_reduce, ms_solve, ms_total; /* kernel time (timing = 1) */
+    long long n_target_reads[PG_MAX_ITERS];  /* dense association: target pixels read   */
 } pg_stats;
 
 /* Defaults listed in pg_config. */

@@ -76,6 +76,7 @@ def lib():
         L.orc_preprocess_frame.argtypes = [P(Problem), C.c_int, dp, dp, P(C.c_ubyte)]
         L.orc_linearize.argtypes = [P(Problem), dp, dp, dp, dp, dp, P(LinStats)]
         L.orc_optimize.argtypes = [P(Problem), dp, C.c_int, P(OptStats)]
+        L.orc_linearize_given.argtypes = [P(Problem), dp, P(C.c_int), dp, dp, dp, dp, P(LinStats)]
         L.orc_associate.argtypes = [P(Problem), dp, C.c_int, C.c_int, P(C.c_int), dp, dp, dp]
         L.orc_dense_frozen.argtypes = [P(Problem), dp, C.c_int, C.c_int, C.c_int, P(C.c_int), P(C.c_int), dp, dp]
         L.orc_feature_eval.argtypes = [P(Problem), dp, C.c_int, C.c_int, dp, dp]
@@ -189,6 +190,30 @@ class OracleProblem:
         assert rc == OK, rc
         return dict(H=H, g=g, H_abs=Ha, g_abs=ga, energy_f=st.energy_f, energy_g=st.energy_g,
                     n_valid_g=st.n_valid_g, n_valid_f=st.n_valid_f)
+
+    def linearize_given(self, poses, targets):
+        """Normal equations with the dense association decisions given:
+        targets is (N(N-1), H*W) int32, ordered pairs in lexicographic order."""
+        poses = np.ascontiguousarray(poses, np.float64)
+        tg = np.ascontiguousarray(targets, np.int32)
+        N = self.n_frames
+        assert tg.shape == (N * (N - 1), self.width * self.height)
+        n6 = 6 * N
+        H = np.zeros((n6, n6))
+        g = np.zeros(n6)
+        Ha = np.zeros((n6, n6))
+        ga = np.zeros(n6)
+        st = LinStats()
+        rc = lib().orc_linearize_given(C.byref(self.c), _ptr(poses, C.c_double), _ptr(tg, C.c_int),
+                                       _ptr(H, C.c_double), _ptr(g, C.c_double), _ptr(Ha, C.c_double),
+                                       _ptr(ga, C.c_double), C.byref(st))
+        assert rc == OK, rc
+        return dict(H=H, g=g, H_abs=Ha, g_abs=ga, energy_f=st.energy_f, energy_g=st.energy_g,
+                    n_valid_g=st.n_valid_g, n_valid_f=st.n_valid_f)
+
+    def ordered_pairs(self):
+        N = self.n_frames
+        return [(i, j) for i in range(N) for j in range(N) if j != i]
 
     def optimize(self, poses, iters=7):
         P = np.ascontiguousarray(np.array(poses, np.float64, copy=True))

@@ -336,8 +336,11 @@ static void pair_transforms(const double *poses, int i, int j, double *A, double
     mat4_mul(poses + 16 * j, Ti_inv, B);   /* frame-i camera -> frame-j camera */
 }
 
+/* Dense term of one ordered pair.  With 'given' (H*W target indices, negative
+ * = no residual) the association decisions are taken from outside instead of
+ * S2, and the residuals, Jacobians and weights are evaluated for them. */
 static void dense_pair(const orc_problem *pb, const frame_maps *fm, const double *poses,
-                       pair_part *pp)
+                       const int *given, pair_part *pp)
 {
     const int i = pp->i, j = pp->j;
     double A[16], B[16];
@@ -345,9 +348,22 @@ static void dense_pair(const orc_problem *pb, const frame_maps *fm, const double
     const size_t hw = (size_t)pb->width * pb->height;
     for (size_t x = 0; x < hw; ++x) {   /* row-major source order */
         double s[3], r;
-        int y = associate_pixel(pb, fm, i, j, A, B, x, s, &r, NULL, NULL);
-        if (y < 0)
-            continue;
+        int y;
+        if (given) {
+            y = given[x];
+            if (y < 0)
+                continue;
+            const double *p = fm[i].vertex + 3 * x;
+            double d[3];
+            apply_T(A, fm[j].vertex + 3 * (size_t)y, s);
+            for (int k = 0; k < 3; ++k)
+                d[k] = s[k] - p[k];
+            r = dot3(fm[i].normal + 3 * x, d);
+        } else {
+            y = associate_pixel(pb, fm, i, j, A, B, x, s, &r, NULL, NULL);
+            if (y < 0)
+                continue;
+        }
         const double *n = fm[i].normal + 3 * x;
         const double *q = fm[j].vertex + 3 * (size_t)y;
         double row[12];
@@ -440,7 +456,8 @@ static int check_problem(const orc_problem *pb)
 }
 
 static int linearize_with(const orc_problem *pb, const frame_maps *fm, const double *poses,
-                          double *H, double *g, double *H_abs, double *g_abs, orc_lin_stats *st)
+                          const int *given, double *H, double *g, double *H_abs, double *g_abs,
+                          orc_lin_stats *st)
 {
     const int N = pb->n_frames, n6 = 6 * N;
     const int n_dense = (pb->lambda_g != 0.0) ? N * (N - 1) : 0;
@@ -464,8 +481,9 @@ static int linearize_with(const orc_problem *pb, const frame_maps *fm, const dou
     const int total = n_dense + n_feat;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
     for (int t = 0; t < total; ++t) {
-        if (t < n_dense)
-            dense_pair(pb, fm, poses, &parts[t]);          /* S2 + S3 */
+        if (t < n_dense)                                   /* S2 + S3 */
+            dense_pair(pb, fm, poses,
+                       given ? given + (size_t)t * pb->width * pb->height : NULL, &parts[t]);
         else
             feature_set(pb, fm, poses, t - n_dense, &parts[t]); /* S4 */
     }
@@ -520,7 +538,21 @@ int orc_linearize(const orc_problem *pb, const double *poses, double *H, double 
     frame_maps *fm = build_frames(pb);
     if (!fm)
         return ORC_ERR_ARG;
-    rc = linearize_with(pb, fm, poses, H, g, H_abs, g_abs, st);
+    rc = linearize_with(pb, fm, poses, NULL, H, g, H_abs, g_abs, st);
+    free_frames(pb, fm);
+    return rc;
+}
+
+int orc_linearize_given(const orc_problem *pb, const double *poses, const int *targets, double *H,
+                        double *g, double *H_abs, double *g_abs, orc_lin_stats *st)
+{
+    int rc = check_problem(pb);
+    if (rc != ORC_OK || !poses || !targets || !H || !g)
+        return ORC_ERR_ARG;
+    frame_maps *fm = build_frames(pb);
+    if (!fm)
+        return ORC_ERR_ARG;
+    rc = linearize_with(pb, fm, poses, targets, H, g, H_abs, g_abs, st);
     free_frames(pb, fm);
     return rc;
 }
@@ -606,7 +638,7 @@ int orc_optimize(const orc_problem *pb, double *poses, int iters, orc_opt_stats 
     rc = ORC_OK;
     for (int it = 0; it < iters; ++it) {
         orc_lin_stats ls;
-        linearize_with(pb, fm, poses, H, g, NULL, NULL, &ls);
+        linearize_with(pb, fm, poses, NULL, H, g, NULL, NULL, &ls);
         if (st) {
             st->energy_f[it] = ls.energy_f;
             st->energy_g[it] = ls.energy_g;

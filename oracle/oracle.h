@@ -72,6 +72,14 @@ int orc_preprocess_frame(const orc_problem *pb, int f, double *vertex, double *n
 int orc_linearize(const orc_problem *pb, const double *poses, double *H, double *g,
                   double *H_abs, double *g_abs, orc_lin_stats *st);
 
+/* As orc_linearize, with the dense association decisions given instead of
+ * taken by S2: targets holds, for every ordered pair in lexicographic order
+ * ((0,1), (0,2), ..., (1,0), (1,2), ...), H*W target pixel indices of the
+ * source pixels of frame i (negative = no residual).  Used to compare the
+ * arithmetic of another implementation on its own decision set. */
+int orc_linearize_given(const orc_problem *pb, const double *poses, const int *targets, double *H,
+                        double *g, double *H_abs, double *g_abs, orc_lin_stats *st);
+
 /* Fixed number of IRLS Gauss-Newton iterations; poses updated in place.  On a
  * singular system the poses of the last completed iteration are kept and
  * ORC_ERR_SINGULAR is returned. */

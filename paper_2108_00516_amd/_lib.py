@@ -22,7 +22,7 @@ PG_ERR_HIP = -7
 STATUS_NAMES = {0: "PG_OK", -1: "PG_ERR_INVALID_ARG", -2: "PG_ERR_NO_DEVICE", -3: "PG_ERR_OUT_OF_MEMORY",
                 -4: "PG_ERR_CAPACITY", -5: "PG_ERR_SINGULAR", -6: "PG_ERR_NONFINITE", -7: "PG_ERR_HIP"}
 
-PG_SOLVER_CHOLESKY, PG_SOLVER_PCG = 0, 1
+PG_SOLVER_AUTO, PG_SOLVER_PCG, PG_SOLVER_CHOLESKY, PG_SOLVER_GAUSS_JORDAN = 0, 1, 2, 3
 PG_WEIGHT_HUBER, PG_WEIGHT_LEARNED = 0, 1
 PG_PREC_FP32, PG_PREC_BF16X3 = 0, 1
 PG_MAX_FRAMES_LIMIT = 32
@@ -50,7 +50,8 @@ class pg_stats(C.Structure):
                 ("n_valid_g", C.c_longlong * PG_MAX_ITERS), ("n_valid_f", C.c_longlong * PG_MAX_ITERS),
                 ("status_bits", C.c_int), ("src_pixels", C.c_longlong), ("n_assoc_launches", C.c_int),
                 ("ms_assoc", C.c_float), ("ms_feature", C.c_float), ("ms_reduce", C.c_float),
-                ("ms_solve", C.c_float), ("ms_total", C.c_float)]
+                ("ms_solve", C.c_float), ("ms_total", C.c_float),
+                ("n_target_reads", C.c_longlong * PG_MAX_ITERS)]
 
 
 # entry point -> (restype, argtypes)
@@ -83,6 +84,13 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    try:
+        # torch supplies device memory and streams; its HIP runtime has the same
+        # soname as the one this library links, so load it first and let the
+        # process use a single runtime whatever the import order
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise RuntimeError(
             f"{path} is missing: build the HIP library first "

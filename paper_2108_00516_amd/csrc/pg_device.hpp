@@ -9,14 +9,21 @@ namespace pg {
 
 constexpr int kMaxFrames = 32;       // hard cap of nodes per graph
 constexpr int kMaxIters = 32;
-constexpr int kDenseFields = 29;     // per pixel-pair sums: 21 (J^T W J upper) + 6 (J^T W r) + E + count
+constexpr int kDenseFields = 30;     // per item sums: 21 (J^T W J upper) + 6 (J^T W r) + E + count + target reads
 constexpr int kDenseStride = 32;     // floats per dense partial record
 constexpr int kFeatFields = 92;      // 78 (12x12 upper) + 12 + E + count
 constexpr int kFeatStride = 96;
 constexpr int kAssocThreads = 256;   // threads per association work item
 constexpr int kTileMaxPixels = 8 * kAssocThreads;  // largest association tile
-constexpr int kNodeStats = 4;        // per node: E_g, E_f, n_g, n_f (doubles)
-constexpr int kIterRecord = 8;       // per iteration: E_f, E_g, n_g, n_f, ...
+constexpr int kNodeStats = 5;        // per node: E_g, E_f, n_g, n_f, target reads (doubles)
+constexpr int kIterRecord = 8;       // per iteration: E_f, E_g, n_g, n_f, target reads
+
+// resolved solver of a graph (GraphDev::solver)
+constexpr int kSolverPCG = 1;
+constexpr int kSolverCholesky = 2;
+constexpr int kSolverGaussJordan = 3;
+constexpr int kGjMaxN = 126;
+constexpr int kSolveStaticLds = 4096;  // static LDS of the solve kernel (upper bound)         // Gauss-Jordan: at most 21 free nodes (n x (n+1) doubles in LDS)
 
 // status bits (sticky, per graph)
 constexpr int kStatusSingular = 1;
@@ -36,6 +43,7 @@ struct WorkItem {
 struct GraphDev {
     int W, H, HW, n_frames;
     float fx, fy, cx, cy;
+    double fx64, fy64, cx64, cy64;
     float ifx, ify;
     float lambda_f, lambda_g, huber_f, huber_g, gate_d2, gate_cos;
     int n_sets;       // feature match sets
@@ -50,16 +58,14 @@ struct GraphDev {
     const float4* src_nz;     // frame f list at f*HW: {nx, ny, nz, z}
     const uint32_t* src_uv;   // frame f list at f*HW: u | v << 16
     const int* n_src;         // valid source pixels per frame
-    const int* item_base;     // per frame: index of its first work item (global)
-    const int* n_tiles;       // per frame: tiles of its source list
+    const int* pair_base;     // N(N-1)+1 prefix sums: partial records of ordered pair p are [pair_base[p], pair_base[p+1])
     float* partials;          // dense partial records (global item index)
-    float* fpartials;         // feature partial records per set
-    const float4* fpts;       // per match: p_m then p_n (w = 1 valid)
+    double* fpartials;        // feature partial records per set (FP64)
+    const float4* fpts;       // per match: {u, v, z, valid} of the pixel in frame i, then in frame j
     const int4* fsets;        // per set: {i, j, first match, count}
     const int* set_of;        // N*N: feature set of node pair, or -1
     float* xf32;              // per ordered pair: A (12) then B (12), rows of [R|t]
     double* xf64;             // per ordered pair: A (12)
-    float* tinv32;            // per node: T^-1 (12)
     double* poses;            // N * 16
     double* Hm;               // 6N * 6N normal matrix, row-major
     double* grad;             // 6N

@@ -22,8 +22,7 @@ void launch_preprocess(const float* depth, const uint8_t* mask, int W, int H, fl
                        float ify, float4* map, uint8_t* flag, int* row_cnt, int* total, float4* src_nz,
                        uint32_t* src_uv, hipStream_t st);
 void launch_match_points(const float* di, const uint8_t* mi, const float* dj, const uint8_t* mj, int W, int H,
-                         float cx, float cy, float ifx, float ify, const float* uvi, const float* uvj, int n,
-                         float4* out, hipStream_t st);
+                         const float* uvi, const float* uvj, int n, float4* out, hipStream_t st);
 int assoc_ppt_supported(int ppt);
 void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, hipStream_t st);
 void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int* target, float* r, float* uv,
@@ -31,6 +30,8 @@ void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int* target, 
 void launch_feature(const GraphDev* gds, const int2* fitems, int n, hipStream_t st);
 void launch_assemble(const GraphDev* gds, const int2* nbs, int n, hipStream_t st);
 size_t solve_lds_bytes(int n_free, int n_frames);
+int gj_slots(int n_free);
+void launch_gj_solve(const GraphDev* gds, int n_graphs, int slots, hipStream_t st);
 hipError_t solve_set_max_lds(size_t bytes);
 void launch_solve(const GraphDev* gds, int n_graphs, size_t lds, int mode, hipStream_t st);
 }  // namespace pg
@@ -81,11 +82,21 @@ struct Schedule {
     size_t lds = 0;
     int ppt = 4;
     int iters = 0;
+    bool gj = false;      // every graph solved by the register Gauss-Jordan kernel
+    int gj_slots = 1;
     hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> events;   // timing: start, then 5 per iteration
+    hipEvent_t fork = nullptr, join = nullptr;   // feature branch of the captured graph
     ~Schedule()
     {
+        if (fork)
+            (void)hipEventDestroy(fork);
+        if (join)
+            (void)hipEventDestroy(join);
         if (exec)
             (void)hipGraphExecDestroy(exec);
+        for (hipEvent_t e : events)
+            (void)hipEventDestroy(e);
     }
 };
 
@@ -96,6 +107,7 @@ struct pg_graph {
     pg_camera cam;
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
+    hipStream_t side_stream = nullptr;    // forked branch during capture
     int device = 0;
     int HW = 0;
     std::string err;
@@ -111,12 +123,14 @@ struct pg_graph {
     std::map<std::pair<int, int>, MatchSetHost> msets;
 
     // per-optimize device state
-    DevBuf d_poses, d_partials, d_fpartials, d_fpts, d_fsets, d_set_of, d_xf32, d_xf64, d_tinv, d_H, d_grad,
-        d_node_stats, d_free_ids, d_status, d_iters, d_iter_stats, d_n_src, d_item_base, d_n_tiles, d_mlp;
+    DevBuf d_poses, d_partials, d_fpartials, d_fpts, d_fsets, d_set_of, d_xf32, d_xf64, d_H, d_grad,
+        d_node_stats, d_free_ids, d_status, d_iters, d_iter_stats, d_n_src, d_pair_base, d_mlp;
     bool poses_dirty = true;          // host mirror newer than d_poses
     int n_sets = 0, n_free = 0, n_items = 0, tile = 0;
+    int solver = kSolverCholesky;     // resolved solver of the current tables
+    int lds_limit = 65536;            // device LDS per workgroup
     unsigned long long tables_version = 0;   // version the tables were built for
-    std::vector<int> item_base, n_tiles;
+    std::vector<int> pair_base;
     std::vector<WorkItem> items;      // local items (graph field 0)
     std::vector<int4> fsets;
     bool has_mlp = false;
@@ -226,16 +240,32 @@ pg_status prepare_graph(pg_graph* g)
         if (!g->fixed[f])
             free_ids.push_back(f);
     g->n_free = (int)free_ids.size();
-    // dense work items, ordered (source frame, tile, target frame)
+    {
+        const int nf = 6 * g->n_free;
+        const bool gj_fits = nf <= kGjMaxN;
+        switch (g->cfg.solver) {
+        case PG_SOLVER_PCG: g->solver = kSolverPCG; break;
+        case PG_SOLVER_CHOLESKY: g->solver = kSolverCholesky; break;
+        case PG_SOLVER_GAUSS_JORDAN:
+            if (!gj_fits)
+                return fail(g, PG_ERR_CAPACITY, "Gauss-Jordan solve of %d unknowns exceeds %d", nf, kGjMaxN);
+            g->solver = kSolverGaussJordan;
+            break;
+        default: g->solver = gj_fits ? kSolverGaussJordan : kSolverCholesky; break;
+        }
+    }
+    // dense work items, ordered (source frame, tile, target frame); the
+    // partial records of each ordered pair are contiguous (pair_base)
+    const int P = N * (N - 1);
+    std::vector<int> n_tiles(N, 0);
+    for (int i = 0; i < N; ++i)
+        n_tiles[i] = (g->n_src[i] + tile - 1) / tile;
+    g->pair_base.assign(P + 1, 0);
+    for (int p = 0; p < P; ++p)
+        g->pair_base[p + 1] = g->pair_base[p] + n_tiles[p / std::max(N - 1, 1)];
     g->items.clear();
-    g->item_base.assign(N, 0);
-    g->n_tiles.assign(N, 0);
-    int slot = 0;
-    for (int i = 0; i < N && N > 1; ++i) {
-        const int nt = (g->n_src[i] + tile - 1) / tile;
-        g->item_base[i] = slot;
-        g->n_tiles[i] = nt;
-        for (int t = 0; t < nt; ++t)
+    for (int i = 0; i < N && N > 1; ++i)
+        for (int t = 0; t < n_tiles[i]; ++t)
             for (int j = 0; j < N; ++j) {
                 if (j == i)
                     continue;
@@ -243,10 +273,10 @@ pg_status prepare_graph(pg_graph* g)
                 w.gij = i | (j << 8);
                 w.start = t * tile;
                 w.count = std::min(tile, g->n_src[i] - t * tile);
-                w.slot = slot++;
+                w.slot = g->pair_base[pair_index(i, j, N)] + t;
                 g->items.push_back(w);
             }
-    }
+    const int slot = g->pair_base[P];
     g->n_items = slot;
     // feature sets, in (i, j) order
     g->fsets.clear();
@@ -267,21 +297,18 @@ pg_status prepare_graph(pg_graph* g)
         off += m.n;
     }
     g->n_sets = (int)g->fsets.size();
-    const int P = N * (N - 1);
     HIP_OR_FAIL(g, g->d_partials.ensure(sizeof(float) * kDenseStride * std::max(g->n_items, 1)));
-    HIP_OR_FAIL(g, g->d_fpartials.ensure(sizeof(float) * kFeatStride * std::max(g->n_sets, 1)));
+    HIP_OR_FAIL(g, g->d_fpartials.ensure(sizeof(double) * kFeatStride * std::max(g->n_sets, 1)));
     HIP_OR_FAIL(g, g->d_fsets.ensure(sizeof(int4) * std::max(g->n_sets, 1)));
     HIP_OR_FAIL(g, g->d_set_of.ensure(sizeof(int) * N * N));
     HIP_OR_FAIL(g, g->d_xf32.ensure(sizeof(float) * 24 * std::max(P, 1)));
     HIP_OR_FAIL(g, g->d_xf64.ensure(sizeof(double) * 12 * std::max(P, 1)));
-    HIP_OR_FAIL(g, g->d_tinv.ensure(sizeof(float) * 12 * N));
     HIP_OR_FAIL(g, g->d_H.ensure(sizeof(double) * 36 * N * N));
     HIP_OR_FAIL(g, g->d_grad.ensure(sizeof(double) * 6 * N));
     HIP_OR_FAIL(g, g->d_node_stats.ensure(sizeof(double) * kNodeStats * N));
     HIP_OR_FAIL(g, g->d_free_ids.ensure(sizeof(int) * std::max(g->n_free, 1)));
     HIP_OR_FAIL(g, g->d_n_src.ensure(sizeof(int) * N));
-    HIP_OR_FAIL(g, g->d_item_base.ensure(sizeof(int) * N));
-    HIP_OR_FAIL(g, g->d_n_tiles.ensure(sizeof(int) * N));
+    HIP_OR_FAIL(g, g->d_pair_base.ensure(sizeof(int) * (P + 1)));
     if (g->n_sets)
         HIP_OR_FAIL(g, hipMemcpyAsync(g->d_fsets.p, g->fsets.data(), sizeof(int4) * g->n_sets,
                                       hipMemcpyHostToDevice, g->stream));
@@ -292,10 +319,8 @@ pg_status prepare_graph(pg_graph* g)
                                       hipMemcpyHostToDevice, g->stream));
     HIP_OR_FAIL(g, hipMemcpyAsync(g->d_n_src.p, g->n_src.data(), sizeof(int) * N, hipMemcpyHostToDevice,
                                   g->stream));
-    HIP_OR_FAIL(g, hipMemcpyAsync(g->d_item_base.p, g->item_base.data(), sizeof(int) * N, hipMemcpyHostToDevice,
-                                  g->stream));
-    HIP_OR_FAIL(g, hipMemcpyAsync(g->d_n_tiles.p, g->n_tiles.data(), sizeof(int) * N, hipMemcpyHostToDevice,
-                                  g->stream));
+    HIP_OR_FAIL(g, hipMemcpyAsync(g->d_pair_base.p, g->pair_base.data(), sizeof(int) * (P + 1),
+                                  hipMemcpyHostToDevice, g->stream));
     // the host copies above read pageable host vectors that stay alive; make
     // sure they completed before the vectors may change
     HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
@@ -315,6 +340,10 @@ GraphDev make_dev(pg_graph* g)
     d.fy = (float)g->cam.fy;
     d.cx = (float)g->cam.cx;
     d.cy = (float)g->cam.cy;
+    d.fx64 = g->cam.fx;
+    d.fy64 = g->cam.fy;
+    d.cx64 = g->cam.cx;
+    d.cy64 = g->cam.cy;
     d.ifx = (float)(1.0 / g->cam.fx);
     d.ify = (float)(1.0 / g->cam.fy);
     d.lambda_f = (float)g->cfg.lambda_f;
@@ -327,23 +356,21 @@ GraphDev make_dev(pg_graph* g)
     d.n_free = g->n_free;
     d.precision = g->cfg.precision;
     d.weighting = g->cfg.weighting;
-    d.solver = g->cfg.solver;
+    d.solver = g->solver;
     d.pcg_max_iters = g->cfg.pcg_max_iters;
     d.pcg_rel_tol = g->cfg.pcg_rel_tol;
     d.maps = g->maps.as<float4>();
     d.src_nz = g->src_nz.as<float4>();
     d.src_uv = g->src_uv.as<uint32_t>();
     d.n_src = g->d_n_src.as<int>();
-    d.item_base = g->d_item_base.as<int>();
-    d.n_tiles = g->d_n_tiles.as<int>();
+    d.pair_base = g->d_pair_base.as<int>();
     d.partials = g->d_partials.as<float>();
-    d.fpartials = g->d_fpartials.as<float>();
+    d.fpartials = g->d_fpartials.as<double>();
     d.fpts = g->d_fpts.as<float4>();
     d.fsets = g->d_fsets.as<int4>();
     d.set_of = g->d_set_of.as<int>();
     d.xf32 = g->d_xf32.as<float>();
     d.xf64 = g->d_xf64.as<double>();
-    d.tinv32 = g->d_tinv.as<float>();
     d.poses = g->d_poses.as<double>();
     d.Hm = g->d_H.as<double>();
     d.grad = g->d_grad.as<double>();
@@ -403,6 +430,19 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
                 nbs.push_back(make_int2((int)k, I | (J << 8)));
         lds = std::max(lds, solve_lds_bytes(g->n_free, g->n_frames));
     }
+    // one solve kernel for the whole schedule: Gauss-Jordan when every graph
+    // resolved to it, else the LDS Cholesky/PCG kernel (Gauss-Jordan graphs
+    // then use Cholesky, which gives the same step)
+    s.gj = true;
+    s.gj_slots = 1;
+    for (pg_graph* g : gs) {
+        s.gj = s.gj && g->solver == kSolverGaussJordan;
+        s.gj_slots = std::max(s.gj_slots, gj_slots(g->n_free));
+    }
+    if (!s.gj)
+        for (GraphDev& d : devs)
+            if (d.solver == kSolverGaussJordan)
+                d.solver = kSolverCholesky;
     // items of all graphs are concatenated; the XCD mapping of the association
     // kernel hands each XCD a contiguous run of them
     s.n_items = (int)items.size();
@@ -433,35 +473,53 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
 }
 
 // Enqueue the whole optimisation: prepare, then per iteration the four phases.
-void enqueue_iters(const Schedule& s, int iters, hipStream_t st)
+// With events (1 + 5 per iteration), each launch is bracketed on the stream.
+// With a side stream (graph capture), the feature kernel, which does not
+// depend on the association, runs on a forked branch beside it.
+hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std::vector<hipEvent_t>* ev,
+                         hipStream_t side = nullptr)
 {
     const GraphDev* gds = s.gds.as<GraphDev>();
     const int ng = (int)s.graphs.size();
-    launch_solve(gds, ng, s.lds, 1, st);
-    for (int it = 0; it < iters; ++it) {
-        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, st);
-        launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
-        launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
-        launch_solve(gds, ng, s.lds, 0, st);
-    }
-}
-
-struct Timers {
-    std::vector<hipEvent_t> ev;
-    ~Timers()
-    {
-        for (auto e : ev)
-            (void)hipEventDestroy(e);
-    }
-    hipEvent_t make()
-    {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess)
-            return nullptr;
-        ev.push_back(e);
+    hipError_t e = hipSuccess;
+    if (ev && (e = hipEventRecord((*ev)[0], st)) != hipSuccess)
         return e;
+    launch_solve(gds, ng, s.lds, 1, st);
+    const bool fork = side && s.n_fitems > 0;
+    for (int it = 0; it < iters; ++it) {
+        const hipEvent_t* m = ev ? ev->data() + 1 + 5 * it : nullptr;
+        if (fork) {
+            if ((e = hipEventRecord(s.fork, st)) != hipSuccess || (e = hipStreamWaitEvent(side, s.fork, 0)) != hipSuccess)
+                return e;
+            launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, side);
+            if ((e = hipEventRecord(s.join, side)) != hipSuccess)
+                return e;
+        }
+        if (m && (e = hipEventRecord(m[0], st)) != hipSuccess)
+            return e;
+        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, st);
+        if (m && (e = hipEventRecord(m[1], st)) != hipSuccess)
+            return e;
+        if (fork) {
+            if ((e = hipStreamWaitEvent(st, s.join, 0)) != hipSuccess)
+                return e;
+        } else {
+            launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
+        }
+        if (m && (e = hipEventRecord(m[2], st)) != hipSuccess)
+            return e;
+        launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
+        if (m && (e = hipEventRecord(m[3], st)) != hipSuccess)
+            return e;
+        if (s.gj)
+            launch_gj_solve(gds, ng, s.gj_slots, st);
+        else
+            launch_solve(gds, ng, s.lds, 0, st);
+        if (m && (e = hipEventRecord(m[4], st)) != hipSuccess)
+            return e;
     }
-};
+    return hipGetLastError();
+}
 
 pg_status run_schedule(Schedule& s, int iters, bool use_graph, bool timing, std::vector<pg_stats*>& stats)
 {
@@ -472,44 +530,17 @@ pg_status run_schedule(Schedule& s, int iters, bool use_graph, bool timing, std:
         if (r != PG_OK)
             return r;
     }
-    float ms[5] = {0, 0, 0, 0, 0};
-    int n_assoc = 0;
-    if (timing) {
-        // events around every launch, on the launch stream
-        Timers T;
-        const GraphDev* gds = s.gds.as<GraphDev>();
-        const int ng = (int)s.graphs.size();
-        hipEvent_t e0 = T.make();
-        HIP_OR_FAIL(g0, hipEventRecord(e0, st));
-        launch_solve(gds, ng, s.lds, 1, st);
-        std::vector<hipEvent_t> marks;
-        for (int it = 0; it < iters; ++it) {
-            hipEvent_t a = T.make(), b = T.make(), c = T.make(), d = T.make(), e = T.make();
-            HIP_OR_FAIL(g0, hipEventRecord(a, st));
-            launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, st);
-            HIP_OR_FAIL(g0, hipEventRecord(b, st));
-            launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
-            HIP_OR_FAIL(g0, hipEventRecord(c, st));
-            launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
-            HIP_OR_FAIL(g0, hipEventRecord(d, st));
-            launch_solve(gds, ng, s.lds, 0, st);
-            HIP_OR_FAIL(g0, hipEventRecord(e, st));
-            marks.insert(marks.end(), {a, b, c, d, e});
-        }
-        HIP_OR_FAIL(g0, hipGetLastError());
-        HIP_OR_FAIL(g0, hipStreamSynchronize(st));
-        for (int it = 0; it < iters; ++it) {
-            float t;
-            for (int k = 0; k < 4; ++k) {
-                HIP_OR_FAIL(g0, hipEventElapsedTime(&t, marks[5 * it + k], marks[5 * it + k + 1]));
-                ms[k] += t;
-            }
-        }
-        float tot;
-        HIP_OR_FAIL(g0, hipEventElapsedTime(&tot, e0, marks.empty() ? e0 : marks.back()));
-        ms[4] = tot;
-        n_assoc = s.n_items > 0 ? iters : 0;
-    } else if (use_graph) {
+    if (timing && s.events.size() != (size_t)(1 + 5 * iters)) {
+        for (hipEvent_t e : s.events)
+            (void)hipEventDestroy(e);
+        s.events.assign(1 + 5 * iters, nullptr);
+        for (auto& e : s.events)
+            HIP_OR_FAIL(g0, hipEventCreate(&e));
+    }
+    const std::vector<hipEvent_t>* ev = timing ? &s.events : nullptr;
+    // events recorded inside a captured graph cannot be queried for elapsed
+    // time, so timing runs the same launches directly on the stream
+    if (use_graph && !timing) {
         if (!s.exec || s.iters != iters) {
             if (s.exec) {
                 (void)hipGraphExecDestroy(s.exec);
@@ -517,11 +548,18 @@ pg_status run_schedule(Schedule& s, int iters, bool use_graph, bool timing, std:
             }
             hipStream_t cs = g0->capture_stream;
             HIP_OR_FAIL(g0, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            enqueue_iters(s, iters, cs);
+            if (!s.fork && (hipEventCreateWithFlags(&s.fork, hipEventDisableTiming) != hipSuccess ||
+                            hipEventCreateWithFlags(&s.join, hipEventDisableTiming) != hipSuccess))
+                return fail(g0, PG_ERR_HIP, "event creation failed");
+            hipError_t ce = enqueue_iters(s, iters, cs, nullptr, g0->side_stream);
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamEndCapture(cs, &graph);
-            if (e != hipSuccess)
-                return fail(g0, PG_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+            if (ce != hipSuccess || e != hipSuccess) {
+                if (graph)
+                    (void)hipGraphDestroy(graph);
+                return fail(g0, PG_ERR_HIP, "graph capture failed: %s",
+                            hipGetErrorString(ce != hipSuccess ? ce : e));
+            }
             e = hipGraphInstantiate(&s.exec, graph, nullptr, nullptr, 0);
             (void)hipGraphDestroy(graph);
             if (e != hipSuccess) {
@@ -532,8 +570,7 @@ pg_status run_schedule(Schedule& s, int iters, bool use_graph, bool timing, std:
         }
         HIP_OR_FAIL(g0, hipGraphLaunch(s.exec, st));
     } else {
-        enqueue_iters(s, iters, st);
-        HIP_OR_FAIL(g0, hipGetLastError());
+        HIP_OR_FAIL(g0, enqueue_iters(s, iters, st, ev));
     }
     // read back poses and statistics of every graph
     for (pg_graph* g : s.graphs) {
@@ -545,6 +582,18 @@ pg_status run_schedule(Schedule& s, int iters, bool use_graph, bool timing, std:
                                        hipMemcpyDeviceToHost, st));
     }
     HIP_OR_FAIL(g0, hipStreamSynchronize(st));
+    float ms[5] = {0, 0, 0, 0, 0};
+    int n_assoc = 0;
+    if (timing) {
+        for (int it = 0; it < iters; ++it)
+            for (int k = 0; k < 4; ++k) {
+                float t = 0.f;
+                HIP_OR_FAIL(g0, hipEventElapsedTime(&t, s.events[1 + 5 * it + k], s.events[2 + 5 * it + k]));
+                ms[k] += t;
+            }
+        HIP_OR_FAIL(g0, hipEventElapsedTime(&ms[4], s.events[0], s.events[5 * iters]));
+        n_assoc = s.n_items > 0 ? iters : 0;
+    }
     pg_status ret = PG_OK;
     for (size_t k = 0; k < s.graphs.size(); ++k) {
         pg_graph* g = s.graphs[k];
@@ -566,6 +615,7 @@ pg_status run_schedule(Schedule& s, int iters, bool use_graph, bool timing, std:
                 out->energy_g[it] = g->h_iter_stats[kIterRecord * it + 1];
                 out->n_valid_g[it] = (long long)g->h_iter_stats[kIterRecord * it + 2];
                 out->n_valid_f[it] = (long long)g->h_iter_stats[kIterRecord * it + 3];
+                out->n_target_reads[it] = (long long)g->h_iter_stats[kIterRecord * it + 4];
             }
             out->status_bits = *g->h_status;
             long long sp = 0;
@@ -602,7 +652,7 @@ void pg_config_default(pg_config* c)
     c->huber_g_m = 0.005;
     c->gate_dist_m = 0.01;
     c->gate_normal_rad = 30.0 * M_PI / 180.0;
-    c->solver = PG_SOLVER_CHOLESKY;
+    c->solver = PG_SOLVER_AUTO;
     c->pcg_max_iters = 500;
     c->pcg_rel_tol = 1e-12;
     c->weighting = PG_WEIGHT_HUBER;
@@ -633,7 +683,7 @@ pg_status pose_graph_create(const pg_config* cfg, const pg_camera* cam, void* hi
     if (!(cfg->huber_f_m > 0 && cfg->huber_g_m > 0 && cfg->gate_dist_m > 0 && cfg->gate_normal_rad > 0 &&
           cfg->gate_normal_rad <= M_PI && cfg->lambda_f >= 0 && cfg->lambda_g >= 0))
         return fail(nullptr, PG_ERR_INVALID_ARG, "bad method parameters");
-    if (cfg->solver != PG_SOLVER_CHOLESKY && cfg->solver != PG_SOLVER_PCG)
+    if (cfg->solver < PG_SOLVER_AUTO || cfg->solver > PG_SOLVER_GAUSS_JORDAN)
         return fail(nullptr, PG_ERR_INVALID_ARG, "unknown solver");
     if (cfg->weighting != PG_WEIGHT_HUBER && cfg->weighting != PG_WEIGHT_LEARNED)
         return fail(nullptr, PG_ERR_INVALID_ARG, "unknown weighting");
@@ -657,19 +707,22 @@ pg_status pose_graph_create(const pg_config* cfg, const pg_camera* cam, void* hi
         delete g;
         return fail(nullptr, PG_ERR_NO_DEVICE, "hipGetDevice failed");
     }
-    // LDS of the solve for a window of max_frames nodes with one fixed
+    // LDS of the solve for a window of max_frames nodes with one fixed: the
+    // packed Cholesky layout must fit; Gauss-Jordan is used where it fits
     int lds_max = 0;
     (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device);
-    const size_t need = solve_lds_bytes(cfg->max_frames - 1, cfg->max_frames) + 4096;
-    if (need > (size_t)lds_max) {
+    g->lds_limit = lds_max - kSolveStaticLds;
+    const size_t need = solve_lds_bytes(cfg->max_frames - 1, cfg->max_frames);
+    if (need > (size_t)g->lds_limit ||
+        (cfg->solver == PG_SOLVER_GAUSS_JORDAN && 6 * (cfg->max_frames - 1) > kGjMaxN)) {
         delete g;
         return fail(nullptr, PG_ERR_CAPACITY, "max_frames %d needs %zu B of LDS for the solve, device has %d",
                     cfg->max_frames, need, lds_max);
     }
-    if (need > 65536 && solve_set_max_lds(need) != hipSuccess) {
+    if (g->lds_limit > 65536 - kSolveStaticLds && solve_set_max_lds(g->lds_limit) != hipSuccess) {
         (void)hipGetLastError();
         delete g;
-        return fail(nullptr, PG_ERR_CAPACITY, "cannot raise the solve kernel's LDS limit to %zu B", need);
+        return fail(nullptr, PG_ERR_CAPACITY, "cannot raise the solve kernel's LDS limit to %d B", g->lds_limit);
     }
     const size_t M = cfg->max_frames, HW = g->HW;
     hipError_t e = hipSuccess;
@@ -692,7 +745,8 @@ pg_status pose_graph_create(const pg_config* cfg, const pg_camera* cam, void* hi
     g->h_iters = g->h_status + 1;
     g->h_iter_stats = (double*)(g->h_status + 2);
     g->h_poses = g->h_iter_stats + kIterRecord * kMaxIters;
-    if ((e = hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
+    if ((e = hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&g->side_stream, hipStreamNonBlocking)) != hipSuccess) {
         pose_graph_destroy(g);
         return fail(nullptr, PG_ERR_HIP, "stream: %s", hipGetErrorString(e));
     }
@@ -774,8 +828,7 @@ pg_status pose_graph_add_matches(pg_graph* g, int id_i, int id_j, const float* u
     const size_t HW = g->HW;
     launch_match_points(g->depth.as<float>() + id_i * HW, g->mask.as<uint8_t>() + id_i * HW,
                         g->depth.as<float>() + id_j * HW, g->mask.as<uint8_t>() + id_j * HW, g->cam.width,
-                        g->cam.height, (float)g->cam.cx, (float)g->cam.cy, (float)(1.0 / g->cam.fx),
-                        (float)(1.0 / g->cam.fy), ui, uj, n, ms.pts.as<float4>(), g->stream);
+                        g->cam.height, ui, uj, n, ms.pts.as<float4>(), g->stream);
     HIP_OR_FAIL(g, hipGetLastError());
     HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
     return PG_OK;
@@ -908,13 +961,15 @@ pg_status pose_graph_linearize(pg_graph* g, double* H, double* grad, pg_stats* s
     HIP_OR_FAIL(g, hipStreamSynchronize(st));
     if (stats) {
         memset(stats, 0, sizeof(*stats));
-        double ef = 0, eg = 0, cf = 0, cg = 0;
+        double ef = 0, eg = 0, cf = 0, cg = 0, rd = 0;
         for (int k = 0; k < N; ++k) {
             eg += ns[kNodeStats * k + 0];
             ef += ns[kNodeStats * k + 1];
             cg += ns[kNodeStats * k + 2];
             cf += ns[kNodeStats * k + 3];
+            rd += ns[kNodeStats * k + 4];
         }
+        stats->n_target_reads[0] = (long long)rd;
         stats->energy_f[0] = ef;
         stats->energy_g[0] = eg;
         stats->n_valid_g[0] = (long long)cg;
@@ -1016,6 +1071,8 @@ void pose_graph_destroy(pg_graph* g)
     g->sched.reset();
     if (g->capture_stream)
         (void)hipStreamDestroy(g->capture_stream);
+    if (g->side_stream)
+        (void)hipStreamDestroy(g->side_stream);
     if (g->h_status)
         (void)hipHostFree(g->h_status);
     delete g;

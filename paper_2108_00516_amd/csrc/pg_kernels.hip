@@ -4,7 +4,7 @@
 // Per Gauss-Newton iteration:
 //   assoc_kernel     dense projective association, point-to-plane residual of
 //                    Eq. (3), Jacobian, Huber IRLS weight and the per-item sum of
-//                    w J_i^T J_i, w r J_i, energy and count (29 values);
+//                    w J_i^T J_i, w r J_i, energy, count and target reads (30 values);
 //   feature_kernel   feature residual of Eq. (2) with its 3x12 Jacobian;
 //   assemble_kernel  FP64 expansion of the per-pair sums into the 6x6 node
 //                    blocks of J^T W J and J^T W r, in a fixed order;
@@ -154,8 +154,7 @@ __global__ void row_scatter_kernel(const float4* __restrict__ map, const uint8_t
 // ------------------------------------------------------------ feature points
 
 __device__ __forceinline__ bool match_point(const float* __restrict__ depth, const uint8_t* __restrict__ mask,
-                                            int W, int H, float cx, float cy, float ifx, float ify, float u,
-                                            float v, float4& p)
+                                            int W, int H, float u, float v, float4& p)
 {
     const float ui = round_half_up(u), vi = round_half_up(v);
     p = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -165,24 +164,24 @@ __device__ __forceinline__ bool match_point(const float* __restrict__ depth, con
     const float z = depth[x];
     if (!depth_ok(z, mask[x]))
         return false;
-    p = make_float4(z * ((ui - cx) * ifx), z * ((vi - cy) * ify), z, 1.0f);
+    p = make_float4(ui, vi, z, 1.0f);
     return true;
 }
 
-// 3-D endpoints of each match (back-projection of the nearest pixel); w = 1
-// when both endpoints have depth, else the match is inert.
+// Endpoints of each match: the nearest pixel and its depth, {u, v, z, valid};
+// valid = 1 when both endpoints have depth, else the match is inert.  The
+// feature kernel back-projects them in FP64.
 __global__ void match_points_kernel(const float* __restrict__ depth_i, const uint8_t* __restrict__ mask_i,
                                     const float* __restrict__ depth_j, const uint8_t* __restrict__ mask_j,
-                                    int W, int H, float cx, float cy, float ifx, float ify,
-                                    const float* __restrict__ uv_i, const float* __restrict__ uv_j, int n,
-                                    float4* __restrict__ out)
+                                    int W, int H, const float* __restrict__ uv_i, const float* __restrict__ uv_j,
+                                    int n, float4* __restrict__ out)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n)
         return;
     float4 pm, pn;
-    const bool a = match_point(depth_i, mask_i, W, H, cx, cy, ifx, ify, uv_i[2 * k], uv_i[2 * k + 1], pm);
-    const bool b = match_point(depth_j, mask_j, W, H, cx, cy, ifx, ify, uv_j[2 * k], uv_j[2 * k + 1], pn);
+    const bool a = match_point(depth_i, mask_i, W, H, uv_i[2 * k], uv_i[2 * k + 1], pm);
+    const bool b = match_point(depth_j, mask_j, W, H, uv_j[2 * k], uv_j[2 * k + 1], pn);
     const float ok = (a && b) ? 1.0f : 0.0f;
     pm.w = ok;
     pn.w = ok;
@@ -324,8 +323,10 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     }
     float4 t[PPT];
 #pragma unroll
-    for (int m = 0; m < PPT; ++m)
+    for (int m = 0; m < PPT; ++m) {
         t[m] = (y[m] >= 0) ? tmap[y[m]] : make_float4(0.f, 0.f, 0.f, 0.f);
+        acc[29] += (y[m] >= 0) ? 1.0f : 0.0f;
+    }
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         if (y[m] < 0)
@@ -411,10 +412,39 @@ __global__ void assoc_debug_kernel(const GraphDev* __restrict__ gds, int i, int 
 
 // -------------------------------------------------------- feature residuals
 
-// One block per match set: e = T_i^-1 p_m - T_j^-1 p_n (Eq. 2), its Jacobian
-// [-R_i^T, R_i^T [p_m]x | R_j^T, -R_j^T [p_n]x], Huber weight; sums of
-// w J^T J (12x12 upper), w J^T e, rho and the count.
-constexpr int kFeatThreads = 128;
+// One block per match set, in FP64 (the residual is a millimetre difference
+// of object-frame points; the whole term is a few thousand matches):
+// e = T_i^-1 p_m - T_j^-1 p_n (Eq. 2), its Jacobian
+// [-R_i^T, R_i^T [p_m]x | R_j^T, -R_j^T [p_n]x], Huber weight; per thread
+// sums of w J^T J (12x12 upper), w J^T e, rho and the count in registers,
+// then a recursive-halving wave reduction (three groups of 32 values) and a
+// fixed-order sum over the waves.
+constexpr int kFeatThreads = 256;
+
+template <int HALF, int OFF, typename T, int L>
+__device__ __forceinline__ void halve_at(T (&acc)[L], int lane)
+{
+    const bool up = (lane & (2 * HALF)) != 0;
+#pragma unroll
+    for (int q = 0; q < HALF; ++q) {
+        const T send = up ? acc[OFF + q] : acc[OFF + q + HALF];
+        const T keep = up ? acc[OFF + q + HALF] : acc[OFF + q];
+        acc[OFF + q] = keep + __shfl_xor(send, 2 * HALF);
+    }
+}
+
+// reduce the 32 values acc[OFF..OFF+31] over the wave: lane l ends with the
+// total of value OFF + (l >> 1) in acc[OFF]
+template <int OFF, typename T, int L>
+__device__ __forceinline__ void wave_reduce32(T (&acc)[L], int lane)
+{
+    halve_at<16, OFF>(acc, lane);
+    halve_at<8, OFF>(acc, lane);
+    halve_at<4, OFF>(acc, lane);
+    halve_at<2, OFF>(acc, lane);
+    halve_at<1, OFF>(acc, lane);
+    acc[OFF] += __shfl_xor(acc[OFF], 1);
+}
 
 __global__ __launch_bounds__(kFeatThreads) void feature_kernel(const GraphDev* __restrict__ gds,
                                                                const int2* __restrict__ fitems)
@@ -424,40 +454,50 @@ __global__ __launch_bounds__(kFeatThreads) void feature_kernel(const GraphDev* _
     if (*gd.status)
         return;
     const int4 S = gd.fsets[fi.y];
-    const float* Ti = gd.tinv32 + 12 * S.x;
-    const float* Tj = gd.tinv32 + 12 * S.y;
-    float acc[kFeatFields];
+    __shared__ double Tinv[2][12];
+    __shared__ double red[kFeatThreads / 64][96];
+    if (threadIdx.x < 24) {
+        const int side = threadIdx.x / 12, e = threadIdx.x % 12, r = e / 4, c = e % 4;
+        const double* T = gd.poses + 16 * (side == 0 ? S.x : S.y);
+        // [R^T | -R^T t]
+        Tinv[side][e] = (c < 3) ? T[4 * c + r] : -(T[r] * T[3] + T[4 + r] * T[7] + T[8 + r] * T[11]);
+    }
+    __syncthreads();
+    const double huber = (double)gd.huber_f;
+    double acc[96];
 #pragma unroll
-    for (int k = 0; k < kFeatFields; ++k)
-        acc[k] = 0.f;
-    const float huber = gd.huber_f;
+    for (int q = 0; q < 96; ++q)
+        acc[q] = 0.0;
     for (int k = threadIdx.x; k < S.w; k += kFeatThreads) {
-        const float4 pm = gd.fpts[2 * (S.z + k)];
-        const float4 pn = gd.fpts[2 * (S.z + k) + 1];
-        if (!(pm.w > 0.f))
+        const float4 qm = gd.fpts[2 * (S.z + k)];
+        const float4 qn = gd.fpts[2 * (S.z + k) + 1];
+        if (!(qm.w > 0.f))
             continue;
-        float e[3], J[3][12];
+        const double zm = qm.z, zn = qn.z;
+        const double pm[3] = {zm * ((double)qm.x - gd.cx64) / gd.fx64, zm * ((double)qm.y - gd.cy64) / gd.fy64, zm};
+        const double pn[3] = {zn * ((double)qn.x - gd.cx64) / gd.fx64, zn * ((double)qn.y - gd.cy64) / gd.fy64, zn};
+        double e[3], J[3][12];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-            const float ai = Ti[4 * r], bi = Ti[4 * r + 1], ci = Ti[4 * r + 2];
-            const float aj = Tj[4 * r], bj = Tj[4 * r + 1], cj = Tj[4 * r + 2];
-            e[r] = (fmaf(ai, pm.x, fmaf(bi, pm.y, fmaf(ci, pm.z, Ti[4 * r + 3])))) -
-                   (fmaf(aj, pn.x, fmaf(bj, pn.y, fmaf(cj, pn.z, Tj[4 * r + 3]))));
-            J[r][0] = -ai;
-            J[r][1] = -bi;
-            J[r][2] = -ci;
-            J[r][3] = bi * pm.z - ci * pm.y;   // row r of R_i^T [p_m]x = (R_i^T)_r x p_m
-            J[r][4] = ci * pm.x - ai * pm.z;
-            J[r][5] = ai * pm.y - bi * pm.x;
-            J[r][6] = aj;
-            J[r][7] = bj;
-            J[r][8] = cj;
-            J[r][9] = -(bj * pn.z - cj * pn.y);
-            J[r][10] = -(cj * pn.x - aj * pn.z);
-            J[r][11] = -(aj * pn.y - bj * pn.x);
+            const double* Ti = Tinv[0] + 4 * r;
+            const double* Tj = Tinv[1] + 4 * r;
+            e[r] = (Ti[0] * pm[0] + Ti[1] * pm[1] + Ti[2] * pm[2] + Ti[3]) -
+                   (Tj[0] * pn[0] + Tj[1] * pn[1] + Tj[2] * pn[2] + Tj[3]);
+            J[r][0] = -Ti[0];
+            J[r][1] = -Ti[1];
+            J[r][2] = -Ti[2];
+            J[r][3] = Ti[1] * pm[2] - Ti[2] * pm[1];   // (R_i^T)_r x p_m
+            J[r][4] = Ti[2] * pm[0] - Ti[0] * pm[2];
+            J[r][5] = Ti[0] * pm[1] - Ti[1] * pm[0];
+            J[r][6] = Tj[0];
+            J[r][7] = Tj[1];
+            J[r][8] = Tj[2];
+            J[r][9] = -(Tj[1] * pn[2] - Tj[2] * pn[1]);
+            J[r][10] = -(Tj[2] * pn[0] - Tj[0] * pn[2]);
+            J[r][11] = -(Tj[0] * pn[1] - Tj[1] * pn[0]);
         }
-        const float ne = sqrtf(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-        const float w = (ne <= huber) ? 1.0f : huber / ne;
+        const double ne = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+        const double w = (ne <= huber) ? 1.0 : huber / ne;
         int q = 0;
 #pragma unroll
         for (int a = 0; a < 12; ++a)
@@ -467,18 +507,24 @@ __global__ __launch_bounds__(kFeatThreads) void feature_kernel(const GraphDev* _
 #pragma unroll
         for (int a = 0; a < 12; ++a)
             acc[78 + a] += w * (J[0][a] * e[0] + J[1][a] * e[1] + J[2][a] * e[2]);
-        acc[90] += (ne <= huber) ? 0.5f * ne * ne : huber * (ne - 0.5f * huber);
-        acc[91] += 1.0f;
+        acc[90] += (ne <= huber) ? 0.5 * ne * ne : huber * (ne - 0.5 * huber);
+        acc[91] += 1.0;
     }
-    __shared__ float red[kFeatThreads * (kFeatFields + 1)];
-#pragma unroll
-    for (int k = 0; k < kFeatFields; ++k)
-        red[threadIdx.x * (kFeatFields + 1) + k] = acc[k];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    wave_reduce32<0>(acc, lane);
+    wave_reduce32<32>(acc, lane);
+    wave_reduce32<64>(acc, lane);
+    if ((lane & 1) == 0) {
+        red[wave][lane >> 1] = acc[0];
+        red[wave][32 + (lane >> 1)] = acc[32];
+        red[wave][64 + (lane >> 1)] = acc[64];
+    }
     __syncthreads();
     if (threadIdx.x < kFeatFields) {
-        float v = 0.f;
-        for (int t = 0; t < kFeatThreads; ++t)
-            v += red[t * (kFeatFields + 1) + threadIdx.x];
+        double v = red[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < kFeatThreads / 64; ++w)
+            v += red[w][threadIdx.x];
         gd.fpartials[(size_t)fi.y * kFeatStride + threadIdx.x] = v;
     }
 }
@@ -506,19 +552,20 @@ __device__ __forceinline__ double sym6(const double* M, int a, int b)
     return (a <= b) ? M[upper_index(a, b, 6)] : M[upper_index(b, a, 6)];
 }
 
-__device__ __forceinline__ double sym12(const float* F, int a, int b)
+__device__ __forceinline__ double sym12(const double* F, int a, int b)
 {
-    return (double)((a <= b) ? F[upper_index(a, b, 12)] : F[upper_index(b, a, 12)]);
+    return (a <= b) ? F[upper_index(a, b, 12)] : F[upper_index(b, a, 12)];
 }
 
-constexpr int kAsmThreads = 256;
+constexpr int kAsmThreads = 512;
 constexpr int kMaxPairsPerBlock = 2 * (kMaxFrames - 1);
 
 // One block per node block (I, J), I >= J, of the 6N x 6N system: reduces the
-// per-item partial records of the ordered pairs touching it in FP64 (tiles in
-// order), expands them with the adjoint, adds the feature blocks (each match
-// counted for both orderings of Eq. 1), and writes H (both triangles), the
-// gradient segment and the node's energy/count record (diagonal blocks).
+// partial records of the ordered pairs touching it in FP64 (each pair's
+// records are contiguous, summed in order with four interleaved partial sums),
+// expands them with the adjoint, adds the feature blocks (each match counted
+// for both orderings of Eq. 1), and writes H (both triangles), the gradient
+// segment and the node's energy/count record (diagonal blocks).
 __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* __restrict__ gds,
                                                                const int2* __restrict__ nbs)
 {
@@ -533,6 +580,9 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
     __shared__ double S[kMaxPairsPerBlock][kDenseFields];
     __shared__ double P[kMaxPairsPerBlock][36];
     __shared__ double X[kMaxPairsPerBlock][42];
+    __shared__ int sset[kMaxFrames];
+    __shared__ int sfirst[kMaxFrames];
+    __shared__ double AX[kMaxPairsPerBlock][12];   // A = T_i T_j^-1 of each pair (FP64)
 
     // pair k: for k < np/2 the pair has I as source, else I as target
     auto pair_of = [&](int k, int& i, int& j) {
@@ -549,16 +599,39 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
         }
     };
 
+    // feature sets of this block and whether I is their first node
+    if (threadIdx.x < N) {
+        const int K = threadIdx.x;
+        int s = -1;
+        if (K != I && (diag || K == J))
+            s = gd.set_of[I * N + K];
+        sset[K] = s;
+        sfirst[K] = (s >= 0 && gd.fsets[s].x == I) ? 1 : 0;
+    }
+    for (int task = threadIdx.x; task < np * 12; task += kAsmThreads) {
+        const int k = task / 12;
+        int i, j;
+        pair_of(k, i, j);
+        AX[k][task % 12] = gd.xf64[12 * pair_index(i, j, N) + task % 12];
+    }
     for (int task = threadIdx.x; task < np * kDenseFields; task += kAsmThreads) {
         const int k = task / kDenseFields, f = task % kDenseFields;
         int i, j;
         pair_of(k, i, j);
-        const int jj = (j < i) ? j : j - 1;
-        const int nt = gd.n_tiles[i], base = gd.item_base[i];
-        double s = 0.0;
-        for (int t = 0; t < nt; ++t)
-            s += (double)gd.partials[(size_t)(base + t * (N - 1) + jj) * kDenseStride + f];
-        S[k][f] = s;
+        const int p = pair_index(i, j, N);
+        const int b0 = gd.pair_base[p], b1 = gd.pair_base[p + 1];
+        const float* __restrict__ src = gd.partials + f;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int t = b0;
+        for (; t + 4 <= b1; t += 4) {
+            s0 += (double)src[(size_t)t * kDenseStride];
+            s1 += (double)src[(size_t)(t + 1) * kDenseStride];
+            s2 += (double)src[(size_t)(t + 2) * kDenseStride];
+            s3 += (double)src[(size_t)(t + 3) * kDenseStride];
+        }
+        for (; t < b1; ++t)
+            s0 += (double)src[(size_t)t * kDenseStride];
+        S[k][f] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
     // P = M Ad (off-diagonal blocks and the target-role diagonal term)
@@ -566,7 +639,10 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
         const int k = task / 36, e = task % 36, a = e / 6, c = e % 6;
         int i, j;
         pair_of(k, i, j);
-        const double* Xa = gd.xf64 + 12 * pair_index(i, j, N);
+        const bool src_role = diag ? (k < N - 1) : (k == 0);
+        if (diag && src_role)
+            continue;
+        const double* Xa = AX[k];
         double v = 0.0;
         for (int l = 0; l < 6; ++l)
             v += sym6(S[k], a, l) * adj(Xa, l, c);
@@ -577,26 +653,27 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
         const int k = task / 42, e = task % 42;
         int i, j;
         pair_of(k, i, j);
-        const bool src = (i == I) && (diag ? k < N - 1 : k == 0);
-        const double* Xa = gd.xf64 + 12 * pair_index(i, j, N);
+        const bool src_role = diag ? (k < N - 1) : (k == 0);
+        const double* Xa = AX[k];
         double v;
         if (e < 36) {
             const int a = e / 6, c = e % 6;
             if (!diag)
-                v = src ? -P[k][e] : -P[k][6 * c + a];       // -M Ad  |  -(M Ad)^T
-            else if (src)
-                v = sym6(S[k], a, c);                         // M
-            else {
-                v = 0.0;                                       // Ad^T M Ad
+                v = src_role ? -P[k][e] : -P[k][6 * c + a];   // -M Ad  |  -(M Ad)^T
+            else if (src_role)
+                v = sym6(S[k], a, c);                          // M
+            else if (a <= c) {
+                v = 0.0;                                        // Ad^T M Ad (upper)
                 for (int l = 0; l < 6; ++l)
                     v += adj(Xa, l, a) * P[k][6 * l + c];
-            }
+            } else
+                v = 0.0;
         } else {
             const int a = e - 36;
-            if (src)
-                v = S[k][21 + a];                              // g_i = v
+            if (src_role)
+                v = S[k][21 + a];                               // g_i = v
             else {
-                v = 0.0;                                       // g_j = -Ad^T v
+                v = 0.0;                                        // g_j = -Ad^T v
                 for (int l = 0; l < 6; ++l)
                     v -= adj(Xa, l, a) * S[k][21 + l];
             }
@@ -609,55 +686,60 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
         if (threadIdx.x < 36) {
             const int e = threadIdx.x, a = e / 6, c = e % 6;
             double h = lg * (X[0][e] + X[1][e]);
-            const int s = gd.set_of[I * N + J];
+            const int s = sset[J];
             if (s >= 0) {
-                const float* F = gd.fpartials + (size_t)s * kFeatStride;
-                const bool first = gd.fsets[s].x == I;
-                h += lf2 * (first ? sym12(F, a, 6 + c) : sym12(F, 6 + a, c));
+                const double* F = gd.fpartials + (size_t)s * kFeatStride;
+                h += lf2 * (sfirst[J] ? sym12(F, a, 6 + c) : sym12(F, 6 + a, c));
             }
             gd.Hm[(size_t)(6 * I + a) * n6 + 6 * J + c] = h;
             gd.Hm[(size_t)(6 * J + c) * n6 + 6 * I + a] = h;
         }
     } else {
-        if (threadIdx.x < 42) {
+        // the upper triangle of the diagonal block is summed and mirrored, so
+        // H is exactly symmetric
+        if (threadIdx.x < 42 && (threadIdx.x >= 36 || threadIdx.x / 6 <= threadIdx.x % 6)) {
             const int e = threadIdx.x;
             double h = 0.0;
             for (int k = 0; k < np; ++k)
                 h += X[k][e];
             h *= lg;
             for (int K = 0; K < N; ++K) {
-                const int s = (K == I) ? -1 : gd.set_of[I * N + K];
+                const int s = sset[K];
                 if (s < 0)
                     continue;
-                const float* F = gd.fpartials + (size_t)s * kFeatStride;
-                const int o = (gd.fsets[s].x == I) ? 0 : 6;
+                const double* F = gd.fpartials + (size_t)s * kFeatStride;
+                const int o = sfirst[K] ? 0 : 6;
                 if (e < 36)
                     h += lf2 * sym12(F, o + e / 6, o + e % 6);
                 else
-                    h += lf2 * (double)F[78 + o + (e - 36)];
+                    h += lf2 * F[78 + o + (e - 36)];
             }
-            if (e < 36)
+            if (e < 36) {
                 gd.Hm[(size_t)(6 * I + e / 6) * n6 + 6 * I + e % 6] = h;
-            else
+                gd.Hm[(size_t)(6 * I + e % 6) * n6 + 6 * I + e / 6] = h;
+            } else {
                 gd.grad[6 * I + (e - 36)] = h;
+            }
         } else if (threadIdx.x == 64) {
-            double Eg = 0.0, cg = 0.0, Ef = 0.0, cf = 0.0;
+            double Eg = 0.0, cg = 0.0, Ef = 0.0, cf = 0.0, rd = 0.0;
             for (int k = 0; k < N - 1; ++k) {
                 Eg += S[k][27];
                 cg += S[k][28];
+                rd += S[k][29];
             }
             for (int K = 0; K < N; ++K) {
-                const int s = (K == I) ? -1 : gd.set_of[I * N + K];
-                if (s < 0 || gd.fsets[s].x != I)
+                const int s = sset[K];
+                if (s < 0 || !sfirst[K])
                     continue;
-                const float* F = gd.fpartials + (size_t)s * kFeatStride;
-                Ef += (double)F[90];
-                cf += (double)F[91];
+                const double* F = gd.fpartials + (size_t)s * kFeatStride;
+                Ef += F[90];
+                cf += F[91];
             }
             gd.node_stats[kNodeStats * I + 0] = lg * Eg;
             gd.node_stats[kNodeStats * I + 1] = lf2 * Ef;
             gd.node_stats[kNodeStats * I + 2] = cg;
             gd.node_stats[kNodeStats * I + 3] = cf;
+            gd.node_stats[kNodeStats * I + 4] = rd;
         }
     }
 }
@@ -708,7 +790,7 @@ __device__ void mat4_mul(const double* A, const double* B, double* C)
 }
 
 // A = T_i T_j^-1, B = T_j T_i^-1 per ordered pair (FP64, stored FP32 and
-// FP64), T^-1 per node (FP32), from the poses in LDS.
+// FP64), from the poses in LDS.
 __device__ void compute_transforms(const GraphDev& gd, const double* __restrict__ Ts)
 {
     const int N = gd.n_frames;
@@ -731,14 +813,6 @@ __device__ void compute_transforms(const GraphDev& gd, const double* __restrict_
             gd.xf32[p * 24 + k] = (float)A[k];
             gd.xf32[p * 24 + 12 + k] = (float)B[k];
             gd.xf64[p * 12 + k] = A[k];
-        }
-    }
-    for (int n = threadIdx.x; n < N; n += blockDim.x) {
-        const double* T = Ts + 16 * n;
-        for (int r = 0; r < 3; ++r) {
-            for (int c = 0; c < 3; ++c)
-                gd.tinv32[12 * n + 4 * r + c] = (float)T[4 * c + r];
-            gd.tinv32[12 * n + 4 * r + 3] = (float)(-(T[r] * T[3] + T[4 + r] * T[7] + T[8 + r] * T[11]));
         }
     }
 }
@@ -775,29 +849,46 @@ __device__ double block_max(double v, double* scratch)
 
 __device__ __forceinline__ double sym_tri(const double* L, int i, int j) { return (i >= j) ? L[tri(i, j)] : L[tri(j, i)]; }
 
+// row/column of entry e of a packed lower triangle (e = i(i+1)/2 + j)
+__device__ __forceinline__ void tri_rc(int e, int& i, int& j)
+{
+    int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+    while ((a + 1) * (a + 2) / 2 <= e)
+        ++a;
+    while (a * (a + 1) / 2 > e)
+        --a;
+    i = a;
+    j = e - a * (a + 1) / 2;
+}
+
 // mode 1: start of an optimize (clear status, iteration counter; transforms).
-// mode 0: one Gauss-Newton solve + update + transforms for the next iteration.
-// Dynamic LDS: packed lower triangle of H_ff, then 6 vectors of n, then 16N poses.
+// mode 0: one Gauss-Newton solve (Cholesky or PCG) + update + transforms for
+// the next iteration.  Dynamic LDS: the packed lower triangle of the bordered
+// matrix with -g_f^T as row n, then 2(n+1) + 4n doubles of vectors, then 16N
+// poses.
 __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __restrict__ gds, int mode)
 {
     const GraphDev& gd = gds[blockIdx.x];
     const int N = gd.n_frames;
     const int n = 6 * gd.n_free, n6 = 6 * N;
+    const int msize = (n + 1) * (n + 2) / 2;
     extern __shared__ double sm[];
-    double* Lm = sm;                               // n(n+1)/2
-    double* bv = Lm + n * (n + 1) / 2;              // rhs, then solution
-    double* dv = bv + n;                            // pivots / diagonal
-    double* xv = dv + n;                            // PCG vectors
+    double* Lm = sm;
+    double* piv = Lm + msize;   // n+1: Cholesky 1/sqrt(pivot); PCG diagonal
+    double* xv = piv + 2 * (n + 1);
     double* rv = xv + n;
     double* pv = rv + n;
     double* qv = pv + n;
-    double* Ts = qv + n;                            // 16 N poses
+    double* Ts = qv + n;        // 16 N poses
     __shared__ double scratch[kSolveThreads / 64];
+    __shared__ double ns[kMaxFrames * kNodeStats];
+    __shared__ int sfree[kMaxFrames];
+    const int tid = threadIdx.x;
 
-    for (int k = threadIdx.x; k < 16 * N; k += blockDim.x)
+    for (int k = tid; k < 16 * N; k += blockDim.x)
         Ts[k] = gd.poses[k];
     if (mode == 1) {
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             *gd.status = 0;
             *gd.iters_done = 0;
         }
@@ -808,124 +899,93 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
     if (*gd.status)
         return;
     const int it = *gd.iters_done;
-    if (threadIdx.x == 0) {
-        double Ef = 0.0, Eg = 0.0, cf = 0.0, cg = 0.0;
-        for (int k = 0; k < N; ++k) {
-            Eg += gd.node_stats[kNodeStats * k + 0];
-            Ef += gd.node_stats[kNodeStats * k + 1];
-            cg += gd.node_stats[kNodeStats * k + 2];
-            cf += gd.node_stats[kNodeStats * k + 3];
-        }
-        double* rec = gd.iter_stats + kIterRecord * it;
-        rec[0] = Ef;
-        rec[1] = Eg;
-        rec[2] = cg;
-        rec[3] = cf;
+    for (int k = tid; k < kNodeStats * N; k += blockDim.x)
+        ns[k] = gd.node_stats[k];
+    for (int k = tid; k < gd.n_free; k += blockDim.x)
+        sfree[k] = gd.free_ids[k];
+    __syncthreads();
+    for (int e = tid; e < msize; e += blockDim.x) {
+        int a, b;
+        tri_rc(e, a, b);
+        double v = 0.0;
+        if (a < n)
+            v = gd.Hm[(size_t)(6 * sfree[a / 6] + a % 6) * n6 + 6 * sfree[b / 6] + b % 6];
+        else if (b < n)
+            v = -gd.grad[6 * sfree[b / 6] + b % 6];
+        Lm[e] = v;
+    }
+    // iteration record: one field per thread, nodes summed in order
+    if (tid < kNodeStats) {
+        const int src[kNodeStats] = {1, 0, 2, 3, 4};   // E_f, E_g, n_g, n_f, target reads
+        double s = 0.0;
+        for (int k = 0; k < N; ++k)
+            s += ns[kNodeStats * k + src[tid]];
+        gd.iter_stats[kIterRecord * it + tid] = s;
     }
     if (n == 0) {                                   // every node fixed
-        __syncthreads();
-        if (threadIdx.x == 0)
+        if (tid == 0)
             *gd.iters_done = it + 1;
         return;
     }
-    // H_ff (lower, packed) and b = -g_f
-    for (int e = threadIdx.x; e < n * (n + 1) / 2; e += blockDim.x) {
-        int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-        while ((a + 1) * (a + 2) / 2 <= e)
-            ++a;
-        while (a * (a + 1) / 2 > e)
-            --a;
-        const int b = e - a * (a + 1) / 2;
-        const int ra = 6 * gd.free_ids[a / 6] + a % 6, rb = 6 * gd.free_ids[b / 6] + b % 6;
-        Lm[e] = gd.Hm[(size_t)ra * n6 + rb];
-    }
-    for (int a = threadIdx.x; a < n; a += blockDim.x)
-        bv[a] = -gd.grad[6 * gd.free_ids[a / 6] + a % 6];
     __syncthreads();
     double md = 0.0;
-    for (int a = threadIdx.x; a < n; a += blockDim.x)
+    for (int a = tid; a < n; a += blockDim.x)
         md = fmax(md, Lm[tri(a, a)]);
     const double maxdiag = block_max(md, scratch);
     bool singular = !(maxdiag > 0.0);
 
-    if (!singular && gd.solver == 0) {
-        // right-looking Cholesky on the packed lower triangle, one barrier per
-        // column: after step k the trailing block holds the Schur complement
-        for (int k = 0; k < n && !singular; ++k) {
+    if (!singular && gd.solver == kSolverCholesky) {
+        // right-looking Cholesky of the bordered matrix, one barrier per
+        // column; the trailing block is updated by a 16 x 32 thread grid.
+        // The border row ends as L^-1 (-g_f) scaled by the pivots.
+        double* dv = piv;
+        const int ty = tid >> 5, tx = tid & 31;
+        for (int k = 0; k < n; ++k) {
             const double akk = Lm[tri(k, k)];
             if (!(akk > 1e-12 * maxdiag)) {
                 singular = true;
                 break;
             }
             const double inv = 1.0 / akk;
-            const int m = n - k - 1, cnt = m * (m + 1) / 2;
-            for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-                int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-                while ((a + 1) * (a + 2) / 2 <= e)
-                    ++a;
-                while (a * (a + 1) / 2 > e)
-                    --a;
-                const int b = e - a * (a + 1) / 2;
-                const int ii = k + 1 + a, jj = k + 1 + b;
-                Lm[tri(ii, jj)] -= Lm[tri(ii, k)] * (Lm[tri(jj, k)] * inv);
+            for (int ii = k + 1 + ty; ii <= n; ii += kSolveThreads / 32) {
+                const double lik = Lm[tri(ii, k)] * inv;
+                const int jmax = (ii < n) ? ii : n - 1;
+                for (int jj = k + 1 + tx; jj <= jmax; jj += 32)
+                    Lm[tri(ii, jj)] -= lik * Lm[tri(jj, k)];
             }
             __syncthreads();
         }
         if (!singular) {
-            for (int k = threadIdx.x; k < n; k += blockDim.x)
-                dv[k] = sqrt(Lm[tri(k, k)]);
+            for (int k = tid; k < n; k += blockDim.x)
+                dv[k] = 1.0 / sqrt(Lm[tri(k, k)]);
             __syncthreads();
-            for (int e = threadIdx.x; e < n * (n + 1) / 2; e += blockDim.x) {
-                int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-                while ((a + 1) * (a + 2) / 2 <= e)
-                    ++a;
-                while (a * (a + 1) / 2 > e)
-                    --a;
-                const int b = e - a * (a + 1) / 2;
-                Lm[e] = (a == b) ? dv[a] : Lm[e] / dv[b];
-            }
-            __syncthreads();
-            // triangular solves by one wave, rows lane + 64 m held in registers
-            if (threadIdx.x < 64) {
-                const int lane = threadIdx.x;
-                double r0 = (lane < n) ? bv[lane] : 0.0;
-                double r1 = (lane + 64 < n) ? bv[lane + 64] : 0.0;
-                double r2 = (lane + 128 < n) ? bv[lane + 128] : 0.0;
-                for (int k = 0; k < n; ++k) {               // L y = b
+            // back substitution L^T x = y by one wave, y_k = border_k / d_k;
+            // with unscaled columns, x_r = (y_r - t_r / d_r) / d_r where
+            // t_r = sum over k > r of Lm(k, r) x_k
+            if (tid < 64) {
+                const int lane = tid;
+                double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+                for (int k = n - 1; k >= 0; --k) {
                     const int mk = k >> 6, lk = k & 63;
-                    const double own = (mk == 0) ? r0 : (mk == 1) ? r1 : r2;
-                    const double yk = __shfl(own, lk) / Lm[tri(k, k)];
-                    if (lane + 0 > k && lane < n) r0 -= Lm[tri(lane, k)] * yk;
-                    if (lane + 64 > k && lane + 64 < n) r1 -= Lm[tri(lane + 64, k)] * yk;
-                    if (lane + 128 > k && lane + 128 < n) r2 -= Lm[tri(lane + 128, k)] * yk;
-                    if (lane == lk) {
-                        if (mk == 0) r0 = yk;
-                        else if (mk == 1) r1 = yk;
-                        else r2 = yk;
-                    }
+                    const double tk = (mk == 0) ? t0 : (mk == 1) ? t1 : t2;
+                    double xk = 0.0;
+                    if (lane == lk)
+                        xk = (Lm[tri(n, k)] * dv[k] - tk * dv[k]) * dv[k];
+                    xk = __shfl(xk, lk);
+                    if (lane < k) t0 += Lm[tri(k, lane)] * xk;
+                    if (lane + 64 < k) t1 += Lm[tri(k, lane + 64)] * xk;
+                    if (lane + 128 < k) t2 += Lm[tri(k, lane + 128)] * xk;
+                    if (lane == lk)
+                        xv[k] = xk;
                 }
-                for (int k = n - 1; k >= 0; --k) {          // L^T x = y
-                    const int mk = k >> 6, lk = k & 63;
-                    const double own = (mk == 0) ? r0 : (mk == 1) ? r1 : r2;
-                    const double xk = __shfl(own, lk) / Lm[tri(k, k)];
-                    if (lane < k) r0 -= Lm[tri(k, lane)] * xk;
-                    if (lane + 64 < k) r1 -= Lm[tri(k, lane + 64)] * xk;
-                    if (lane + 128 < k) r2 -= Lm[tri(k, lane + 128)] * xk;
-                    if (lane == lk) {
-                        if (mk == 0) r0 = xk;
-                        else if (mk == 1) r1 = xk;
-                        else r2 = xk;
-                    }
-                }
-                if (lane < n) xv[lane] = r0;
-                if (lane + 64 < n) xv[lane + 64] = r1;
-                if (lane + 128 < n) xv[lane + 128] = r2;
             }
             __syncthreads();
         }
     } else if (!singular) {
         // Jacobi-preconditioned conjugate gradients (the solver the paper names)
-        for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        double* dv = piv;
+        const double* bv = Lm + tri(n, 0);
+        for (int a = tid; a < n; a += blockDim.x) {
             dv[a] = Lm[tri(a, a)];
             xv[a] = 0.0;
             rv[a] = bv[a];
@@ -933,7 +993,7 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
         }
         __syncthreads();
         double rz = 0.0, bb = 0.0;
-        for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        for (int a = tid; a < n; a += blockDim.x) {
             rz += rv[a] * rv[a] / dv[a];
             bb += bv[a] * bv[a];
         }
@@ -942,7 +1002,7 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
         const double tol2 = gd.pcg_rel_tol * gd.pcg_rel_tol * bb;
         for (int iter = 0; iter < gd.pcg_max_iters; ++iter) {
             double pq = 0.0;
-            for (int a = threadIdx.x; a < n; a += blockDim.x) {
+            for (int a = tid; a < n; a += blockDim.x) {
                 double s = 0.0;
                 for (int c = 0; c < n; ++c)
                     s += sym_tri(Lm, a, c) * pv[c];
@@ -956,7 +1016,7 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
             }
             const double alpha = rz / pq;
             double rr = 0.0, rzn = 0.0;
-            for (int a = threadIdx.x; a < n; a += blockDim.x) {
+            for (int a = tid; a < n; a += blockDim.x) {
                 xv[a] += alpha * pv[a];
                 rv[a] -= alpha * qv[a];
                 rr += rv[a] * rv[a];
@@ -968,28 +1028,28 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
                 break;
             const double beta = rzn / rz;
             rz = rzn;
-            for (int a = threadIdx.x; a < n; a += blockDim.x)
+            for (int a = tid; a < n; a += blockDim.x)
                 pv[a] = rv[a] / dv[a] + beta * pv[a];
             __syncthreads();
         }
         __syncthreads();
     }
     if (singular) {
-        if (threadIdx.x == 0)
+        if (tid == 0)
             *gd.status |= kStatusSingular;
         return;
     }
     bool bad = false;
-    for (int a = threadIdx.x; a < n; a += blockDim.x)
+    for (int a = tid; a < n; a += blockDim.x)
         bad |= !isfinite(xv[a]);
     if (__syncthreads_or(bad)) {
-        if (threadIdx.x == 0)
+        if (tid == 0)
             *gd.status |= kStatusNonFinite;
         return;
     }
     // T <- Exp(delta) T for the free nodes
-    for (int a = threadIdx.x; a < gd.n_free; a += blockDim.x) {
-        const int node = gd.free_ids[a];
+    for (int a = tid; a < gd.n_free; a += blockDim.x) {
+        const int node = sfree[a];
         double E[16], Tn[16];
         se3_exp(xv + 6 * a, E);
         mat4_mul(E, Ts + 16 * node, Tn);
@@ -999,7 +1059,179 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0)
+    if (tid == 0)
+        *gd.iters_done = it + 1;
+    compute_transforms(gd, Ts);
+}
+
+// ------------------------------------------------- register Gauss-Jordan
+
+constexpr int kGjThreads = 256;   // a 16 x 16 thread grid
+
+// One Gauss-Newton solve by Gauss-Jordan elimination without pivoting of the
+// augmented system [H_ff | -g_f] (symmetric positive definite: the pivots are
+// the Schur-complement pivots of the Cholesky factorisation, so the same
+// singularity test applies and no back substitution is needed).  The n x (n+1)
+// entries live in registers: thread (tr, tc) owns rows tr + 16a and columns
+// tc + 16b (a, b < T) for the whole elimination, so a step reads T row and
+// T column multipliers from LDS for T x T entries.  Step k updates every entry
+// (i != k, j > k) by v -= v(i,k) v(k,j) / v(k,k); the owners of column and row
+// k+1 publish them to double-buffered LDS vectors: one barrier per column, and
+// no branch inside a step (the pivots are checked once after the elimination;
+// a failed pivot only spoils values that are then discarded).  Then the update
+// T <- Exp(x) T and the transforms of the next iteration.
+template <int T>
+__global__ __launch_bounds__(kGjThreads) void gj_solve_kernel(const GraphDev* __restrict__ gds)
+{
+    const GraphDev& gd = gds[blockIdx.x];
+    const int N = gd.n_frames;
+    const int n = 6 * gd.n_free, n6 = 6 * N;
+    __shared__ double colb[2][kGjMaxN + 2];
+    __shared__ double rowb[2][kGjMaxN + 2];
+    __shared__ double piv[kGjMaxN + 1], xs[kGjMaxN + 1];
+    __shared__ double Ts[16 * kMaxFrames];
+    __shared__ double ns[kMaxFrames * kNodeStats];
+    __shared__ double scratch[kGjThreads / 64];
+    __shared__ int sfree[kMaxFrames];
+    const int tid = threadIdx.x;
+    const int tr = tid >> 4, tc = tid & 15;
+    if (*gd.status)
+        return;
+    const int it = *gd.iters_done;
+    for (int k = tid; k < 16 * N; k += kGjThreads)
+        Ts[k] = gd.poses[k];
+    for (int k = tid; k < kNodeStats * N; k += kGjThreads)
+        ns[k] = gd.node_stats[k];
+    for (int k = tid; k < gd.n_free; k += kGjThreads)
+        sfree[k] = gd.free_ids[k];
+    __syncthreads();
+    if (tid < kNodeStats) {
+        const int src[kNodeStats] = {1, 0, 2, 3, 4};   // E_f, E_g, n_g, n_f, target reads
+        double s = 0.0;
+        for (int k = 0; k < N; ++k)
+            s += ns[kNodeStats * k + src[tid]];
+        gd.iter_stats[kIterRecord * it + tid] = s;
+    }
+    if (n == 0) {
+        if (tid == 0)
+            *gd.iters_done = it + 1;
+        return;
+    }
+    int ri[T], cj[T];   // owned rows / columns, -1 beyond the matrix
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+        ri[a] = (tr + 16 * a < n) ? tr + 16 * a : -1;
+        cj[a] = (tc + 16 * a <= n) ? tc + 16 * a : -1;
+    }
+    double v[T][T];
+    double md = 0.0;
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+        const int i = ri[a];
+        const int r = (i >= 0) ? 6 * sfree[i / 6] + i % 6 : 0;
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            const int j = cj[b];
+            double x = 0.0;
+            if (i >= 0 && j >= 0) {
+                x = (j < n) ? gd.Hm[(size_t)r * n6 + 6 * sfree[j / 6] + j % 6] : -gd.grad[r];
+                if (i == j)
+                    md = fmax(md, x);
+                if (j == 0)
+                    colb[0][i] = x;
+                if (i == 0)
+                    rowb[0][j] = x;
+                if (i == 0 && j == 0)
+                    piv[0] = x;
+            }
+            v[a][b] = x;
+        }
+    }
+    const double maxdiag = block_max(md, scratch);   // includes barriers
+    for (int k = 0; k < n; ++k) {
+        const int bf = k & 1;
+        const double pk = piv[k];
+        double f[T], r[T];
+#pragma unroll
+        for (int a = 0; a < T; ++a) {
+            f[a] = colb[bf][ri[a] < 0 ? 0 : ri[a]];
+            r[a] = rowb[bf][cj[a] < 0 ? 0 : cj[a]];
+        }
+        // reciprocal pivot: hardware estimate refined by one Newton step
+        double ik = __builtin_amdgcn_rcp(pk);
+        ik = ik * (2.0 - pk * ik);
+        // entries that must not change get a zero multiplier: the pivot row,
+        // rows beyond n, and columns j <= k (v - 0 * x == v exactly)
+#pragma unroll
+        for (int a = 0; a < T; ++a) {
+            f[a] = (ri[a] >= 0 && ri[a] != k) ? f[a] * ik : 0.0;
+            r[a] = (cj[a] > k) ? r[a] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            if (16 * b + 15 <= k)   // every column of this slot is finished (wave-uniform)
+                continue;
+#pragma unroll
+            for (int a = 0; a < T; ++a)
+                v[a][b] = fma(-f[a], r[b], v[a][b]);
+        }
+        // column and row k+1 to the other buffer; pivot k+1
+        const int kn = k + 1, sb = kn >> 4, st = kn & 15;
+#pragma unroll
+        for (int b = 0; b < T; ++b)
+            if (b == sb && tc == st)
+#pragma unroll
+                for (int a = 0; a < T; ++a)
+                    if (ri[a] >= 0)
+                        colb[bf ^ 1][ri[a]] = v[a][b];
+#pragma unroll
+        for (int a = 0; a < T; ++a)
+            if (a == sb && tr == st)
+#pragma unroll
+                for (int b = 0; b < T; ++b)
+                    if (cj[b] >= 0) {
+                        rowb[bf ^ 1][cj[b]] = v[a][b];
+                        if (b == sb && tc == st)
+                            piv[kn] = v[a][b];
+                    }
+        __syncthreads();
+    }
+    bool singular = !(maxdiag > 0.0);
+    for (int a = tid; a < n; a += kGjThreads)
+        singular |= !(piv[a] > 1e-12 * maxdiag);
+    if (__syncthreads_or(singular)) {
+        if (tid == 0)
+            *gd.status |= kStatusSingular;
+        return;
+    }
+    // x_a = v(a, n) / pivot_a
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b)
+            if (ri[a] >= 0 && cj[b] == n)
+                xs[ri[a]] = v[a][b] / piv[ri[a]];
+    bool bad = false;
+    __syncthreads();
+    for (int a = tid; a < n; a += kGjThreads)
+        bad |= !isfinite(xs[a]);
+    if (__syncthreads_or(bad)) {
+        if (tid == 0)
+            *gd.status |= kStatusNonFinite;
+        return;
+    }
+    for (int a = tid; a < gd.n_free; a += kGjThreads) {
+        const int node = sfree[a];
+        double E[16], Tn[16];
+        se3_exp(xs + 6 * a, E);
+        mat4_mul(E, Ts + 16 * node, Tn);
+        for (int k = 0; k < 16; ++k) {
+            Ts[16 * node + k] = Tn[k];
+            gd.poses[16 * node + k] = Tn[k];
+        }
+    }
+    __syncthreads();
+    if (tid == 0)
         *gd.iters_done = it + 1;
     compute_transforms(gd, Ts);
 }
@@ -1018,12 +1250,10 @@ void launch_preprocess(const float* depth, const uint8_t* mask, int W, int H, fl
 }
 
 void launch_match_points(const float* di, const uint8_t* mi, const float* dj, const uint8_t* mj, int W, int H,
-                         float cx, float cy, float ifx, float ify, const float* uvi, const float* uvj, int n,
-                         float4* out, hipStream_t st)
+                         const float* uvi, const float* uvj, int n, float4* out, hipStream_t st)
 {
     if (n > 0)
-        match_points_kernel<<<(n + 255) / 256, 256, 0, st>>>(di, mi, dj, mj, W, H, cx, cy, ifx, ify, uvi, uvj, n,
-                                                             out);
+        match_points_kernel<<<(n + 255) / 256, 256, 0, st>>>(di, mi, dj, mj, W, H, uvi, uvj, n, out);
 }
 
 int assoc_ppt_supported(int ppt) { return ppt == 1 || ppt == 2 || ppt == 4 || ppt == 8; }
@@ -1063,7 +1293,24 @@ void launch_assemble(const GraphDev* gds, const int2* nbs, int n, hipStream_t st
 size_t solve_lds_bytes(int n_free, int n_frames)
 {
     const size_t n = 6 * (size_t)n_free;
-    return sizeof(double) * (n * (n + 1) / 2 + 6 * n + 16 * (size_t)n_frames);
+    return sizeof(double) * ((n + 1) * (n + 2) / 2 + 2 * (n + 1) + 4 * n + 16 * (size_t)n_frames);
+}
+
+// tile side T of the Gauss-Jordan solve of n_free free nodes: 16T >= n + 1
+int gj_slots(int n_free)
+{
+    const int need = (6 * n_free + 1 + 15) / 16;
+    return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
+}
+
+void launch_gj_solve(const GraphDev* gds, int n_graphs, int tile, hipStream_t st)
+{
+    switch (tile) {
+    case 1: gj_solve_kernel<1><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
+    case 2: gj_solve_kernel<2><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
+    case 4: gj_solve_kernel<4><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
+    default: gj_solve_kernel<8><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
+    }
 }
 
 hipError_t solve_set_max_lds(size_t bytes)

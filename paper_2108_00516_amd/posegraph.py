@@ -33,7 +33,7 @@ class Config:
     huber_g_m: float = 0.005
     gate_dist_m: float = 0.01
     gate_normal_rad: float = math.radians(30.0)
-    solver: int = L.PG_SOLVER_CHOLESKY
+    solver: int = L.PG_SOLVER_AUTO
     pcg_max_iters: int = 500
     pcg_rel_tol: float = 1e-12
     weighting: int = L.PG_WEIGHT_HUBER
@@ -67,6 +67,7 @@ def stats_to_dict(s: L.pg_stats, iters: int) -> dict:
     k = max(0, min(iters, L.PG_MAX_ITERS))
     return dict(iters_done=s.iters_done, energy_f=np.array(s.energy_f[:k]), energy_g=np.array(s.energy_g[:k]),
                 n_valid_g=np.array(s.n_valid_g[:k]), n_valid_f=np.array(s.n_valid_f[:k]),
+                n_target_reads=np.array(s.n_target_reads[:k]),
                 status_bits=s.status_bits, src_pixels=s.src_pixels, n_assoc_launches=s.n_assoc_launches,
                 ms_assoc=s.ms_assoc, ms_feature=s.ms_feature, ms_reduce=s.ms_reduce, ms_solve=s.ms_solve,
                 ms_total=s.ms_total)
@@ -216,10 +217,14 @@ class PoseGraph:
                                                   uv.ctypes.data_as(C.POINTER(C.c_float))))
         return tgt, r, uv.reshape(hw, 2)
 
-    def frame_info(self, i: int):
+    def frame_info(self, i: int, with_map: bool = True):
+        """(packed map (H, W, 4) or None, number of valid source pixels)."""
+        n = C.c_int()
+        if not with_map:
+            self._check(self.lib.pose_graph_frame_info(self.h, i, None, C.byref(n)))
+            return None, n.value
         hw = self.camera.width * self.camera.height
         m = np.zeros(4 * hw, np.float32)
-        n = C.c_int()
         self._check(self.lib.pose_graph_frame_info(self.h, i, m.ctypes.data_as(C.POINTER(C.c_float)), C.byref(n)))
         return m.reshape(self.camera.height, self.camera.width, 4), n.value
 

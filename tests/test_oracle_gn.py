@@ -193,3 +193,29 @@ def test_threads_do_not_change_results(oracle_lib, graph_t):
     oracle.set_threads(1)
     assert np.array_equal(P1, P4)
     assert np.array_equal(s1["energy_g"], s4["energy_g"])
+
+
+def test_linearize_given_own_decisions_is_identical(oracle_lib, graph_t):
+    # fed the oracle's own association decisions, the given-decision entry
+    # reproduces orc_linearize bit for bit
+    pb = oracle.OracleProblem.from_synth(graph_t)
+    P = graph_t.poses_init
+    tg = np.stack([pb.associate(P, i, j)[0] for (i, j) in pb.ordered_pairs()])
+    a = pb.linearize(P)
+    b = pb.linearize_given(P, tg)
+    for k in ("H", "g", "H_abs", "g_abs"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["energy_g"] == b["energy_g"] and a["n_valid_g"] == b["n_valid_g"]
+    # dropping one decision removes exactly that residual's contribution
+    i, j = pb.ordered_pairs()[0]
+    x = np.flatnonzero(tg[0] >= 0)[0]
+    tg2 = tg.copy()
+    tg2[0, x] = -1
+    c = pb.linearize_given(P, tg2)
+    assert c["n_valid_g"] == a["n_valid_g"] - 1
+    r, J = pb.dense_frozen(P, i, j, [x], [tg[0, x]])
+    w = oracle.huber_weight(abs(r[0]), pb.params.huber_g)
+    idx = np.r_[6 * i:6 * i + 6, 6 * j:6 * j + 6]
+    dH = np.zeros_like(a["H"])
+    dH[np.ix_(idx, idx)] = w * np.outer(J[0], J[0])
+    assert np.allclose(a["H"] - c["H"], dH, atol=1e-9 * np.abs(a["H"]).max())
