@@ -91,6 +91,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-events", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--workload", choices=["paper", "batch"], default="paper",
+                    help="paper: the 10-keyframe 640x480 window (the headline); batch: 64 uneven windows "
+                         "(4-20 keyframes, 320x240 / 480x360 / 640x480) in one batched schedule")
+    ap.add_argument("--graphs", type=int, default=64, help="windows in the batched workload")
+    ap.add_argument("--tile", type=int, default=0, help="association tile (pixels); 0 = library choice")
+    ap.add_argument("--autotune", metavar="JSON", default="",
+                    help="time every association tile for the workload, write the table to JSON and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (to scale HBM counters)")
     args = ap.parse_args()
@@ -118,9 +125,22 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     torch.zeros(1, device="cuda")
+    if args.workload == "batch":
+        return run_batch(args)
     iters = 7
     g = synth.make_graph("P")
-    cfg = Config(max_frames=g.n_frames, gn_iters=iters, use_graph=1, timing=0)
+    if args.autotune:
+        from paper_2108_00516_amd import autotune
+
+        def make(tile):
+            c = Config(max_frames=g.n_frames, gn_iters=iters, tile_pixels=tile)
+            return [from_synth(g, c, device_inputs=True)], [g.poses_init]
+        table = autotune.tune({autotune.bucket_key(g.width, g.height, g.n_frames): make},
+                              log=lambda m: print(m, file=sys.stderr, flush=True))
+        autotune.save(table, args.autotune)
+        print(json.dumps(table), flush=True)
+        return
+    cfg = Config(max_frames=g.n_frames, gn_iters=iters, use_graph=1, timing=0, tile_pixels=args.tile)
     pg = from_synth(g, cfg, device_inputs=True)
 
     def run(steps, timing):
@@ -151,7 +171,7 @@ def main():
     ev = None
     if not args.no_events:
         pg.close()
-        cfg_t = Config(max_frames=g.n_frames, gn_iters=iters, use_graph=0, timing=1)
+        cfg_t = Config(max_frames=g.n_frames, gn_iters=iters, use_graph=0, timing=1, tile_pixels=args.tile)
         pg = from_synth(g, cfg_t, device_inputs=True)
         for _ in range(args.warmup):
             pg.set_poses(g.poses_init)
@@ -203,6 +223,84 @@ def main():
         out["cpu_baseline"] = cb
         out["max_pose_diff_vs_oracle"] = {"rad": dr, "m": dt}
     pg.close()
+    print(json.dumps(out), flush=True)
+
+
+def _make_batch_graph(k):
+    import synth
+    return synth.make_graph(f"B{k}")
+
+
+def run_batch(args):
+    """64 independent windows of uneven node counts (4-20) and resolutions in
+    one batched schedule: one launch per phase for all graphs, the 7
+    iterations replayed as one hipGraph.  value = graph-iterations per second
+    (GN iterations summed over the graphs)."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import torch
+
+    from paper_2108_00516_amd import Config, from_synth, optimize_batch
+    iters = 7
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        graphs = pool.map(_make_batch_graph, range(args.graphs))
+
+    def build(timing):
+        return [from_synth(g, Config(max_frames=g.n_frames, gn_iters=iters, use_graph=0 if timing else 1,
+                                     timing=1 if timing else 0, tile_pixels=args.tile), device_inputs=True)
+                for g in graphs]
+
+    def run(pgs, steps):
+        launches, ms, reads, src = 0, np.zeros(5), 0.0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for pg, g in zip(pgs, graphs):
+                pg.set_poses(g.poses_init)
+            rc, st = optimize_batch(pgs)
+            s0 = st[0]
+            launches += s0["n_assoc_launches"]
+            ms += [s0["ms_assoc"], s0["ms_feature"], s0["ms_reduce"], s0["ms_solve"], s0["ms_total"]]
+            reads = sum(float(np.mean(x["n_target_reads"])) for x in st)
+            src = sum(x["src_pixels"] for x in st)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, launches, ms, reads, src
+
+    pgs = build(False)
+    for _ in range(args.warmup):
+        optimize_batch(pgs)
+    el, _, _, reads, src = run(pgs, args.steps)
+    for pg in pgs:
+        pg.close()
+    out = {
+        "metric": "batched GN graph-iterations/s (64 uneven windows)",
+        "value": round(iters * len(graphs) * args.steps / el, 2),
+        "unit": "graph GN iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * el / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(graphs)} windows, 4-20 keyframes, 320x240/480x360/640x480, 7 GN iterations",
+                   "keyframes": [g.n_frames for g in graphs],
+                   "resolutions": [f"{g.width}x{g.height}" for g in graphs]},
+        "residual_px_per_s": round(src * iters * args.steps / el, 1),
+        "source_pixels_per_iteration": int(src),
+    }
+    if not args.no_events:
+        pgs = build(True)
+        for _ in range(args.warmup):
+            optimize_batch(pgs)
+        _, launches, ms, reads, src = run(pgs, args.steps)
+        for pg in pgs:
+            pg.close()
+        avg_s = ms[0] / launches / 1000.0
+        bytes_alg = SRC_BYTES * src + TGT_BYTES * reads
+        achieved = bytes_alg / avg_s / 1e9
+        out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "assoc_kernel",
+                           "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_bytes_per_launch": int(bytes_alg)}
+        out["events_pass"] = {"gpu_ms_per_step": {k: round(v / args.steps, 4) for k, v in
+                                                  zip(["assoc", "feature", "assemble", "solve", "total"], ms)}}
     print(json.dumps(out), flush=True)
 
 

@@ -46,6 +46,8 @@ class Problem(C.Structure):
         ("lambda_f", C.c_double), ("lambda_g", C.c_double),
         ("huber_f", C.c_double), ("huber_g", C.c_double),
         ("gate_dist", C.c_double), ("gate_angle", C.c_double),
+        ("mlp", C.POINTER(C.c_double)), ("keep", C.POINTER(C.c_ubyte)),
+        ("prune_frac", C.c_double), ("mlp_iters", C.c_int), ("iteration", C.c_int),
     ]
 
 
@@ -86,6 +88,12 @@ def lib():
         L.orc_huber_weight.argtypes = [C.c_double, C.c_double]
         L.orc_huber_weight.restype = C.c_double
         L.orc_cholesky_solve.argtypes = [C.c_int, dp, dp, dp]
+        L.orc_mlp_forward.argtypes = [dp, C.c_int, dp, dp]
+        L.orc_pair_features.argtypes = [P(Problem), dp, C.c_int, C.c_int, C.c_int, P(C.c_int), dp]
+        L.orc_prune_scores.argtypes = [P(Problem), dp, dp]
+        L.orc_prune_select.argtypes = [P(Problem), dp, C.c_double, P(C.c_ubyte)]
+        L.orc_mlp_bce.argtypes = [dp, C.c_int, dp, dp, dp]
+        L.orc_mlp_bce.restype = C.c_double
         _lib = L
     return _lib
 
@@ -106,6 +114,9 @@ class Params:
     huber_g: float = 0.005
     gate_dist: float = 0.01
     gate_angle: float = float(np.deg2rad(30.0))
+    mlp: Optional[np.ndarray] = None      # 1313 network parameters (learned weighting)
+    prune_frac: float = 0.0               # fraction of source pixels pruned by optimize
+    mlp_iters: int = 7                    # iteration-feature normalisation
 
 
 class OracleProblem:
@@ -154,6 +165,45 @@ class OracleProblem:
         c.lambda_f, c.lambda_g = p.lambda_f, p.lambda_g
         c.huber_f, c.huber_g = p.huber_f, p.huber_g
         c.gate_dist, c.gate_angle = p.gate_dist, p.gate_angle
+        self._mlp = None if p.mlp is None else np.ascontiguousarray(p.mlp, np.float64)
+        c.mlp = _ptr(self._mlp, C.c_double) if self._mlp is not None else None
+        c.keep = _ptr(self._keep, C.c_ubyte) if getattr(self, "_keep", None) is not None else None
+        c.prune_frac = p.prune_frac
+        c.mlp_iters = p.mlp_iters
+        c.iteration = getattr(self, "_iteration", 0)
+
+    def set_keep(self, keep):
+        """Kept source pixels (n_frames, H, W) bytes, or None for all."""
+        self._keep = None if keep is None else np.ascontiguousarray(keep, np.uint8).reshape(-1)
+        self._fill()
+
+    def set_iteration(self, it: int):
+        self._iteration = int(it)
+        self._fill()
+
+    def pair_features(self, poses, i, j, iteration=0):
+        poses = np.ascontiguousarray(poses, np.float64)
+        hw = self.width * self.height
+        tgt = np.zeros(hw, np.int32)
+        f = np.zeros((hw, 6))
+        rc = lib().orc_pair_features(C.byref(self.c), _ptr(poses, C.c_double), i, j, iteration,
+                                     _ptr(tgt, C.c_int), _ptr(f, C.c_double))
+        assert rc == OK
+        return tgt, f
+
+    def prune_scores(self, poses):
+        poses = np.ascontiguousarray(poses, np.float64)
+        sc = np.zeros(self.n_frames * self.width * self.height)
+        rc = lib().orc_prune_scores(C.byref(self.c), _ptr(poses, C.c_double), _ptr(sc, C.c_double))
+        assert rc == OK
+        return sc.reshape(self.n_frames, self.height, self.width)
+
+    def prune_select(self, score, frac):
+        sc = np.ascontiguousarray(score, np.float64)
+        keep = np.zeros(sc.size, np.uint8)
+        rc = lib().orc_prune_select(C.byref(self.c), _ptr(sc, C.c_double), float(frac), _ptr(keep, C.c_ubyte))
+        assert rc == OK
+        return keep.reshape(self.n_frames, self.height, self.width)
 
     def set_params(self, **kw):
         for k, v in kw.items():
@@ -278,6 +328,29 @@ def cholesky_solve(A, b):
     x = np.zeros_like(b)
     rc = lib().orc_cholesky_solve(len(b), _ptr(A, C.c_double), _ptr(b, C.c_double), _ptr(x, C.c_double))
     return rc, x
+
+
+MLP_PARAMS = 1313
+
+
+def mlp_forward(params, x):
+    """Outputs (n,) of the 6-32-32-1 weighting network for inputs (n, 6)."""
+    p = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 6)
+    y = np.zeros(len(x))
+    lib().orc_mlp_forward(_ptr(p, C.c_double), len(x), _ptr(x, C.c_double), _ptr(y, C.c_double))
+    return y
+
+
+def mlp_bce(params, x, labels, with_grad=True):
+    """(mean binary cross-entropy, gradient (1313,) or None)."""
+    p = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 6)
+    t = np.ascontiguousarray(labels, np.float64)
+    g = np.zeros(MLP_PARAMS) if with_grad else None
+    loss = lib().orc_mlp_bce(_ptr(p, C.c_double), len(x), _ptr(x, C.c_double), _ptr(t, C.c_double),
+                             _ptr(g, C.c_double) if with_grad else None)
+    return loss, g
 
 
 def set_threads(n: int):

@@ -236,6 +236,10 @@ static void free_frames(const orc_problem *pb, frame_maps *fm)
 
 /* --------------------------------------------- per-pair partial normal eqs */
 
+static double mlp_sigmoid_of(const double *P, const double *f);
+static void mlp_features(const orc_problem *pb, const frame_maps *fm, int i, size_t x, double r,
+                         double dist, double cosang, int iteration, double *f);
+
 typedef struct {
     int i, j;                 /* node ids of the 12 columns: [i (6) | j (6)] */
     double H[144], g[12];
@@ -340,27 +344,32 @@ static void pair_transforms(const double *poses, int i, int j, double *A, double
  * = no residual) the association decisions are taken from outside instead of
  * S2, and the residuals, Jacobians and weights are evaluated for them. */
 static void dense_pair(const orc_problem *pb, const frame_maps *fm, const double *poses,
-                       const int *given, pair_part *pp)
+                       const int *given, const unsigned char *keep, int iteration, pair_part *pp)
 {
     const int i = pp->i, j = pp->j;
     double A[16], B[16];
     pair_transforms(poses, i, j, A, B);
     const size_t hw = (size_t)pb->width * pb->height;
     for (size_t x = 0; x < hw; ++x) {   /* row-major source order */
-        double s[3], r;
+        if (keep && !keep[(size_t)i * hw + x])
+            continue;
+        double s[3], r, gate[2];
         int y;
         if (given) {
             y = given[x];
             if (y < 0)
                 continue;
             const double *p = fm[i].vertex + 3 * x;
-            double d[3];
+            double d[3], Rnq[3];
             apply_T(A, fm[j].vertex + 3 * (size_t)y, s);
             for (int k = 0; k < 3; ++k)
                 d[k] = s[k] - p[k];
             r = dot3(fm[i].normal + 3 * x, d);
+            apply_R(A, fm[j].normal + 3 * (size_t)y, Rnq);
+            gate[0] = sqrt(dot3(d, d));
+            gate[1] = dot3(fm[i].normal + 3 * x, Rnq);
         } else {
-            y = associate_pixel(pb, fm, i, j, A, B, x, s, &r, NULL, NULL);
+            y = associate_pixel(pb, fm, i, j, A, B, x, s, &r, NULL, gate);
             if (y < 0)
                 continue;
         }
@@ -369,9 +378,15 @@ static void dense_pair(const orc_problem *pb, const frame_maps *fm, const double
         double row[12];
         dense_jacobian(A, n, s, q, row);
         double ar = fabs(r);
-        double w = pb->lambda_g * orc_huber_weight(ar, pb->huber_g);
+        double sig = 1.0;   /* learned factor of the IRLS weight */
+        if (pb->mlp) {
+            double f[6];
+            mlp_features(pb, fm, i, x, r, gate[0], gate[1], iteration, f);
+            sig = mlp_sigmoid_of(pb->mlp, f);
+        }
+        double w = pb->lambda_g * sig * orc_huber_weight(ar, pb->huber_g);
         add_row(pp, row, w, r);
-        pp->energy += pb->lambda_g * orc_huber_rho(ar, pb->huber_g);
+        pp->energy += pb->lambda_g * sig * orc_huber_rho(ar, pb->huber_g);
         pp->count += 1;
     }
 }
@@ -456,8 +471,8 @@ static int check_problem(const orc_problem *pb)
 }
 
 static int linearize_with(const orc_problem *pb, const frame_maps *fm, const double *poses,
-                          const int *given, double *H, double *g, double *H_abs, double *g_abs,
-                          orc_lin_stats *st)
+                          const int *given, const unsigned char *keep, int iteration, double *H, double *g,
+                          double *H_abs, double *g_abs, orc_lin_stats *st)
 {
     const int N = pb->n_frames, n6 = 6 * N;
     const int n_dense = (pb->lambda_g != 0.0) ? N * (N - 1) : 0;
@@ -482,8 +497,8 @@ static int linearize_with(const orc_problem *pb, const frame_maps *fm, const dou
 #pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
     for (int t = 0; t < total; ++t) {
         if (t < n_dense)                                   /* S2 + S3 */
-            dense_pair(pb, fm, poses,
-                       given ? given + (size_t)t * pb->width * pb->height : NULL, &parts[t]);
+            dense_pair(pb, fm, poses, given ? given + (size_t)t * pb->width * pb->height : NULL, keep,
+                       iteration, &parts[t]);
         else
             feature_set(pb, fm, poses, t - n_dense, &parts[t]); /* S4 */
     }
@@ -538,7 +553,7 @@ int orc_linearize(const orc_problem *pb, const double *poses, double *H, double 
     frame_maps *fm = build_frames(pb);
     if (!fm)
         return ORC_ERR_ARG;
-    rc = linearize_with(pb, fm, poses, NULL, H, g, H_abs, g_abs, st);
+    rc = linearize_with(pb, fm, poses, NULL, pb->keep, pb->iteration, H, g, H_abs, g_abs, st);
     free_frames(pb, fm);
     return rc;
 }
@@ -552,7 +567,7 @@ int orc_linearize_given(const orc_problem *pb, const double *poses, const int *t
     frame_maps *fm = build_frames(pb);
     if (!fm)
         return ORC_ERR_ARG;
-    rc = linearize_with(pb, fm, poses, targets, H, g, H_abs, g_abs, st);
+    rc = linearize_with(pb, fm, poses, targets, pb->keep, pb->iteration, H, g, H_abs, g_abs, st);
     free_frames(pb, fm);
     return rc;
 }
@@ -635,10 +650,22 @@ int orc_optimize(const orc_problem *pb, double *poses, int iters, orc_opt_stats 
     frame_maps *fm = build_frames(pb);
     if (st)
         memset(st, 0, sizeof(*st));
+    /* learned weighting: prune the source pixels once, at the initial poses */
+    const unsigned char *keep = pb->keep;
+    unsigned char *own_keep = NULL;
+    if (pb->mlp && !keep && pb->prune_frac > 0.0) {
+        const size_t tot = (size_t)N * pb->width * pb->height;
+        double *score = (double *)malloc(sizeof(double) * tot);
+        own_keep = (unsigned char *)malloc(tot);
+        orc_prune_scores(pb, poses, score);
+        orc_prune_select(pb, score, pb->prune_frac, own_keep);
+        free(score);
+        keep = own_keep;
+    }
     rc = ORC_OK;
     for (int it = 0; it < iters; ++it) {
         orc_lin_stats ls;
-        linearize_with(pb, fm, poses, NULL, H, g, NULL, NULL, &ls);
+        linearize_with(pb, fm, poses, NULL, keep, it, H, g, NULL, NULL, &ls);
         if (st) {
             st->energy_f[it] = ls.energy_f;
             st->energy_g[it] = ls.energy_g;
@@ -670,6 +697,7 @@ int orc_optimize(const orc_problem *pb, double *poses, int iters, orc_opt_stats 
             st->iters_done = it + 1;
     }
     free_frames(pb, fm);
+    free(own_keep);
     free(free_ids);
     free(H);
     free(g);
@@ -753,4 +781,210 @@ int orc_feature_eval(const orc_problem *pb, const double *poses, int s, int k, d
     }
     free_frames(pb, fm);
     return ok;
+}
+
+/* ---------------------------------------------- learned weighting network */
+
+/* parameter offsets: W1 (32x6), b1, W2 (32x32), b2, W3 (1x32), b3 */
+#define MLP_W1 0
+#define MLP_B1 (MLP_W1 + ORC_MLP_HID * ORC_MLP_IN)
+#define MLP_W2 (MLP_B1 + ORC_MLP_HID)
+#define MLP_B2 (MLP_W2 + ORC_MLP_HID * ORC_MLP_HID)
+#define MLP_W3 (MLP_B2 + ORC_MLP_HID)
+#define MLP_B3 (MLP_W3 + ORC_MLP_HID)
+
+static double sigmoid(double t) { return 1.0 / (1.0 + exp(-t)); }
+
+/* one input: hidden pre-activations a1, a2, activations h1, h2, logit */
+static double mlp_eval(const double *P, const double *x, double *a1, double *h1, double *a2, double *h2)
+{
+    for (int o = 0; o < ORC_MLP_HID; ++o) {
+        double s = P[MLP_B1 + o];
+        for (int k = 0; k < ORC_MLP_IN; ++k)
+            s += P[MLP_W1 + ORC_MLP_IN * o + k] * x[k];
+        a1[o] = s;
+        h1[o] = s > 0.0 ? s : 0.0;
+    }
+    for (int o = 0; o < ORC_MLP_HID; ++o) {
+        double s = P[MLP_B2 + o];
+        for (int k = 0; k < ORC_MLP_HID; ++k)
+            s += P[MLP_W2 + ORC_MLP_HID * o + k] * h1[k];
+        a2[o] = s;
+        h2[o] = s > 0.0 ? s : 0.0;
+    }
+    double z = P[MLP_B3];
+    for (int k = 0; k < ORC_MLP_HID; ++k)
+        z += P[MLP_W3 + k] * h2[k];
+    return z;
+}
+
+void orc_mlp_forward(const double *params, int n, const double *x, double *y)
+{
+    double a1[ORC_MLP_HID], h1[ORC_MLP_HID], a2[ORC_MLP_HID], h2[ORC_MLP_HID];
+    for (int i = 0; i < n; ++i)
+        y[i] = sigmoid(mlp_eval(params, x + ORC_MLP_IN * (size_t)i, a1, h1, a2, h2));
+}
+
+double orc_mlp_bce(const double *params, int n, const double *x, const double *labels, double *grad)
+{
+    double a1[ORC_MLP_HID], h1[ORC_MLP_HID], a2[ORC_MLP_HID], h2[ORC_MLP_HID];
+    double d1[ORC_MLP_HID], d2[ORC_MLP_HID];
+    if (grad)
+        memset(grad, 0, sizeof(double) * ORC_MLP_PARAMS);
+    double loss = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double *xi = x + ORC_MLP_IN * (size_t)i;
+        const double z = mlp_eval(params, xi, a1, h1, a2, h2);
+        const double t = labels[i];
+        /* -[t log s(z) + (1 - t) log(1 - s(z))] = log(1 + e^z) - t z, evaluated stably */
+        loss += (z > 0.0 ? z + log1p(exp(-z)) : log1p(exp(z))) - t * z;
+        if (!grad)
+            continue;
+        const double dz = (sigmoid(z) - t) / n;   /* d loss / d z (mean over the batch) */
+        grad[MLP_B3] += dz;
+        for (int k = 0; k < ORC_MLP_HID; ++k) {
+            grad[MLP_W3 + k] += dz * h2[k];
+            d2[k] = (a2[k] > 0.0) ? dz * params[MLP_W3 + k] : 0.0;
+        }
+        for (int o = 0; o < ORC_MLP_HID; ++o) {
+            grad[MLP_B2 + o] += d2[o];
+            for (int k = 0; k < ORC_MLP_HID; ++k)
+                grad[MLP_W2 + ORC_MLP_HID * o + k] += d2[o] * h1[k];
+        }
+        for (int k = 0; k < ORC_MLP_HID; ++k) {
+            double s = 0.0;
+            for (int o = 0; o < ORC_MLP_HID; ++o)
+                s += params[MLP_W2 + ORC_MLP_HID * o + k] * d2[o];
+            d1[k] = (a1[k] > 0.0) ? s : 0.0;
+        }
+        for (int o = 0; o < ORC_MLP_HID; ++o) {
+            grad[MLP_B1 + o] += d1[o];
+            for (int k = 0; k < ORC_MLP_IN; ++k)
+                grad[MLP_W1 + ORC_MLP_IN * o + k] += d1[o] * xi[k];
+        }
+    }
+    return loss / n;
+}
+
+static double mlp_sigmoid_of(const double *P, const double *f)
+{
+    double a1[ORC_MLP_HID], h1[ORC_MLP_HID], a2[ORC_MLP_HID], h2[ORC_MLP_HID];
+    return sigmoid(mlp_eval(P, f, a1, h1, a2, h2));
+}
+
+static void mlp_features(const orc_problem *pb, const frame_maps *fm, int i, size_t x, double r,
+                         double dist, double cosang, int iteration, double *f)
+{
+    const int W = pb->width, H = pb->height;
+    const double u = (double)(x % (size_t)W), v = (double)(x / (size_t)W);
+    const double c = cosang > 1.0 ? 1.0 : (cosang < -1.0 ? -1.0 : cosang);
+    const int den = pb->mlp_iters > 1 ? pb->mlp_iters - 1 : 1;
+    f[0] = r / pb->huber_g;
+    f[1] = acos(c) / (3.14159265358979323846 / 6.0);   /* angle in units of 30 degrees */
+    f[2] = fm[i].vertex[3 * x + 2] / 0.8;
+    f[3] = sqrt((u - pb->cx) * (u - pb->cx) + (v - pb->cy) * (v - pb->cy)) /
+           sqrt(0.25 * W * W + 0.25 * H * H);
+    f[4] = dist / pb->gate_dist;
+    f[5] = (double)iteration / den;
+}
+
+int orc_pair_features(const orc_problem *pb, const double *poses, int i, int j, int iteration,
+                      int *target, double *features)
+{
+    if (check_problem(pb) != ORC_OK || !poses || i == j || i < 0 || j < 0 || i >= pb->n_frames ||
+        j >= pb->n_frames)
+        return ORC_ERR_ARG;
+    frame_maps *fm = build_frames(pb);
+    double A[16], B[16];
+    pair_transforms(poses, i, j, A, B);
+    const size_t hw = (size_t)pb->width * pb->height;
+    for (size_t x = 0; x < hw; ++x) {
+        double r = 0.0, gate[2] = {0.0, 0.0};
+        int y = associate_pixel(pb, fm, i, j, A, B, x, NULL, &r, NULL, gate);
+        if (target)
+            target[x] = y;
+        double *f = features + 6 * x;
+        if (y >= 0)
+            mlp_features(pb, fm, i, x, r, gate[0], gate[1], iteration, f);
+        else
+            f[0] = f[1] = f[2] = f[3] = f[4] = f[5] = 0.0;
+    }
+    free_frames(pb, fm);
+    return ORC_OK;
+}
+
+int orc_prune_scores(const orc_problem *pb, const double *poses, double *score)
+{
+    if (check_problem(pb) != ORC_OK || !pb->mlp || !poses || !score)
+        return ORC_ERR_ARG;
+    frame_maps *fm = build_frames(pb);
+    const int N = pb->n_frames;
+    const size_t hw = (size_t)pb->width * pb->height;
+    for (int i = 0; i < N; ++i) {
+        double *sc = score + (size_t)i * hw;
+        for (size_t x = 0; x < hw; ++x)
+            sc[x] = ((fm[i].valid[x] & 3) == 3) ? 0.0 : -1.0;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+        for (long long xx = 0; xx < (long long)hw; ++xx) {
+            const size_t x = (size_t)xx;
+            if (sc[x] < 0.0)
+                continue;
+            for (int j = 0; j < N; ++j) {
+                if (j == i)
+                    continue;
+                double A[16], B[16], r = 0.0, gate[2];
+                pair_transforms(poses, i, j, A, B);
+                if (associate_pixel(pb, fm, i, j, A, B, x, NULL, &r, NULL, gate) < 0)
+                    continue;
+                double f[6];
+                mlp_features(pb, fm, i, x, r, gate[0], gate[1], 0, f);
+                const double s = mlp_sigmoid_of(pb->mlp, f);
+                if (s > sc[x])
+                    sc[x] = s;
+            }
+        }
+    }
+    free_frames(pb, fm);
+    return ORC_OK;
+}
+
+typedef struct {
+    double score;
+    size_t pos;
+} scored_px;
+
+static int cmp_scored(const void *a, const void *b)
+{
+    const scored_px *p = (const scored_px *)a, *q = (const scored_px *)b;
+    if (p->score != q->score)
+        return p->score < q->score ? -1 : 1;
+    return p->pos < q->pos ? -1 : (p->pos > q->pos ? 1 : 0);
+}
+
+int orc_prune_select(const orc_problem *pb, const double *score, double frac, unsigned char *keep)
+{
+    if (!pb || !score || !keep || frac < 0.0 || frac > 1.0)
+        return ORC_ERR_ARG;
+    const size_t hw = (size_t)pb->width * pb->height;
+    scored_px *buf = (scored_px *)malloc(sizeof(scored_px) * hw);
+    for (int f = 0; f < pb->n_frames; ++f) {
+        const double *sc = score + (size_t)f * hw;
+        unsigned char *kp = keep + (size_t)f * hw;
+        size_t V = 0;
+        for (size_t x = 0; x < hw; ++x) {
+            kp[x] = 0;
+            if (sc[x] >= 0.0) {
+                buf[V].score = sc[x];
+                buf[V].pos = x;
+                ++V;
+                kp[x] = 1;
+            }
+        }
+        const size_t drop = (size_t)floor(frac * (double)V);
+        qsort(buf, V, sizeof(scored_px), cmp_scored);
+        for (size_t k = 0; k < drop; ++k)
+            kp[buf[k].pos] = 0;
+    }
+    free(buf);
+    return ORC_OK;
 }

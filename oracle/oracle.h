@@ -39,6 +39,14 @@ typedef struct {
     double huber_f, huber_g;     /* Huber thresholds (metres)                        */
     double gate_dist;            /* dense association distance gate (metres)         */
     double gate_angle;           /* dense association normal-angle gate (radians)    */
+    /* learned weighting (project addition; NULL mlp = Huber weights only):
+     * dense weight = Huber weight * sigmoid(MLP(features)), energy sigma * rho */
+    const double *mlp;           /* ORC_MLP_PARAMS parameters                        */
+    const unsigned char *keep;   /* n_frames*H*W kept source pixels, or NULL          */
+    double prune_frac;           /* optimize: fraction of source pixels pruned at its
+                                    start when keep is NULL (0 = none)                */
+    int mlp_iters;               /* iteration-feature normalisation (GN iterations)  */
+    int iteration;               /* iteration feature of orc_linearize*              */
 } orc_problem;
 
 /* Per-call statistics. */
@@ -116,6 +124,41 @@ double orc_huber_weight(double s, double delta);
 /* Dense Cholesky solve of the SPD system A x = b (n x n row-major).
  * Returns ORC_ERR_SINGULAR when a pivot is <= 1e-12 * max diagonal. */
 int orc_cholesky_solve(int n, const double *A, const double *b, double *x);
+
+/* ---- learned correspondence weighting (a project addition to the IRLS
+ * weights W of Sec. IV-D): a 6-32-32-1 multilayer perceptron,
+ * y = sigmoid(W3 relu(W2 relu(W1 x + b1) + b2) + b3).  Parameters are 1313
+ * doubles in the order W1 (32x6, row-major), b1 (32), W2 (32x32), b2 (32),
+ * W3 (1x32), b3 (1). */
+#define ORC_MLP_PARAMS 1313
+#define ORC_MLP_IN 6
+#define ORC_MLP_HID 32
+
+/* Features of one gated-in pixel-pair: r / huber_g, normal angle / 30 deg,
+ * source depth / 0.8 m, pixel radius / half-diagonal, |s - p| / gate_dist,
+ * iteration / (mlp_iters - 1).  For every pixel x of frame i associated into
+ * frame j at the given poses, features[6x..6x+5] (zeros where rejected) and
+ * the decision code as orc_associate. */
+int orc_pair_features(const orc_problem *pb, const double *poses, int i, int j, int iteration,
+                      int *target, double *features);
+
+/* Pruning scores at the given poses (iteration feature 0): for every source
+ * pixel the largest network output over its gated-in pairs (0 if none), -1
+ * where the pixel is not a valid source; n_frames*H*W doubles. */
+int orc_prune_scores(const orc_problem *pb, const double *poses, double *score);
+
+/* Pruning decision from scores: per frame, the floor(frac * V) valid source
+ * pixels lowest in (score, row-major position) order are dropped; keep gets 1
+ * for the others (n_frames*H*W bytes). */
+int orc_prune_select(const orc_problem *pb, const double *score, double frac, unsigned char *keep);
+
+/* Output of the network for each of n inputs (n x 6, row-major). */
+void orc_mlp_forward(const double *params, int n, const double *x, double *y);
+
+/* Mean binary cross-entropy of the outputs against labels in {0, 1} and its
+ * gradient with respect to the parameters (1313 doubles; grad may be NULL). */
+double orc_mlp_bce(const double *params, int n, const double *x, const double *labels,
+                   double *grad);
 
 #ifdef __cplusplus
 }

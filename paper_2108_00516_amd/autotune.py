@@ -1,0 +1,85 @@
+"""Tile-size autotuner of the association kernel.
+
+The association work item is one ordered keyframe pair times a tile of the
+source frame's valid-pixel list (256 threads x 1, 2, 4 or 8 pixels).  The best
+tile depends on the resolution and the number of keyframes (how many items a
+launch has to fill 256 CUs with).  This module times whole optimisations on
+the GPU for each candidate tile and keeps a JSON table keyed by
+"<width>x<height>/<node bucket>", which Config.tile_pixels can be filled from.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Callable, Dict, Iterable, Optional, Sequence
+
+TILES = (256, 512, 1024, 2048)
+NODE_BUCKETS = ((2, 7), (8, 11), (12, 15), (16, 32))
+
+
+def bucket_key(width: int, height: int, n_frames: int) -> str:
+    for lo, hi in NODE_BUCKETS:
+        if lo <= n_frames <= hi:
+            return f"{width}x{height}/{lo}-{hi}"
+    return f"{width}x{height}/other"
+
+
+def time_optimize(make_graphs: Callable[[int], Sequence], tile: int, steps: int = 10, warmup: int = 3) -> float:
+    """Median wall time (ms) of one optimize (or batched optimize) of the
+    graphs make_graphs(tile) returns, poses reset before every call."""
+    import torch
+
+    from .posegraph import optimize_batch
+    pgs, inits = make_graphs(tile)
+    times = []
+    for k in range(warmup + steps):
+        for pg, P in zip(pgs, inits):
+            pg.set_poses(P)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if len(pgs) == 1:
+            pgs[0].optimize()
+        else:
+            optimize_batch(pgs)
+        torch.cuda.synchronize()
+        if k >= warmup:
+            times.append(1000.0 * (time.perf_counter() - t0))
+    for pg in pgs:
+        pg.close()
+    times.sort()
+    return times[len(times) // 2]
+
+
+def tune(classes: Dict[str, Callable[[int], Sequence]], tiles: Iterable[int] = TILES, steps: int = 10,
+         log: Optional[Callable[[str], None]] = print) -> Dict[str, dict]:
+    """For each class (key -> graph factory taking the tile size), time every
+    tile and keep the fastest.  Returns {key: {"tile": t, "ms": {tile: ms}}}."""
+    table = {}
+    for key, make in classes.items():
+        ms = {}
+        for t in tiles:
+            ms[t] = time_optimize(make, t, steps=steps)
+            if log:
+                log(f"autotune {key}: tile {t} -> {ms[t]:.3f} ms")
+        best = min(ms, key=ms.get)
+        table[key] = {"tile": int(best), "ms": {str(k): round(v, 4) for k, v in ms.items()}}
+    return table
+
+
+def save(table: Dict[str, dict], path: str) -> None:
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+
+
+def load(path: str) -> Dict[str, dict]:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def lookup(table: Dict[str, dict], width: int, height: int, n_frames: int, default: int = 0) -> int:
+    """Tuned tile for a window (0 = the library's own choice)."""
+    e = table.get(bucket_key(width, height, n_frames))
+    return int(e["tile"]) if e else default

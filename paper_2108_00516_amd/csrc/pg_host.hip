@@ -24,7 +24,7 @@ void launch_preprocess(const float* depth, const uint8_t* mask, int W, int H, fl
 void launch_match_points(const float* di, const uint8_t* mi, const float* dj, const uint8_t* mj, int W, int H,
                          const float* uvi, const float* uvj, int n, float4* out, hipStream_t st);
 int assoc_ppt_supported(int ppt);
-void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, hipStream_t st);
+void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision, hipStream_t st);
 void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int* target, float* r, float* uv,
                         hipStream_t st);
 void launch_feature(const GraphDev* gds, const int2* fitems, int n, hipStream_t st);
@@ -83,6 +83,7 @@ struct Schedule {
     int ppt = 4;
     int iters = 0;
     bool gj = false;      // every graph solved by the register Gauss-Jordan kernel
+    int precision = 0;    // PG_PREC_* of every graph of the schedule
     int gj_slots = 1;
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> events;   // timing: start, then 5 per iteration
@@ -413,10 +414,14 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
         s.versions.push_back(g->version);
         int p;
         pick_tile(g, &p);
-        if (k == 0)
+        if (k == 0) {
             ppt = p;
-        else if (p != ppt)
+            s.precision = g->cfg.precision;
+        } else if (p != ppt) {
             return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must use one tile size");
+        } else if (g->cfg.precision != s.precision) {
+            return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must use one precision");
+        }
         devs.push_back(make_dev(g));
         for (const WorkItem& w : g->items) {
             WorkItem v = w;
@@ -497,7 +502,7 @@ hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std
         }
         if (m && (e = hipEventRecord(m[0], st)) != hipSuccess)
             return e;
-        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, st);
+        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, st);
         if (m && (e = hipEventRecord(m[1], st)) != hipSuccess)
             return e;
         if (fork) {
@@ -863,8 +868,8 @@ pg_status pose_graph_optimize(pg_graph* g, pg_stats* stats)
 {
     if (!g)
         return PG_ERR_INVALID_ARG;
-    if (g->cfg.weighting == PG_WEIGHT_LEARNED || g->cfg.precision == PG_PREC_BF16X3)
-        return fail(g, PG_ERR_INVALID_ARG, "learned weighting / BF16x3 precision are not available in this build");
+    if (g->cfg.weighting == PG_WEIGHT_LEARNED)
+        return fail(g, PG_ERR_INVALID_ARG, "learned weighting is not available in this build");
     if (!g->sched)
         g->sched.reset(new (std::nothrow) Schedule());
     if (!g->sched)
@@ -895,8 +900,8 @@ pg_status pose_graph_optimize_batch(pg_graph* const* graphs, int n_graphs, pg_st
             return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must share one device and stream");
         if (g->cfg.gn_iters != g0->cfg.gn_iters)
             return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must share gn_iters");
-        if (g->cfg.weighting == PG_WEIGHT_LEARNED || g->cfg.precision == PG_PREC_BF16X3)
-            return fail(g0, PG_ERR_INVALID_ARG, "learned weighting / BF16x3 precision are not available in this build");
+        if (g->cfg.weighting == PG_WEIGHT_LEARNED)
+            return fail(g0, PG_ERR_INVALID_ARG, "learned weighting is not available in this build");
     }
     std::lock_guard<std::mutex> lk(g_batch_mutex);
     Schedule* s = nullptr;
@@ -946,7 +951,7 @@ pg_status pose_graph_linearize(pg_graph* g, double* H, double* grad, pg_stats* s
     const GraphDev* gds = s.gds.as<GraphDev>();
     hipStream_t st = g->stream;
     launch_solve(gds, 1, s.lds, 1, st);
-    launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, st);
+    launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, st);
     launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
     launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
     HIP_OR_FAIL(g, hipGetLastError());

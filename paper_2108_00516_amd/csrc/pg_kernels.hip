@@ -374,6 +374,146 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     }
 }
 
+// ------------------------------------------- BF16x3 split-precision MFMA form
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Same association, residual and weight as assoc_kernel; the 6x6 sums
+// w J_i^T J_i and w r J_i come from matrix cores instead: each pixel's
+// x = sqrt(w) [J_i, r] (padded to 16) is split into bf16 hi = rn(x) and
+// lo = rn(x - hi), a wave's 64 pixels are transposed through LDS, and
+// v_mfma_f32_16x16x32_bf16 accumulates X_hi^T X_hi + X_hi^T X_lo + X_lo^T X_hi
+// in FP32 (the dropped X_lo^T X_lo term and the two splits bound the relative
+// error of each product by about 3 * 2^-16).  For X^T X the A and B operands
+// of the instruction coincide: lane l holds feature l % 16 of the 8 pixels
+// 8 (l / 16) .. 8 (l / 16) + 7 of a 32-pixel half.  Energy and counts stay on
+// the VALU.  The partial record has the same layout as assoc_kernel's.
+template <int PPT>
+__global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const GraphDev* __restrict__ gds,
+                                                                     const WorkItem* __restrict__ items,
+                                                                     int n_items, int per_xcd)
+{
+    const int b = blockIdx.x;
+    const int L = (b & 7) * per_xcd + (b >> 3);
+    if (L >= n_items)
+        return;
+    const WorkItem it = items[L];
+    const int gid = it.gij >> 16, i = it.gij & 0xff, j = (it.gij >> 8) & 0xff;
+    const GraphDev& gd = gds[gid];
+    if (*gd.status)
+        return;
+    const int p = pair_index(i, j, gd.n_frames);
+    float A[12], B[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        A[k] = gd.xf32[p * 24 + k];
+        B[k] = gd.xf32[p * 24 + 12 + k];
+    }
+    const float4* __restrict__ src_nz = gd.src_nz + (size_t)i * gd.HW;
+    const uint32_t* __restrict__ src_uv = gd.src_uv + (size_t)i * gd.HW;
+    const float4* __restrict__ tmap = gd.maps + (size_t)j * gd.HW;
+    const float huber = gd.huber_g;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // per wave: [hi, lo][16 features][64 pixels]
+    __shared__ __attribute__((aligned(16))) __bf16 stage[kAssocThreads / 64][2][16][64];
+    for (int e = lane; e < 2 * 9 * 64; e += 64)
+        stage[wave][e / (9 * 64)][7 + (e / 64) % 9][e % 64] = (__bf16)0.0f;
+
+    float4 s[PPT];
+    float px[PPT], py[PPT];
+    int y[PPT];
+    const int end = it.start + it.count;
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int k = it.start + threadIdx.x + m * kAssocThreads;
+        y[m] = -1;
+        s[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+        px[m] = py[m] = 0.f;
+        if (k < end) {
+            s[m] = src_nz[k];
+            const uint32_t uv = src_uv[k];
+            const float z = s[m].w;
+            px[m] = z * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
+            py[m] = z * (((float)(uv >> 16) - gd.cy) * gd.ify);
+            float uf, vf;
+            y[m] = project_px(B, px[m], py[m], z, gd, uf, vf);
+        }
+    }
+    float4 t[PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m)
+        t[m] = (y[m] >= 0) ? tmap[y[m]] : make_float4(0.f, 0.f, 0.f, 0.f);
+
+    float energy = 0.f, count = 0.f, reads = 0.f;
+    f32x4 C = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        float x[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (y[m] >= 0) {
+            reads += 1.0f;
+            float r, J[6];
+            if (finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J) >= 0) {
+                const float ar = fabsf(r);
+                const float w = (ar <= huber) ? 1.0f : huber / ar;
+                energy += (ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber);
+                count += 1.0f;
+                const float sw = sqrtf(w);
+#pragma unroll
+                for (int a = 0; a < 6; ++a)
+                    x[a] = sw * J[a];
+                x[6] = sw * r;
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < 7; ++f) {
+            const __bf16 hi = (__bf16)x[f];
+            stage[wave][0][f][lane] = hi;
+            stage[wave][1][f][lane] = (__bf16)(x[f] - (float)hi);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int f = lane & 15, p0 = 32 * c + 8 * (lane >> 4);
+            const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&stage[wave][0][f][p0]);
+            const bf16x8 al = *reinterpret_cast<const bf16x8*>(&stage[wave][1][f][p0]);
+            C = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, ah, C, 0, 0, 0);
+            C = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, al, C, 0, 0, 0);
+            C = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, ah, C, 0, 0, 0);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        energy += __shfl_xor(energy, o);
+        count += __shfl_xor(count, o);
+        reads += __shfl_xor(reads, o);
+    }
+    __shared__ float red[kAssocThreads / 64][32];
+    // lane l holds D[4 (l / 16) + r][l % 16] in C[r]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ii = 4 * (lane >> 4) + r, jj = lane & 15;
+        if (ii <= jj && jj < 6)
+            red[wave][upper_index(ii, jj, 6)] = C[r];
+        else if (jj == 6 && ii < 6)
+            red[wave][21 + ii] = C[r];
+    }
+    if (lane == 0) {
+        red[wave][27] = energy;
+        red[wave][28] = count;
+        red[wave][29] = reads;
+        red[wave][30] = 0.f;
+        red[wave][31] = 0.f;
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float v = red[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < kAssocThreads / 64; ++w)
+            v += red[w][threadIdx.x];
+        gd.partials[(size_t)it.slot * kDenseStride + threadIdx.x] = v;
+    }
+}
+
 // Association decisions of one ordered pair for inspection: the same
 // projection and gating code as the association kernel, one thread per pixel.
 __global__ void assoc_debug_kernel(const GraphDev* __restrict__ gds, int i, int j, int* __restrict__ target,
@@ -1258,12 +1398,21 @@ void launch_match_points(const float* di, const uint8_t* mi, const float* dj, co
 
 int assoc_ppt_supported(int ppt) { return ppt == 1 || ppt == 2 || ppt == 4 || ppt == 8; }
 
-void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, hipStream_t st)
+void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision, hipStream_t st)
 {
     if (n_items <= 0)
         return;
     const int per_xcd = (n_items + 7) / 8;
     const int grid = 8 * per_xcd;
+    if (precision == 1) {
+        switch (ppt) {
+        case 1: assoc_bf16x3_kernel<1><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
+        case 2: assoc_bf16x3_kernel<2><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
+        case 8: assoc_bf16x3_kernel<8><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
+        default: assoc_bf16x3_kernel<4><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
+        }
+        return;
+    }
     switch (ppt) {
     case 1: assoc_kernel<1><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
     case 2: assoc_kernel<2><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
