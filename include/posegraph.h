@@ -172,11 +172,40 @@ pg_status pose_graph_associate(pg_graph *g, int i, int j, int32_t *target, float
  * and the number of valid source pixels.  Either output may be NULL. */
 pg_status pose_graph_frame_info(pg_graph *g, int id, float *map, int *n_valid);
 
-/* Learned correspondence weighting: parameters of the 6-32-32-1 MLP as fp16,
- * layout W1[32x6] b1[32] W2[32x32] b2[32] W3[1x32] b3[1] (row-major, 1313
- * values).  Used when cfg.weighting == PG_WEIGHT_LEARNED.  Errors:
- * PG_ERR_INVALID_ARG when n_bytes != 2626. */
+/* Learned correspondence weighting (an extension of the Huber weighting of
+ * Sec. IV-D; the paper itself weights every residual by the M-estimator
+ * only): parameters of a 6-32-32-1 perceptron (ReLU hidden layers, sigmoid
+ * output) as fp16, layout W1[32x6] b1[32] W2[32x32] b2[32] W3[1x32] b3[1]
+ * (row-major, 1313 values); evaluated in FP32 from these values.  With
+ * cfg.weighting == PG_WEIGHT_LEARNED every gated-in dense residual's IRLS
+ * weight and energy are multiplied by the network output sigma(f) of its
+ * features f (pose_graph_pair_features), and, when cfg.prune_frac > 0, each
+ * optimize first drops per frame the floor(prune_frac * V) of its V source
+ * pixels with the lowest score (pose_graph_prune), ties by position.
+ * Errors: PG_ERR_INVALID_ARG when n_bytes != 2626. */
 pg_status pose_graph_set_mlp(pg_graph *g, const void *fp16_params, size_t n_bytes);
+
+/* Features of the dense association of ordered pair (i, j) at the current
+ * poses, as the learned weighting sees them at Gauss-Newton iteration
+ * 'iteration' (0-based): for each pixel x of frame i with a gated-in target,
+ * features[6x..6x+5] = { r / huber_g_m, normal angle / 30 deg, source depth
+ * / 0.8 m, |(u, v) - (cx, cy)| / half image diagonal, |A q - p| /
+ * gate_dist_m, iteration / max(gn_iters - 1, 1) }, zeros elsewhere;
+ * sigma[x] = network output (0 where rejected; needs pose_graph_set_mlp);
+ * target[x] as in pose_graph_associate.  Outputs are host or device memory
+ * (detected), H*W entries (6*H*W floats for features); any may be NULL.
+ * Errors: PG_ERR_INVALID_ARG. */
+pg_status pose_graph_pair_features(pg_graph *g, int i, int j, int iteration, float *features,
+                                   float *sigma, int32_t *target);
+
+/* Pruning pass of the learned weighting at the current poses (the pass an
+ * optimize runs on its starting poses): score[f*H*W + x] = the largest network
+ * output over the target frames source pixel x of frame f is gated in with
+ * (iteration 0), 0 if none, -1 if x is not a valid source pixel;
+ * keep[f*H*W + x] = 1 for the source pixels kept.  Host memory, N*H*W entries
+ * each; either may be NULL.  Errors: PG_ERR_INVALID_ARG unless
+ * cfg.weighting == PG_WEIGHT_LEARNED and cfg.prune_frac > 0. */
+pg_status pose_graph_prune(pg_graph *g, float *score, uint8_t *keep);
 
 /* Number of nodes. */
 int pose_graph_num_frames(const pg_graph *g);
@@ -187,6 +216,47 @@ const char *pose_graph_last_error(const pg_graph *g);
 
 /* Release the graph and its device memory.  NULL-safe. */
 void pose_graph_destroy(pg_graph *g);
+
+/* ------------------------------------------------------------------------
+ * Trainer of the learned weighting network: FP32 master parameters, Adam
+ * moments and an fp16 copy in device memory.  Loss: mean binary cross-entropy
+ * of sigmoid(network(x)) against labels in {0, 1}; gradients are summed in a
+ * fixed order (FP32 within 64-sample blocks, FP64 across blocks), so results
+ * are reproducible.  Batches are device memory: x is n*6 floats (row-major
+ * feature vectors as pose_graph_pair_features writes them), labels n floats.
+ * All work is ordered on the stream given at creation. */
+typedef struct pg_mlp pg_mlp; /* opaque, library-owned */
+
+/* max_samples: largest batch (1..2^26).  Parameters start at zero.
+ * Errors: PG_ERR_INVALID_ARG, PG_ERR_NO_DEVICE, PG_ERR_OUT_OF_MEMORY. */
+pg_status pg_mlp_create(int max_samples, void *hip_stream, pg_mlp **out);
+void pg_mlp_destroy(pg_mlp *t);
+
+/* Set the 1313 FP32 parameters (host or device memory, layout as in
+ * pose_graph_set_mlp) and reset the Adam state. */
+pg_status pg_mlp_set_params(pg_mlp *t, const float *params);
+
+/* Read the FP32 parameters and/or their fp16 copy (host memory; either may
+ * be NULL). */
+pg_status pg_mlp_get_params(pg_mlp *t, float *params_out, void *fp16_out);
+
+/* Mean loss and its gradient (1313 doubles; may be NULL) at the current
+ * parameters over a batch, in host memory.  Errors: PG_ERR_INVALID_ARG (n out
+ * of range, host batch). */
+pg_status pg_mlp_loss_grad(pg_mlp *t, const float *x, const float *labels, int n, double *loss_out,
+                           double *grad_out);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with
+ * learning rate lr on the batch's mean-loss gradient; loss_out (host, may be
+ * NULL) receives the batch loss before the step. */
+pg_status pg_mlp_adam_step(pg_mlp *t, const float *x, const float *labels, int n, double lr,
+                           double *loss_out);
+
+/* y[s] = sigmoid(network(x[s])) at the FP32 parameters; x and y device memory. */
+pg_status pg_mlp_forward(pg_mlp *t, const float *x, int n, float *y);
+
+/* Message of the last failed call on t (of the last failed create when NULL). */
+const char *pg_mlp_last_error(const pg_mlp *t);
 
 #ifdef __cplusplus
 }

@@ -71,6 +71,16 @@ SIGNATURES = {
                                        C.POINTER(C.c_float)]),
     "pose_graph_frame_info": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_int)]),
     "pose_graph_set_mlp": (C.c_int, [_vp, _vp, C.c_size_t]),
+    "pose_graph_pair_features": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp]),
+    "pose_graph_prune": (C.c_int, [_vp, _vp, _vp]),
+    "pg_mlp_create": (C.c_int, [C.c_int, _vp, C.POINTER(_vp)]),
+    "pg_mlp_destroy": (None, [_vp]),
+    "pg_mlp_set_params": (C.c_int, [_vp, _vp]),
+    "pg_mlp_get_params": (C.c_int, [_vp, _vp, _vp]),
+    "pg_mlp_loss_grad": (C.c_int, [_vp, _vp, _vp, C.c_int, _dp, _dp]),
+    "pg_mlp_adam_step": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, _dp]),
+    "pg_mlp_forward": (C.c_int, [_vp, _vp, C.c_int, _vp]),
+    "pg_mlp_last_error": (C.c_char_p, [_vp]),
     "pose_graph_num_frames": (C.c_int, [_vp]),
     "pose_graph_last_error": (C.c_char_p, [_vp]),
     "pose_graph_destroy": (None, [_vp]),

@@ -74,7 +74,14 @@ struct GraphDev {
     int* status;              // sticky status bits
     int* iters_done;
     double* iter_stats;       // kMaxIters * kIterRecord
-    const __half* mlp;        // learned weighting parameters (fp16)
+    const __half* mlp;        // learned weighting parameters (fp16, as given)
+    // learned weighting
+    const float* mlp32;       // the same parameters as FP32 (read with uniform addresses)
+    float gate_dist, inv_halfdiag, inv_iters;
+    float4* psrc_nz;          // pruned source lists (learned weighting), frame f at f*HW;
+    uint32_t* psrc_uv;        //   the unpruned lists when nothing is pruned
+    unsigned int* score;      // per frame f: score bits of its source list entries at f*HW
+    const int* n_drop;        // per frame: source pixels pruned
 };
 
 __host__ __device__ inline int pair_index(int i, int j, int n) { return i * (n - 1) + (j < i ? j : j - 1); }

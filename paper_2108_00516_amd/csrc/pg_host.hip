@@ -24,9 +24,13 @@ void launch_preprocess(const float* depth, const uint8_t* mask, int W, int H, fl
 void launch_match_points(const float* di, const uint8_t* mi, const float* dj, const uint8_t* mj, int W, int H,
                          const float* uvi, const float* uvj, int n, float4* out, hipStream_t st);
 int assoc_ppt_supported(int ppt);
-void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision, hipStream_t st);
-void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int* target, float* r, float* uv,
-                        hipStream_t st);
+void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision, bool learned,
+                  int iteration, hipStream_t st);
+void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int iteration, int* target, float* r,
+                        float* uv, float* feat, float* sigma, hipStream_t st);
+void launch_prune(const GraphDev* gds, const WorkItem* pitems, int n_pitems, const int2* pframes, int n_pframes,
+                  hipStream_t st);
+void launch_mlp_to_float(const __half* p16, float* p32, hipStream_t st);
 void launch_feature(const GraphDev* gds, const int2* fitems, int n, hipStream_t st);
 void launch_assemble(const GraphDev* gds, const int2* nbs, int n, hipStream_t st);
 size_t solve_lds_bytes(int n_free, int n_frames);
@@ -77,8 +81,9 @@ struct MatchSetHost {
 struct Schedule {
     std::vector<pg_graph*> graphs;
     std::vector<unsigned long long> versions;
-    DevBuf gds, items, fitems, nbs;
-    int n_items = 0, n_fitems = 0, n_nbs = 0;
+    DevBuf gds, items, fitems, nbs, pitems, pframes;
+    int n_items = 0, n_fitems = 0, n_nbs = 0, n_pitems = 0, n_pframes = 0;
+    bool learned = false; // learned weighting in every graph of the schedule
     size_t lds = 0;
     int ppt = 4;
     int iters = 0;
@@ -126,6 +131,8 @@ struct pg_graph {
     // per-optimize device state
     DevBuf d_poses, d_partials, d_fpartials, d_fpts, d_fsets, d_set_of, d_xf32, d_xf64, d_H, d_grad,
         d_node_stats, d_free_ids, d_status, d_iters, d_iter_stats, d_n_src, d_pair_base, d_mlp;
+    // learned weighting: FP32 parameters, pruned source lists, scores, drop counts
+    DevBuf d_mlp32, d_psrc_nz, d_psrc_uv, d_score, d_n_drop;
     bool poses_dirty = true;          // host mirror newer than d_poses
     int n_sets = 0, n_free = 0, n_items = 0, tile = 0;
     int solver = kSolverCholesky;     // resolved solver of the current tables
@@ -135,6 +142,10 @@ struct pg_graph {
     std::vector<WorkItem> items;      // local items (graph field 0)
     std::vector<int4> fsets;
     bool has_mlp = false;
+    bool learned = false, pruned = false;   // of the current tables
+    std::vector<int> n_drop;          // source pixels pruned per frame
+    std::vector<int> n_eff;           // source pixels associated per frame (n_src - n_drop)
+    std::vector<WorkItem> pitems;     // pruning score items (frame, 256-entry tile)
 
     std::unique_ptr<Schedule> sched;  // single-graph schedule cache
     // pinned readback
@@ -255,12 +266,35 @@ pg_status prepare_graph(pg_graph* g)
         default: g->solver = gj_fits ? kSolverGaussJordan : kSolverCholesky; break;
         }
     }
+    // learned weighting: each frame keeps its n_src - floor(frac * n_src)
+    // best-scored source pixels; the counts are known here, the choice is
+    // made on the device at the start of every optimize
+    g->learned = g->cfg.weighting == PG_WEIGHT_LEARNED;
+    if (g->learned && !g->has_mlp)
+        return fail(g, PG_ERR_INVALID_ARG, "learned weighting needs the network parameters (pose_graph_set_mlp)");
+    g->pruned = g->learned && g->cfg.prune_frac > 0.0;
+    g->n_drop.assign(N, 0);
+    g->n_eff = g->n_src;
+    g->pitems.clear();
+    if (g->pruned)
+        for (int i = 0; i < N; ++i) {
+            g->n_drop[i] = (int)floor(g->cfg.prune_frac * (double)g->n_src[i]);
+            g->n_eff[i] = g->n_src[i] - g->n_drop[i];
+            for (int k = 0; k < g->n_src[i]; k += 256) {
+                WorkItem w;
+                w.gij = i;
+                w.start = k;
+                w.count = std::min(256, g->n_src[i] - k);
+                w.slot = 0;
+                g->pitems.push_back(w);
+            }
+        }
     // dense work items, ordered (source frame, tile, target frame); the
     // partial records of each ordered pair are contiguous (pair_base)
     const int P = N * (N - 1);
     std::vector<int> n_tiles(N, 0);
     for (int i = 0; i < N; ++i)
-        n_tiles[i] = (g->n_src[i] + tile - 1) / tile;
+        n_tiles[i] = (g->n_eff[i] + tile - 1) / tile;
     g->pair_base.assign(P + 1, 0);
     for (int p = 0; p < P; ++p)
         g->pair_base[p + 1] = g->pair_base[p] + n_tiles[p / std::max(N - 1, 1)];
@@ -273,7 +307,7 @@ pg_status prepare_graph(pg_graph* g)
                 WorkItem w;
                 w.gij = i | (j << 8);
                 w.start = t * tile;
-                w.count = std::min(tile, g->n_src[i] - t * tile);
+                w.count = std::min(tile, g->n_eff[i] - t * tile);
                 w.slot = g->pair_base[pair_index(i, j, N)] + t;
                 g->items.push_back(w);
             }
@@ -310,6 +344,15 @@ pg_status prepare_graph(pg_graph* g)
     HIP_OR_FAIL(g, g->d_free_ids.ensure(sizeof(int) * std::max(g->n_free, 1)));
     HIP_OR_FAIL(g, g->d_n_src.ensure(sizeof(int) * N));
     HIP_OR_FAIL(g, g->d_pair_base.ensure(sizeof(int) * (P + 1)));
+    if (g->pruned) {
+        const size_t NHW = (size_t)N * g->HW;
+        HIP_OR_FAIL(g, g->d_psrc_nz.ensure(sizeof(float4) * NHW));
+        HIP_OR_FAIL(g, g->d_psrc_uv.ensure(sizeof(uint32_t) * NHW));
+        HIP_OR_FAIL(g, g->d_score.ensure(sizeof(unsigned int) * NHW));
+        HIP_OR_FAIL(g, g->d_n_drop.ensure(sizeof(int) * N));
+        HIP_OR_FAIL(g, hipMemcpyAsync(g->d_n_drop.p, g->n_drop.data(), sizeof(int) * N, hipMemcpyHostToDevice,
+                                      g->stream));
+    }
     if (g->n_sets)
         HIP_OR_FAIL(g, hipMemcpyAsync(g->d_fsets.p, g->fsets.data(), sizeof(int4) * g->n_sets,
                                       hipMemcpyHostToDevice, g->stream));
@@ -381,6 +424,16 @@ GraphDev make_dev(pg_graph* g)
     d.iters_done = g->d_iters.as<int>();
     d.iter_stats = g->d_iter_stats.as<double>();
     d.mlp = g->d_mlp.as<__half>();
+    d.mlp32 = g->has_mlp ? g->d_mlp32.as<float>() : nullptr;
+    d.gate_dist = (float)g->cfg.gate_dist_m;
+    d.inv_halfdiag = (float)(1.0 / sqrt(0.25 * d.W * d.W + 0.25 * d.H * d.H));
+    d.inv_iters = (float)(1.0 / std::max(g->cfg.gn_iters - 1, 1));
+    if (g->learned) {
+        d.psrc_nz = g->pruned ? g->d_psrc_nz.as<float4>() : g->src_nz.as<float4>();
+        d.psrc_uv = g->pruned ? g->d_psrc_uv.as<uint32_t>() : g->src_uv.as<uint32_t>();
+        d.score = g->pruned ? g->d_score.as<unsigned int>() : nullptr;
+        d.n_drop = g->pruned ? g->d_n_drop.as<int>() : nullptr;
+    }
     return d;
 }
 
@@ -403,7 +456,8 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
     s.versions.clear();
     std::vector<GraphDev> devs;
     std::vector<WorkItem> items;
-    std::vector<int2> fitems, nbs;
+    std::vector<int2> fitems, nbs, pframes;
+    std::vector<WorkItem> pitems;
     size_t lds = 0;
     int ppt = 4;
     for (size_t k = 0; k < gs.size(); ++k) {
@@ -417,6 +471,9 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
         if (k == 0) {
             ppt = p;
             s.precision = g->cfg.precision;
+            s.learned = g->learned;
+        } else if (g->learned != s.learned) {
+            return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must use one weighting");
         } else if (p != ppt) {
             return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must use one tile size");
         } else if (g->cfg.precision != s.precision) {
@@ -430,6 +487,14 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
         }
         for (int t = 0; t < g->n_sets; ++t)
             fitems.push_back(make_int2((int)k, t));
+        for (const WorkItem& w : g->pitems) {
+            WorkItem v = w;
+            v.gij |= (int)k << 16;
+            pitems.push_back(v);
+        }
+        if (g->pruned)
+            for (int f = 0; f < g->n_frames; ++f)
+                pframes.push_back(make_int2((int)k, f));
         for (int I = 0; I < g->n_frames; ++I)
             for (int J = 0; J <= I; ++J)
                 nbs.push_back(make_int2((int)k, I | (J << 8)));
@@ -453,12 +518,16 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
     s.n_items = (int)items.size();
     s.n_fitems = (int)fitems.size();
     s.n_nbs = (int)nbs.size();
+    s.n_pitems = (int)pitems.size();
+    s.n_pframes = (int)pframes.size();
     s.lds = lds;
     s.ppt = ppt;
     HIP_OR_FAIL(g0, s.gds.ensure(sizeof(GraphDev) * devs.size()));
     HIP_OR_FAIL(g0, s.items.ensure(sizeof(WorkItem) * std::max<size_t>(items.size(), 1)));
     HIP_OR_FAIL(g0, s.fitems.ensure(sizeof(int2) * std::max<size_t>(fitems.size(), 1)));
     HIP_OR_FAIL(g0, s.nbs.ensure(sizeof(int2) * std::max<size_t>(nbs.size(), 1)));
+    HIP_OR_FAIL(g0, s.pitems.ensure(sizeof(WorkItem) * std::max<size_t>(pitems.size(), 1)));
+    HIP_OR_FAIL(g0, s.pframes.ensure(sizeof(int2) * std::max<size_t>(pframes.size(), 1)));
     hipStream_t st = g0->stream;
     HIP_OR_FAIL(g0, hipMemcpyAsync(s.gds.p, devs.data(), sizeof(GraphDev) * devs.size(), hipMemcpyHostToDevice, st));
     if (!items.empty())
@@ -469,6 +538,12 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
                                        hipMemcpyHostToDevice, st));
     if (!nbs.empty())
         HIP_OR_FAIL(g0, hipMemcpyAsync(s.nbs.p, nbs.data(), sizeof(int2) * nbs.size(), hipMemcpyHostToDevice, st));
+    if (!pitems.empty())
+        HIP_OR_FAIL(g0, hipMemcpyAsync(s.pitems.p, pitems.data(), sizeof(WorkItem) * pitems.size(),
+                                       hipMemcpyHostToDevice, st));
+    if (!pframes.empty())
+        HIP_OR_FAIL(g0, hipMemcpyAsync(s.pframes.p, pframes.data(), sizeof(int2) * pframes.size(),
+                                       hipMemcpyHostToDevice, st));
     HIP_OR_FAIL(g0, hipStreamSynchronize(st));
     if (s.exec) {
         (void)hipGraphExecDestroy(s.exec);
@@ -490,6 +565,8 @@ hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std
     if (ev && (e = hipEventRecord((*ev)[0], st)) != hipSuccess)
         return e;
     launch_solve(gds, ng, s.lds, 1, st);
+    // learned weighting: score and prune the source pixels at the starting poses
+    launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, st);
     const bool fork = side && s.n_fitems > 0;
     for (int it = 0; it < iters; ++it) {
         const hipEvent_t* m = ev ? ev->data() + 1 + 5 * it : nullptr;
@@ -502,7 +579,7 @@ hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std
         }
         if (m && (e = hipEventRecord(m[0], st)) != hipSuccess)
             return e;
-        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, st);
+        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, it, st);
         if (m && (e = hipEventRecord(m[1], st)) != hipSuccess)
             return e;
         if (fork) {
@@ -625,7 +702,7 @@ pg_status run_schedule(Schedule& s, int iters, bool use_graph, bool timing, std:
             out->status_bits = *g->h_status;
             long long sp = 0;
             for (int f = 0; f < g->n_frames; ++f)
-                sp += (long long)g->n_src[f] * (g->n_frames - 1);
+                sp += (long long)g->n_eff[f] * (g->n_frames - 1);
             out->src_pixels = sp;
             out->n_assoc_launches = n_assoc;
             out->ms_assoc = ms[0];
@@ -868,8 +945,6 @@ pg_status pose_graph_optimize(pg_graph* g, pg_stats* stats)
 {
     if (!g)
         return PG_ERR_INVALID_ARG;
-    if (g->cfg.weighting == PG_WEIGHT_LEARNED)
-        return fail(g, PG_ERR_INVALID_ARG, "learned weighting is not available in this build");
     if (!g->sched)
         g->sched.reset(new (std::nothrow) Schedule());
     if (!g->sched)
@@ -900,8 +975,6 @@ pg_status pose_graph_optimize_batch(pg_graph* const* graphs, int n_graphs, pg_st
             return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must share one device and stream");
         if (g->cfg.gn_iters != g0->cfg.gn_iters)
             return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must share gn_iters");
-        if (g->cfg.weighting == PG_WEIGHT_LEARNED)
-            return fail(g0, PG_ERR_INVALID_ARG, "learned weighting is not available in this build");
     }
     std::lock_guard<std::mutex> lk(g_batch_mutex);
     Schedule* s = nullptr;
@@ -951,7 +1024,8 @@ pg_status pose_graph_linearize(pg_graph* g, double* H, double* grad, pg_stats* s
     const GraphDev* gds = s.gds.as<GraphDev>();
     hipStream_t st = g->stream;
     launch_solve(gds, 1, s.lds, 1, st);
-    launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, st);
+    launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, st);
+    launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, st);
     launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
     launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
     HIP_OR_FAIL(g, hipGetLastError());
@@ -981,7 +1055,7 @@ pg_status pose_graph_linearize(pg_graph* g, double* H, double* grad, pg_stats* s
         stats->n_valid_f[0] = (long long)cf;
         long long sp = 0;
         for (int f = 0; f < N; ++f)
-            sp += (long long)g->n_src[f] * (N - 1);
+            sp += (long long)g->n_eff[f] * (N - 1);
         stats->src_pixels = sp;
     }
     return PG_OK;
@@ -1014,7 +1088,7 @@ pg_status pose_graph_associate(pg_graph* g, int i, int j, int32_t* target, float
     float* dr = (float*)(dt + HW);
     float* duv = dr + HW;
     launch_solve(s.gds.as<GraphDev>(), 1, s.lds, 1, g->stream);
-    launch_assoc_debug(s.gds.as<GraphDev>(), (int)HW, i, j, dt, dr, duv, g->stream);
+    launch_assoc_debug(s.gds.as<GraphDev>(), (int)HW, i, j, 0, dt, dr, duv, nullptr, nullptr, g->stream);
     HIP_OR_FAIL(g, hipGetLastError());
     if (target)
         HIP_OR_FAIL(g, hipMemcpyAsync(target, dt, HW * sizeof(int), hipMemcpyDeviceToHost, g->stream));
@@ -1023,6 +1097,113 @@ pg_status pose_graph_associate(pg_graph* g, int i, int j, int32_t* target, float
     if (uv)
         HIP_OR_FAIL(g, hipMemcpyAsync(uv, duv, 2 * HW * sizeof(float), hipMemcpyDeviceToHost, g->stream));
     HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    return PG_OK;
+}
+
+// tables and transforms of a single-graph schedule at the current poses
+static pg_status ready_single(pg_graph* g)
+{
+    if (!g->sched)
+        g->sched.reset(new (std::nothrow) Schedule());
+    if (!g->sched)
+        return fail(g, PG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    pg_status rc = prepare_graph(g);
+    if (rc != PG_OK)
+        return rc;
+    if (g->sched->versions.empty() || g->sched->versions[0] != g->version) {
+        rc = build_schedule({g}, *g->sched);
+        if (rc != PG_OK)
+            return rc;
+    }
+    rc = upload_poses(g);
+    if (rc != PG_OK)
+        return rc;
+    launch_solve(g->sched->gds.as<GraphDev>(), 1, g->sched->lds, 1, g->stream);
+    HIP_OR_FAIL(g, hipGetLastError());
+    return PG_OK;
+}
+
+pg_status pose_graph_pair_features(pg_graph* g, int i, int j, int iteration, float* features, float* sigma,
+                                   int32_t* target)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (i < 0 || j < 0 || i >= g->n_frames || j >= g->n_frames || i == j)
+        return fail(g, PG_ERR_INVALID_ARG, "bad node pair (%d, %d)", i, j);
+    if (iteration < 0 || iteration >= PG_MAX_ITERS)
+        return fail(g, PG_ERR_INVALID_ARG, "iteration %d out of [0, %d)", iteration, PG_MAX_ITERS);
+    if (sigma && !g->has_mlp)
+        return fail(g, PG_ERR_INVALID_ARG, "network weights need the parameters (pose_graph_set_mlp)");
+    pg_status rc = ready_single(g);
+    if (rc != PG_OK)
+        return rc;
+    const size_t HW = g->HW;
+    // device outputs are written in place, host outputs through a staging buffer
+    DevBuf stage;
+    HIP_OR_FAIL(g, stage.ensure(HW * 8 * sizeof(float)));
+    float* sf = stage.as<float>();
+    float* ss = sf + 6 * HW;
+    int* st = (int*)(ss + HW);
+    float* df = features ? (is_device_ptr(features) ? features : sf) : nullptr;
+    float* ds = sigma ? (is_device_ptr(sigma) ? sigma : ss) : nullptr;
+    int* dt = target ? (is_device_ptr(target) ? (int*)target : st) : nullptr;
+    launch_assoc_debug(g->sched->gds.as<GraphDev>(), (int)HW, i, j, iteration, dt, nullptr, nullptr, df, ds,
+                       g->stream);
+    HIP_OR_FAIL(g, hipGetLastError());
+    if (features && df == sf)
+        HIP_OR_FAIL(g, hipMemcpyAsync(features, sf, 6 * HW * sizeof(float), hipMemcpyDeviceToHost, g->stream));
+    if (sigma && ds == ss)
+        HIP_OR_FAIL(g, hipMemcpyAsync(sigma, ss, HW * sizeof(float), hipMemcpyDeviceToHost, g->stream));
+    if (target && dt == st)
+        HIP_OR_FAIL(g, hipMemcpyAsync(target, st, HW * sizeof(int), hipMemcpyDeviceToHost, g->stream));
+    HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    return PG_OK;
+}
+
+pg_status pose_graph_prune(pg_graph* g, float* score, uint8_t* keep)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (g->cfg.weighting != PG_WEIGHT_LEARNED || !(g->cfg.prune_frac > 0.0))
+        return fail(g, PG_ERR_INVALID_ARG, "pruning needs learned weighting and prune_frac > 0");
+    pg_status rc = ready_single(g);
+    if (rc != PG_OK)
+        return rc;
+    Schedule& s = *g->sched;
+    launch_prune(s.gds.as<GraphDev>(), s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes,
+                 g->stream);
+    HIP_OR_FAIL(g, hipGetLastError());
+    const int N = g->n_frames;
+    const size_t HW = g->HW, NHW = (size_t)N * HW;
+    std::vector<uint32_t> uv(NHW), puv(NHW), sc(NHW);
+    HIP_OR_FAIL(g, hipMemcpyAsync(uv.data(), g->src_uv.p, sizeof(uint32_t) * NHW, hipMemcpyDeviceToHost, g->stream));
+    HIP_OR_FAIL(g, hipMemcpyAsync(puv.data(), g->d_psrc_uv.p, sizeof(uint32_t) * NHW, hipMemcpyDeviceToHost,
+                                  g->stream));
+    HIP_OR_FAIL(g, hipMemcpyAsync(sc.data(), g->d_score.p, sizeof(uint32_t) * NHW, hipMemcpyDeviceToHost,
+                                  g->stream));
+    HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    const int W = g->cam.width;
+    for (int f = 0; f < N; ++f) {
+        const size_t b = (size_t)f * HW;
+        if (score)
+            for (size_t x = 0; x < HW; ++x)
+                score[b + x] = -1.0f;
+        if (keep)
+            memset(keep + b, 0, HW);
+        for (int k = 0; k < g->n_src[f]; ++k) {
+            const uint32_t e = uv[b + k];
+            const size_t x = (size_t)(e >> 16) * W + (e & 0xffffu);
+            float v;
+            memcpy(&v, &sc[b + k], sizeof(float));
+            if (score)
+                score[b + x] = v;
+        }
+        if (keep)
+            for (int k = 0; k < g->n_eff[f]; ++k) {
+                const uint32_t e = puv[b + k];
+                keep[b + (size_t)(e >> 16) * W + (e & 0xffffu)] = 1;
+            }
+    }
     return PG_OK;
 }
 
@@ -1049,7 +1230,12 @@ pg_status pose_graph_set_mlp(pg_graph* g, const void* params, size_t n_bytes)
     if (!params || n_bytes != 2626)
         return fail(g, PG_ERR_INVALID_ARG, "expected 1313 fp16 parameters (2626 bytes), got %zu bytes", n_bytes);
     HIP_OR_FAIL(g, copy_in(g->d_mlp.p, params, n_bytes, g->stream));
+    HIP_OR_FAIL(g, g->d_mlp32.ensure(sizeof(float) * 1320));
+    launch_mlp_to_float(g->d_mlp.as<__half>(), g->d_mlp32.as<float>(), g->stream);
+    HIP_OR_FAIL(g, hipGetLastError());
     HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    if (!g->has_mlp)
+        g->version++;   // the parameter pointer enters the schedule's tables
     g->has_mlp = true;
     return PG_OK;
 }

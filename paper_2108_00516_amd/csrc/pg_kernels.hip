@@ -17,6 +17,7 @@
 // 6x6 block w J_i^T J_i (21 unique values), w r J_i, rho and a count; the
 // (i,j), (j,i) and (j,j) blocks follow exactly from Ad_A in FP64.
 #include "pg_device.hpp"
+#include "pg_mlp.hpp"
 
 #include <math.h>
 
@@ -218,7 +219,7 @@ __device__ __forceinline__ int project_px(const float (&B)[12], float px, float 
 // residual r = n . (A q - p) and J_i = [n, s x n] (s = A q).
 __device__ __forceinline__ int finish_px(const float (&A)[12], float px, float py, float pz, float nx, float ny,
                                          float nz, int y, float4 t, const GraphDev& gd, float& r,
-                                         float (&J)[6])
+                                         float (&J)[6], float& d2_out, float& c_out, float& sn_out)
 {
     if (!(t.w > 0.0f))
         return -4;
@@ -231,12 +232,22 @@ __device__ __forceinline__ int finish_px(const float (&A)[12], float px, float p
     const float sz = fmaf(A[8], qx, fmaf(A[9], qy, fmaf(A[10], qz, A[11])));
     const float dx = sx - px, dy = sy - py, dz = sz - pz;
     const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    d2_out = d2;
+    c_out = 0.0f;
+    sn_out = 0.0f;
     if (!(d2 < gd.gate_d2))
         return -5;
     const float rnx = fmaf(A[0], t.x, fmaf(A[1], t.y, A[2] * t.z));
     const float rny = fmaf(A[4], t.x, fmaf(A[5], t.y, A[6] * t.z));
     const float rnz = fmaf(A[8], t.x, fmaf(A[9], t.y, A[10] * t.z));
     const float c = fmaf(nx, rnx, fmaf(ny, rny, nz * rnz));
+    c_out = c;
+    {
+        // |n x R n_q|: with the cosine, the angle between the normals as atan2
+        // (well conditioned near 0, unlike acos of the cosine)
+        const float ex = ny * rnz - nz * rny, ey = nz * rnx - nx * rnz, ez = nx * rny - ny * rnx;
+        sn_out = sqrtf(fmaf(ex, ex, fmaf(ey, ey, ez * ez)));
+    }
     if (!(c > gd.gate_cos))
         return -6;
     r = fmaf(nx, dx, fmaf(ny, dy, nz * dz));
@@ -248,6 +259,24 @@ __device__ __forceinline__ int finish_px(const float (&A)[12], float px, float p
     J[5] = sx * ny - sy * nx;
     return y;
 }
+
+// ------------------------------------------------ learned weighting network
+
+// Features of a gated-in pixel-pair: r / huber_g, normal angle / 30 deg
+// (from its cosine c and sine sn), source depth / 0.8 m, pixel radius /
+// half-diagonal, |s - p| / gate_dist, iteration / (iterations - 1).
+__device__ __forceinline__ void learned_features(const GraphDev& gd, float r, float d2, float c, float sn, float z,
+                                                 uint32_t uv, int iteration, float (&f)[6])
+{
+    const float u = (float)(uv & 0xffffu) - gd.cx, v = (float)(uv >> 16) - gd.cy;
+    f[0] = r / gd.huber_g;
+    f[1] = atan2f(sn, c) * (6.0f / 3.14159265358979f);
+    f[2] = z * (1.0f / 0.8f);
+    f[3] = sqrtf(u * u + v * v) * gd.inv_halfdiag;
+    f[4] = sqrtf(d2) / gd.gate_dist;
+    f[5] = (float)iteration * gd.inv_iters;
+}
+
 
 // recursive-halving step of the wave reduction: lanes differing in bit
 // log2(2*HALF) exchange half of their values, each keeping the half its bit
@@ -268,10 +297,10 @@ __device__ __forceinline__ void halve(float (&acc)[32], int lane)
 // associated into frame j.  Blocks are mapped so that each XCD (blockIdx mod
 // 8) walks a contiguous run of the item list, which is ordered source tile
 // first: the items that re-read one source tile share an L2.
-template <int PPT>
+template <int PPT, bool LEARNED>
 __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __restrict__ gds,
                                                               const WorkItem* __restrict__ items, int n_items,
-                                                              int per_xcd)
+                                                              int per_xcd, int iteration)
 {
     const int b = blockIdx.x;
     const int L = (b & 7) * per_xcd + (b >> 3);
@@ -289,8 +318,8 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
         A[k] = gd.xf32[p * 24 + k];
         B[k] = gd.xf32[p * 24 + 12 + k];
     }
-    const float4* __restrict__ src_nz = gd.src_nz + (size_t)i * gd.HW;
-    const uint32_t* __restrict__ src_uv = gd.src_uv + (size_t)i * gd.HW;
+    const float4* __restrict__ src_nz = (LEARNED ? gd.psrc_nz : gd.src_nz) + (size_t)i * gd.HW;
+    const uint32_t* __restrict__ src_uv = (LEARNED ? gd.psrc_uv : gd.src_uv) + (size_t)i * gd.HW;
     const float4* __restrict__ tmap = gd.maps + (size_t)j * gd.HW;
     const float huber = gd.huber_g;
 
@@ -304,6 +333,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     float4 s[PPT];
     float px[PPT], py[PPT];
     int y[PPT];
+    uint32_t uvs[PPT];
     const int end = it.start + it.count;
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
@@ -311,9 +341,11 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
         y[m] = -1;
         s[m] = make_float4(0.f, 0.f, 0.f, 0.f);
         px[m] = py[m] = 0.f;
+        uvs[m] = 0;
         if (k < end) {
             s[m] = src_nz[k];
             const uint32_t uv = src_uv[k];
+            uvs[m] = uv;
             const float z = s[m].w;
             px[m] = z * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
             py[m] = z * (((float)(uv >> 16) - gd.cy) * gd.ify);
@@ -331,12 +363,19 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     for (int m = 0; m < PPT; ++m) {
         if (y[m] < 0)
             continue;
-        float r, J[6];
-        if (finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J) < 0)
+        float r, J[6], d2, cg, sn;
+        if (finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J, d2, cg, sn) < 0)
             continue;
         const float ar = fabsf(r);
-        const float w = (ar <= huber) ? 1.0f : huber / ar;
-        const float e = (ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber);
+        float w = (ar <= huber) ? 1.0f : huber / ar;
+        float e = (ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber);
+        if (LEARNED) {
+            float f[6];
+            learned_features(gd, r, d2, cg, sn, s[m].w, uvs[m], iteration, f);
+            const float sg = mlp_sigma(gd.mlp32, f);
+            w *= sg;
+            e *= sg;
+        }
         float wJ[6];
 #pragma unroll
         for (int a = 0; a < 6; ++a)
@@ -389,10 +428,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // of the instruction coincide: lane l holds feature l % 16 of the 8 pixels
 // 8 (l / 16) .. 8 (l / 16) + 7 of a 32-pixel half.  Energy and counts stay on
 // the VALU.  The partial record has the same layout as assoc_kernel's.
-template <int PPT>
+template <int PPT, bool LEARNED>
 __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const GraphDev* __restrict__ gds,
                                                                      const WorkItem* __restrict__ items,
-                                                                     int n_items, int per_xcd)
+                                                                     int n_items, int per_xcd, int iteration)
 {
     const int b = blockIdx.x;
     const int L = (b & 7) * per_xcd + (b >> 3);
@@ -410,8 +449,8 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
         A[k] = gd.xf32[p * 24 + k];
         B[k] = gd.xf32[p * 24 + 12 + k];
     }
-    const float4* __restrict__ src_nz = gd.src_nz + (size_t)i * gd.HW;
-    const uint32_t* __restrict__ src_uv = gd.src_uv + (size_t)i * gd.HW;
+    const float4* __restrict__ src_nz = (LEARNED ? gd.psrc_nz : gd.src_nz) + (size_t)i * gd.HW;
+    const uint32_t* __restrict__ src_uv = (LEARNED ? gd.psrc_uv : gd.src_uv) + (size_t)i * gd.HW;
     const float4* __restrict__ tmap = gd.maps + (size_t)j * gd.HW;
     const float huber = gd.huber_g;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -423,6 +462,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
     float4 s[PPT];
     float px[PPT], py[PPT];
     int y[PPT];
+    uint32_t uvs[PPT];
     const int end = it.start + it.count;
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
@@ -430,9 +470,11 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
         y[m] = -1;
         s[m] = make_float4(0.f, 0.f, 0.f, 0.f);
         px[m] = py[m] = 0.f;
+        uvs[m] = 0;
         if (k < end) {
             s[m] = src_nz[k];
             const uint32_t uv = src_uv[k];
+            uvs[m] = uv;
             const float z = s[m].w;
             px[m] = z * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
             py[m] = z * (((float)(uv >> 16) - gd.cy) * gd.ify);
@@ -452,11 +494,19 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
         float x[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (y[m] >= 0) {
             reads += 1.0f;
-            float r, J[6];
-            if (finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J) >= 0) {
+            float r, J[6], d2, cg, sn;
+            if (finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J, d2, cg, sn) >= 0) {
                 const float ar = fabsf(r);
-                const float w = (ar <= huber) ? 1.0f : huber / ar;
-                energy += (ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber);
+                float w = (ar <= huber) ? 1.0f : huber / ar;
+                float e = (ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber);
+                if (LEARNED) {
+                    float f[6];
+                    learned_features(gd, r, d2, cg, sn, s[m].w, uvs[m], iteration, f);
+                    const float sg = mlp_sigma(gd.mlp32, f);
+                    w *= sg;
+                    e *= sg;
+                }
+                energy += e;
                 count += 1.0f;
                 const float sw = sqrtf(w);
 #pragma unroll
@@ -516,8 +566,9 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
 
 // Association decisions of one ordered pair for inspection: the same
 // projection and gating code as the association kernel, one thread per pixel.
-__global__ void assoc_debug_kernel(const GraphDev* __restrict__ gds, int i, int j, int* __restrict__ target,
-                                   float* __restrict__ res, float* __restrict__ uv)
+__global__ void assoc_debug_kernel(const GraphDev* __restrict__ gds, int i, int j, int iteration,
+                                   int* __restrict__ target, float* __restrict__ res, float* __restrict__ uv,
+                                   float* __restrict__ feat, float* __restrict__ sigma)
 {
     const GraphDev& gd = gds[0];
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -532,22 +583,209 @@ __global__ void assoc_debug_kernel(const GraphDev* __restrict__ gds, int i, int 
     const float4 s = gd.maps[(size_t)i * gd.HW + x];
     int code = -1;
     float r = 0.f, uf = __builtin_nanf(""), vf = uf;
+    float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float sg = 0.f;
     if (s.w > 0.f) {
-        const float px = s.w * (((float)(x % gd.W) - gd.cx) * gd.ifx);
-        const float py = s.w * (((float)(x / gd.W) - gd.cy) * gd.ify);
+        const int u = x % gd.W, v = x / gd.W;
+        const float px = s.w * (((float)u - gd.cx) * gd.ifx);
+        const float py = s.w * (((float)v - gd.cy) * gd.ify);
         code = project_px(B, px, py, s.w, gd, uf, vf);
         if (code >= 0) {
-            float J[6], rr;
+            float J[6], rr, d2, c, sn;
             const float4 t = gd.maps[(size_t)j * gd.HW + code];
-            code = finish_px(A, px, py, s.w, s.x, s.y, s.z, code, t, gd, rr, J);
-            if (code >= 0)
+            code = finish_px(A, px, py, s.w, s.x, s.y, s.z, code, t, gd, rr, J, d2, c, sn);
+            if (code >= 0) {
                 r = rr;
+                if (feat || sigma) {
+                    learned_features(gd, rr, d2, c, sn, s.w, (uint32_t)u | ((uint32_t)v << 16), iteration, f);
+                    if (sigma && gd.mlp32)
+                        sg = mlp_sigma(gd.mlp32, f);
+                }
+            }
         }
     }
-    target[x] = code;
-    res[x] = r;
-    uv[2 * x] = uf;
-    uv[2 * x + 1] = vf;
+    if (target)
+        target[x] = code;
+    if (res)
+        res[x] = r;
+    if (uv) {
+        uv[2 * x] = uf;
+        uv[2 * x + 1] = vf;
+    }
+    if (feat)
+        for (int k = 0; k < 6; ++k)
+            feat[6 * (size_t)x + k] = f[k];
+    if (sigma)
+        sigma[x] = sg;
+}
+
+// ------------------------------------------------ pruning of source pixels
+
+// Score of every source pixel at the poses of the start of an optimize: the
+// largest network weight over the target frames it is gated in with
+// (iteration feature 0), 0 when it is gated in nowhere.  One thread per
+// source-list entry, looping over the target frames (no atomics: the score is
+// a per-thread maximum).  Items: gij = frame | graph << 16, start, count <= 256.
+constexpr int kPruneThreads = 256;
+
+__global__ __launch_bounds__(kPruneThreads) void prune_score_kernel(const GraphDev* __restrict__ gds,
+                                                                    const WorkItem* __restrict__ items)
+{
+    const WorkItem it = items[blockIdx.x];
+    const GraphDev& gd = gds[it.gij >> 16];
+    const int i = it.gij & 0xff;
+    if ((int)threadIdx.x >= it.count)
+        return;
+    const size_t e = (size_t)i * gd.HW + it.start + threadIdx.x;
+    const float4 s = gd.src_nz[e];
+    const uint32_t uv = gd.src_uv[e];
+    const float px = s.w * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
+    const float py = s.w * (((float)(uv >> 16) - gd.cy) * gd.ify);
+    float best = 0.0f;
+    for (int j = 0; j < gd.n_frames; ++j) {
+        if (j == i)
+            continue;
+        const int p = pair_index(i, j, gd.n_frames);
+        float A[12], B[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            A[k] = gd.xf32[p * 24 + k];
+            B[k] = gd.xf32[p * 24 + 12 + k];
+        }
+        float uf, vf;
+        const int y = project_px(B, px, py, s.w, gd, uf, vf);
+        if (y < 0)
+            continue;
+        const float4 t = gd.maps[(size_t)j * gd.HW + y];
+        float r, J[6], d2, c, sn;
+        if (finish_px(A, px, py, s.w, s.x, s.y, s.z, y, t, gd, r, J, d2, c, sn) < 0)
+            continue;
+        float f[6];
+        learned_features(gd, r, d2, c, sn, s.w, uv, 0, f);
+        best = fmaxf(best, mlp_sigma(gd.mlp32, f));
+    }
+    gd.score[e] = __float_as_uint(best);
+}
+
+// Exclusive prefix of flag over the block (1024 threads = 16 waves) and the
+// block total; wave counts go through LDS.
+__device__ __forceinline__ int block_excl_scan(bool flag, int* wave_cnt, int& total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long bal = __ballot(flag);
+    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0)
+        wave_cnt[wv] = __popcll(bal);
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        const int c = wave_cnt[w];
+        off += (w < wv) ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return off + pre;
+}
+
+// Per frame (one block of 1024 threads): drop the n_drop source pixels of
+// lowest score, ties by position in the row-major source list, and compact the
+// kept ones in order into the pruned lists.  The n_drop-th smallest key is
+// found by an MSB-first radix select (four 8-bit passes, LDS histograms with
+// integer atomics: the result does not depend on their order).
+constexpr int kSelectThreads = 1024;
+
+__global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const GraphDev* __restrict__ gds,
+                                                                      const int2* __restrict__ frames)
+{
+    __shared__ int hist[256];
+    __shared__ int wave_cnt[16];
+    __shared__ unsigned int s_prefix;
+    __shared__ int s_rank;
+    const int2 fr = frames[blockIdx.x];
+    const GraphDev& gd = gds[fr.x];
+    const int i = fr.y;
+    const int V = gd.n_src[i];
+    const int drop = gd.n_drop[i];
+    const size_t base = (size_t)i * gd.HW;
+    const unsigned int* __restrict__ key = gd.score + base;
+    const int tid = threadIdx.x;
+
+    unsigned int tau = 0;   // key of the last dropped entry in (key, position) order
+    int need = 0;           // entries equal to tau that are dropped (lowest positions first)
+    if (drop > 0) {
+        unsigned int prefix = 0, mask = 0;
+        int rank = drop - 1;    // 0-based rank of the entry sought
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            for (int b = tid; b < 256; b += kSelectThreads)
+                hist[b] = 0;
+            __syncthreads();
+            for (int k = tid; k < V; k += kSelectThreads) {
+                const unsigned int kk = key[k];
+                if ((kk & mask) == prefix)
+                    atomicAdd(&hist[(kk >> shift) & 255u], 1);
+            }
+            __syncthreads();
+            if (tid < 64) {
+                // lane l holds bins 4l..4l+3; inclusive scan of the lane sums
+                const int h0 = hist[4 * tid], h1 = hist[4 * tid + 1], h2 = hist[4 * tid + 2], h3 = hist[4 * tid + 3];
+                const int sum = h0 + h1 + h2 + h3;
+                int incl = sum;
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int o = __shfl_up(incl, d, 64);
+                    if (tid >= d)
+                        incl += o;
+                }
+                const int excl = incl - sum;
+                const unsigned long long hit = __ballot(incl > rank);
+                const int first = __ffsll((long long)hit) - 1;
+                if (tid == first) {
+                    int r = rank - excl, b = 4 * tid;
+                    if (r >= h0) {
+                        r -= h0;
+                        ++b;
+                        if (r >= h1) {
+                            r -= h1;
+                            ++b;
+                            if (r >= h2) {
+                                r -= h2;
+                                ++b;
+                            }
+                        }
+                    }
+                    s_prefix = prefix | ((unsigned int)b << shift);
+                    s_rank = r;
+                }
+            }
+            __syncthreads();
+            prefix = s_prefix;
+            rank = s_rank;
+            mask |= 255u << shift;
+            __syncthreads();
+        }
+        tau = prefix;
+        need = rank + 1;
+    }
+    // ordered compaction: entry k is kept unless key < tau, or key == tau and
+    // it is among the first 'need' entries equal to tau
+    int out = 0, eq_seen = 0;
+    for (int k0 = 0; k0 < V; k0 += kSelectThreads) {
+        const int k = k0 + tid;
+        const bool live = k < V;
+        const unsigned int kk = live ? key[k] : 0u;
+        const bool eq = live && drop > 0 && kk == tau;
+        int eq_tot;
+        const int eq_rank = eq_seen + block_excl_scan(eq, wave_cnt, eq_tot);
+        const bool keep = live && (drop == 0 || kk > tau || (eq && eq_rank >= need));
+        int keep_tot;
+        const int pos = out + block_excl_scan(keep, wave_cnt, keep_tot);
+        if (keep) {
+            gd.psrc_nz[base + pos] = gd.src_nz[base + k];
+            gd.psrc_uv[base + pos] = gd.src_uv[base + k];
+        }
+        out += keep_tot;
+        eq_seen += eq_tot;
+    }
 }
 
 // -------------------------------------------------------- feature residuals
@@ -1398,33 +1636,63 @@ void launch_match_points(const float* di, const uint8_t* mi, const float* dj, co
 
 int assoc_ppt_supported(int ppt) { return ppt == 1 || ppt == 2 || ppt == 4 || ppt == 8; }
 
-void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision, hipStream_t st)
+template <bool LEARNED>
+static void launch_assoc_t(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision,
+                           int iteration, hipStream_t st)
+{
+    const int per_xcd = (n_items + 7) / 8;
+    const int grid = 8 * per_xcd;
+#define PG_ASSOC_LAUNCH(K)                                                                                  \
+    switch (ppt) {                                                                                          \
+    case 1: K<1, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration); break;  \
+    case 2: K<2, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration); break;  \
+    case 8: K<8, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration); break;  \
+    default: K<4, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration); break; \
+    }
+    if (precision == 1) {
+        PG_ASSOC_LAUNCH(assoc_bf16x3_kernel)
+    } else {
+        PG_ASSOC_LAUNCH(assoc_kernel)
+    }
+#undef PG_ASSOC_LAUNCH
+}
+
+void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision, bool learned,
+                  int iteration, hipStream_t st)
 {
     if (n_items <= 0)
         return;
-    const int per_xcd = (n_items + 7) / 8;
-    const int grid = 8 * per_xcd;
-    if (precision == 1) {
-        switch (ppt) {
-        case 1: assoc_bf16x3_kernel<1><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
-        case 2: assoc_bf16x3_kernel<2><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
-        case 8: assoc_bf16x3_kernel<8><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
-        default: assoc_bf16x3_kernel<4><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
-        }
-        return;
-    }
-    switch (ppt) {
-    case 1: assoc_kernel<1><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
-    case 2: assoc_kernel<2><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
-    case 8: assoc_kernel<8><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
-    default: assoc_kernel<4><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd); break;
-    }
+    if (learned)
+        launch_assoc_t<true>(gds, items, n_items, ppt, precision, iteration, st);
+    else
+        launch_assoc_t<false>(gds, items, n_items, ppt, precision, iteration, st);
 }
 
-void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int* target, float* r, float* uv,
-                        hipStream_t st)
+void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int iteration, int* target, float* r,
+                        float* uv, float* feat, float* sigma, hipStream_t st)
 {
-    assoc_debug_kernel<<<(HW + 255) / 256, 256, 0, st>>>(gds, i, j, target, r, uv);
+    assoc_debug_kernel<<<(HW + 255) / 256, 256, 0, st>>>(gds, i, j, iteration, target, r, uv, feat, sigma);
+}
+
+__global__ void mlp_to_float_kernel(const __half* __restrict__ p16, float* __restrict__ p32)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < kMlpParams)
+        p32[q] = __half2float(p16[q]);
+}
+
+void launch_mlp_to_float(const __half* p16, float* p32, hipStream_t st)
+{
+    mlp_to_float_kernel<<<(kMlpParams + 255) / 256, 256, 0, st>>>(p16, p32);
+}
+
+void launch_prune(const GraphDev* gds, const WorkItem* pitems, int n_pitems, const int2* pframes, int n_pframes,
+                  hipStream_t st)
+{
+    if (n_pitems > 0)
+        prune_score_kernel<<<n_pitems, kPruneThreads, 0, st>>>(gds, pitems);
+    if (n_pframes > 0)
+        prune_select_kernel<<<n_pframes, kSelectThreads, 0, st>>>(gds, pframes);
 }
 
 void launch_feature(const GraphDev* gds, const int2* fitems, int n, hipStream_t st)

@@ -229,8 +229,111 @@ class PoseGraph:
         return m.reshape(self.camera.height, self.camera.width, 4), n.value
 
     def set_mlp(self, params_fp16):
+        """Network parameters of the learned weighting (1313 values, fp16)."""
         p = np.ascontiguousarray(params_fp16, dtype=np.float16)
         self._check(self.lib.pose_graph_set_mlp(self.h, C.c_void_p(p.ctypes.data), p.nbytes))
+
+    def pair_features(self, i: int, j: int, iteration: int = 0, sigma: bool = False, out=None):
+        """Learned-weighting features of ordered pair (i, j) at the current
+        poses: (features (H*W, 6), sigma (H*W) or None, target (H*W)).  With
+        out = (features, sigma, target) torch tensors on the device they are
+        filled in place (sigma may be None) and returned."""
+        hw = self.camera.width * self.camera.height
+        if out is not None:
+            f, sg, t = out
+            self._check(self.lib.pose_graph_pair_features(
+                self.h, i, j, iteration, C.c_void_p(f.data_ptr()),
+                C.c_void_p(sg.data_ptr()) if sg is not None else None, C.c_void_p(t.data_ptr())))
+            return f, sg, t
+        f = np.zeros((hw, 6), np.float32)
+        t = np.zeros(hw, np.int32)
+        sg = np.zeros(hw, np.float32) if sigma else None
+        self._check(self.lib.pose_graph_pair_features(self.h, i, j, iteration, C.c_void_p(f.ctypes.data),
+                                                      C.c_void_p(sg.ctypes.data) if sigma else None,
+                                                      C.c_void_p(t.ctypes.data)))
+        return f, sg, t
+
+    def prune(self):
+        """Pruning pass at the current poses: (score (N, H*W), keep (N, H*W))."""
+        n = self.n_frames * self.camera.width * self.camera.height
+        sc = np.zeros(n, np.float32)
+        kp = np.zeros(n, np.uint8)
+        self._check(self.lib.pose_graph_prune(self.h, C.c_void_p(sc.ctypes.data), C.c_void_p(kp.ctypes.data)))
+        return sc.reshape(self.n_frames, -1), kp.reshape(self.n_frames, -1).astype(bool)
+
+
+class MlpTrainer:
+    """Trainer of the learned weighting network (pg_mlp_* handle).  Batches
+    are device tensors: x (n, 6) float32, labels (n,) float32."""
+
+    N_PARAMS = 1313
+
+    def __init__(self, max_samples: int, stream=None):
+        self.lib = L.load()
+        st = _current_stream() if stream is None else C.c_void_p(stream if isinstance(stream, int)
+                                                                else stream.cuda_stream)
+        h = C.c_void_p()
+        rc = self.lib.pg_mlp_create(int(max_samples), st, C.byref(h))
+        if rc != L.PG_OK:
+            raise PoseGraphError(rc, self.lib.pg_mlp_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != L.PG_OK:
+            raise PoseGraphError(rc, self.lib.pg_mlp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pg_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _dev(t, cols=None):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError("expected a contiguous float32 device tensor")
+        if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+            raise ValueError(f"expected shape (n, {cols})")
+        return C.c_void_p(t.data_ptr())
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (self.N_PARAMS,):
+            raise ValueError("expected 1313 parameters")
+        self._check(self.lib.pg_mlp_set_params(self.h, C.c_void_p(p.ctypes.data)))
+
+    def params(self):
+        p = np.zeros(self.N_PARAMS, np.float32)
+        self._check(self.lib.pg_mlp_get_params(self.h, C.c_void_p(p.ctypes.data), None))
+        return p
+
+    def params_fp16(self):
+        p = np.zeros(self.N_PARAMS, np.float16)
+        self._check(self.lib.pg_mlp_get_params(self.h, None, C.c_void_p(p.ctypes.data)))
+        return p
+
+    def loss_grad(self, x, labels):
+        loss = C.c_double()
+        g = np.zeros(self.N_PARAMS)
+        self._check(self.lib.pg_mlp_loss_grad(self.h, self._dev(x, 6), self._dev(labels), x.shape[0],
+                                              C.byref(loss), g.ctypes.data_as(C.POINTER(C.c_double))))
+        return loss.value, g
+
+    def adam_step(self, x, labels, lr: float, want_loss: bool = False):
+        loss = C.c_double()
+        self._check(self.lib.pg_mlp_adam_step(self.h, self._dev(x, 6), self._dev(labels), x.shape[0], float(lr),
+                                              C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def forward(self, x, y):
+        self._check(self.lib.pg_mlp_forward(self.h, self._dev(x, 6), x.shape[0], self._dev(y)))
+        return y
 
 
 def optimize_batch(graphs: Sequence[PoseGraph], check: bool = True):

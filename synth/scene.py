@@ -265,12 +265,16 @@ def perturb_pose(rng, T, max_rot_rad, max_trans_m):
 
 def make_graph(preset: str = "T", seed: Optional[int] = None, *, n_frames=None, width=None, height=None,
                noise_sigma: float = DEPTH_NOISE_SIGMA, init_rot_deg: float = 1.0, init_trans_m: float = 0.005,
-               n_matches=None, outlier_frac=None, background: bool = True) -> SynthGraph:
+               n_matches=None, outlier_frac=None, background: bool = True, mask_dilate: int = 0) -> SynthGraph:
     """Build one seeded keyframe window.
 
     preset: 'T', 'P', 'X', 'L' (see PRESETS) or 'B<k>' for the k-th graph of the
     batched workload (node count in 4..20, resolution from BATCH_RESOLUTIONS).
     Keyword overrides change sizes without changing the recipe.
+    mask_dilate > 0 grows each mask by that many pixels (a square structuring
+    element): the grown band covers back-wall pixels, the segmentation leaks a
+    real pipeline's masks have at object boundaries.  Matches are drawn from
+    the true object masks either way.
     """
     if preset.startswith("B"):
         k = int(preset[1:]) if len(preset) > 1 else 0
@@ -318,6 +322,10 @@ def make_graph(preset: str = "T", seed: Optional[int] = None, *, n_frames=None, 
             mrng = np.random.default_rng([seed, i, j])
             matches.append(_make_matches(mrng, depth_clean, mask, poses, i, j, p["n_matches"],
                                          p["outlier_frac"], K))
+    if mask_dilate > 0:
+        from scipy.ndimage import binary_dilation
+        st = np.ones((2 * mask_dilate + 1, 2 * mask_dilate + 1), bool)
+        mask = np.stack([binary_dilation(m > 0, structure=st) for m in mask]).astype(np.uint8)
     prng = np.random.default_rng([seed, 7777])
     init = poses.copy()
     for k in range(1, N):
