@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-events", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--no-forms", action="store_true", help="skip the learned / BF16x3 forms")
     ap.add_argument("--workload", choices=["paper", "batch"], default="paper",
                     help="paper: the 10-keyframe 640x480 window (the headline); batch: 64 uneven windows "
                          "(4-20 keyframes, 320x240 / 480x360 / 640x480) in one batched schedule")
@@ -122,11 +123,17 @@ def main():
     import synth
     from paper_2108_00516_amd import Config, from_synth
 
+    graphs = None
+    if args.workload == "batch":
+        # scene generation in forked CPU workers, before this process touches the GPU
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+            graphs = pool.map(_make_batch_graph, range(args.graphs))
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     torch.zeros(1, device="cuda")
     if args.workload == "batch":
-        return run_batch(args)
+        return run_batch(args, graphs)
     iters = 7
     g = synth.make_graph("P")
     if args.autotune:
@@ -223,7 +230,63 @@ def main():
         out["cpu_baseline"] = cb
         out["max_pose_diff_vs_oracle"] = {"rad": dr, "m": dt}
     pg.close()
+    if not args.no_forms:
+        out["forms"] = other_forms(g, iters, P_gpu, min(args.steps, 50), args.tile)
     print(json.dumps(out), flush=True)
+
+
+WEIGHTS = os.path.join(ROOT, "paper_2108_00516_amd", "weights", "weightnet.npy")
+
+
+def other_forms(g, iters, P_plain, steps, tile):
+    """The learned (25% of source pixels pruned), BF16x3 and combined forms on
+    the same window: GN iterations/s over graph-replayed steps and the largest
+    pose difference to the plain FP32 result; pose error of each against the
+    generator's ground truth."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2108_00516_amd import Config, _lib, from_synth
+    trained = os.path.exists(WEIGHTS)
+    if trained:
+        p16 = np.load(WEIGHTS, allow_pickle=False).astype(np.float16)
+    else:
+        from paper_2108_00516_amd.learn import init_params
+        p16 = init_params(0).astype(np.float16)
+
+    def gt_err(P):
+        e = [oracle.pose_error(P[k], g.poses_gt[k]) for k in range(g.n_frames)]
+        return {"rad": max(x[0] for x in e), "m": max(x[1] for x in e)}
+
+    res = {"weights": "trained (learn.py)" if trained else "untrained initialisation",
+           "plain_fp32": {"error_vs_ground_truth": gt_err(P_plain)}}
+    for name, kw in [("learned", dict(weighting=_lib.PG_WEIGHT_LEARNED, prune_frac=0.25)),
+                     ("bf16x3", dict(precision=_lib.PG_PREC_BF16X3)),
+                     ("learned_bf16x3", dict(weighting=_lib.PG_WEIGHT_LEARNED, prune_frac=0.25,
+                                             precision=_lib.PG_PREC_BF16X3))]:
+        pg = from_synth(g, Config(max_frames=g.n_frames, gn_iters=iters, tile_pixels=tile, **kw),
+                        device_inputs=True)
+        if kw.get("weighting") == _lib.PG_WEIGHT_LEARNED:
+            pg.set_mlp(p16)
+        for _ in range(3):
+            pg.set_poses(g.poses_init)
+            pg.optimize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pg.set_poses(g.poses_init)
+            st = pg.optimize()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        P = pg.poses
+        dr = max(oracle.pose_error(P[k], P_plain[k])[0] for k in range(g.n_frames))
+        dt = max(oracle.pose_error(P[k], P_plain[k])[1] for k in range(g.n_frames))
+        res[name] = {"gn_iters_per_s": round(iters * steps / el, 2), "ms_per_step": round(1000 * el / steps, 4),
+                     "source_pixels_per_iteration": int(st["src_pixels"]),
+                     "max_pose_diff_vs_plain": {"rad": dr, "m": dt}, "error_vs_ground_truth": gt_err(P)}
+        pg.close()
+    return res
 
 
 def _make_batch_graph(k):
@@ -231,20 +294,16 @@ def _make_batch_graph(k):
     return synth.make_graph(f"B{k}")
 
 
-def run_batch(args):
+def run_batch(args, graphs):
     """64 independent windows of uneven node counts (4-20) and resolutions in
     one batched schedule: one launch per phase for all graphs, the 7
     iterations replayed as one hipGraph.  value = graph-iterations per second
     (GN iterations summed over the graphs)."""
-    import multiprocessing as mp
-
     import numpy as np
     import torch
 
     from paper_2108_00516_amd import Config, from_synth, optimize_batch
     iters = 7
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        graphs = pool.map(_make_batch_graph, range(args.graphs))
 
     def build(timing):
         return [from_synth(g, Config(max_frames=g.n_frames, gn_iters=iters, use_graph=0 if timing else 1,

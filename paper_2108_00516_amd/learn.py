@@ -43,12 +43,15 @@ def _pairs(n: int) -> List[Tuple[int, int]]:
 
 
 def collect(windows: Iterable[Tuple[object, np.ndarray]], iters: int = 7, inlier_m: float = 0.003,
-            config: Optional[Config] = None):
+            config: Optional[Config] = None, sample_frac: float = 1.0, seed: int = 0):
     """Samples of (features (n, 6), labels (n,)) as float32 device tensors.
 
     windows: (SynthGraph with leaky masks, reference poses (N, 4, 4)).
-    Features are taken at the first `iters` iterates of the plain optimiser."""
+    Features are taken at the first `iters` iterates of the plain optimiser;
+    sample_frac < 1 keeps a seeded random subset of each pair's samples."""
     import torch
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
     feats, labels = [], []
     base = config or Config()
     for g, ref in windows:
@@ -72,6 +75,8 @@ def collect(windows: Iterable[Tuple[object, np.ndarray]], iters: int = 7, inlier
             for (i, j) in _pairs(g.n_frames):
                 fg.pair_features(i, j, k, out=(f, None, t))
                 sel = t >= 0
+                if sample_frac < 1.0:
+                    sel &= torch.rand(hw, device="cuda", generator=gen) < sample_frac
                 feats.append(f[sel].clone())
                 labels.append(good[(i, j)][sel].float())
             sg.set_poses(P)
@@ -118,3 +123,68 @@ def reference_poses(g_clean, config: Optional[Config] = None) -> np.ndarray:
     P = pg.poses
     pg.close()
     return P
+
+
+def _training_window(k: int):
+    """k-th training window: a 4-keyframe 160x120 scene (seed 10000 + k) with
+    its true masks and with masks grown by k mod 6 pixels."""
+    import synth
+    seed = 10_000 + k
+    return synth.make_graph("T", seed=seed), synth.make_graph("T", seed=seed, mask_dilate=k % 6)
+
+
+def main(argv=None):
+    """Train the weighting network on seeded synthetic windows and write its
+    fp16 parameters (.npy) and a record of the run (.json)."""
+    import argparse
+    import json
+    import multiprocessing as mp
+    import os
+    import time
+
+    import torch
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--graphs", type=int, default=10_000)
+    ap.add_argument("--sample-frac", type=float, default=0.02)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--batch", type=int, default=65536)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--out", required=True, help="output .npy (fp16 parameters)")
+    a = ap.parse_args(argv)
+    t0 = time.time()
+    xs, ys = [], []
+    # the workers only build scenes on the CPU; they are forked before this
+    # process touches the GPU
+    with mp.get_context("fork").Pool(max(1, min(a.workers, os.cpu_count() or 1))) as pool:
+        torch.cuda.set_device(0)
+        done = 0
+        for clean, leaky in pool.imap(_training_window, range(a.graphs), chunksize=8):
+            ref = reference_poses(clean)
+            x, y = collect([(leaky, ref)], sample_frac=a.sample_frac, seed=a.seed + done)
+            xs.append(x)
+            ys.append(y)
+            done += 1
+            if done % 500 == 0:
+                print(f"{done} windows, {sum(len(v) for v in ys)} samples, {time.time() - t0:.0f} s", flush=True)
+    x, y = torch.cat(xs), torch.cat(ys)
+    t1 = time.time()
+    p16, tr = train(x, y, steps=a.steps, lr=a.lr, batch=a.batch, seed=a.seed,
+                    log=lambda m: print(m, flush=True))
+    m = min(len(y), a.batch)
+    loss, _ = tr.loss_grad(x[:m].contiguous(), y[:m].contiguous())
+    tr.close()
+    np.save(a.out, p16, allow_pickle=False)
+    rec = dict(graphs=a.graphs, samples=int(len(y)), inlier_fraction=float(y.mean()), steps=a.steps, lr=a.lr,
+               batch=a.batch, seed=a.seed, sample_frac=a.sample_frac, final_loss_first_batch=loss,
+               collect_s=round(t1 - t0, 1), train_s=round(time.time() - t1, 1),
+               windows="4 keyframes 160x120 (seeds 10000..), masks grown by k mod 6 px; labels: gated in "
+                       "with |r| < 3 mm at the plain optimiser's poses on the true masks")
+    with open(os.path.splitext(a.out)[0] + ".json", "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()
