@@ -198,6 +198,14 @@ pg_status pose_graph_set_mlp(pg_graph *g, const void *fp16_params, size_t n_byte
 pg_status pose_graph_pair_features(pg_graph *g, int i, int j, int iteration, float *features,
                                    float *sigma, int32_t *target);
 
+/* Timing of the dense association kernel alone at the current poses (for
+ * roofline figures): after one untimed launch, reps (1..10000) launches of
+ * iteration 0 back to back on the graph's stream between two HIP events;
+ * *ms_per_launch = elapsed / reps.  With learned weighting the pruning pass
+ * runs first, untimed.  Leaves the poses unchanged.  Errors:
+ * PG_ERR_INVALID_ARG. */
+pg_status pose_graph_time_assoc(pg_graph *g, int reps, double *ms_per_launch);
+
 /* Pruning pass of the learned weighting at the current poses (the pass an
  * optimize runs on its starting poses): score[f*H*W + x] = the largest network
  * output over the target frames source pixel x of frame f is gated in with

@@ -89,6 +89,9 @@ def lib():
         L.orc_huber_weight.restype = C.c_double
         L.orc_cholesky_solve.argtypes = [C.c_int, dp, dp, dp]
         L.orc_mlp_forward.argtypes = [dp, C.c_int, dp, dp]
+        L.orc_mlp_forward_half.argtypes = [dp, C.c_int, dp, dp]
+        L.orc_round_half.argtypes = [C.c_double]
+        L.orc_round_half.restype = C.c_double
         L.orc_pair_features.argtypes = [P(Problem), dp, C.c_int, C.c_int, C.c_int, P(C.c_int), dp]
         L.orc_prune_scores.argtypes = [P(Problem), dp, dp]
         L.orc_prune_select.argtypes = [P(Problem), dp, C.c_double, P(C.c_ubyte)]
@@ -340,6 +343,20 @@ def mlp_forward(params, x):
     y = np.zeros(len(x))
     lib().orc_mlp_forward(_ptr(p, C.c_double), len(x), _ptr(x, C.c_double), _ptr(y, C.c_double))
     return y
+
+
+def mlp_forward_half(params, x):
+    """Outputs of the network as the dense term evaluates it: binary16 inputs
+    and first-layer activations, exact products and sums."""
+    p = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 6)
+    y = np.zeros(len(x))
+    lib().orc_mlp_forward_half(_ptr(p, C.c_double), len(x), _ptr(x, C.c_double), _ptr(y, C.c_double))
+    return y
+
+
+def round_half(x):
+    return lib().orc_round_half(float(x))
 
 
 def mlp_bce(params, x, labels, with_grad=True):

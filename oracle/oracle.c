@@ -866,10 +866,52 @@ double orc_mlp_bce(const double *params, int n, const double *x, const double *l
     return loss / n;
 }
 
+double orc_round_half(double x)
+{
+    if (x == 0.0 || !isfinite(x))
+        return x;
+    int e;
+    frexp(fabs(x), &e);   /* |x| = m 2^e, m in [0.5, 1) */
+    /* binary16: 11 significant bits for normal values (|x| >= 2^-14, i.e.
+     * e >= -13); below, the fixed quantum 2^-24 of the subnormals */
+    const double q = (e >= -13) ? ldexp(1.0, e - 11) : ldexp(1.0, -24);
+    const double r = nearbyint(x / q) * q;   /* default rounding: nearest, ties to even */
+    if (fabs(r) > 65504.0)
+        return x > 0.0 ? INFINITY : -INFINITY;
+    return r;
+}
+
+/* network evaluation with binary16 inputs and first-layer activations */
+static double mlp_eval_half(const double *P, const double *f)
+{
+    double x[ORC_MLP_IN], h1[ORC_MLP_HID];
+    for (int k = 0; k < ORC_MLP_IN; ++k)
+        x[k] = orc_round_half(f[k]);
+    for (int o = 0; o < ORC_MLP_HID; ++o) {
+        double s = P[MLP_B1 + o];
+        for (int k = 0; k < ORC_MLP_IN; ++k)
+            s += P[MLP_W1 + ORC_MLP_IN * o + k] * x[k];
+        h1[o] = orc_round_half(s > 0.0 ? s : 0.0);
+    }
+    double z = P[MLP_B3];
+    for (int o = 0; o < ORC_MLP_HID; ++o) {
+        double s = P[MLP_B2 + o];
+        for (int k = 0; k < ORC_MLP_HID; ++k)
+            s += P[MLP_W2 + ORC_MLP_HID * o + k] * h1[k];
+        z += P[MLP_W3 + o] * (s > 0.0 ? s : 0.0);
+    }
+    return z;
+}
+
+void orc_mlp_forward_half(const double *params, int n, const double *x, double *y)
+{
+    for (int i = 0; i < n; ++i)
+        y[i] = sigmoid(mlp_eval_half(params, x + ORC_MLP_IN * (size_t)i));
+}
+
 static double mlp_sigmoid_of(const double *P, const double *f)
 {
-    double a1[ORC_MLP_HID], h1[ORC_MLP_HID], a2[ORC_MLP_HID], h2[ORC_MLP_HID];
-    return sigmoid(mlp_eval(P, f, a1, h1, a2, h2));
+    return sigmoid(mlp_eval_half(P, f));
 }
 
 static void mlp_features(const orc_problem *pb, const frame_maps *fm, int i, size_t x, double r,

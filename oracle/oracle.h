@@ -155,6 +155,18 @@ int orc_prune_select(const orc_problem *pb, const double *score, double frac, un
 /* Output of the network for each of n inputs (n x 6, row-major). */
 void orc_mlp_forward(const double *params, int n, const double *x, double *y);
 
+/* The network as the dense term evaluates it, in the FP16 arithmetic of the
+ * learned-weighting design (6-32-32-1 "in FP16"): the inputs and the first
+ * hidden layer's activations are rounded to binary16 (nearest, ties to even)
+ * before they enter the two products; products and sums are exact here
+ * (FP64).  Used by the dense term, orc_pair_features' consumers and
+ * orc_prune_scores whenever pb->mlp is set. */
+void orc_mlp_forward_half(const double *params, int n, const double *x, double *y);
+
+/* x rounded to the nearest IEEE binary16 value (ties to even; overflow to
+ * +-inf; subnormals kept), returned as a double. */
+double orc_round_half(double x);
+
 /* Mean binary cross-entropy of the outputs against labels in {0, 1} and its
  * gradient with respect to the parameters (1313 doubles; grad may be NULL). */
 double orc_mlp_bce(const double *params, int n, const double *x, const double *labels,

@@ -73,6 +73,7 @@ SIGNATURES = {
     "pose_graph_set_mlp": (C.c_int, [_vp, _vp, C.c_size_t]),
     "pose_graph_pair_features": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp]),
     "pose_graph_prune": (C.c_int, [_vp, _vp, _vp]),
+    "pose_graph_time_assoc": (C.c_int, [_vp, C.c_int, _dp]),
     "pg_mlp_create": (C.c_int, [C.c_int, _vp, C.POINTER(_vp)]),
     "pg_mlp_destroy": (None, [_vp]),
     "pg_mlp_set_params": (C.c_int, [_vp, _vp]),

@@ -1160,6 +1160,44 @@ pg_status pose_graph_pair_features(pg_graph* g, int i, int j, int iteration, flo
     return PG_OK;
 }
 
+pg_status pose_graph_time_assoc(pg_graph* g, int reps, double* ms_per_launch)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (reps < 1 || reps > 10000 || !ms_per_launch)
+        return fail(g, PG_ERR_INVALID_ARG, "reps must be 1..10000 and ms_per_launch non-NULL");
+    pg_status rc = ready_single(g);
+    if (rc != PG_OK)
+        return rc;
+    Schedule& s = *g->sched;
+    const GraphDev* gds = s.gds.as<GraphDev>();
+    launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, g->stream);
+    // one untimed launch, then reps back-to-back launches between two events
+    launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, g->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OR_FAIL(g, hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e == hipSuccess)
+        e = hipEventRecord(e0, g->stream);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) {
+        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, g->stream);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(e1, g->stream);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    HIP_OR_FAIL(g, e);
+    *ms_per_launch = (double)ms / reps;
+    return PG_OK;
+}
+
 pg_status pose_graph_prune(pg_graph* g, float* score, uint8_t* keep)
 {
     if (!g)

@@ -322,6 +322,15 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     const uint32_t* __restrict__ src_uv = (LEARNED ? gd.psrc_uv : gd.src_uv) + (size_t)i * gd.HW;
     const float4* __restrict__ tmap = gd.maps + (size_t)j * gd.HW;
     const float huber = gd.huber_g;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // learned weighting: network operands (registers) and output-layer constants (LDS)
+    __shared__ __attribute__((aligned(16))) float s_tail[kMlpTail];
+    MlpFrags M;
+    if (LEARNED) {
+        mlp_tail_load(gd.mlp32, s_tail);
+        mlp_frags_load(gd.mlp32, M, lane);
+        __syncthreads();
+    }
 
     float acc[32];
 #pragma unroll
@@ -361,21 +370,24 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     }
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-        if (y[m] < 0)
-            continue;
-        float r, J[6], d2, cg, sn;
-        if (finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J, d2, cg, sn) < 0)
+        float r = 0.f, J[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, d2 = 0.f, cg = 0.f, sn = 0.f;
+        bool gated = false;
+        if (y[m] >= 0)
+            gated = finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J, d2, cg, sn) >= 0;
+        float sg = 1.0f;
+        if (LEARNED) {
+            // the network runs wave-wide: every lane takes part, gated in or not
+            float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (gated)
+                learned_features(gd, r, d2, cg, sn, s[m].w, uvs[m], iteration, f);
+            if (__ballot(gated))
+                sg = mlp_sigma_wave(M, s_tail, f, lane);
+        }
+        if (!gated)
             continue;
         const float ar = fabsf(r);
-        float w = (ar <= huber) ? 1.0f : huber / ar;
-        float e = (ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber);
-        if (LEARNED) {
-            float f[6];
-            learned_features(gd, r, d2, cg, sn, s[m].w, uvs[m], iteration, f);
-            const float sg = mlp_sigma(gd.mlp32, f);
-            w *= sg;
-            e *= sg;
-        }
+        const float w = ((ar <= huber) ? 1.0f : huber / ar) * sg;
+        const float e = ((ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber)) * sg;
         float wJ[6];
 #pragma unroll
         for (int a = 0; a < 6; ++a)
@@ -393,7 +405,6 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
         acc[28] += 1.0f;
     }
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     halve<16>(acc, lane);
     halve<8>(acc, lane);
     halve<4>(acc, lane);
@@ -454,6 +465,14 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
     const float4* __restrict__ tmap = gd.maps + (size_t)j * gd.HW;
     const float huber = gd.huber_g;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // learned weighting: network operands (registers) and output-layer constants (LDS)
+    __shared__ __attribute__((aligned(16))) float s_tail[kMlpTail];
+    MlpFrags M;
+    if (LEARNED) {
+        mlp_tail_load(gd.mlp32, s_tail);
+        mlp_frags_load(gd.mlp32, M, lane);
+        __syncthreads();
+    }
     // per wave: [hi, lo][16 features][64 pixels]
     __shared__ __attribute__((aligned(16))) __bf16 stage[kAssocThreads / 64][2][16][64];
     for (int e = lane; e < 2 * 9 * 64; e += 64)
@@ -492,28 +511,31 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         float x[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        float r = 0.f, J[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, d2 = 0.f, cg = 0.f, sn = 0.f;
+        bool gated = false;
         if (y[m] >= 0) {
             reads += 1.0f;
-            float r, J[6], d2, cg, sn;
-            if (finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J, d2, cg, sn) >= 0) {
-                const float ar = fabsf(r);
-                float w = (ar <= huber) ? 1.0f : huber / ar;
-                float e = (ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber);
-                if (LEARNED) {
-                    float f[6];
-                    learned_features(gd, r, d2, cg, sn, s[m].w, uvs[m], iteration, f);
-                    const float sg = mlp_sigma(gd.mlp32, f);
-                    w *= sg;
-                    e *= sg;
-                }
-                energy += e;
-                count += 1.0f;
-                const float sw = sqrtf(w);
+            gated = finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J, d2, cg, sn) >= 0;
+        }
+        float sg = 1.0f;
+        if (LEARNED) {
+            // the network runs wave-wide: every lane takes part, gated in or not
+            float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (gated)
+                learned_features(gd, r, d2, cg, sn, s[m].w, uvs[m], iteration, f);
+            if (__ballot(gated))
+                sg = mlp_sigma_wave(M, s_tail, f, lane);
+        }
+        if (gated) {
+            const float ar = fabsf(r);
+            const float w = ((ar <= huber) ? 1.0f : huber / ar) * sg;
+            energy += ((ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber)) * sg;
+            count += 1.0f;
+            const float sw = sqrtf(w);
 #pragma unroll
-                for (int a = 0; a < 6; ++a)
-                    x[a] = sw * J[a];
-                x[6] = sw * r;
-            }
+            for (int a = 0; a < 6; ++a)
+                x[a] = sw * J[a];
+            x[6] = sw * r;
         }
 #pragma unroll
         for (int f = 0; f < 7; ++f) {
@@ -566,25 +588,33 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
 
 // Association decisions of one ordered pair for inspection: the same
 // projection and gating code as the association kernel, one thread per pixel.
-__global__ void assoc_debug_kernel(const GraphDev* __restrict__ gds, int i, int j, int iteration,
-                                   int* __restrict__ target, float* __restrict__ res, float* __restrict__ uv,
-                                   float* __restrict__ feat, float* __restrict__ sigma)
+__global__ __launch_bounds__(256) void assoc_debug_kernel(const GraphDev* __restrict__ gds, int i, int j,
+                                                          int iteration, int* __restrict__ target,
+                                                          float* __restrict__ res, float* __restrict__ uv,
+                                                          float* __restrict__ feat, float* __restrict__ sigma)
 {
     const GraphDev& gd = gds[0];
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= gd.HW)
-        return;
+    const bool live = x < gd.HW;
+    const int lane = threadIdx.x & 63;
+    const bool want_sigma = sigma != nullptr && gd.mlp32 != nullptr;   // uniform
+    __shared__ __attribute__((aligned(16))) float s_tail[kMlpTail];
+    MlpFrags M;
+    if (want_sigma) {
+        mlp_tail_load(gd.mlp32, s_tail);
+        mlp_frags_load(gd.mlp32, M, lane);
+        __syncthreads();
+    }
     const int p = pair_index(i, j, gd.n_frames);
     float A[12], B[12];
     for (int k = 0; k < 12; ++k) {
         A[k] = gd.xf32[p * 24 + k];
         B[k] = gd.xf32[p * 24 + 12 + k];
     }
-    const float4 s = gd.maps[(size_t)i * gd.HW + x];
+    const float4 s = live ? gd.maps[(size_t)i * gd.HW + x] : make_float4(0.f, 0.f, 0.f, 0.f);
     int code = -1;
     float r = 0.f, uf = __builtin_nanf(""), vf = uf;
     float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float sg = 0.f;
     if (s.w > 0.f) {
         const int u = x % gd.W, v = x / gd.W;
         const float px = s.w * (((float)u - gd.cx) * gd.ifx);
@@ -596,14 +626,18 @@ __global__ void assoc_debug_kernel(const GraphDev* __restrict__ gds, int i, int 
             code = finish_px(A, px, py, s.w, s.x, s.y, s.z, code, t, gd, rr, J, d2, c, sn);
             if (code >= 0) {
                 r = rr;
-                if (feat || sigma) {
-                    learned_features(gd, rr, d2, c, sn, s.w, (uint32_t)u | ((uint32_t)v << 16), iteration, f);
-                    if (sigma && gd.mlp32)
-                        sg = mlp_sigma(gd.mlp32, f);
-                }
+                learned_features(gd, rr, d2, c, sn, s.w, (uint32_t)u | ((uint32_t)v << 16), iteration, f);
             }
         }
     }
+    // the network as the association kernels evaluate it (wave-wide)
+    float sg = 0.f;
+    if (want_sigma && __ballot(code >= 0)) {
+        const float o = mlp_sigma_wave(M, s_tail, f, lane);
+        sg = (code >= 0) ? o : 0.f;
+    }
+    if (!live)
+        return;
     if (target)
         target[x] = code;
     if (res)
@@ -634,9 +668,15 @@ __global__ __launch_bounds__(kPruneThreads) void prune_score_kernel(const GraphD
     const WorkItem it = items[blockIdx.x];
     const GraphDev& gd = gds[it.gij >> 16];
     const int i = it.gij & 0xff;
-    if ((int)threadIdx.x >= it.count)
-        return;
-    const size_t e = (size_t)i * gd.HW + it.start + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    __shared__ __attribute__((aligned(16))) float s_tail[kMlpTail];
+    MlpFrags M;
+    mlp_tail_load(gd.mlp32, s_tail);
+    mlp_frags_load(gd.mlp32, M, lane);
+    __syncthreads();
+    // every lane stays to the end: the network runs wave-wide
+    const bool live = (int)threadIdx.x < it.count;
+    const size_t e = (size_t)i * gd.HW + it.start + (live ? threadIdx.x : 0);
     const float4 s = gd.src_nz[e];
     const uint32_t uv = gd.src_uv[e];
     const float px = s.w * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
@@ -652,19 +692,28 @@ __global__ __launch_bounds__(kPruneThreads) void prune_score_kernel(const GraphD
             A[k] = gd.xf32[p * 24 + k];
             B[k] = gd.xf32[p * 24 + 12 + k];
         }
-        float uf, vf;
-        const int y = project_px(B, px, py, s.w, gd, uf, vf);
-        if (y < 0)
-            continue;
-        const float4 t = gd.maps[(size_t)j * gd.HW + y];
-        float r, J[6], d2, c, sn;
-        if (finish_px(A, px, py, s.w, s.x, s.y, s.z, y, t, gd, r, J, d2, c, sn) < 0)
-            continue;
-        float f[6];
-        learned_features(gd, r, d2, c, sn, s.w, uv, 0, f);
-        best = fmaxf(best, mlp_sigma(gd.mlp32, f));
+        bool gated = false;
+        float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (live) {
+            float uf, vf;
+            const int y = project_px(B, px, py, s.w, gd, uf, vf);
+            if (y >= 0) {
+                const float4 t = gd.maps[(size_t)j * gd.HW + y];
+                float r, J[6], d2, c, sn;
+                if (finish_px(A, px, py, s.w, s.x, s.y, s.z, y, t, gd, r, J, d2, c, sn) >= 0) {
+                    gated = true;
+                    learned_features(gd, r, d2, c, sn, s.w, uv, 0, f);
+                }
+            }
+        }
+        if (__ballot(gated)) {
+            const float sg = mlp_sigma_wave(M, s_tail, f, lane);
+            if (gated)
+                best = fmaxf(best, sg);
+        }
     }
-    gd.score[e] = __float_as_uint(best);
+    if (live)
+        gd.score[e] = __float_as_uint(best);
 }
 
 // Exclusive prefix of flag over the block (1024 threads = 16 waves) and the
@@ -935,15 +984,41 @@ __device__ __forceinline__ double sym12(const double* F, int a, int b)
     return (a <= b) ? F[upper_index(a, b, 12)] : F[upper_index(b, a, 12)];
 }
 
-constexpr int kAsmThreads = 512;
+constexpr int kAsmThreads = 1024;
 constexpr int kMaxPairsPerBlock = 2 * (kMaxFrames - 1);
+constexpr int kMaxTgtPairs = kMaxFrames - 1;
+constexpr int kAsmChunks = 8;   // tile-sum chunks per field of an off-diagonal block
 
-// One block per node block (I, J), I >= J, of the 6N x 6N system: reduces the
-// partial records of the ordered pairs touching it in FP64 (each pair's
-// records are contiguous, summed in order with four interleaved partial sums),
-// expands them with the adjoint, adds the feature blocks (each match counted
-// for both orderings of Eq. 1), and writes H (both triangles), the gradient
-// segment and the node's energy/count record (diagonal blocks).
+// Sum of the partial records [t0, t1) of one field, in order, with four
+// interleaved accumulators (loads of a chunk are independent and in flight
+// together).
+__device__ __forceinline__ double sum_records(const float* __restrict__ src, int t0, int t1)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int t = t0;
+    for (; t + 4 <= t1; t += 4) {
+        s0 += (double)src[(size_t)t * kDenseStride];
+        s1 += (double)src[(size_t)(t + 1) * kDenseStride];
+        s2 += (double)src[(size_t)(t + 2) * kDenseStride];
+        s3 += (double)src[(size_t)(t + 3) * kDenseStride];
+    }
+    for (; t < t1; ++t)
+        s0 += (double)src[(size_t)t * kDenseStride];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// One block per node block (I, J), I >= J, of the 6N x 6N system.  A diagonal
+// block sums the 2(N-1) ordered pairs touching node I (source role: M and v
+// as they are; target role: Ad^T M Ad and -Ad^T v), an off-diagonal block the
+// pairs (I, J) and (J, I) (-M Ad and -(M Ad)^T); the feature blocks of Eq. 2
+// (each match counted for both orderings of Eq. 1) are added; H is written in
+// both triangles (diagonal blocks: the upper triangle, mirrored, so H is
+// exactly symmetric), with the gradient segment and the node's energy/count
+// record.  First phase: every global read of the block at once (partial
+// records of each pair and field, summed in FP64 in a fixed order - split into
+// kAsmChunks contiguous chunks for the two pairs of an off-diagonal block -,
+// the pairs' FP64 transforms and the oriented feature entries); then the
+// adjoint expansion in LDS.
 __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* __restrict__ gds,
                                                                const int2* __restrict__ nbs)
 {
@@ -954,15 +1029,17 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
     const int I = nb.y & 0xff, J = (nb.y >> 8) & 0xff;
     const int N = gd.n_frames, n6 = 6 * N;
     const bool diag = (I == J);
-    const int np = diag ? 2 * (N - 1) : 2;
+    const int np = diag ? 2 * (N - 1) : 2;       // pairs summed
+    const int nt = diag ? N - 1 : 2;             // pairs expanded with the adjoint (P, AX)
+    const int kt0 = diag ? N - 1 : 0;            // pair index of expanded pair 0
     __shared__ double S[kMaxPairsPerBlock][kDenseFields];
-    __shared__ double P[kMaxPairsPerBlock][36];
-    __shared__ double X[kMaxPairsPerBlock][42];
-    __shared__ int sset[kMaxFrames];
-    __shared__ int sfirst[kMaxFrames];
-    __shared__ double AX[kMaxPairsPerBlock][12];   // A = T_i T_j^-1 of each pair (FP64)
+    __shared__ double P[kMaxTgtPairs][36];
+    __shared__ double X[kMaxTgtPairs][42];       // off-diagonal blocks: chunk sums
+    __shared__ double AX[kMaxTgtPairs][12];      // A = T_i T_j^-1 of the expanded pairs (FP64)
+    __shared__ double FS[kMaxFrames][44];        // oriented feature entries per neighbour
+    double* const chunk = &X[0][0];
 
-    // pair k: for k < np/2 the pair has I as source, else I as target
+    // pair k: diagonal: k < N-1 (I, j), else (i, I); off-diagonal: (I, J), (J, I)
     auto pair_of = [&](int k, int& i, int& j) {
         if (!diag) {
             i = (k == 0) ? I : J;
@@ -977,148 +1054,149 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
         }
     };
 
-    // feature sets of this block and whether I is their first node
-    if (threadIdx.x < N) {
-        const int K = threadIdx.x;
-        int s = -1;
-        if (K != I && (diag || K == J))
-            s = gd.set_of[I * N + K];
-        sset[K] = s;
-        sfirst[K] = (s >= 0 && gd.fsets[s].x == I) ? 1 : 0;
-    }
-    for (int task = threadIdx.x; task < np * 12; task += kAsmThreads) {
-        const int k = task / 12;
-        int i, j;
-        pair_of(k, i, j);
-        AX[k][task % 12] = gd.xf64[12 * pair_index(i, j, N) + task % 12];
-    }
-    for (int task = threadIdx.x; task < np * kDenseFields; task += kAsmThreads) {
-        const int k = task / kDenseFields, f = task % kDenseFields;
-        int i, j;
-        pair_of(k, i, j);
-        const int p = pair_index(i, j, N);
-        const int b0 = gd.pair_base[p], b1 = gd.pair_base[p + 1];
-        const float* __restrict__ src = gd.partials + f;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int t = b0;
-        for (; t + 4 <= b1; t += 4) {
-            s0 += (double)src[(size_t)t * kDenseStride];
-            s1 += (double)src[(size_t)(t + 1) * kDenseStride];
-            s2 += (double)src[(size_t)(t + 2) * kDenseStride];
-            s3 += (double)src[(size_t)(t + 3) * kDenseStride];
+    // ---- phase 1: all global reads
+    const int n_sum = diag ? np * kDenseFields : kAsmChunks * 2 * kDenseFields;
+    const int n_ax = nt * 12;
+    const int n_fs = diag ? N * 44 : 36;
+    for (int task = threadIdx.x; task < n_sum + n_ax + n_fs; task += kAsmThreads) {
+        if (task < n_sum) {
+            int k, f, c;
+            if (diag) {
+                k = task / kDenseFields;
+                f = task % kDenseFields;
+                c = 0;
+            } else {
+                c = task / (2 * kDenseFields);
+                k = (task / kDenseFields) & 1;
+                f = task % kDenseFields;
+            }
+            int i, j;
+            pair_of(k, i, j);
+            const int p = pair_index(i, j, N);
+            const int b0 = gd.pair_base[p], b1 = gd.pair_base[p + 1];
+            if (diag) {
+                S[k][f] = sum_records(gd.partials + f, b0, b1);
+            } else {
+                const int len = b1 - b0;
+                const int t0 = b0 + (int)(((long long)len * c) / kAsmChunks);
+                const int t1 = b0 + (int)(((long long)len * (c + 1)) / kAsmChunks);
+                chunk[c * 2 * kDenseFields + k * kDenseFields + f] = sum_records(gd.partials + f, t0, t1);
+            }
+        } else if (task < n_sum + n_ax) {
+            const int q = task - n_sum, pk = q / 12;
+            int i, j;
+            pair_of(kt0 + pk, i, j);
+            AX[pk][q % 12] = gd.xf64[12 * pair_index(i, j, N) + q % 12];
+        } else {
+            const int q = task - n_sum - n_ax;
+            const int K = diag ? q / 44 : J, e = diag ? q % 44 : q;
+            double v = 0.0;
+            const int s = (K != I) ? gd.set_of[I * N + K] : -1;
+            if (s >= 0) {
+                const double* F = gd.fpartials + (size_t)s * kFeatStride;
+                const bool first = gd.fsets[s].x == I;
+                if (diag) {
+                    const int o = first ? 0 : 6;
+                    if (e < 36)
+                        v = sym12(F, o + e / 6, o + e % 6);
+                    else if (e < 42)
+                        v = F[78 + o + (e - 36)];
+                    else
+                        v = first ? F[90 + (e - 42)] : 0.0;   // energy and count once per set
+                } else {
+                    const int a = e / 6, c = e % 6;
+                    v = first ? sym12(F, a, 6 + c) : sym12(F, 6 + a, c);
+                }
+            }
+            FS[K][e] = v;
         }
-        for (; t < b1; ++t)
-            s0 += (double)src[(size_t)t * kDenseStride];
-        S[k][f] = (s0 + s1) + (s2 + s3);
     }
     __syncthreads();
-    // P = M Ad (off-diagonal blocks and the target-role diagonal term)
-    for (int task = threadIdx.x; task < np * 36; task += kAsmThreads) {
-        const int k = task / 36, e = task % 36, a = e / 6, c = e % 6;
-        int i, j;
-        pair_of(k, i, j);
-        const bool src_role = diag ? (k < N - 1) : (k == 0);
-        if (diag && src_role)
-            continue;
-        const double* Xa = AX[k];
+    if (!diag) {
+        // chunk sums of the two pairs, in chunk order
+        if (threadIdx.x < 2 * kDenseFields) {
+            const int k = threadIdx.x / kDenseFields, f = threadIdx.x % kDenseFields;
+            double v = 0.0;
+            for (int c = 0; c < kAsmChunks; ++c)
+                v += chunk[c * 2 * kDenseFields + k * kDenseFields + f];
+            S[k][f] = v;
+        }
+        __syncthreads();
+    }
+    // ---- phase 2: P = M Ad of the expanded pairs
+    for (int task = threadIdx.x; task < nt * 36; task += kAsmThreads) {
+        const int pk = task / 36, e = task % 36, a = e / 6, c = e % 6;
+        const double* Sk = S[kt0 + pk];
         double v = 0.0;
         for (int l = 0; l < 6; ++l)
-            v += sym6(S[k], a, l) * adj(Xa, l, c);
-        P[k][e] = v;
-    }
-    __syncthreads();
-    for (int task = threadIdx.x; task < np * 42; task += kAsmThreads) {
-        const int k = task / 42, e = task % 42;
-        int i, j;
-        pair_of(k, i, j);
-        const bool src_role = diag ? (k < N - 1) : (k == 0);
-        const double* Xa = AX[k];
-        double v;
-        if (e < 36) {
-            const int a = e / 6, c = e % 6;
-            if (!diag)
-                v = src_role ? -P[k][e] : -P[k][6 * c + a];   // -M Ad  |  -(M Ad)^T
-            else if (src_role)
-                v = sym6(S[k], a, c);                          // M
-            else if (a <= c) {
-                v = 0.0;                                        // Ad^T M Ad (upper)
-                for (int l = 0; l < 6; ++l)
-                    v += adj(Xa, l, a) * P[k][6 * l + c];
-            } else
-                v = 0.0;
-        } else {
-            const int a = e - 36;
-            if (src_role)
-                v = S[k][21 + a];                               // g_i = v
-            else {
-                v = 0.0;                                        // g_j = -Ad^T v
-                for (int l = 0; l < 6; ++l)
-                    v -= adj(Xa, l, a) * S[k][21 + l];
-            }
-        }
-        X[k][e] = v;
+            v += sym6(Sk, a, l) * adj(AX[pk], l, c);
+        P[pk][e] = v;
     }
     __syncthreads();
     const double lg = (double)gd.lambda_g, lf2 = 2.0 * (double)gd.lambda_f;
     if (!diag) {
         if (threadIdx.x < 36) {
             const int e = threadIdx.x, a = e / 6, c = e % 6;
-            double h = lg * (X[0][e] + X[1][e]);
-            const int s = sset[J];
-            if (s >= 0) {
-                const double* F = gd.fpartials + (size_t)s * kFeatStride;
-                h += lf2 * (sfirst[J] ? sym12(F, a, 6 + c) : sym12(F, 6 + a, c));
-            }
+            // -M Ad of (I, J) and -(M Ad)^T of (J, I)
+            double h = lg * (-P[0][e] + -P[1][6 * c + a]);
+            h += lf2 * FS[J][e];
             gd.Hm[(size_t)(6 * I + a) * n6 + 6 * J + c] = h;
             gd.Hm[(size_t)(6 * J + c) * n6 + 6 * I + a] = h;
         }
-    } else {
-        // the upper triangle of the diagonal block is summed and mirrored, so
-        // H is exactly symmetric
-        if (threadIdx.x < 42 && (threadIdx.x >= 36 || threadIdx.x / 6 <= threadIdx.x % 6)) {
-            const int e = threadIdx.x;
-            double h = 0.0;
-            for (int k = 0; k < np; ++k)
-                h += X[k][e];
-            h *= lg;
-            for (int K = 0; K < N; ++K) {
-                const int s = sset[K];
-                if (s < 0)
-                    continue;
-                const double* F = gd.fpartials + (size_t)s * kFeatStride;
-                const int o = sfirst[K] ? 0 : 6;
-                if (e < 36)
-                    h += lf2 * sym12(F, o + e / 6, o + e % 6);
-                else
-                    h += lf2 * F[78 + o + (e - 36)];
-            }
-            if (e < 36) {
-                gd.Hm[(size_t)(6 * I + e / 6) * n6 + 6 * I + e % 6] = h;
-                gd.Hm[(size_t)(6 * I + e % 6) * n6 + 6 * I + e / 6] = h;
-            } else {
-                gd.grad[6 * I + (e - 36)] = h;
-            }
-        } else if (threadIdx.x == 64) {
-            double Eg = 0.0, cg = 0.0, Ef = 0.0, cf = 0.0, rd = 0.0;
-            for (int k = 0; k < N - 1; ++k) {
-                Eg += S[k][27];
-                cg += S[k][28];
-                rd += S[k][29];
-            }
-            for (int K = 0; K < N; ++K) {
-                const int s = sset[K];
-                if (s < 0 || !sfirst[K])
-                    continue;
-                const double* F = gd.fpartials + (size_t)s * kFeatStride;
-                Ef += F[90];
-                cf += F[91];
-            }
-            gd.node_stats[kNodeStats * I + 0] = lg * Eg;
-            gd.node_stats[kNodeStats * I + 1] = lf2 * Ef;
-            gd.node_stats[kNodeStats * I + 2] = cg;
-            gd.node_stats[kNodeStats * I + 3] = cf;
-            gd.node_stats[kNodeStats * I + 4] = rd;
+        return;
+    }
+    // ---- phase 3 (diagonal): target-role terms Ad^T M Ad (upper) and -Ad^T v
+    for (int task = threadIdx.x; task < nt * 42; task += kAsmThreads) {
+        const int pk = task / 42, e = task % 42;
+        const double* Xa = AX[pk];
+        double v = 0.0;
+        if (e < 36) {
+            const int a = e / 6, c = e % 6;
+            if (a <= c)
+                for (int l = 0; l < 6; ++l)
+                    v += adj(Xa, l, a) * P[pk][6 * l + c];
+        } else {
+            const int a = e - 36;
+            for (int l = 0; l < 6; ++l)
+                v -= adj(Xa, l, a) * S[kt0 + pk][21 + l];
         }
+        X[pk][e] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 42 && (threadIdx.x >= 36 || threadIdx.x / 6 <= threadIdx.x % 6)) {
+        const int e = threadIdx.x;
+        double h = 0.0;
+        for (int k = 0; k < N - 1; ++k)   // source role: M and v
+            h += (e < 36) ? sym6(S[k], e / 6, e % 6) : S[k][21 + (e - 36)];
+        for (int pk = 0; pk < nt; ++pk)   // target role
+            h += X[pk][e];
+        h *= lg;
+        double f = 0.0;
+        for (int K = 0; K < N; ++K)
+            f += FS[K][e];
+        h += lf2 * f;
+        if (e < 36) {
+            gd.Hm[(size_t)(6 * I + e / 6) * n6 + 6 * I + e % 6] = h;
+            gd.Hm[(size_t)(6 * I + e % 6) * n6 + 6 * I + e / 6] = h;
+        } else {
+            gd.grad[6 * I + (e - 36)] = h;
+        }
+    } else if (threadIdx.x == 64) {
+        double Eg = 0.0, cg = 0.0, Ef = 0.0, cf = 0.0, rd = 0.0;
+        for (int k = 0; k < N - 1; ++k) {
+            Eg += S[k][27];
+            cg += S[k][28];
+            rd += S[k][29];
+        }
+        for (int K = 0; K < N; ++K) {
+            Ef += FS[K][42];
+            cf += FS[K][43];
+        }
+        gd.node_stats[kNodeStats * I + 0] = lg * Eg;
+        gd.node_stats[kNodeStats * I + 1] = lf2 * Ef;
+        gd.node_stats[kNodeStats * I + 2] = cg;
+        gd.node_stats[kNodeStats * I + 3] = cf;
+        gd.node_stats[kNodeStats * I + 4] = rd;
     }
 }
 
@@ -1130,14 +1208,21 @@ constexpr int kSolveThreads = 512;
 __device__ void se3_exp(const double* xi, double* T)
 {
     const double w0 = xi[3], w1 = xi[4], w2 = xi[5];
-    const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
+    // a = sin t / t, b = (1 - cos t) / t^2, c = (t - sin t) / t^3
     double a, b, c;
-    if (th < 1e-6) {
-        a = 1.0 - th2 / 6.0;
-        b = 0.5 - th2 / 24.0;
-        c = 1.0 / 6.0 - th2 / 120.0;
+    if (th2 < 0.25) {
+        // |t| < 0.5 (every Gauss-Newton step in practice): Taylor series in
+        // t^2 through t^16, truncation below 1e-22; no cancellation
+        const double x = th2;
+        a = 1.0 - x * (1.0 / 6) * (1.0 - x * (1.0 / 20) * (1.0 - x * (1.0 / 42) * (1.0 - x * (1.0 / 72) *
+            (1.0 - x * (1.0 / 110) * (1.0 - x * (1.0 / 156) * (1.0 - x * (1.0 / 210) * (1.0 - x * (1.0 / 272))))))));
+        b = 0.5 * (1.0 - x * (1.0 / 12) * (1.0 - x * (1.0 / 30) * (1.0 - x * (1.0 / 56) * (1.0 - x * (1.0 / 90) *
+            (1.0 - x * (1.0 / 132) * (1.0 - x * (1.0 / 182) * (1.0 - x * (1.0 / 240) * (1.0 - x * (1.0 / 306)))))))));
+        c = (1.0 / 6) * (1.0 - x * (1.0 / 20) * (1.0 - x * (1.0 / 42) * (1.0 - x * (1.0 / 72) * (1.0 - x * (1.0 / 110) *
+            (1.0 - x * (1.0 / 156) * (1.0 - x * (1.0 / 210) * (1.0 - x * (1.0 / 272) * (1.0 - x * (1.0 / 342)))))))));
     } else {
-        const double sn = sin(th), cs = cos(th);
+        const double th = sqrt(th2), sn = sin(th), cs = cos(th);
         a = sn / th;
         b = (1.0 - cs) / th2;
         c = (th - sn) / (th2 * th);
@@ -1444,35 +1529,56 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
 
 // ------------------------------------------------- register Gauss-Jordan
 
-constexpr int kGjThreads = 256;   // a 16 x 16 thread grid
+constexpr int kGjGrid = 16;                    // a 16 x 16 thread grid
+constexpr int kGjThreads = kGjGrid * kGjGrid;
 
-// One Gauss-Newton solve by Gauss-Jordan elimination without pivoting of the
-// augmented system [H_ff | -g_f] (symmetric positive definite: the pivots are
-// the Schur-complement pivots of the Cholesky factorisation, so the same
-// singularity test applies and no back substitution is needed).  The n x (n+1)
-// entries live in registers: thread (tr, tc) owns rows tr + 16a and columns
-// tc + 16b (a, b < T) for the whole elimination, so a step reads T row and
-// T column multipliers from LDS for T x T entries.  Step k updates every entry
-// (i != k, j > k) by v -= v(i,k) v(k,j) / v(k,k); the owners of column and row
-// k+1 publish them to double-buffered LDS vectors: one barrier per column, and
-// no branch inside a step (the pivots are checked once after the elimination;
-// a failed pivot only spoils values that are then discarded).  Then the update
-// T <- Exp(x) T and the transforms of the next iteration.
+// 3x3 inverse by cofactors (any invertible M, row-major); also the LU pivots
+// of M without pivoting (M00, the 2x2 Schur pivot, det / 2x2 minor)
+__device__ __forceinline__ void inv3_pivots(const double (&M)[9], double (&Mi)[9], double (&pv)[3])
+{
+    const double c00 = M[4] * M[8] - M[5] * M[7], c01 = M[2] * M[7] - M[1] * M[8], c02 = M[1] * M[5] - M[2] * M[4];
+    const double c10 = M[5] * M[6] - M[3] * M[8], c11 = M[0] * M[8] - M[2] * M[6], c12 = M[2] * M[3] - M[0] * M[5];
+    const double c20 = M[3] * M[7] - M[4] * M[6], c21 = M[1] * M[6] - M[0] * M[7], c22 = M[0] * M[4] - M[1] * M[3];
+    const double det = M[0] * c00 + M[1] * c10 + M[2] * c20;
+    const double id = 1.0 / det;
+    Mi[0] = c00 * id; Mi[1] = c01 * id; Mi[2] = c02 * id;
+    Mi[3] = c10 * id; Mi[4] = c11 * id; Mi[5] = c12 * id;
+    Mi[6] = c20 * id; Mi[7] = c21 * id; Mi[8] = c22 * id;
+    pv[0] = M[0];
+    pv[1] = c22 / M[0];
+    pv[2] = det / c22;
+}
+
+// One Gauss-Newton solve by block Gauss-Jordan elimination without pivoting
+// of the augmented system [H_ff | -g_f], with 3 x 3 pivot blocks (n = 6 x
+// free nodes is a multiple of 3).  H_ff is symmetric positive definite: the
+// LU pivots of each pivot block are the Schur-complement pivots of the
+// Cholesky factorisation, so the usual singularity test applies, and at the
+// end the right-hand column holds the solution (no back substitution).  The
+// n x (n+1) entries live in registers: thread (tr, tc) of a 16 x 16 grid owns
+// rows tr + 16a and columns tc + 16b (a, b < T).  Block step K: every thread
+// reads the 3 x 3 pivot block from the published row panel and inverts it
+// itself (cofactors: no communication), forms the normalised pivot rows
+// R = D^-1 RP for its own columns, and updates its entries: pivot rows take
+// R, other rows v -= v(i, block K) R.  The owners of the next block's three
+// columns and rows publish them to double-buffered LDS panels: one barrier per
+// block step.  Then the update T <- Exp(x) T and the next iteration's
+// transforms.
 template <int T>
 __global__ __launch_bounds__(kGjThreads) void gj_solve_kernel(const GraphDev* __restrict__ gds)
 {
     const GraphDev& gd = gds[blockIdx.x];
     const int N = gd.n_frames;
     const int n = 6 * gd.n_free, n6 = 6 * N;
-    __shared__ double colb[2][kGjMaxN + 2];
-    __shared__ double rowb[2][kGjMaxN + 2];
-    __shared__ double piv[kGjMaxN + 1], xs[kGjMaxN + 1];
+    __shared__ double CP[2][kGjMaxN][3];          // column panel: v(i, 3K + l)
+    __shared__ double RP[2][3][kGjMaxN + 2];      // row panel: v(3K + l, j)
+    __shared__ double xs[kGjMaxN + 1];
     __shared__ double Ts[16 * kMaxFrames];
     __shared__ double ns[kMaxFrames * kNodeStats];
     __shared__ double scratch[kGjThreads / 64];
     __shared__ int sfree[kMaxFrames];
     const int tid = threadIdx.x;
-    const int tr = tid >> 4, tc = tid & 15;
+    const int tr = tid / kGjGrid, tc = tid % kGjGrid;
     if (*gd.status)
         return;
     const int it = *gd.iters_done;
@@ -1498,97 +1604,130 @@ __global__ __launch_bounds__(kGjThreads) void gj_solve_kernel(const GraphDev* __
     int ri[T], cj[T];   // owned rows / columns, -1 beyond the matrix
 #pragma unroll
     for (int a = 0; a < T; ++a) {
-        ri[a] = (tr + 16 * a < n) ? tr + 16 * a : -1;
-        cj[a] = (tc + 16 * a <= n) ? tc + 16 * a : -1;
+        ri[a] = (tr + kGjGrid * a < n) ? tr + kGjGrid * a : -1;
+        cj[a] = (tc + kGjGrid * a <= n) ? tc + kGjGrid * a : -1;
     }
+    // every load at once: clamped (always valid) addresses, validity applied after
     double v[T][T];
     double md = 0.0;
 #pragma unroll
     for (int a = 0; a < T; ++a) {
-        const int i = ri[a];
-        const int r = (i >= 0) ? 6 * sfree[i / 6] + i % 6 : 0;
+        const int i = ri[a] < 0 ? 0 : ri[a];
+        const int r = 6 * sfree[i / 6] + i % 6;
+        const double gr = gd.grad[r];
 #pragma unroll
         for (int b = 0; b < T; ++b) {
-            const int j = cj[b];
-            double x = 0.0;
-            if (i >= 0 && j >= 0) {
-                x = (j < n) ? gd.Hm[(size_t)r * n6 + 6 * sfree[j / 6] + j % 6] : -gd.grad[r];
-                if (i == j)
-                    md = fmax(md, x);
-                if (j == 0)
-                    colb[0][i] = x;
-                if (i == 0)
-                    rowb[0][j] = x;
-                if (i == 0 && j == 0)
-                    piv[0] = x;
-            }
-            v[a][b] = x;
+            const int j = cj[b] < 0 ? 0 : (cj[b] < n ? cj[b] : 0);
+            const double h = gd.Hm[(size_t)r * n6 + 6 * sfree[j / 6] + j % 6];
+            v[a][b] = (cj[b] == n) ? -gr : h;
         }
     }
-    const double maxdiag = block_max(md, scratch);   // includes barriers
-    for (int k = 0; k < n; ++k) {
-        const int bf = k & 1;
-        const double pk = piv[k];
-        double f[T], r[T];
 #pragma unroll
-        for (int a = 0; a < T; ++a) {
-            f[a] = colb[bf][ri[a] < 0 ? 0 : ri[a]];
-            r[a] = rowb[bf][cj[a] < 0 ? 0 : cj[a]];
-        }
-        // reciprocal pivot: hardware estimate refined by one Newton step
-        double ik = __builtin_amdgcn_rcp(pk);
-        ik = ik * (2.0 - pk * ik);
-        // entries that must not change get a zero multiplier: the pivot row,
-        // rows beyond n, and columns j <= k (v - 0 * x == v exactly)
-#pragma unroll
-        for (int a = 0; a < T; ++a) {
-            f[a] = (ri[a] >= 0 && ri[a] != k) ? f[a] * ik : 0.0;
-            r[a] = (cj[a] > k) ? r[a] : 0.0;
-        }
+    for (int a = 0; a < T; ++a)
 #pragma unroll
         for (int b = 0; b < T; ++b) {
-            if (16 * b + 15 <= k)   // every column of this slot is finished (wave-uniform)
-                continue;
-#pragma unroll
-            for (int a = 0; a < T; ++a)
-                v[a][b] = fma(-f[a], r[b], v[a][b]);
+            const int i = ri[a], j = cj[b];
+            if (i < 0 || j < 0)
+                v[a][b] = 0.0;
+            if (i >= 0 && i == j)
+                md = fmax(md, v[a][b]);
+            if (i >= 0 && j >= 0 && j < 3)
+                CP[0][i][j] = v[a][b];
+            if (i >= 0 && i < 3 && j >= 0)
+                RP[0][i][j] = v[a][b];
         }
-        // column and row k+1 to the other buffer; pivot k+1
-        const int kn = k + 1, sb = kn >> 4, st = kn & 15;
+    const double maxdiag = block_max(md, scratch);   // includes barriers
+    const double tol = 1e-12 * maxdiag;
+    bool singular = !(maxdiag > 0.0);
+    for (int K = 0; 3 * K < n; ++K) {
+        const int bf = K & 1, c0 = 3 * K, c1 = c0 + 3;
+        // pivot block and its inverse (every thread, from the broadcast panel)
+        double D[9], Di[9], pv[3];
 #pragma unroll
-        for (int b = 0; b < T; ++b)
-            if (b == sb && tc == st)
+        for (int l = 0; l < 3; ++l)
 #pragma unroll
-                for (int a = 0; a < T; ++a)
-                    if (ri[a] >= 0)
-                        colb[bf ^ 1][ri[a]] = v[a][b];
+            for (int m = 0; m < 3; ++m)
+                D[3 * l + m] = RP[bf][l][c0 + m];
+        double Cm[T][3], Rp[3][T];
 #pragma unroll
         for (int a = 0; a < T; ++a)
-            if (a == sb && tr == st)
 #pragma unroll
-                for (int b = 0; b < T; ++b)
-                    if (cj[b] >= 0) {
-                        rowb[bf ^ 1][cj[b]] = v[a][b];
-                        if (b == sb && tc == st)
-                            piv[kn] = v[a][b];
-                    }
+            for (int l = 0; l < 3; ++l) {
+                Cm[a][l] = CP[bf][ri[a] < 0 ? 0 : ri[a]][l];
+                Rp[l][a] = RP[bf][l][cj[a] < 0 ? 0 : cj[a]];
+            }
+        inv3_pivots(D, Di, pv);
+        singular |= !(pv[0] > tol) || !(pv[1] > tol) || !(pv[2] > tol);
+        // normalised pivot rows for the owned columns
+        double R[3][T];
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int b = 0; b < T; ++b)
+                R[l][b] = fma(Di[3 * l], Rp[0][b], fma(Di[3 * l + 1], Rp[1][b], Di[3 * l + 2] * Rp[2][b]));
+        // Update.  Entries of rows beyond n and of eliminated columns are never
+        // read again (publishing takes live columns and rows only), so they
+        // are updated like the others instead of being masked; only the pivot
+        // rows, which can sit in two row slots at most, take R instead.
+        const int ap0 = c0 / kGjGrid, ap1 = (c0 + 2) / kGjGrid;   // uniform
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            if (kGjGrid * b + kGjGrid - 1 < c1)   // every column of this slot is eliminated (uniform)
+                continue;
+#pragma unroll
+            for (int a = 0; a < T; ++a) {
+                const double upd = fma(-Cm[a][0], R[0][b], fma(-Cm[a][1], R[1][b], fma(-Cm[a][2], R[2][b], v[a][b])));
+                if (a == ap0 || a == ap1) {   // uniform
+                    const int l = ri[a] - c0;
+                    const double piv_row = (l == 0) ? R[0][b] : (l == 1) ? R[1][b] : R[2][b];
+                    v[a][b] = (l >= 0 && l < 3) ? piv_row : upd;
+                } else {
+                    v[a][b] = upd;
+                }
+            }
+        }
+        // publish the next block's three columns and rows (their owners only)
+        if (c1 < n) {
+            const int b0 = c1 / kGjGrid, b1 = (c1 + 2) / kGjGrid;   // slots holding them (uniform)
+#pragma unroll
+            for (int b = 0; b < T; ++b) {
+                if (b != b0 && b != b1)
+                    continue;
+                const int jc = cj[b] - c1;   // column index within the next block
+                if (jc >= 0 && jc < 3) {
+#pragma unroll
+                    for (int a = 0; a < T; ++a)
+                        if (ri[a] >= 0)
+                            CP[bf ^ 1][ri[a]][jc] = v[a][b];
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < T; ++a) {
+                if (a != b0 && a != b1)
+                    continue;
+                const int ir = ri[a] - c1;   // row index within the next block
+                if (ir >= 0 && ir < 3) {
+#pragma unroll
+                    for (int b = 0; b < T; ++b)
+                        if (cj[b] >= 0)
+                            RP[bf ^ 1][ir][cj[b]] = v[a][b];
+                }
+            }
+        }
         __syncthreads();
     }
-    bool singular = !(maxdiag > 0.0);
-    for (int a = tid; a < n; a += kGjThreads)
-        singular |= !(piv[a] > 1e-12 * maxdiag);
     if (__syncthreads_or(singular)) {
         if (tid == 0)
             *gd.status |= kStatusSingular;
         return;
     }
-    // x_a = v(a, n) / pivot_a
+    // the right-hand column holds the solution
 #pragma unroll
     for (int a = 0; a < T; ++a)
 #pragma unroll
         for (int b = 0; b < T; ++b)
             if (ri[a] >= 0 && cj[b] == n)
-                xs[ri[a]] = v[a][b] / piv[ri[a]];
+                xs[ri[a]] = v[a][b];
     bool bad = false;
     __syncthreads();
     for (int a = tid; a < n; a += kGjThreads)
@@ -1716,17 +1855,18 @@ size_t solve_lds_bytes(int n_free, int n_frames)
 // tile side T of the Gauss-Jordan solve of n_free free nodes: 16T >= n + 1
 int gj_slots(int n_free)
 {
-    const int need = (6 * n_free + 1 + 15) / 16;
+    const int need = (6 * n_free + 1 + kGjGrid - 1) / kGjGrid;
     return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
 }
 
 void launch_gj_solve(const GraphDev* gds, int n_graphs, int tile, hipStream_t st)
 {
+    constexpr int kTopSlots = (kGjMaxN + 1 + kGjGrid - 1) / kGjGrid <= 4 ? 4 : 8;
     switch (tile) {
     case 1: gj_solve_kernel<1><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
     case 2: gj_solve_kernel<2><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
     case 4: gj_solve_kernel<4><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
-    default: gj_solve_kernel<8><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
+    default: gj_solve_kernel<kTopSlots><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
     }
 }
 

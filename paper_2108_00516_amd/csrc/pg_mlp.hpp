@@ -49,4 +49,108 @@ __device__ __forceinline__ float mlp_sigma(const float* __restrict__ P, const fl
     return 1.0f / (1.0f + expf(-mlp_logit(P, f)));
 }
 
+// ---------------------------------------------------------------------------
+// The network on the matrix cores, one wave = 64 samples (one per lane), as
+// the dense term evaluates it: inputs and first-layer activations in fp16,
+// products on v_mfma_f32_32x32x16_f16 with FP32 sums, the output layer in
+// FP32.  Both layers are computed transposed (hidden units as rows, samples
+// as columns), so the first layer's output registers are already the second
+// layer's B operand: a 32x32x16 product leaves row 8j + 4(lane/32) + i,
+// column lane%32 in c[4j + i], and the two K steps of the second layer take
+// c[0..7] and c[8..15] when the second layer's A operand (W2) has its hidden
+// index permuted to match (hid = 8(2s + t/4) + 4(lane/32) + t%4 for step s,
+// element t).  Samples 0..31 are lanes 0..31's own; samples 32..63 belong to
+// lanes 32..63 and reach the B operand of lanes 0..31 by a cross-half
+// exchange.  Every lane of the wave must call it (the products are
+// wave-wide).
+typedef _Float16 mlp_half8 __attribute__((ext_vector_type(8)));
+typedef float mlp_f32x16 __attribute__((ext_vector_type(16)));
+
+struct MlpFrags {
+    mlp_half8 w1;      // first-layer A operand: hidden lane%32, inputs 8(lane/32) + t (bias at input 6)
+    mlp_half8 w2[2];   // second-layer A operands of the two K steps
+};
+
+// b2 (32), w3 (32), b3: the output-layer constants a block keeps in LDS
+constexpr int kMlpTail = 65;
+
+__device__ __forceinline__ void mlp_tail_load(const float* __restrict__ P, float* __restrict__ tail)
+{
+    for (int q = threadIdx.x; q < kMlpTail; q += blockDim.x)
+        tail[q] = (q < 32) ? P[kMlpB2 + q] : (q < 64) ? P[kMlpW3 + q - 32] : P[kMlpB3];
+}
+
+__device__ __forceinline__ void mlp_frags_load(const float* __restrict__ P, MlpFrags& M, int lane)
+{
+    const int r = lane & 31, g = lane >> 5;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        float w = 0.0f;
+        if (g == 0)
+            w = (t < kMlpIn) ? P[kMlpW1 + kMlpIn * r + t] : (t == kMlpIn) ? P[kMlpB1 + r] : 0.0f;
+        M.w1[t] = (_Float16)w;
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int hid = 8 * (2 * s + t / 4) + 4 * g + (t % 4);
+            M.w2[s][t] = (_Float16)P[kMlpW2 + kMlpHid * r + hid];
+        }
+}
+
+__device__ __forceinline__ float mlp_sigma_wave(const MlpFrags& M, const float* __restrict__ tail,
+                                                const float (&f)[kMlpIn], int lane)
+{
+    const int g = lane >> 5;
+    float fo[kMlpIn];
+#pragma unroll
+    for (int k = 0; k < kMlpIn; ++k)
+        fo[k] = __shfl_xor(f[k], 32);
+    mlp_half8 x0, x1;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const float a = (t < kMlpIn) ? f[t < kMlpIn ? t : 0] : (t == kMlpIn) ? 1.0f : 0.0f;
+        const float b = (t < kMlpIn) ? fo[t < kMlpIn ? t : 0] : (t == kMlpIn) ? 1.0f : 0.0f;
+        x0[t] = (_Float16)(g == 0 ? a : 0.0f);
+        x1[t] = (_Float16)(g == 0 ? b : 0.0f);
+    }
+    mlp_f32x16 zero;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        zero[q] = 0.0f;
+    const mlp_f32x16 c0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(M.w1, x0, zero, 0, 0, 0);
+    const mlp_f32x16 c1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(M.w1, x1, zero, 0, 0, 0);
+    mlp_f32x16 d0 = zero, d1 = zero;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        mlp_half8 h0, h1;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            h0[t] = (_Float16)fmaxf(c0[8 * s + t], 0.0f);
+            h1[t] = (_Float16)fmaxf(c1[8 * s + t], 0.0f);
+        }
+        d0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(M.w2[s], h0, d0, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f32_32x32x16_f16(M.w2[s], h1, d1, 0, 0, 0);
+    }
+    float p0 = 0.0f, p1 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float4 b2 = reinterpret_cast<const float4*>(tail)[2 * j + g];
+        const float4 w3 = reinterpret_cast<const float4*>(tail + 32)[2 * j + g];
+        p0 = fmaf(w3.x, fmaxf(d0[4 * j + 0] + b2.x, 0.0f), p0);
+        p0 = fmaf(w3.y, fmaxf(d0[4 * j + 1] + b2.y, 0.0f), p0);
+        p0 = fmaf(w3.z, fmaxf(d0[4 * j + 2] + b2.z, 0.0f), p0);
+        p0 = fmaf(w3.w, fmaxf(d0[4 * j + 3] + b2.w, 0.0f), p0);
+        p1 = fmaf(w3.x, fmaxf(d1[4 * j + 0] + b2.x, 0.0f), p1);
+        p1 = fmaf(w3.y, fmaxf(d1[4 * j + 1] + b2.y, 0.0f), p1);
+        p1 = fmaf(w3.z, fmaxf(d1[4 * j + 2] + b2.z, 0.0f), p1);
+        p1 = fmaf(w3.w, fmaxf(d1[4 * j + 3] + b2.w, 0.0f), p1);
+    }
+    p0 += __shfl_xor(p0, 32);
+    p1 += __shfl_xor(p1, 32);
+    const float z = (g == 0 ? p0 : p1) + tail[64];
+    return 1.0f / (1.0f + expf(-z));
+}
+
 }  // namespace pg

@@ -253,6 +253,13 @@ class PoseGraph:
                                                       C.c_void_p(t.ctypes.data)))
         return f, sg, t
 
+    def time_assoc(self, reps: int = 100) -> float:
+        """Milliseconds per association launch (reps back-to-back launches
+        between HIP events on the graph's stream)."""
+        ms = C.c_double()
+        self._check(self.lib.pose_graph_time_assoc(self.h, int(reps), C.byref(ms)))
+        return ms.value
+
     def prune(self):
         """Pruning pass at the current poses: (score (N, H*W), keep (N, H*W))."""
         n = self.n_frames * self.camera.width * self.camera.height

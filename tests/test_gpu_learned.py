@@ -167,8 +167,20 @@ def test_pair_features_and_weights_match_oracle():
         # r / huber and |s - p| / gate carry FP32 rounding of millimetre
         # differences; the others are O(1e-6)
         assert np.all(df.max(axis=0) <= np.array([2e-4, 2e-5, 1e-6, 1e-6, 2e-4, 0.0]))
-        so = oracle.mlp_forward(p16.astype(np.float64), fo[same])
-        assert np.abs(sg[same] - so).max() <= 5e-5
+        # the association evaluates the network with fp16 inputs and first
+        # activations (matrix cores); the oracle rounds the same values.  On
+        # the GPU's own features the outputs agree to FP32 summation error,
+        # except where a first-layer activation sits on a binary16 rounding
+        # boundary (one fp16 ulp moves sigma by < 1e-3); on the oracle's
+        # features (within 2e-4 of the GPU's), an input itself may round to
+        # the neighbouring binary16 value
+        net = p16.astype(np.float64)
+        d = np.abs(sg[same] - oracle.mlp_forward_half(net, f[same].astype(np.float64)))
+        say(f"  sigma on the GPU features: {100 * np.mean(d <= 2e-6):.3f}% within 2e-6, max {d.max():.2e}")
+        assert np.mean(d <= 2e-6) >= 0.999 and d.max() <= 2e-3
+        d = np.abs(sg[same] - oracle.mlp_forward_half(net, fo[same]))
+        say(f"  sigma on the oracle features: {100 * np.mean(d <= 2e-5):.3f}% within 2e-5, max {d.max():.2e}")
+        assert np.mean(d <= 2e-5) >= 0.95 and d.max() <= 2e-3
         assert np.all(f[t < 0] == 0) and np.all(sg[t < 0] == 0)
     pg.close()
 

@@ -134,7 +134,7 @@ def test_prune_scores_and_selection_brute_force(oracle_lib):
             tgt, f = pb.pair_features(g.poses_init, i, j, iteration=0)
             sel = tgt >= 0
             y = np.zeros(len(tgt))
-            y[sel] = oracle.mlp_forward(net, f[sel])
+            y[sel] = oracle.mlp_forward_half(net, f[sel])
             best = np.where(sel, np.maximum(best, y), best)
         assert np.allclose(sc[i].ravel(), best, rtol=0, atol=1e-15)
     keep = pb.prune_select(sc, 0.25)
@@ -161,3 +161,52 @@ def test_pruned_optimize_equals_explicit_keep(oracle_lib):
     Pb, sb = b.optimize(g.poses_init, 5)
     assert np.array_equal(Pa, Pb)
     assert sa["n_valid_g"][0] < oracle.OracleProblem.from_synth(g).linearize(g.poses_init)["n_valid_g"]
+
+
+def test_round_half_matches_numpy_binary16(oracle_lib):
+    """Pinned to numpy's float64 -> float16 conversion (nearest, ties to even),
+    over normal, subnormal, tie and overflow values."""
+    rng = np.random.default_rng(11)
+    xs = np.concatenate([rng.normal(scale=s, size=2000) for s in (1e-6, 1e-3, 1.0, 1e3, 3e4)])
+    # exact ties between neighbouring binary16 values, and the extremes
+    h = rng.normal(size=500).astype(np.float16).astype(np.float64)
+    ties = h + np.spacing(h.astype(np.float16)).astype(np.float64) / 2
+    xs = np.concatenate([xs, ties, [0.0, -0.0, 65504.0, 65519.0, 65520.0, -70000.0, 2.0 ** -24, 2.0 ** -25,
+                                    3 * 2.0 ** -26, 6.0e-8]])
+    got = np.array([oracle.round_half(x) for x in xs])
+    want = xs.astype(np.float16).astype(np.float64)
+    assert np.array_equal(got, want)
+
+
+def test_half_network_matches_exact_network_on_binary16_values(oracle_lib):
+    """With inputs, weights and every first-layer activation exactly
+    representable in binary16, the FP16 evaluation equals the exact one."""
+    rng = np.random.default_rng(12)
+    p = np.zeros(oracle.MLP_PARAMS)
+    # small dyadic weights and inputs: products and sums of a few terms stay
+    # within binary16's 11 significant bits
+    p[0:192] = rng.integers(-4, 5, 192) / 8.0
+    p[192:224] = rng.integers(-4, 5, 32) / 8.0
+    p[224:1248] = rng.normal(size=1024)
+    p[1280:1313] = rng.normal(size=33)
+    x = rng.integers(-8, 9, size=(300, 6)) / 4.0
+    assert np.array_equal(oracle.mlp_forward_half(p, x), oracle.mlp_forward(p, x))
+
+
+def test_half_network_rounds_inputs_and_first_activations(oracle_lib):
+    """A one-path network y = sigmoid(w3 relu(w2 relu(w1 x0))) : the FP16
+    evaluation equals the exact network applied to x0 rounded to binary16 and
+    the first activation rounded to binary16."""
+    p = np.zeros(oracle.MLP_PARAMS)
+    w1, w2, w3 = 1.0 / 3.0, 0.7, 1.3
+    p[0] = w1            # W1[0][0]
+    p[224] = w2          # W2[0][0]
+    p[1280] = w3         # W3[0]
+    for x0 in (0.1, 1.2345, 3.14159, 7.3):
+        x = np.zeros((1, 6))
+        x[0, 0] = x0
+        xh = float(np.float16(x0))
+        h1 = float(np.float16(w1 * xh))
+        want = 1.0 / (1.0 + np.exp(-(w3 * (w2 * h1))))
+        assert oracle.mlp_forward_half(p, x)[0] == pytest.approx(want, rel=1e-15)
+        assert oracle.mlp_forward_half(p, x)[0] != oracle.mlp_forward(p, x)[0]
