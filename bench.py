@@ -78,7 +78,7 @@ def cpu_baseline(g, iters, seconds, P_gpu):
     worst_r = max(oracle.pose_error(P_gpu[k], P[k])[0] for k in range(g.n_frames))
     worst_t = max(oracle.pose_error(P_gpu[k], P[k])[1] for k in range(g.n_frames))
     return dict(value=iters * reps / el, unit="GN iters/s", cores=threads, kind="oracle",
-                sample=f"{reps} full optimisations of the same 10-keyframe 640x480 window "
+                sample=f"{reps} full optimisations of the same {g.n_frames}-keyframe {g.width}x{g.height} window "
                        f"({iters} GN iterations each), {el:.1f} s, {threads} threads, {cpu_model()}"), \
         (worst_r, worst_t)
 
@@ -97,6 +97,8 @@ def main():
                     help="paper: the 10-keyframe 640x480 window (the headline); batch: 64 uneven windows "
                          "(4-20 keyframes, 320x240 / 480x360 / 640x480) in one batched schedule")
     ap.add_argument("--graphs", type=int, default=64, help="windows in the batched workload")
+    ap.add_argument("--window", choices=["P", "X"], default="P",
+                    help="paper workload window: P = 10 keyframes 640x480 (the headline), X = 20 keyframes 640x480")
     ap.add_argument("--tile", type=int, default=0, help="association tile (pixels); 0 = library choice")
     ap.add_argument("--autotune", metavar="JSON", default="",
                     help="time every association tile for the workload, write the table to JSON and exit")
@@ -136,7 +138,7 @@ def main():
     if args.workload == "batch":
         return run_batch(args, graphs)
     iters = 7
-    g = synth.make_graph("P")
+    g = synth.make_graph(args.window)
     if args.autotune:
         from paper_2108_00516_amd import autotune
 
@@ -206,8 +208,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "10 keyframes, 640x480 depth, 90 ordered pairs, 45 x 200 feature matches "
-                               "(20% outliers), 7 Gauss-Newton iterations per step",
+        "config": {"workload": f"{g.n_frames} keyframes, {g.width}x{g.height} depth, "
+                               f"{g.n_frames * (g.n_frames - 1)} ordered pairs, {len(g.matches)} x 200 feature "
+                               "matches (20% outliers), 7 Gauss-Newton iterations per step",
                    "keyframes": g.n_frames, "width": g.width, "height": g.height, "gn_iters": iters,
                    "valid_source_pixels_per_frame": [pg.frame_info(f, with_map=False)[1]
                                                      for f in range(g.n_frames)],

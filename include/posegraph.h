@@ -135,6 +135,9 @@ pg_status pose_graph_add_matches(pg_graph *g, int id_i, int id_j, const float *u
 pg_status pose_graph_set_pose(pg_graph *g, int id, const double T[16]);
 pg_status pose_graph_get_pose(const pg_graph *g, int id, double T_out[16]);
 
+/* Set all n = pose_graph_num_frames(g) poses at once (16 n doubles, host). */
+pg_status pose_graph_set_poses(pg_graph *g, int n, const double *T);
+
 /* Run cfg.gn_iters iterations: per iteration, dense association and
  * residuals of every ordered pair, feature residuals, the fused reduction into
  * the 6N x 6N normal equations (J^T W J) delta = -J^T W r, the solve over the

@@ -64,6 +64,7 @@ SIGNATURES = {
     "pose_graph_add_matches": (C.c_int, [_vp, C.c_int, C.c_int, _vp, _vp, C.c_int]),
     "pose_graph_set_pose": (C.c_int, [_vp, C.c_int, _dp]),
     "pose_graph_get_pose": (C.c_int, [_vp, C.c_int, _dp]),
+    "pose_graph_set_poses": (C.c_int, [_vp, C.c_int, _dp]),
     "pose_graph_optimize": (C.c_int, [_vp, C.POINTER(pg_stats)]),
     "pose_graph_optimize_batch": (C.c_int, [C.POINTER(_vp), C.c_int, C.POINTER(pg_stats)]),
     "pose_graph_linearize": (C.c_int, [_vp, _dp, _dp, C.POINTER(pg_stats)]),

@@ -92,13 +92,8 @@ struct Schedule {
     int gj_slots = 1;
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> events;   // timing: start, then 5 per iteration
-    hipEvent_t fork = nullptr, join = nullptr;   // feature branch of the captured graph
     ~Schedule()
     {
-        if (fork)
-            (void)hipEventDestroy(fork);
-        if (join)
-            (void)hipEventDestroy(join);
         if (exec)
             (void)hipGraphExecDestroy(exec);
         for (hipEvent_t e : events)
@@ -113,7 +108,6 @@ struct pg_graph {
     pg_camera cam;
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
-    hipStream_t side_stream = nullptr;    // forked branch during capture
     int device = 0;
     int HW = 0;
     std::string err;
@@ -129,8 +123,17 @@ struct pg_graph {
     std::map<std::pair<int, int>, MatchSetHost> msets;
 
     // per-optimize device state
-    DevBuf d_poses, d_partials, d_fpartials, d_fpts, d_fsets, d_set_of, d_xf32, d_xf64, d_H, d_grad,
-        d_node_stats, d_free_ids, d_status, d_iters, d_iter_stats, d_n_src, d_pair_base, d_mlp;
+    DevBuf d_partials, d_fpartials, d_fpts, d_fsets, d_set_of, d_xf32, d_xf64, d_H, d_grad, d_node_stats,
+        d_free_ids, d_n_src, d_pair_base, d_mlp;
+    // results of an optimize, one block read back with one copy (same layout
+    // as the pinned host mirror): status, iterations done, per-iteration
+    // records (kMaxIters), poses (max_frames)
+    DevBuf d_result;
+    int* dev_status() const { return d_result.as<int>(); }
+    int* dev_iters() const { return d_result.as<int>() + 1; }
+    double* dev_iter_stats() const { return reinterpret_cast<double*>(d_result.as<int>() + 2); }
+    double* dev_poses() const { return dev_iter_stats() + kIterRecord * kMaxIters; }
+    size_t result_bytes() const { return sizeof(int) * 2 + sizeof(double) * (kIterRecord * kMaxIters + 16 * n_frames); }
     // learned weighting: FP32 parameters, pruned source lists, scores, drop counts
     DevBuf d_mlp32, d_psrc_nz, d_psrc_uv, d_score, d_n_drop;
     bool poses_dirty = true;          // host mirror newer than d_poses
@@ -153,6 +156,8 @@ struct pg_graph {
     int* h_iters = nullptr;
     double* h_iter_stats = nullptr;
     double* h_poses = nullptr;
+    double* h_up = nullptr;           // pinned staging of pose uploads
+    hipEvent_t up_done = nullptr;     // the last upload from h_up has completed
 };
 
 namespace {
@@ -415,14 +420,14 @@ GraphDev make_dev(pg_graph* g)
     d.set_of = g->d_set_of.as<int>();
     d.xf32 = g->d_xf32.as<float>();
     d.xf64 = g->d_xf64.as<double>();
-    d.poses = g->d_poses.as<double>();
+    d.poses = g->dev_poses();
     d.Hm = g->d_H.as<double>();
     d.grad = g->d_grad.as<double>();
     d.node_stats = g->d_node_stats.as<double>();
     d.free_ids = g->d_free_ids.as<int>();
-    d.status = g->d_status.as<int>();
-    d.iters_done = g->d_iters.as<int>();
-    d.iter_stats = g->d_iter_stats.as<double>();
+    d.status = g->dev_status();
+    d.iters_done = g->dev_iters();
+    d.iter_stats = g->dev_iter_stats();
     d.mlp = g->d_mlp.as<__half>();
     d.mlp32 = g->has_mlp ? g->d_mlp32.as<float>() : nullptr;
     d.gate_dist = (float)g->cfg.gate_dist_m;
@@ -441,9 +446,14 @@ pg_status upload_poses(pg_graph* g)
 {
     if (!g->poses_dirty)
         return PG_OK;
-    HIP_OR_FAIL(g, hipMemcpyAsync(g->d_poses.p, g->poses.data(), sizeof(double) * 16 * g->n_frames,
+    // staged through pinned memory: the copy is truly asynchronous, ordered
+    // before the work that follows on the stream; the staging buffer is
+    // reused only once the previous upload from it has completed
+    HIP_OR_FAIL(g, hipEventSynchronize(g->up_done));
+    memcpy(g->h_up, g->poses.data(), sizeof(double) * 16 * g->n_frames);
+    HIP_OR_FAIL(g, hipMemcpyAsync(g->dev_poses(), g->h_up, sizeof(double) * 16 * g->n_frames,
                                   hipMemcpyHostToDevice, g->stream));
-    HIP_OR_FAIL(g, hipStreamSynchronize(g->stream));
+    HIP_OR_FAIL(g, hipEventRecord(g->up_done, g->stream));
     g->poses_dirty = false;
     return PG_OK;
 }
@@ -552,12 +562,12 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
     return PG_OK;
 }
 
-// Enqueue the whole optimisation: prepare, then per iteration the four phases.
-// With events (1 + 5 per iteration), each launch is bracketed on the stream.
-// With a side stream (graph capture), the feature kernel, which does not
-// depend on the association, runs on a forked branch beside it.
-hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std::vector<hipEvent_t>* ev,
-                         hipStream_t side = nullptr)
+// Enqueue the whole optimisation: prepare (and the pruning pass of the
+// learned weighting), then per iteration the four phases on one stream.  The
+// feature term runs first: it is independent of the association, and as a
+// forked graph branch its fork and join cost more than it does.  With events
+// (1 + 5 per iteration), each launch is bracketed on the stream.
+hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std::vector<hipEvent_t>* ev)
 {
     const GraphDev* gds = s.gds.as<GraphDev>();
     const int ng = (int)s.graphs.size();
@@ -565,29 +575,15 @@ hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std
     if (ev && (e = hipEventRecord((*ev)[0], st)) != hipSuccess)
         return e;
     launch_solve(gds, ng, s.lds, 1, st);
-    // learned weighting: score and prune the source pixels at the starting poses
     launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, st);
-    const bool fork = side && s.n_fitems > 0;
     for (int it = 0; it < iters; ++it) {
         const hipEvent_t* m = ev ? ev->data() + 1 + 5 * it : nullptr;
-        if (fork) {
-            if ((e = hipEventRecord(s.fork, st)) != hipSuccess || (e = hipStreamWaitEvent(side, s.fork, 0)) != hipSuccess)
-                return e;
-            launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, side);
-            if ((e = hipEventRecord(s.join, side)) != hipSuccess)
-                return e;
-        }
         if (m && (e = hipEventRecord(m[0], st)) != hipSuccess)
             return e;
-        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, it, st);
+        launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
         if (m && (e = hipEventRecord(m[1], st)) != hipSuccess)
             return e;
-        if (fork) {
-            if ((e = hipStreamWaitEvent(st, s.join, 0)) != hipSuccess)
-                return e;
-        } else {
-            launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
-        }
+        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, it, st);
         if (m && (e = hipEventRecord(m[2], st)) != hipSuccess)
             return e;
         launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
@@ -630,10 +626,7 @@ pg_status run_schedule(Schedule& s, int iters, bool use_graph, bool timing, std:
             }
             hipStream_t cs = g0->capture_stream;
             HIP_OR_FAIL(g0, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            if (!s.fork && (hipEventCreateWithFlags(&s.fork, hipEventDisableTiming) != hipSuccess ||
-                            hipEventCreateWithFlags(&s.join, hipEventDisableTiming) != hipSuccess))
-                return fail(g0, PG_ERR_HIP, "event creation failed");
-            hipError_t ce = enqueue_iters(s, iters, cs, nullptr, g0->side_stream);
+            hipError_t ce = enqueue_iters(s, iters, cs, nullptr);
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamEndCapture(cs, &graph);
             if (ce != hipSuccess || e != hipSuccess) {
@@ -656,22 +649,18 @@ pg_status run_schedule(Schedule& s, int iters, bool use_graph, bool timing, std:
     }
     // read back poses and statistics of every graph
     for (pg_graph* g : s.graphs) {
-        HIP_OR_FAIL(g0, hipMemcpyAsync(g->h_poses, g->d_poses.p, sizeof(double) * 16 * g->n_frames,
-                                       hipMemcpyDeviceToHost, st));
-        HIP_OR_FAIL(g0, hipMemcpyAsync(g->h_status, g->d_status.p, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIP_OR_FAIL(g0, hipMemcpyAsync(g->h_iters, g->d_iters.p, sizeof(int), hipMemcpyDeviceToHost, st));
-        HIP_OR_FAIL(g0, hipMemcpyAsync(g->h_iter_stats, g->d_iter_stats.p, sizeof(double) * kIterRecord * iters,
-                                       hipMemcpyDeviceToHost, st));
+        HIP_OR_FAIL(g0, hipMemcpyAsync(g->h_status, g->d_result.p, g->result_bytes(), hipMemcpyDeviceToHost, st));
     }
     HIP_OR_FAIL(g0, hipStreamSynchronize(st));
-    float ms[5] = {0, 0, 0, 0, 0};
+    float ms[5] = {0, 0, 0, 0, 0};   // assoc, feature, assemble, solve, total
     int n_assoc = 0;
     if (timing) {
+        const int slot[4] = {1, 0, 2, 3};   // event intervals: feature, assoc, assemble, solve
         for (int it = 0; it < iters; ++it)
             for (int k = 0; k < 4; ++k) {
                 float t = 0.f;
                 HIP_OR_FAIL(g0, hipEventElapsedTime(&t, s.events[1 + 5 * it + k], s.events[2 + 5 * it + k]));
-                ms[k] += t;
+                ms[slot[k]] += t;
             }
         HIP_OR_FAIL(g0, hipEventElapsedTime(&ms[4], s.events[0], s.events[5 * iters]));
         n_assoc = s.n_items > 0 ? iters : 0;
@@ -814,11 +803,10 @@ pg_status pose_graph_create(const pg_config* cfg, const pg_camera* cam, void* hi
         (e = g->src_uv.ensure(sizeof(uint32_t) * M * HW)) != hipSuccess || (e = g->flag.ensure(HW)) != hipSuccess ||
         (e = g->rowcnt.ensure(sizeof(int) * cam->height)) != hipSuccess ||
         (e = g->total.ensure(sizeof(int))) != hipSuccess ||
-        (e = g->d_poses.ensure(sizeof(double) * 16 * M)) != hipSuccess ||
-        (e = g->d_status.ensure(sizeof(int))) != hipSuccess || (e = g->d_iters.ensure(sizeof(int))) != hipSuccess ||
-        (e = g->d_iter_stats.ensure(sizeof(double) * kIterRecord * kMaxIters)) != hipSuccess ||
+        (e = g->d_result.ensure(sizeof(int) * 2 + sizeof(double) * (kIterRecord * kMaxIters + 16 * M))) !=
+            hipSuccess ||
         (e = g->d_mlp.ensure(2 * 1320)) != hipSuccess ||
-        (e = hipHostMalloc((void**)&g->h_status, sizeof(int) * 2 + sizeof(double) * (kIterRecord * kMaxIters + 16 * M))) !=
+        (e = hipHostMalloc((void**)&g->h_status, sizeof(int) * 2 + sizeof(double) * (kIterRecord * kMaxIters + 32 * M))) !=
             hipSuccess) {
         pose_graph_destroy(g);
         return fail(nullptr, e == hipErrorOutOfMemory ? PG_ERR_OUT_OF_MEMORY : PG_ERR_HIP, "allocation: %s",
@@ -827,13 +815,13 @@ pg_status pose_graph_create(const pg_config* cfg, const pg_camera* cam, void* hi
     g->h_iters = g->h_status + 1;
     g->h_iter_stats = (double*)(g->h_status + 2);
     g->h_poses = g->h_iter_stats + kIterRecord * kMaxIters;
+    g->h_up = g->h_poses + 16 * M;
     if ((e = hipStreamCreateWithFlags(&g->capture_stream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&g->side_stream, hipStreamNonBlocking)) != hipSuccess) {
+        (e = hipEventCreateWithFlags(&g->up_done, hipEventDisableTiming)) != hipSuccess) {
         pose_graph_destroy(g);
         return fail(nullptr, PG_ERR_HIP, "stream: %s", hipGetErrorString(e));
     }
-    if ((e = hipMemsetAsync(g->d_status.p, 0, sizeof(int), g->stream)) != hipSuccess ||
-        (e = hipMemsetAsync(g->d_iters.p, 0, sizeof(int), g->stream)) != hipSuccess ||
+    if ((e = hipMemsetAsync(g->d_result.p, 0, sizeof(int) * 2, g->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(g->stream)) != hipSuccess) {
         pose_graph_destroy(g);
         return fail(nullptr, PG_ERR_HIP, "init: %s", hipGetErrorString(e));
@@ -925,6 +913,20 @@ pg_status pose_graph_set_pose(pg_graph* g, int id, const double T[16])
     if (!finite_pose(T))
         return fail(g, PG_ERR_INVALID_ARG, "pose is not a rigid transform");
     memcpy(g->poses.data() + 16 * id, T, sizeof(double) * 16);
+    g->poses_dirty = true;
+    return PG_OK;
+}
+
+pg_status pose_graph_set_poses(pg_graph* g, int n, const double* T)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (n != g->n_frames || !T)
+        return fail(g, PG_ERR_INVALID_ARG, "expected %d poses", g->n_frames);
+    for (int k = 0; k < n; ++k)
+        if (!finite_pose(T + 16 * k))
+            return fail(g, PG_ERR_INVALID_ARG, "pose %d is not a rigid transform", k);
+    memcpy(g->poses.data(), T, sizeof(double) * 16 * n);
     g->poses_dirty = true;
     return PG_OK;
 }
@@ -1300,8 +1302,8 @@ void pose_graph_destroy(pg_graph* g)
     g->sched.reset();
     if (g->capture_stream)
         (void)hipStreamDestroy(g->capture_stream);
-    if (g->side_stream)
-        (void)hipStreamDestroy(g->side_stream);
+    if (g->up_done)
+        (void)hipEventDestroy(g->up_done);
     if (g->h_status)
         (void)hipHostFree(g->h_status);
     delete g;

@@ -737,6 +737,33 @@ __device__ __forceinline__ int block_excl_scan(bool flag, int* wave_cnt, int& to
     return off + pre;
 }
 
+// Exclusive prefix sum of v over the block (1024 threads) and the block total.
+__device__ __forceinline__ int block_excl_scan_int(int v, int* wave_sums, int& total)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(incl, d, 64);
+        if (lane >= d)
+            incl += o;
+    }
+    if (lane == 63)
+        wave_sums[wv] = incl;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        const int c = wave_sums[w];
+        off += (w < wv) ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return off + incl - v;
+}
+
+constexpr int kSelectPer = 8;   // consecutive entries per thread in the compaction
+
 // Per frame (one block of 1024 threads): drop the n_drop source pixels of
 // lowest score, ties by position in the row-major source list, and compact the
 // kept ones in order into the pruned lists.  The n_drop-th smallest key is
@@ -816,22 +843,40 @@ __global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const Grap
         need = rank + 1;
     }
     // ordered compaction: entry k is kept unless key < tau, or key == tau and
-    // it is among the first 'need' entries equal to tau
+    // it is among the first 'need' entries equal to tau.  Chunks of
+    // kSelectThreads x kSelectPer entries, each thread a contiguous run of
+    // kSelectPer; block scans of the per-thread counts keep the order.
     int out = 0, eq_seen = 0;
-    for (int k0 = 0; k0 < V; k0 += kSelectThreads) {
-        const int k = k0 + tid;
-        const bool live = k < V;
-        const unsigned int kk = live ? key[k] : 0u;
-        const bool eq = live && drop > 0 && kk == tau;
-        int eq_tot;
-        const int eq_rank = eq_seen + block_excl_scan(eq, wave_cnt, eq_tot);
-        const bool keep = live && (drop == 0 || kk > tau || (eq && eq_rank >= need));
-        int keep_tot;
-        const int pos = out + block_excl_scan(keep, wave_cnt, keep_tot);
-        if (keep) {
-            gd.psrc_nz[base + pos] = gd.src_nz[base + k];
-            gd.psrc_uv[base + pos] = gd.src_uv[base + k];
+    for (int k0 = 0; k0 < V; k0 += kSelectThreads * kSelectPer) {
+        const int kb = k0 + tid * kSelectPer;
+        unsigned int kk[kSelectPer];
+        int n_eq = 0;
+#pragma unroll
+        for (int q = 0; q < kSelectPer; ++q) {
+            kk[q] = (kb + q < V) ? key[kb + q] : 0u;
+            n_eq += (kb + q < V && drop > 0 && kk[q] == tau) ? 1 : 0;
         }
+        int eq_tot;
+        int eq_rank = eq_seen + block_excl_scan_int(n_eq, wave_cnt, eq_tot);
+        bool keep[kSelectPer];
+        int n_keep = 0;
+#pragma unroll
+        for (int q = 0; q < kSelectPer; ++q) {
+            const bool live = kb + q < V;
+            const bool eq = live && drop > 0 && kk[q] == tau;
+            keep[q] = live && (drop == 0 || kk[q] > tau || (eq && eq_rank >= need));
+            eq_rank += eq ? 1 : 0;
+            n_keep += keep[q] ? 1 : 0;
+        }
+        int keep_tot;
+        int pos = out + block_excl_scan_int(n_keep, wave_cnt, keep_tot);
+#pragma unroll
+        for (int q = 0; q < kSelectPer; ++q)
+            if (keep[q]) {
+                gd.psrc_nz[base + pos] = gd.src_nz[base + kb + q];
+                gd.psrc_uv[base + pos] = gd.src_uv[base + kb + q];
+                ++pos;
+            }
         out += keep_tot;
         eq_seen += eq_tot;
     }

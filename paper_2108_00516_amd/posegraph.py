@@ -185,8 +185,10 @@ class PoseGraph:
         return np.stack([self.get_pose(i) for i in range(self.n_frames)]) if self.n_frames else np.zeros((0, 4, 4))
 
     def set_poses(self, P):
-        for i, T in enumerate(np.asarray(P)):
-            self.set_pose(i, T)
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        if P.shape != (self.n_frames, 4, 4):
+            raise ValueError(f"expected ({self.n_frames}, 4, 4) poses")
+        self._check(self.lib.pose_graph_set_poses(self.h, self.n_frames, P.ctypes.data_as(C.POINTER(C.c_double))))
 
     def optimize(self, check: bool = True) -> dict:
         s = L.pg_stats()
