@@ -97,6 +97,8 @@ def main():
                     help="paper: the 10-keyframe 640x480 window (the headline); batch: 64 uneven windows "
                          "(4-20 keyframes, 320x240 / 480x360 / 640x480) in one batched schedule")
     ap.add_argument("--graphs", type=int, default=64, help="windows in the batched workload")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="CPU processes building the batched workload's scenes (0 or 1: in this process)")
     ap.add_argument("--window", choices=["P", "X"], default="P",
                     help="paper workload window: P = 10 keyframes 640x480 (the headline), X = 20 keyframes 640x480")
     ap.add_argument("--tile", type=int, default=0, help="association tile (pixels); 0 = library choice")
@@ -128,10 +130,16 @@ def main():
 
     graphs = None
     if args.workload == "batch":
-        # scene generation in forked CPU workers, before this process touches the GPU
-        import multiprocessing as mp
-        with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        # scene generation in forked CPU workers, before this process touches
+        # the GPU; the workers finish and exit on their own (close + join)
+        if args.gen_workers > 1:
+            import multiprocessing as mp
+            pool = mp.get_context("fork").Pool(min(args.gen_workers, os.cpu_count() or 1))
             graphs = pool.map(_make_batch_graph, range(args.graphs))
+            pool.close()
+            pool.join()
+        else:
+            graphs = [_make_batch_graph(k) for k in range(args.graphs)]
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     torch.zeros(1, device="cuda")
