@@ -77,9 +77,17 @@ def cpu_baseline(g, iters, seconds, P_gpu):
             break
     worst_r = max(oracle.pose_error(P_gpu[k], P[k])[0] for k in range(g.n_frames))
     worst_t = max(oracle.pose_error(P_gpu[k], P[k])[1] for k in range(g.n_frames))
+    # one optimisation on one thread, for the per-core figure
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    pb.optimize(g.poses_init, iters)
+    el1 = time.perf_counter() - t1
+    oracle.set_threads(threads)
     return dict(value=iters * reps / el, unit="GN iters/s", cores=threads, kind="oracle",
                 sample=f"{reps} full optimisations of the same {g.n_frames}-keyframe {g.width}x{g.height} window "
-                       f"({iters} GN iterations each), {el:.1f} s, {threads} threads, {cpu_model()}"), \
+                       f"({iters} GN iterations each), {el:.1f} s, {threads} threads, {cpu_model()}",
+                one_thread={"value": iters / el1, "unit": "GN iters/s", "cores": 1,
+                            "sample": f"1 optimisation ({iters} GN iterations), {el1:.1f} s"}), \
         (worst_r, worst_t)
 
 
@@ -104,6 +112,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="association tile (pixels); 0 = library choice")
     ap.add_argument("--autotune", metavar="JSON", default="",
                     help="time every association tile for the workload, write the table to JSON and exit")
+    ap.add_argument("--tune-table", default="", metavar="JSON",
+                    help="autotuner table to take the association tile from (batched workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (to scale HBM counters)")
     args = ap.parse_args()
@@ -324,9 +334,14 @@ def run_batch(args, graphs):
     from paper_2108_00516_amd import Config, from_synth, optimize_batch
     iters = 7
 
+    tile = args.tile
+    if tile == 0 and args.tune_table:
+        from paper_2108_00516_amd import autotune
+        tile = autotune.load(args.tune_table).get(autotune.BATCH_KEY, {}).get("tile", 0)
+
     def build(timing):
         return [from_synth(g, Config(max_frames=g.n_frames, gn_iters=iters, use_graph=0 if timing else 1,
-                                     timing=1 if timing else 0, tile_pixels=args.tile), device_inputs=True)
+                                     timing=1 if timing else 0, tile_pixels=tile), device_inputs=True)
                 for g in graphs]
 
     def run(pgs, steps):
@@ -345,6 +360,17 @@ def run_batch(args, graphs):
         torch.cuda.synchronize()
         return time.perf_counter() - t0, launches, ms, reads, src
 
+    if args.autotune:
+        from paper_2108_00516_amd import autotune
+
+        def make(tile):
+            return ([from_synth(g, Config(max_frames=g.n_frames, gn_iters=iters, tile_pixels=tile),
+                                device_inputs=True) for g in graphs], [g.poses_init for g in graphs])
+        table = autotune.tune({autotune.BATCH_KEY: make}, steps=5,
+                              log=lambda m: print(m, file=sys.stderr, flush=True))
+        autotune.save(table, args.autotune)
+        print(json.dumps(table), flush=True)
+        return
     pgs = build(False)
     for _ in range(args.warmup):
         optimize_batch(pgs)
@@ -359,6 +385,7 @@ def run_batch(args, graphs):
         "ms_per_step": round(1000.0 * el / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{len(graphs)} windows, 4-20 keyframes, 320x240/480x360/640x480, 7 GN iterations",
+                   "tile_pixels": tile,
                    "keyframes": [g.n_frames for g in graphs],
                    "resolutions": [f"{g.width}x{g.height}" for g in graphs]},
         "residual_px_per_s": round(src * iters * args.steps / el, 1),

@@ -15,6 +15,7 @@ import time
 from typing import Callable, Dict, Iterable, Optional, Sequence
 
 TILES = (256, 512, 1024, 2048)
+BATCH_KEY = "batch"   # table key of a whole batched schedule (one tile for every window)
 NODE_BUCKETS = ((2, 7), (8, 11), (12, 15), (16, 32))
 
 

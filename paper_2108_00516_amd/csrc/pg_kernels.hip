@@ -106,18 +106,56 @@ __global__ void row_count_kernel(const uint8_t* __restrict__ flag, int W, int* _
         row_cnt[v] = part[0] + part[1] + part[2] + part[3];
 }
 
-// exclusive scan of the row counts (single thread; rows <= 8192)
-__global__ void row_scan_kernel(int* __restrict__ row_cnt, int H, int* __restrict__ total)
+// Exclusive prefix sum of v over the block (up to 1024 threads) and the block total.
+__device__ __forceinline__ int block_excl_scan_int(int v, int* wave_sums, int& total)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int s = 0;
-        for (int v = 0; v < H; ++v) {
-            const int c = row_cnt[v];
-            row_cnt[v] = s;
-            s += c;
-        }
-        *total = s;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(incl, d, 64);
+        if (lane >= d)
+            incl += o;
     }
+    if (lane == 63)
+        wave_sums[wv] = incl;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        const int c = wave_sums[w];
+        off += (w < wv) ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return off + incl - v;
+}
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;   // rows per thread: up to 8192 rows
+
+// Exclusive prefix sum of the per-row counts (in place) and their total.
+__global__ __launch_bounds__(kScanThreads) void row_scan_kernel(int* __restrict__ row_cnt, int H,
+                                                                  int* __restrict__ total)
+{
+    __shared__ int wave_sums[kScanThreads / 64];
+    const int r0 = threadIdx.x * kScanPer;
+    int c[kScanPer], sum = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        c[q] = (r0 + q < H) ? row_cnt[r0 + q] : 0;
+        sum += c[q];
+    }
+    int tot;
+    int off = block_excl_scan_int(sum, wave_sums, tot);
+#pragma unroll
+    for (int q = 0; q < kScanPer; ++q) {
+        if (r0 + q < H)
+            row_cnt[r0 + q] = off;
+        off += c[q];
+    }
+    if (threadIdx.x == 0)
+        *total = tot;
 }
 
 // row-major compaction of the valid pixels: the source list of a frame
@@ -737,55 +775,39 @@ __device__ __forceinline__ int block_excl_scan(bool flag, int* wave_cnt, int& to
     return off + pre;
 }
 
-// Exclusive prefix sum of v over the block (1024 threads) and the block total.
-__device__ __forceinline__ int block_excl_scan_int(int v, int* wave_sums, int& total)
-{
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int o = __shfl_up(incl, d, 64);
-        if (lane >= d)
-            incl += o;
-    }
-    if (lane == 63)
-        wave_sums[wv] = incl;
-    __syncthreads();
-    int off = 0, tot = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-        const int c = wave_sums[w];
-        off += (w < wv) ? c : 0;
-        tot += c;
-    }
-    __syncthreads();
-    total = tot;
-    return off + incl - v;
-}
-
 constexpr int kSelectPer = 8;   // consecutive entries per thread in the compaction
 
-// Per frame (one block of 1024 threads): drop the n_drop source pixels of
-// lowest score, ties by position in the row-major source list, and compact the
-// kept ones in order into the pruned lists.  The n_drop-th smallest key is
-// found by an MSB-first radix select (four 8-bit passes, LDS histograms with
-// integer atomics: the result does not depend on their order).
+// Per frame, kSelectBlocks blocks of 1024 threads: drop the n_drop source
+// pixels of lowest score, ties by position in the row-major source list, and
+// compact the kept ones in order into the pruned lists.  Every block finds
+// the n_drop-th smallest key itself (the same computation on the same data,
+// so all agree): an MSB-first radix select, four 8-bit passes over LDS
+// histograms kept in 16 copies (lane % 16) so that lanes hitting one bin do
+// not serialise on one address; integer counts, so the result does not
+// depend on the order of the atomics.  Block b then compacts its own segment
+// of the list; its output offset and its rank among the keys equal to the
+// threshold come from counting the keys before the segment.
 constexpr int kSelectThreads = 1024;
+constexpr int kSelectBlocks = 8;
+constexpr int kHistCopies = 16;
 
 __global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const GraphDev* __restrict__ gds,
                                                                       const int2* __restrict__ frames)
 {
+    __shared__ int hist16[256 * kHistCopies];
     __shared__ int hist[256];
     __shared__ int wave_cnt[16];
     __shared__ unsigned int s_prefix;
     __shared__ int s_rank;
-    const int2 fr = frames[blockIdx.x];
+    const int2 fr = frames[blockIdx.x / kSelectBlocks];
+    const int seg = blockIdx.x % kSelectBlocks;
     const GraphDev& gd = gds[fr.x];
     const int i = fr.y;
     const int V = gd.n_src[i];
     const int drop = gd.n_drop[i];
     const size_t base = (size_t)i * gd.HW;
     const unsigned int* __restrict__ key = gd.score + base;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
 
     unsigned int tau = 0;   // key of the last dropped entry in (key, position) order
     int need = 0;           // entries equal to tau that are dropped (lowest positions first)
@@ -793,13 +815,26 @@ __global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const Grap
         unsigned int prefix = 0, mask = 0;
         int rank = drop - 1;    // 0-based rank of the entry sought
         for (int shift = 24; shift >= 0; shift -= 8) {
-            for (int b = tid; b < 256; b += kSelectThreads)
-                hist[b] = 0;
+            for (int q = tid; q < 256 * kHistCopies; q += kSelectThreads)
+                hist16[q] = 0;
             __syncthreads();
-            for (int k = tid; k < V; k += kSelectThreads) {
-                const unsigned int kk = key[k];
-                if ((kk & mask) == prefix)
-                    atomicAdd(&hist[(kk >> shift) & 255u], 1);
+            for (int k0 = tid * kSelectPer; k0 < V; k0 += kSelectThreads * kSelectPer) {
+                unsigned int kk[kSelectPer];
+#pragma unroll
+                for (int q = 0; q < kSelectPer; ++q)
+                    kk[q] = key[min(k0 + q, V - 1)];
+#pragma unroll
+                for (int q = 0; q < kSelectPer; ++q)
+                    if (k0 + q < V && (kk[q] & mask) == prefix)
+                        atomicAdd(&hist16[((kk[q] >> shift) & 255u) * kHistCopies + (lane & (kHistCopies - 1))], 1);
+            }
+            __syncthreads();
+            if (tid < 256) {
+                int h = 0;
+#pragma unroll
+                for (int c = 0; c < kHistCopies; ++c)
+                    h += hist16[tid * kHistCopies + c];
+                hist[tid] = h;
             }
             __syncthreads();
             if (tid < 64) {
@@ -842,41 +877,66 @@ __global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const Grap
         tau = prefix;
         need = rank + 1;
     }
-    // ordered compaction: entry k is kept unless key < tau, or key == tau and
-    // it is among the first 'need' entries equal to tau.  Chunks of
-    // kSelectThreads x kSelectPer entries, each thread a contiguous run of
+    // this block's segment [s0, s1) of the list; keys before it give the
+    // output offset and the rank among the keys equal to tau
+    const int s0 = (int)(((long long)V * seg) / kSelectBlocks);
+    const int s1 = (int)(((long long)V * (seg + 1)) / kSelectBlocks);
+    int n_lt = 0, n_eq = 0;
+    if (drop > 0)
+        for (int k0 = tid * kSelectPer; k0 < s0; k0 += kSelectThreads * kSelectPer) {
+            unsigned int kk[kSelectPer];
+#pragma unroll
+            for (int q = 0; q < kSelectPer; ++q)
+                kk[q] = key[min(k0 + q, V - 1)];
+#pragma unroll
+            for (int q = 0; q < kSelectPer; ++q) {
+                n_lt += (k0 + q < s0 && kk[q] < tau) ? 1 : 0;
+                n_eq += (k0 + q < s0 && kk[q] == tau) ? 1 : 0;
+            }
+        }
+    int lt_before, eq_seen;
+    (void)block_excl_scan_int(n_lt, wave_cnt, lt_before);
+    (void)block_excl_scan_int(n_eq, wave_cnt, eq_seen);
+    int out = s0 - lt_before - min(need, eq_seen);
+    // ordered compaction of the segment: entry k is kept unless key < tau, or
+    // key == tau and it is among the first 'need' entries equal to tau.
+    // Chunks of kSelectThreads x kSelectPer entries, each thread a run of
     // kSelectPer; block scans of the per-thread counts keep the order.
-    int out = 0, eq_seen = 0;
-    for (int k0 = 0; k0 < V; k0 += kSelectThreads * kSelectPer) {
+    for (int k0 = s0; k0 < s1; k0 += kSelectThreads * kSelectPer) {
         const int kb = k0 + tid * kSelectPer;
         unsigned int kk[kSelectPer];
-        int n_eq = 0;
+        int m_eq = 0;
 #pragma unroll
         for (int q = 0; q < kSelectPer; ++q) {
-            kk[q] = (kb + q < V) ? key[kb + q] : 0u;
-            n_eq += (kb + q < V && drop > 0 && kk[q] == tau) ? 1 : 0;
+            kk[q] = key[min(kb + q, V - 1)];
+            m_eq += (kb + q < s1 && drop > 0 && kk[q] == tau) ? 1 : 0;
         }
         int eq_tot;
-        int eq_rank = eq_seen + block_excl_scan_int(n_eq, wave_cnt, eq_tot);
-        bool keep[kSelectPer];
-        int n_keep = 0;
+        int eq_rank = eq_seen + block_excl_scan_int(m_eq, wave_cnt, eq_tot);
+        unsigned int keep = 0;   // bit q: entry kb + q is kept
 #pragma unroll
         for (int q = 0; q < kSelectPer; ++q) {
-            const bool live = kb + q < V;
+            const bool live = kb + q < s1;
             const bool eq = live && drop > 0 && kk[q] == tau;
-            keep[q] = live && (drop == 0 || kk[q] > tau || (eq && eq_rank >= need));
+            const bool kq = live && (drop == 0 || kk[q] > tau || (eq && eq_rank >= need));
             eq_rank += eq ? 1 : 0;
-            n_keep += keep[q] ? 1 : 0;
+            keep |= (kq ? 1u : 0u) << q;
         }
         int keep_tot;
-        int pos = out + block_excl_scan_int(n_keep, wave_cnt, keep_tot);
+        const int pos = out + block_excl_scan_int(__popc(keep), wave_cnt, keep_tot);
+        // the source records of the run, loaded together after the scans, and
+        // stored at their ranks among the kept entries of the run
 #pragma unroll
-        for (int q = 0; q < kSelectPer; ++q)
-            if (keep[q]) {
-                gd.psrc_nz[base + pos] = gd.src_nz[base + kb + q];
-                gd.psrc_uv[base + pos] = gd.src_uv[base + kb + q];
-                ++pos;
+        for (int q = 0; q < kSelectPer; ++q) {
+            const int kq = min(kb + q, V - 1);
+            const float4 nz = gd.src_nz[base + kq];
+            const uint32_t uv = gd.src_uv[base + kq];
+            if ((keep >> q) & 1u) {
+                const int at = pos + __popc(keep & ((1u << q) - 1u));
+                gd.psrc_nz[base + at] = nz;
+                gd.psrc_uv[base + at] = uv;
             }
+        }
         out += keep_tot;
         eq_seen += eq_tot;
     }
@@ -1807,7 +1867,7 @@ void launch_preprocess(const float* depth, const uint8_t* mask, int W, int H, fl
     dim3 blk(32, 8), grd((W + 31) / 32, (H + 7) / 8);
     preprocess_map_kernel<<<grd, blk, 0, st>>>(depth, mask, W, H, cx, cy, ifx, ify, map, flag);
     row_count_kernel<<<H, 256, 0, st>>>(flag, W, row_cnt);
-    row_scan_kernel<<<1, 64, 0, st>>>(row_cnt, H, total);
+    row_scan_kernel<<<1, kScanThreads, 0, st>>>(row_cnt, H, total);
     row_scatter_kernel<<<H, 256, 0, st>>>(map, flag, row_cnt, W, src_nz, src_uv);
 }
 
@@ -1876,7 +1936,7 @@ void launch_prune(const GraphDev* gds, const WorkItem* pitems, int n_pitems, con
     if (n_pitems > 0)
         prune_score_kernel<<<n_pitems, kPruneThreads, 0, st>>>(gds, pitems);
     if (n_pframes > 0)
-        prune_select_kernel<<<n_pframes, kSelectThreads, 0, st>>>(gds, pframes);
+        prune_select_kernel<<<n_pframes * kSelectBlocks, kSelectThreads, 0, st>>>(gds, pframes);
 }
 
 void launch_feature(const GraphDev* gds, const int2* fitems, int n, hipStream_t st)
