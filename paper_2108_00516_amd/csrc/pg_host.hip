@@ -34,8 +34,8 @@ void launch_mlp_to_float(const __half* p16, float* p32, hipStream_t st);
 void launch_feature(const GraphDev* gds, const int2* fitems, int n, hipStream_t st);
 void launch_assemble(const GraphDev* gds, const int2* nbs, int n, hipStream_t st);
 size_t solve_lds_bytes(int n_free, int n_frames);
-int gj_slots(int n_free);
-void launch_gj_solve(const GraphDev* gds, int n_graphs, int slots, hipStream_t st);
+int gj_slots(int n_free);   // columns of the Gauss-Jordan system
+void launch_gj_solve(const GraphDev* gds, int n_graphs, int cols, hipStream_t st);
 hipError_t solve_set_max_lds(size_t bytes);
 void launch_solve(const GraphDev* gds, int n_graphs, size_t lds, int mode, hipStream_t st);
 }  // namespace pg
@@ -89,7 +89,7 @@ struct Schedule {
     int iters = 0;
     bool gj = false;      // every graph solved by the register Gauss-Jordan kernel
     int precision = 0;    // PG_PREC_* of every graph of the schedule
-    int gj_slots = 1;
+    int gj_slots = 1;   // widest Gauss-Jordan system (columns) of the schedule
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> events;   // timing: start, then 5 per iteration
     ~Schedule()

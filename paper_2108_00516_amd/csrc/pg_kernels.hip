@@ -946,11 +946,16 @@ __global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const Grap
 
 // One block per match set, in FP64 (the residual is a millimetre difference
 // of object-frame points; the whole term is a few thousand matches):
-// e = T_i^-1 p_m - T_j^-1 p_n (Eq. 2), its Jacobian
-// [-R_i^T, R_i^T [p_m]x | R_j^T, -R_j^T [p_n]x], Huber weight; per thread
-// sums of w J^T J (12x12 upper), w J^T e, rho and the count in registers,
-// then a recursive-halving wave reduction (three groups of 32 values) and a
-// fixed-order sum over the waves.
+// e = T_i^-1 p_m - T_j^-1 p_n (Eq. 2), Huber weight w.  Every entry of the
+// Jacobian [-R_i^T, R_i^T [p_m]x | R_j^T, -R_j^T [p_n]x] and of e is linear in
+// u = (1, p_m, p_n), so the sums of w J^T J and w J^T e over a set follow
+// exactly from the weighted second moments S = sum w u u^T (28 values): with
+// J_r = B_r u and e_r = A_r . u per residual row r,
+//   sum w J^T J [a][c] = sum_r B_r[a]^T S B_r[c],  sum w J^T e [a] = sum_r B_r[a]^T S A_r.
+// Per thread: S, the Huber energy and the count (30 values) in registers,
+// a recursive-halving wave reduction, a fixed-order sum over the waves, then
+// the 12x12 upper triangle, the 12 gradient entries, energy and count
+// expanded from S in FP64, one output per thread.
 constexpr int kFeatThreads = 256;
 
 template <int HALF, int OFF, typename T, int L>
@@ -978,6 +983,84 @@ __device__ __forceinline__ void wave_reduce32(T (&acc)[L], int lane)
     acc[OFF] += __shfl_xor(acc[OFF], 1);
 }
 
+// Value of v held by the partner lane across lane bit B (the partner is
+// lane ^ (1 << B)): DPP quad permutations for bits 0 and 1, a row rotation by
+// 8 for bit 3, a bit-mask swizzle for bits 2 and 4, a permute for bit 5.
+template <int B>
+__device__ __forceinline__ double lane_swap(double v)
+{
+    const long long x = __double_as_longlong(v);
+    int lo = (int)x, hi = (int)(x >> 32);
+    if constexpr (B == 0) {
+        lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);   // quad_perm [1, 0, 3, 2]
+        hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (B == 1) {
+        lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);   // quad_perm [2, 3, 0, 1]
+        hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (B == 3) {
+        lo = __builtin_amdgcn_mov_dpp(lo, 0x128, 0xF, 0xF, false);  // row_ror 8 (within 16 lanes)
+        hi = __builtin_amdgcn_mov_dpp(hi, 0x128, 0xF, 0xF, false);
+    } else if constexpr (B == 2 || B == 4) {
+        constexpr int kSwz = 0x1F | ((1 << B) << 10);                // and 0x1f, xor 1 << B
+        lo = __builtin_amdgcn_ds_swizzle(lo, kSwz);
+        hi = __builtin_amdgcn_ds_swizzle(hi, kSwz);
+    } else {
+        return __shfl_xor(v, 1 << B);
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One recursive-halving level over lane bit B: the lanes with the bit clear
+// keep values [0, HALF) of acc, the others [HALF, 2 HALF), each adding its
+// partner's copy; the kept half moves to acc[0, HALF).
+template <int HALF, int B, int L>
+__device__ __forceinline__ void halve_bit(double (&acc)[L], int lane)
+{
+    const bool up = (lane >> B) & 1;
+#pragma unroll
+    for (int q = 0; q < HALF; ++q) {
+        const double send = up ? acc[q] : acc[q + HALF];
+        const double keep = up ? acc[q + HALF] : acc[q];
+        acc[q] = keep + lane_swap<B>(send);
+    }
+}
+
+// Sum the 32 values acc[0..31] over the wave: on return acc[0] of lane l
+// holds the total of value wave_sum32_index(l).
+template <int L>
+__device__ __forceinline__ void wave_sum32(double (&acc)[L], int lane)
+{
+    halve_bit<16, 0>(acc, lane);
+    halve_bit<8, 1>(acc, lane);
+    halve_bit<4, 3>(acc, lane);
+    halve_bit<2, 2>(acc, lane);
+    halve_bit<1, 4>(acc, lane);
+    acc[0] += lane_swap<5>(acc[0]);
+}
+
+__device__ __forceinline__ int wave_sum32_index(int lane)
+{
+    return 16 * (lane & 1) + 8 * ((lane >> 1) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 2) & 1) +
+           ((lane >> 4) & 1);
+}
+
+// Non-zero coefficients of u = (1, p_m, p_n) in Jacobian column a of residual
+// row r (rho = row r of R_i^T, sig = row r of R_j^T): J[r][a] = c0 u_i0 + c1 u_i1.
+__device__ __forceinline__ void feat_jac_sparse(const double* __restrict__ rho, const double* __restrict__ sig,
+                                                int a, int& i0, double& c0, int& i1, double& c1)
+{
+    const int q = a % 3, q1 = (q + 1) % 3, q2 = (q + 2) % 3;
+    if (a < 3) {            // -R_i^T
+        i0 = 0; c0 = -rho[q]; i1 = 0; c1 = 0.0;
+    } else if (a < 6) {     // R_i^T [p_m]x: row r is rho x p_m
+        i0 = 1 + q2; c0 = rho[q1]; i1 = 1 + q1; c1 = -rho[q2];
+    } else if (a < 9) {     // R_j^T
+        i0 = 0; c0 = sig[q]; i1 = 0; c1 = 0.0;
+    } else {                // -R_j^T [p_n]x
+        i0 = 4 + q2; c0 = -sig[q1]; i1 = 4 + q1; c1 = sig[q2];
+    }
+}
+
 __global__ __launch_bounds__(kFeatThreads) void feature_kernel(const GraphDev* __restrict__ gds,
                                                                const int2* __restrict__ fitems)
 {
@@ -987,7 +1070,8 @@ __global__ __launch_bounds__(kFeatThreads) void feature_kernel(const GraphDev* _
         return;
     const int4 S = gd.fsets[fi.y];
     __shared__ double Tinv[2][12];
-    __shared__ double red[kFeatThreads / 64][96];
+    __shared__ double red[kFeatThreads / 64][32];
+    __shared__ double Sm[7][8];  // the moments as a full symmetric matrix; [0][7], [1][7]: energy, count
     if (threadIdx.x < 24) {
         const int side = threadIdx.x / 12, e = threadIdx.x % 12, r = e / 4, c = e % 4;
         const double* T = gd.poses + 16 * (side == 0 ? S.x : S.y);
@@ -996,69 +1080,112 @@ __global__ __launch_bounds__(kFeatThreads) void feature_kernel(const GraphDev* _
     }
     __syncthreads();
     const double huber = (double)gd.huber_f;
-    double acc[96];
+    const double ifx = 1.0 / gd.fx64, ify = 1.0 / gd.fy64;
+    double acc[32];
 #pragma unroll
-    for (int q = 0; q < 96; ++q)
+    for (int q = 0; q < 32; ++q)
         acc[q] = 0.0;
+#pragma unroll 1
     for (int k = threadIdx.x; k < S.w; k += kFeatThreads) {
         const float4 qm = gd.fpts[2 * (S.z + k)];
         const float4 qn = gd.fpts[2 * (S.z + k) + 1];
         if (!(qm.w > 0.f))
             continue;
         const double zm = qm.z, zn = qn.z;
-        const double pm[3] = {zm * ((double)qm.x - gd.cx64) / gd.fx64, zm * ((double)qm.y - gd.cy64) / gd.fy64, zm};
-        const double pn[3] = {zn * ((double)qn.x - gd.cx64) / gd.fx64, zn * ((double)qn.y - gd.cy64) / gd.fy64, zn};
-        double e[3], J[3][12];
+        const double u[7] = {1.0,
+                             zm * (((double)qm.x - gd.cx64) * ifx), zm * (((double)qm.y - gd.cy64) * ify), zm,
+                             zn * (((double)qn.x - gd.cx64) * ifx), zn * (((double)qn.y - gd.cy64) * ify), zn};
+        double e[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             const double* Ti = Tinv[0] + 4 * r;
             const double* Tj = Tinv[1] + 4 * r;
-            e[r] = (Ti[0] * pm[0] + Ti[1] * pm[1] + Ti[2] * pm[2] + Ti[3]) -
-                   (Tj[0] * pn[0] + Tj[1] * pn[1] + Tj[2] * pn[2] + Tj[3]);
-            J[r][0] = -Ti[0];
-            J[r][1] = -Ti[1];
-            J[r][2] = -Ti[2];
-            J[r][3] = Ti[1] * pm[2] - Ti[2] * pm[1];   // (R_i^T)_r x p_m
-            J[r][4] = Ti[2] * pm[0] - Ti[0] * pm[2];
-            J[r][5] = Ti[0] * pm[1] - Ti[1] * pm[0];
-            J[r][6] = Tj[0];
-            J[r][7] = Tj[1];
-            J[r][8] = Tj[2];
-            J[r][9] = -(Tj[1] * pn[2] - Tj[2] * pn[1]);
-            J[r][10] = -(Tj[2] * pn[0] - Tj[0] * pn[2]);
-            J[r][11] = -(Tj[0] * pn[1] - Tj[1] * pn[0]);
+            e[r] = (Ti[0] * u[1] + Ti[1] * u[2] + Ti[2] * u[3] + Ti[3]) -
+                   (Tj[0] * u[4] + Tj[1] * u[5] + Tj[2] * u[6] + Tj[3]);
         }
         const double ne = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
         const double w = (ne <= huber) ? 1.0 : huber / ne;
         int q = 0;
 #pragma unroll
-        for (int a = 0; a < 12; ++a)
+        for (int a = 0; a < 7; ++a) {
+            const double wa = w * u[a];
 #pragma unroll
-            for (int c = a; c < 12; ++c)
-                acc[q++] += w * (J[0][a] * J[0][c] + J[1][a] * J[1][c] + J[2][a] * J[2][c]);
-#pragma unroll
-        for (int a = 0; a < 12; ++a)
-            acc[78 + a] += w * (J[0][a] * e[0] + J[1][a] * e[1] + J[2][a] * e[2]);
-        acc[90] += (ne <= huber) ? 0.5 * ne * ne : huber * (ne - 0.5 * huber);
-        acc[91] += 1.0;
+            for (int c = a; c < 7; ++c)
+                acc[q++] += wa * u[c];
+        }
+        acc[28] += (ne <= huber) ? 0.5 * ne * ne : huber * (ne - 0.5 * huber);
+        acc[29] += 1.0;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    wave_reduce32<0>(acc, lane);
-    wave_reduce32<32>(acc, lane);
-    wave_reduce32<64>(acc, lane);
-    if ((lane & 1) == 0) {
-        red[wave][lane >> 1] = acc[0];
-        red[wave][32 + (lane >> 1)] = acc[32];
-        red[wave][64 + (lane >> 1)] = acc[64];
-    }
+    wave_sum32(acc, lane);
+    if (lane < 32)
+        red[wave][wave_sum32_index(lane)] = acc[0];
     __syncthreads();
-    if (threadIdx.x < kFeatFields) {
+    if (threadIdx.x < 30) {
         double v = red[0][threadIdx.x];
 #pragma unroll
         for (int w = 1; w < kFeatThreads / 64; ++w)
             v += red[w][threadIdx.x];
-        gd.fpartials[(size_t)fi.y * kFeatStride + threadIdx.x] = v;
+        if (threadIdx.x >= 28) {
+            Sm[threadIdx.x - 28][7] = v;
+        } else {
+            int k = 0, rem = threadIdx.x;   // (k, l), k <= l, of the upper index
+            while (rem >= 7 - k) {
+                rem -= 7 - k;
+                ++k;
+            }
+            Sm[k][k + rem] = v;
+            Sm[k + rem][k] = v;
+        }
     }
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t >= kFeatFields)
+        return;
+    double v;
+    if (t >= 90) {
+        v = Sm[t - 90][7];   // energy, count
+    } else {
+        int a, c = -1;
+        if (t < 78) {
+            // upper index of (a, c) in a 12 x 12 upper triangle, row-major
+            a = 0;
+            int rem = t;
+            while (rem >= 12 - a) {
+                rem -= 12 - a;
+                ++a;
+            }
+            c = a + rem;
+        } else {
+            a = t - 78;
+        }
+        v = 0.0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const double* Ti = Tinv[0] + 4 * r;
+            const double* Tj = Tinv[1] + 4 * r;
+            int ia0, ia1;
+            double ca0, ca1;
+            feat_jac_sparse(Ti, Tj, a, ia0, ca0, ia1, ca1);
+            if (c >= 0) {
+                int ic0, ic1;
+                double cc0, cc1;
+                feat_jac_sparse(Ti, Tj, c, ic0, cc0, ic1, cc1);
+                v += ca0 * (cc0 * Sm[ia0][ic0] + cc1 * Sm[ia0][ic1]) + ca1 * (cc0 * Sm[ia1][ic0] + cc1 * Sm[ia1][ic1]);
+            } else {
+                // e_r = (t'_i - t'_j)_r + rho . p_m - sig . p_n
+                const double ar[7] = {Ti[3] - Tj[3], Ti[0], Ti[1], Ti[2], -Tj[0], -Tj[1], -Tj[2]};
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int l = 0; l < 7; ++l) {
+                    s0 += Sm[ia0][l] * ar[l];
+                    s1 += Sm[ia1][l] * ar[l];
+                }
+                v += ca0 * s0 + ca1 * s1;
+            }
+        }
+    }
+    gd.fpartials[(size_t)fi.y * kFeatStride + t] = v;
 }
 
 // --------------------------------------------------- FP64 normal equations
@@ -1634,8 +1761,6 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
 
 // ------------------------------------------------- register Gauss-Jordan
 
-constexpr int kGjGrid = 16;                    // a 16 x 16 thread grid
-constexpr int kGjThreads = kGjGrid * kGjGrid;
 
 // 3x3 inverse by cofactors (any invertible M, row-major); also the LU pivots
 // of M without pivoting (M00, the 2x2 Schur pivot, det / 2x2 minor)
@@ -1660,8 +1785,8 @@ __device__ __forceinline__ void inv3_pivots(const double (&M)[9], double (&Mi)[9
 // LU pivots of each pivot block are the Schur-complement pivots of the
 // Cholesky factorisation, so the usual singularity test applies, and at the
 // end the right-hand column holds the solution (no back substitution).  The
-// n x (n+1) entries live in registers: thread (tr, tc) of a 16 x 16 grid owns
-// rows tr + 16a and columns tc + 16b (a, b < T).  Block step K: every thread
+// n x (n+1) entries live in registers: thread (tr, tc) of a G x G grid owns
+// rows tr + Ga and columns tc + Gb (a, b < T).  Block step K: every thread
 // reads the 3 x 3 pivot block from the published row panel and inverts it
 // itself (cofactors: no communication), forms the normalised pivot rows
 // R = D^-1 RP for its own columns, and updates its entries: pivot rows take
@@ -1669,8 +1794,8 @@ __device__ __forceinline__ void inv3_pivots(const double (&M)[9], double (&Mi)[9
 // columns and rows publish them to double-buffered LDS panels: one barrier per
 // block step.  Then the update T <- Exp(x) T and the next iteration's
 // transforms.
-template <int T>
-__global__ __launch_bounds__(kGjThreads) void gj_solve_kernel(const GraphDev* __restrict__ gds)
+template <int G, int T>
+__global__ __launch_bounds__(G * G) void gj_solve_kernel(const GraphDev* __restrict__ gds)
 {
     const GraphDev& gd = gds[blockIdx.x];
     const int N = gd.n_frames;
@@ -1680,18 +1805,19 @@ __global__ __launch_bounds__(kGjThreads) void gj_solve_kernel(const GraphDev* __
     __shared__ double xs[kGjMaxN + 1];
     __shared__ double Ts[16 * kMaxFrames];
     __shared__ double ns[kMaxFrames * kNodeStats];
-    __shared__ double scratch[kGjThreads / 64];
+    constexpr int kThreads = G * G;
+    __shared__ double scratch[(kThreads + 63) / 64];
     __shared__ int sfree[kMaxFrames];
     const int tid = threadIdx.x;
-    const int tr = tid / kGjGrid, tc = tid % kGjGrid;
+    const int tr = tid / G, tc = tid % G;
     if (*gd.status)
         return;
     const int it = *gd.iters_done;
-    for (int k = tid; k < 16 * N; k += kGjThreads)
+    for (int k = tid; k < 16 * N; k += kThreads)
         Ts[k] = gd.poses[k];
-    for (int k = tid; k < kNodeStats * N; k += kGjThreads)
+    for (int k = tid; k < kNodeStats * N; k += kThreads)
         ns[k] = gd.node_stats[k];
-    for (int k = tid; k < gd.n_free; k += kGjThreads)
+    for (int k = tid; k < gd.n_free; k += kThreads)
         sfree[k] = gd.free_ids[k];
     __syncthreads();
     if (tid < kNodeStats) {
@@ -1709,8 +1835,8 @@ __global__ __launch_bounds__(kGjThreads) void gj_solve_kernel(const GraphDev* __
     int ri[T], cj[T];   // owned rows / columns, -1 beyond the matrix
 #pragma unroll
     for (int a = 0; a < T; ++a) {
-        ri[a] = (tr + kGjGrid * a < n) ? tr + kGjGrid * a : -1;
-        cj[a] = (tc + kGjGrid * a <= n) ? tc + kGjGrid * a : -1;
+        ri[a] = (tr + G * a < n) ? tr + G * a : -1;
+        cj[a] = (tc + G * a <= n) ? tc + G * a : -1;
     }
     // every load at once: clamped (always valid) addresses, validity applied after
     double v[T][T];
@@ -1774,10 +1900,10 @@ __global__ __launch_bounds__(kGjThreads) void gj_solve_kernel(const GraphDev* __
         // read again (publishing takes live columns and rows only), so they
         // are updated like the others instead of being masked; only the pivot
         // rows, which can sit in two row slots at most, take R instead.
-        const int ap0 = c0 / kGjGrid, ap1 = (c0 + 2) / kGjGrid;   // uniform
+        const int ap0 = c0 / G, ap1 = (c0 + 2) / G;   // uniform
 #pragma unroll
         for (int b = 0; b < T; ++b) {
-            if (kGjGrid * b + kGjGrid - 1 < c1)   // every column of this slot is eliminated (uniform)
+            if (G * b + G - 1 < c1)   // every column of this slot is eliminated (uniform)
                 continue;
 #pragma unroll
             for (int a = 0; a < T; ++a) {
@@ -1793,7 +1919,7 @@ __global__ __launch_bounds__(kGjThreads) void gj_solve_kernel(const GraphDev* __
         }
         // publish the next block's three columns and rows (their owners only)
         if (c1 < n) {
-            const int b0 = c1 / kGjGrid, b1 = (c1 + 2) / kGjGrid;   // slots holding them (uniform)
+            const int b0 = c1 / G, b1 = (c1 + 2) / G;   // slots holding them (uniform)
 #pragma unroll
             for (int b = 0; b < T; ++b) {
                 if (b != b0 && b != b1)
@@ -1835,14 +1961,14 @@ __global__ __launch_bounds__(kGjThreads) void gj_solve_kernel(const GraphDev* __
                 xs[ri[a]] = v[a][b];
     bool bad = false;
     __syncthreads();
-    for (int a = tid; a < n; a += kGjThreads)
+    for (int a = tid; a < n; a += kThreads)
         bad |= !isfinite(xs[a]);
     if (__syncthreads_or(bad)) {
         if (tid == 0)
             *gd.status |= kStatusNonFinite;
         return;
     }
-    for (int a = tid; a < gd.n_free; a += kGjThreads) {
+    for (int a = tid; a < gd.n_free; a += kThreads) {
         const int node = sfree[a];
         double E[16], Tn[16];
         se3_exp(xs + 6 * a, E);
@@ -1957,21 +2083,24 @@ size_t solve_lds_bytes(int n_free, int n_frames)
     return sizeof(double) * ((n + 1) * (n + 2) / 2 + 2 * (n + 1) + 4 * n + 16 * (size_t)n_frames);
 }
 
-// tile side T of the Gauss-Jordan solve of n_free free nodes: 16T >= n + 1
-int gj_slots(int n_free)
-{
-    const int need = (6 * n_free + 1 + kGjGrid - 1) / kGjGrid;
-    return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
-}
+// columns (n + 1) of the Gauss-Jordan system of n_free free nodes
+int gj_slots(int n_free) { return 6 * n_free + 1; }
 
-void launch_gj_solve(const GraphDev* gds, int n_graphs, int tile, hipStream_t st)
+// A 16 x 16 grid of four wavefronts with T slots, 16T >= n + 1.  (A single
+// wavefront on an 8 x 8 grid measured 1.5x slower at n = 54: the solve is
+// bound by per-entry FP64 issue, which four SIMDs share.)
+void launch_gj_solve(const GraphDev* gds, int n_graphs, int cols, hipStream_t st)
 {
-    constexpr int kTopSlots = (kGjMaxN + 1 + kGjGrid - 1) / kGjGrid <= 4 ? 4 : 8;
-    switch (tile) {
-    case 1: gj_solve_kernel<1><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
-    case 2: gj_solve_kernel<2><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
-    case 4: gj_solve_kernel<4><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
-    default: gj_solve_kernel<kTopSlots><<<n_graphs, kGjThreads, 0, st>>>(gds); break;
+    static_assert(kGjMaxN + 1 <= 16 * 8, "Gauss-Jordan grid too small for kGjMaxN");
+    switch ((cols + 15) / 16) {
+    case 1: gj_solve_kernel<16, 1><<<n_graphs, 256, 0, st>>>(gds); break;
+    case 2: gj_solve_kernel<16, 2><<<n_graphs, 256, 0, st>>>(gds); break;
+    case 3: gj_solve_kernel<16, 3><<<n_graphs, 256, 0, st>>>(gds); break;
+    case 4: gj_solve_kernel<16, 4><<<n_graphs, 256, 0, st>>>(gds); break;
+    case 5: gj_solve_kernel<16, 5><<<n_graphs, 256, 0, st>>>(gds); break;
+    case 6: gj_solve_kernel<16, 6><<<n_graphs, 256, 0, st>>>(gds); break;
+    case 7: gj_solve_kernel<16, 7><<<n_graphs, 256, 0, st>>>(gds); break;
+    default: gj_solve_kernel<16, 8><<<n_graphs, 256, 0, st>>>(gds); break;
     }
 }
 
