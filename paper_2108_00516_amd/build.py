@@ -18,6 +18,8 @@ def hipcc_command(out: str = LIB, extra=()):
     return [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
             # keep packed FP32 instructions out of the generated code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # matrix-core results in VGPRs (no accumulator copies between steps)
+            "-mllvm", "-amdgpu-mfma-vgpr-form",
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
             *[os.path.join(CSRC, s) for s in SOURCES], "-o", out, *extra]

@@ -71,6 +71,8 @@ struct GraphDev {
     double* grad;             // 6N
     double* node_stats;       // N * kNodeStats
     const int* free_ids;      // n_free node ids
+    const int* free_pos;      // per node: index among the free nodes, -1 if fixed
+    double* Hff;              // free-node system [H_ff | -g_f], 6 n_free rows of 6 n_free + 1, row-major
     int* status;              // sticky status bits
     int* iters_done;
     double* iter_stats;       // kMaxIters * kIterRecord

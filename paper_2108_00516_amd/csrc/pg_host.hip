@@ -124,7 +124,7 @@ struct pg_graph {
 
     // per-optimize device state
     DevBuf d_partials, d_fpartials, d_fpts, d_fsets, d_set_of, d_xf32, d_xf64, d_H, d_grad, d_node_stats,
-        d_free_ids, d_n_src, d_pair_base, d_mlp;
+        d_free_ids, d_free_pos, d_Hff, d_n_src, d_pair_base, d_mlp;
     // results of an optimize, one block read back with one copy (same layout
     // as the pinned host mirror): status, iterations done, per-iteration
     // records (kMaxIters), poses (max_frames)
@@ -347,6 +347,8 @@ pg_status prepare_graph(pg_graph* g)
     HIP_OR_FAIL(g, g->d_grad.ensure(sizeof(double) * 6 * N));
     HIP_OR_FAIL(g, g->d_node_stats.ensure(sizeof(double) * kNodeStats * N));
     HIP_OR_FAIL(g, g->d_free_ids.ensure(sizeof(int) * std::max(g->n_free, 1)));
+    HIP_OR_FAIL(g, g->d_free_pos.ensure(sizeof(int) * N));
+    HIP_OR_FAIL(g, g->d_Hff.ensure(sizeof(double) * std::max(6 * g->n_free * (6 * g->n_free + 1), 1)));
     HIP_OR_FAIL(g, g->d_n_src.ensure(sizeof(int) * N));
     HIP_OR_FAIL(g, g->d_pair_base.ensure(sizeof(int) * (P + 1)));
     if (g->pruned) {
@@ -366,6 +368,11 @@ pg_status prepare_graph(pg_graph* g)
     if (g->n_free)
         HIP_OR_FAIL(g, hipMemcpyAsync(g->d_free_ids.p, free_ids.data(), sizeof(int) * g->n_free,
                                       hipMemcpyHostToDevice, g->stream));
+    std::vector<int> free_pos(N, -1);
+    for (int k = 0; k < g->n_free; ++k)
+        free_pos[free_ids[k]] = k;
+    HIP_OR_FAIL(g, hipMemcpyAsync(g->d_free_pos.p, free_pos.data(), sizeof(int) * N, hipMemcpyHostToDevice,
+                                  g->stream));
     HIP_OR_FAIL(g, hipMemcpyAsync(g->d_n_src.p, g->n_src.data(), sizeof(int) * N, hipMemcpyHostToDevice,
                                   g->stream));
     HIP_OR_FAIL(g, hipMemcpyAsync(g->d_pair_base.p, g->pair_base.data(), sizeof(int) * (P + 1),
@@ -425,6 +432,8 @@ GraphDev make_dev(pg_graph* g)
     d.grad = g->d_grad.as<double>();
     d.node_stats = g->d_node_stats.as<double>();
     d.free_ids = g->d_free_ids.as<int>();
+    d.free_pos = g->d_free_pos.as<int>();
+    d.Hff = g->d_Hff.as<double>();
     d.status = g->dev_status();
     d.iters_done = g->dev_iters();
     d.iter_stats = g->dev_iter_stats();

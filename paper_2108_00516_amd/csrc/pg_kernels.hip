@@ -1260,6 +1260,8 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
         return;
     const int I = nb.y & 0xff, J = (nb.y >> 8) & 0xff;
     const int N = gd.n_frames, n6 = 6 * N;
+    const int fI = gd.free_pos[I], fJ = gd.free_pos[J];   // free-node positions (-1: fixed)
+    const int nf1 = 6 * gd.n_free + 1;                       // row length of the free-node system
     const bool diag = (I == J);
     const int np = diag ? 2 * (N - 1) : 2;       // pairs summed
     const int nt = diag ? N - 1 : 2;             // pairs expanded with the adjoint (P, AX)
@@ -1374,6 +1376,10 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
             h += lf2 * FS[J][e];
             gd.Hm[(size_t)(6 * I + a) * n6 + 6 * J + c] = h;
             gd.Hm[(size_t)(6 * J + c) * n6 + 6 * I + a] = h;
+            if (fI >= 0 && fJ >= 0) {
+                gd.Hff[(size_t)(6 * fI + a) * nf1 + 6 * fJ + c] = h;
+                gd.Hff[(size_t)(6 * fJ + c) * nf1 + 6 * fI + a] = h;
+            }
         }
         return;
     }
@@ -1410,8 +1416,14 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
         if (e < 36) {
             gd.Hm[(size_t)(6 * I + e / 6) * n6 + 6 * I + e % 6] = h;
             gd.Hm[(size_t)(6 * I + e % 6) * n6 + 6 * I + e / 6] = h;
+            if (fI >= 0) {
+                gd.Hff[(size_t)(6 * fI + e / 6) * nf1 + 6 * fI + e % 6] = h;
+                gd.Hff[(size_t)(6 * fI + e % 6) * nf1 + 6 * fI + e / 6] = h;
+            }
         } else {
             gd.grad[6 * I + (e - 36)] = h;
+            if (fI >= 0)
+                gd.Hff[(size_t)(6 * fI + (e - 36)) * nf1 + nf1 - 1] = -h;
         }
     } else if (threadIdx.x == 64) {
         double Eg = 0.0, cg = 0.0, Ef = 0.0, cf = 0.0, rd = 0.0;
@@ -1779,6 +1791,28 @@ __device__ __forceinline__ void inv3_pivots(const double (&M)[9], double (&Mi)[9
     pv[2] = det / c22;
 }
 
+// 3x3 inverse by cofactors of a block expected symmetric positive definite,
+// all nine entries materialised; returns whether its LU (Schur) pivots M00,
+// c22 / M00 and det / c22 all exceed tol, tested by products (no divisions).
+// 1/det: hardware reciprocal and two Newton steps.
+__device__ __forceinline__ bool inv3_spd(const double (&M)[9], double (&Mi)[9], double tol)
+{
+    const double c00 = M[4] * M[8] - M[5] * M[7], c01 = M[2] * M[7] - M[1] * M[8], c02 = M[1] * M[5] - M[2] * M[4];
+    const double c10 = M[5] * M[6] - M[3] * M[8], c11 = M[0] * M[8] - M[2] * M[6], c12 = M[2] * M[3] - M[0] * M[5];
+    const double c20 = M[3] * M[7] - M[4] * M[6], c21 = M[1] * M[6] - M[0] * M[7], c22 = M[0] * M[4] - M[1] * M[3];
+    const double det = M[0] * c00 + M[1] * c10 + M[2] * c20;
+    double id = __builtin_amdgcn_rcp(det);
+    id = fma(id, fma(-det, id, 1.0), id);
+    id = fma(id, fma(-det, id, 1.0), id);
+    Mi[0] = c00 * id; Mi[1] = c01 * id; Mi[2] = c02 * id;
+    Mi[3] = c10 * id; Mi[4] = c11 * id; Mi[5] = c12 * id;
+    Mi[6] = c20 * id; Mi[7] = c21 * id; Mi[8] = c22 * id;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        asm volatile("" : "+v"(Mi[k]));   // keep all nine (a lane selects its row afterwards)
+    return (M[0] > tol) && (c22 > tol * M[0]) && (det > tol * c22);
+}
+
 // One Gauss-Newton solve by block Gauss-Jordan elimination without pivoting
 // of the augmented system [H_ff | -g_f], with 3 x 3 pivot blocks (n = 6 x
 // free nodes is a multiple of 3).  H_ff is symmetric positive definite: the
@@ -1984,6 +2018,238 @@ __global__ __launch_bounds__(G * G) void gj_solve_kernel(const GraphDev* __restr
     compute_transforms(gd, Ts);
 }
 
+// ------------------------------------------------- matrix-core Gauss-Jordan
+
+typedef double gj_d4 __attribute__((ext_vector_type(4)));
+
+// The same block Gauss-Jordan elimination (3 x 3 pivot blocks, no pivoting,
+// Schur-pivot singularity test, solution left in the right-hand column) with
+// the rank-3 update of each block step on the FP64 matrix cores.  The
+// augmented n x (n+1) system is padded with zeros to NT x NT tiles of 16 x 16;
+// wave w of the four owns the tiles (tr, tc) with (tr + tc) mod 4 = w, so the
+// tile columns that elimination retires drop out of every wave alike.  A tile
+// lives in one v_mfma_f64_16x16x4f64 accumulator: lane l holds entries
+// (16 tr + 4 v + l / 16, 16 tc + l % 16), v < 4; the A operand of lane l is
+// entry (l % 16, l / 16) of the 16 x 4 column block, the B operand entry
+// (l / 16, l % 16) of the 4 x 16 row block (k = 3 is zero padding).  The
+// trailing (not yet eliminated) part of the system stays symmetric, so the
+// pivot rows' entries RP there are read from the published pivot columns; only
+// their right-hand side is published apart.  Block step K: every lane inverts
+// the pivot block D and forms its entry of R = D^-1 RP, and each live tile takes
+// V <- V - (C - E) R in one matrix instruction, E holding the unit entries of
+// the pivot rows: other rows get V - C R, the pivot rows RP - D R + R = R up to
+// one rounding (no separate pass over them).  The owners of the next
+// block's columns (and right-hand side) publish them to double-buffered LDS
+// panels: one barrier per block step.  Then the update T <- Exp(x) T and the next
+// iteration's transforms.
+template <int NT>
+__global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict__ gds)
+{
+    constexpr int kS = (NT + 3) / 4;   // tile slots per tile row and wave
+    constexpr int kM = 16 * NT;        // padded side
+    const GraphDev& gd = gds[blockIdx.x];
+    const int N = gd.n_frames;
+    const int n = 6 * gd.n_free, n6 = 6 * N;
+    __shared__ double CP[2][3][kM];    // column panel v(i, 3K + m), by column
+    __shared__ double RPn[2][3];       // right-hand side of the pivot rows v(3K + m, n)
+    __shared__ double xs[kM];
+    __shared__ double Ts[16 * kMaxFrames];
+    __shared__ double ns[kMaxFrames * kNodeStats];
+    __shared__ double scratch[4];
+    __shared__ int sfree[kMaxFrames];
+    __shared__ int sflags;             // 1: singular pivot, 2: non-finite solution
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lr = lane >> 4, lc = lane & 15;
+    // the owned tiles of [H_ff | -g_f], every load issued first, from clamped
+    // addresses (padding applied once the system size is checked)
+    gj_d4 acc[NT][kS];
+    double md = 0.0;
+    const double* __restrict__ Hff = gd.Hff;
+#pragma unroll
+    for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+        for (int s = 0; s < kS; ++s) {
+            const int tc = ((wave - tr) & 3) + 4 * s;
+            const int j = 16 * tc + lc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * tr + 4 * v + lr;
+                const bool in = tc < NT && i < n && j <= n;
+                acc[tr][s][v] = Hff[in ? (size_t)i * (n + 1) + j : 0];
+            }
+        }
+    if (*gd.status)
+        return;
+    const int it = *gd.iters_done;
+    for (int k = tid; k < 16 * N; k += 256)
+        Ts[k] = gd.poses[k];
+    for (int k = tid; k < kNodeStats * N; k += 256)
+        ns[k] = gd.node_stats[k];
+    for (int k = tid; k < gd.n_free; k += 256)
+        sfree[k] = gd.free_ids[k];
+    if (tid == 0)
+        sflags = 0;
+    __syncthreads();
+    if (tid < kNodeStats) {
+        const int src[kNodeStats] = {1, 0, 2, 3, 4};   // E_f, E_g, n_g, n_f, target reads
+        double s = 0.0;
+        for (int k = 0; k < N; ++k)
+            s += ns[kNodeStats * k + src[tid]];
+        gd.iter_stats[kIterRecord * it + tid] = s;
+    }
+    if (n == 0) {
+        if (tid == 0)
+            *gd.iters_done = it + 1;
+        return;
+    }
+    // zero padding and the first panels
+#pragma unroll
+    for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+        for (int s = 0; s < kS; ++s) {
+            const int tc = ((wave - tr) & 3) + 4 * s;
+            const int j = 16 * tc + lc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * tr + 4 * v + lr;
+                const bool in = tc < NT && i < n && j <= n;
+                const double h = in ? acc[tr][s][v] : 0.0;
+                acc[tr][s][v] = h;
+                if (in && i == j)
+                    md = fmax(md, h);
+                if (tc < NT && j < 3)
+                    CP[0][j][i] = h;
+                if (in && i < 3 && j == n)
+                    RPn[0][i] = h;
+            }
+        }
+    const double maxdiag = block_max(md, scratch);   // includes barriers
+    const double tol = 1e-12 * maxdiag;
+    bool singular = !(maxdiag > 0.0);
+    for (int K = 0; 3 * K < n; ++K) {
+        const int bf = K & 1, c0 = 3 * K, c1 = c0 + 3;
+        // pivot block and row panel from the column panel: the trailing part of
+        // the system stays symmetric under elimination, so row c0 + m of it is
+        // column c0 + m; only the right-hand side of the pivot rows is separate
+        double D[9], Di[9];
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+                D[3 * l + m] = CP[bf][m][c0 + l];
+        // operands of every owned tile, read together: A from the column panel,
+        // the three panel entries of the lane's column for B
+        double ca[NT], rb[NT][kS][3];
+#pragma unroll
+        for (int tr = 0; tr < NT; ++tr) {
+            ca[tr] = CP[bf][lr < 3 ? lr : 0][16 * tr + lc];
+#pragma unroll
+            for (int s = 0; s < kS; ++s) {
+                const int tc = ((wave - tr) & 3) + 4 * s;
+                const int j = 16 * (tc < NT ? tc : 0) + lc;
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    rb[tr][s][m] = (j == n) ? RPn[bf][m] : CP[bf][m][j];
+            }
+        }
+        singular |= !inv3_spd(D, Di, tol);
+        // row lr of D^-1 (zero for the padding row k = 3)
+        double Dl[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            Dl[m] = (lr == 0) ? Di[m] : (lr == 1) ? Di[3 + m] : (lr == 2) ? Di[6 + m] : 0.0;
+        // A operand: -(C - E)(16 tr + lc, lr), E the unit entries of the pivot
+        // rows, so the update leaves R in the pivot rows: V - C R + E R
+        double a[NT];
+#pragma unroll
+        for (int tr = 0; tr < NT; ++tr) {
+            const int ia = 16 * tr + lc;
+            a[tr] = (lr < 3) ? ((ia == c0 + lr ? 1.0 : 0.0) - ca[tr]) : 0.0;
+        }
+#pragma unroll
+        for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+            for (int s = 0; s < kS; ++s) {
+                const int tc = ((wave - tr) & 3) + 4 * s;
+                if (tc >= NT || 16 * tc + 15 < c1)   // not owned, or every column eliminated (uniform)
+                    continue;
+                const double b = fma(Dl[0], rb[tr][s][0], fma(Dl[1], rb[tr][s][1], Dl[2] * rb[tr][s][2]));
+                acc[tr][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[tr], b, acc[tr][s], 0, 0, 0);
+            }
+        // publish the next block's three columns, and the right-hand side of its
+        // rows (their owners only)
+        if (c1 < n) {
+#pragma unroll
+            for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+                for (int s = 0; s < kS; ++s) {
+                    const int tc = ((wave - tr) & 3) + 4 * s;
+                    if (tc >= NT || 16 * tc + 15 < c1)
+                        continue;
+                    const int j = 16 * tc + lc;
+                    const int m = j - c1;
+                    if (m >= 0 && m < 3) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            CP[bf ^ 1][m][16 * tr + 4 * v + lr] = acc[tr][s][v];
+                    }
+                    if (j == n && 16 * tr <= c1 + 2 && c1 < 16 * tr + 16) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int d = 16 * tr + 4 * v + lr - c1;
+                            if (d >= 0 && d < 3)
+                                RPn[bf ^ 1][d] = acc[tr][s][v];
+                        }
+                    }
+                }
+        }
+        __syncthreads();
+    }
+    // the right-hand column holds the solution; one barrier publishes it with
+    // the singularity and finiteness flags
+    bool bad = false;
+#pragma unroll
+    for (int tr = 0; tr < NT; ++tr)
+#pragma unroll
+        for (int s = 0; s < kS; ++s) {
+            const int tc = ((wave - tr) & 3) + 4 * s;
+            if (tc < NT && 16 * tc + lc == n) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * tr + 4 * v + lr;
+                    if (i < n) {
+                        xs[i] = acc[tr][s][v];
+                        bad |= !isfinite(acc[tr][s][v]);
+                    }
+                }
+            }
+        }
+    if (singular || bad)
+        atomicOr(&sflags, (singular ? 1 : 0) | (bad ? 2 : 0));
+    __syncthreads();
+    const int flags = sflags;
+    if (flags) {
+        if (tid == 0)
+            *gd.status |= (flags & 1) ? kStatusSingular : kStatusNonFinite;
+        return;
+    }
+    for (int a = tid; a < gd.n_free; a += 256) {
+        const int node = sfree[a];
+        double E[16], Tn[16];
+        se3_exp(xs + 6 * a, E);
+        mat4_mul(E, Ts + 16 * node, Tn);
+        for (int k = 0; k < 16; ++k) {
+            Ts[16 * node + k] = Tn[k];
+            gd.poses[16 * node + k] = Tn[k];
+        }
+    }
+    __syncthreads();
+    if (tid == 0)
+        *gd.iters_done = it + 1;
+    compute_transforms(gd, Ts);
+}
+
 // ------------------------------------------------------------ launchers
 
 void launch_preprocess(const float* depth, const uint8_t* mask, int W, int H, float cx, float cy, float ifx,
@@ -2086,22 +2352,16 @@ size_t solve_lds_bytes(int n_free, int n_frames)
 // columns (n + 1) of the Gauss-Jordan system of n_free free nodes
 int gj_slots(int n_free) { return 6 * n_free + 1; }
 
-// A 16 x 16 grid of four wavefronts with T slots, 16T >= n + 1.  (A single
-// wavefront on an 8 x 8 grid measured 1.5x slower at n = 54: the solve is
-// bound by per-entry FP64 issue, which four SIMDs share.)
+// Matrix-core variant: NT x NT tiles of 16 x 16, 16 NT >= n + 1.
 void launch_gj_solve(const GraphDev* gds, int n_graphs, int cols, hipStream_t st)
 {
-    static_assert(kGjMaxN + 1 <= 16 * 8, "Gauss-Jordan grid too small for kGjMaxN");
-    switch ((cols + 15) / 16) {
-    case 1: gj_solve_kernel<16, 1><<<n_graphs, 256, 0, st>>>(gds); break;
-    case 2: gj_solve_kernel<16, 2><<<n_graphs, 256, 0, st>>>(gds); break;
-    case 3: gj_solve_kernel<16, 3><<<n_graphs, 256, 0, st>>>(gds); break;
-    case 4: gj_solve_kernel<16, 4><<<n_graphs, 256, 0, st>>>(gds); break;
-    case 5: gj_solve_kernel<16, 5><<<n_graphs, 256, 0, st>>>(gds); break;
-    case 6: gj_solve_kernel<16, 6><<<n_graphs, 256, 0, st>>>(gds); break;
-    case 7: gj_solve_kernel<16, 7><<<n_graphs, 256, 0, st>>>(gds); break;
-    default: gj_solve_kernel<16, 8><<<n_graphs, 256, 0, st>>>(gds); break;
-    }
+    static_assert(kGjMaxN + 1 <= 16 * 8, "Gauss-Jordan tiles too few for kGjMaxN");
+    if (cols <= 32)
+        gj_mfma_kernel<2><<<n_graphs, 256, 0, st>>>(gds);
+    else if (cols <= 64)
+        gj_mfma_kernel<4><<<n_graphs, 256, 0, st>>>(gds);
+    else
+        gj_mfma_kernel<8><<<n_graphs, 256, 0, st>>>(gds);
 }
 
 hipError_t solve_set_max_lds(size_t bytes)
