@@ -2052,6 +2052,7 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
     const int n = 6 * gd.n_free, n6 = 6 * N;
     __shared__ double CP[2][3][kM];    // column panel v(i, 3K + m), by column
     __shared__ double RPn[2][3];       // right-hand side of the pivot rows v(3K + m, n)
+    __shared__ double sink[256];       // publish target of the lanes that own nothing to publish
     __shared__ double xs[kM];
     __shared__ double Ts[16 * kMaxFrames];
     __shared__ double ns[kMaxFrames * kNodeStats];
@@ -2127,6 +2128,8 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
     const double maxdiag = block_max(md, scratch);   // includes barriers
     const double tol = 1e-12 * maxdiag;
     bool singular = !(maxdiag > 0.0);
+    // weights selecting row lr of D^-1 (all zero for the padding row k = 3)
+    const double w0 = (lr == 0) ? 1.0 : 0.0, w1 = (lr == 1) ? 1.0 : 0.0, w2 = (lr == 2) ? 1.0 : 0.0;
     for (int K = 0; 3 * K < n; ++K) {
         const int bf = K & 1, c0 = 3 * K, c1 = c0 + 3;
         // pivot block and row panel from the column panel: the trailing part of
@@ -2158,7 +2161,7 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
         double Dl[3];
 #pragma unroll
         for (int m = 0; m < 3; ++m)
-            Dl[m] = (lr == 0) ? Di[m] : (lr == 1) ? Di[3 + m] : (lr == 2) ? Di[6 + m] : 0.0;
+            Dl[m] = fma(w0, Di[m], fma(w1, Di[3 + m], w2 * Di[6 + m]));
         // A operand: -(C - E)(16 tr + lc, lr), E the unit entries of the pivot
         // rows, so the update leaves R in the pivot rows: V - C R + E R
         double a[NT];
@@ -2189,10 +2192,15 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
                         continue;
                     const int j = 16 * tc + lc;
                     const int m = j - c1;
-                    if (m >= 0 && m < 3) {
+                    if (tc == (c1 >> 4) || tc == ((c1 + 2) >> 4)) {   // uniform: the tile holds next columns
+                        // every lane writes: the owners of columns c1.. to the
+                        // panel, the others to their sink slot
+                        const bool own = m >= 0 && m < 3;
+                        double* dst = own ? &CP[bf ^ 1][own ? m : 0][16 * tr + lr] : &sink[tid];
+                        const int step = own ? 4 : 0;
 #pragma unroll
                         for (int v = 0; v < 4; ++v)
-                            CP[bf ^ 1][m][16 * tr + 4 * v + lr] = acc[tr][s][v];
+                            dst[step * v] = acc[tr][s][v];
                     }
                     if (j == n && 16 * tr <= c1 + 2 && c1 < 16 * tr + 16) {
 #pragma unroll

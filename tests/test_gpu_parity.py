@@ -179,6 +179,30 @@ def test_optimize_parity(name):
     pg.close()
 
 
+@pytest.mark.parametrize("name,fixed,solver", [("T", (0, 2), "GAUSS_JORDAN"), ("P", (0, 4, 7), "GAUSS_JORDAN"),
+                                                ("P", (0, 4, 7), "CHOLESKY")])
+def test_interior_fixed_nodes(name, fixed, solver):
+    """Fixed nodes inside the window: the free-node system skips their rows and
+    columns (node -> free position table), the poses of fixed nodes stay put."""
+    from paper_2108_00516_amd import _lib
+    g0 = graph(name)
+    fx = np.zeros(g0.n_frames, np.int32)
+    fx[list(fixed)] = 1
+    g = synth.SynthGraph(**{**g0.__dict__, "fixed": fx})
+    say(f"interior fixed nodes {fixed} {name}, {solver}")
+    pg = gpu_graph(g, solver=getattr(_lib, "PG_SOLVER_" + solver))
+    st = pg.optimize()
+    Pg = pg.poses
+    Po, so = oracle.OracleProblem.from_synth(g).optimize(g.poses_init, 7)
+    dr, dt = max_pose_diff(Pg, Po)
+    say(f"  max pose difference vs oracle: {dr:.2e} rad, {dt:.2e} m")
+    assert st["iters_done"] == 7 and so["iters_done"] == 7
+    assert dr <= POSE_TOL_RAD and dt <= POSE_TOL_M
+    for k in fixed:
+        assert np.array_equal(Pg[k], g.poses_init[k])
+    pg.close()
+
+
 def test_determinism_and_graph_replay():
     g = graph("T")
     say("determinism / graph replay T")
