@@ -52,9 +52,10 @@ typedef enum {
 } pg_status;
 
 /* Solvers of the Gauss-Newton step (all exact up to rounding):
- * AUTO picks Gauss-Jordan when the augmented system fits one workgroup's LDS
- * (at most 21 free nodes), else Cholesky; PCG is the Jacobi-preconditioned
- * conjugate gradient the paper names (Sec. IV-D). */
+ * AUTO picks Gauss-Jordan (3x3 pivot blocks, rank-3 updates on the FP64 matrix
+ * cores, one workgroup per graph) when the system has at most 126 unknowns
+ * (21 free nodes), else Cholesky; PCG is the Jacobi-preconditioned conjugate
+ * gradient the paper names (Sec. IV-D). */
 enum { PG_SOLVER_AUTO = 0, PG_SOLVER_PCG = 1, PG_SOLVER_CHOLESKY = 2, PG_SOLVER_GAUSS_JORDAN = 3 };
 enum { PG_WEIGHT_HUBER = 0, PG_WEIGHT_LEARNED = 1 };
 enum { PG_PREC_FP32 = 0, PG_PREC_BF16X3 = 1 };

@@ -5,11 +5,17 @@
 //   assoc_kernel     dense projective association, point-to-plane residual of
 //                    Eq. (3), Jacobian, Huber IRLS weight and the per-item sum of
 //                    w J_i^T J_i, w r J_i, energy, count and target reads (30 values);
-//   feature_kernel   feature residual of Eq. (2) with its 3x12 Jacobian;
+//   feature_kernel   feature residual of Eq. (2): weighted second moments of
+//                    (1, p_m, p_n) per match set, expanded exactly into the
+//                    12x12 block and gradient of its 3x12 Jacobian (FP64);
 //   assemble_kernel  FP64 expansion of the per-pair sums into the 6x6 node
-//                    blocks of J^T W J and J^T W r, in a fixed order;
-//   solve_kernel     FP64 Cholesky (or Jacobi-PCG) solve over the free nodes,
-//                    T <- Exp(delta) T, and the next iteration's transforms.
+//                    blocks of J^T W J and J^T W r, in a fixed order (also
+//                    written as the free-node system [H_ff | -g_f]);
+//   gj_mfma_kernel   FP64 block Gauss-Jordan solve of the free-node system on
+//                    the matrix cores (default), or
+//   solve_kernel     FP64 Cholesky (or Jacobi-PCG) solve over the free nodes;
+//                    both then T <- Exp(delta) T and the next iteration's
+//                    transforms.
 //
 // The dense residual depends on the two poses only through A = T_i T_j^-1, so
 // its Jacobian w.r.t. a left perturbation of T_j is minus the Jacobian w.r.t.
@@ -1771,25 +1777,7 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
     compute_transforms(gd, Ts);
 }
 
-// ------------------------------------------------- register Gauss-Jordan
-
-
-// 3x3 inverse by cofactors (any invertible M, row-major); also the LU pivots
-// of M without pivoting (M00, the 2x2 Schur pivot, det / 2x2 minor)
-__device__ __forceinline__ void inv3_pivots(const double (&M)[9], double (&Mi)[9], double (&pv)[3])
-{
-    const double c00 = M[4] * M[8] - M[5] * M[7], c01 = M[2] * M[7] - M[1] * M[8], c02 = M[1] * M[5] - M[2] * M[4];
-    const double c10 = M[5] * M[6] - M[3] * M[8], c11 = M[0] * M[8] - M[2] * M[6], c12 = M[2] * M[3] - M[0] * M[5];
-    const double c20 = M[3] * M[7] - M[4] * M[6], c21 = M[1] * M[6] - M[0] * M[7], c22 = M[0] * M[4] - M[1] * M[3];
-    const double det = M[0] * c00 + M[1] * c10 + M[2] * c20;
-    const double id = 1.0 / det;
-    Mi[0] = c00 * id; Mi[1] = c01 * id; Mi[2] = c02 * id;
-    Mi[3] = c10 * id; Mi[4] = c11 * id; Mi[5] = c12 * id;
-    Mi[6] = c20 * id; Mi[7] = c21 * id; Mi[8] = c22 * id;
-    pv[0] = M[0];
-    pv[1] = c22 / M[0];
-    pv[2] = det / c22;
-}
+// ------------------------------------------------- Gauss-Jordan solve
 
 // 3x3 inverse by cofactors of a block expected symmetric positive definite,
 // all nine entries materialised; returns whether its LU (Schur) pivots M00,
@@ -1813,218 +1801,15 @@ __device__ __forceinline__ bool inv3_spd(const double (&M)[9], double (&Mi)[9], 
     return (M[0] > tol) && (c22 > tol * M[0]) && (det > tol * c22);
 }
 
-// One Gauss-Newton solve by block Gauss-Jordan elimination without pivoting
-// of the augmented system [H_ff | -g_f], with 3 x 3 pivot blocks (n = 6 x
-// free nodes is a multiple of 3).  H_ff is symmetric positive definite: the
-// LU pivots of each pivot block are the Schur-complement pivots of the
-// Cholesky factorisation, so the usual singularity test applies, and at the
-// end the right-hand column holds the solution (no back substitution).  The
-// n x (n+1) entries live in registers: thread (tr, tc) of a G x G grid owns
-// rows tr + Ga and columns tc + Gb (a, b < T).  Block step K: every thread
-// reads the 3 x 3 pivot block from the published row panel and inverts it
-// itself (cofactors: no communication), forms the normalised pivot rows
-// R = D^-1 RP for its own columns, and updates its entries: pivot rows take
-// R, other rows v -= v(i, block K) R.  The owners of the next block's three
-// columns and rows publish them to double-buffered LDS panels: one barrier per
-// block step.  Then the update T <- Exp(x) T and the next iteration's
-// transforms.
-template <int G, int T>
-__global__ __launch_bounds__(G * G) void gj_solve_kernel(const GraphDev* __restrict__ gds)
-{
-    const GraphDev& gd = gds[blockIdx.x];
-    const int N = gd.n_frames;
-    const int n = 6 * gd.n_free, n6 = 6 * N;
-    __shared__ double CP[2][kGjMaxN][3];          // column panel: v(i, 3K + l)
-    __shared__ double RP[2][3][kGjMaxN + 2];      // row panel: v(3K + l, j)
-    __shared__ double xs[kGjMaxN + 1];
-    __shared__ double Ts[16 * kMaxFrames];
-    __shared__ double ns[kMaxFrames * kNodeStats];
-    constexpr int kThreads = G * G;
-    __shared__ double scratch[(kThreads + 63) / 64];
-    __shared__ int sfree[kMaxFrames];
-    const int tid = threadIdx.x;
-    const int tr = tid / G, tc = tid % G;
-    if (*gd.status)
-        return;
-    const int it = *gd.iters_done;
-    for (int k = tid; k < 16 * N; k += kThreads)
-        Ts[k] = gd.poses[k];
-    for (int k = tid; k < kNodeStats * N; k += kThreads)
-        ns[k] = gd.node_stats[k];
-    for (int k = tid; k < gd.n_free; k += kThreads)
-        sfree[k] = gd.free_ids[k];
-    __syncthreads();
-    if (tid < kNodeStats) {
-        const int src[kNodeStats] = {1, 0, 2, 3, 4};   // E_f, E_g, n_g, n_f, target reads
-        double s = 0.0;
-        for (int k = 0; k < N; ++k)
-            s += ns[kNodeStats * k + src[tid]];
-        gd.iter_stats[kIterRecord * it + tid] = s;
-    }
-    if (n == 0) {
-        if (tid == 0)
-            *gd.iters_done = it + 1;
-        return;
-    }
-    int ri[T], cj[T];   // owned rows / columns, -1 beyond the matrix
-#pragma unroll
-    for (int a = 0; a < T; ++a) {
-        ri[a] = (tr + G * a < n) ? tr + G * a : -1;
-        cj[a] = (tc + G * a <= n) ? tc + G * a : -1;
-    }
-    // every load at once: clamped (always valid) addresses, validity applied after
-    double v[T][T];
-    double md = 0.0;
-#pragma unroll
-    for (int a = 0; a < T; ++a) {
-        const int i = ri[a] < 0 ? 0 : ri[a];
-        const int r = 6 * sfree[i / 6] + i % 6;
-        const double gr = gd.grad[r];
-#pragma unroll
-        for (int b = 0; b < T; ++b) {
-            const int j = cj[b] < 0 ? 0 : (cj[b] < n ? cj[b] : 0);
-            const double h = gd.Hm[(size_t)r * n6 + 6 * sfree[j / 6] + j % 6];
-            v[a][b] = (cj[b] == n) ? -gr : h;
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < T; ++a)
-#pragma unroll
-        for (int b = 0; b < T; ++b) {
-            const int i = ri[a], j = cj[b];
-            if (i < 0 || j < 0)
-                v[a][b] = 0.0;
-            if (i >= 0 && i == j)
-                md = fmax(md, v[a][b]);
-            if (i >= 0 && j >= 0 && j < 3)
-                CP[0][i][j] = v[a][b];
-            if (i >= 0 && i < 3 && j >= 0)
-                RP[0][i][j] = v[a][b];
-        }
-    const double maxdiag = block_max(md, scratch);   // includes barriers
-    const double tol = 1e-12 * maxdiag;
-    bool singular = !(maxdiag > 0.0);
-    for (int K = 0; 3 * K < n; ++K) {
-        const int bf = K & 1, c0 = 3 * K, c1 = c0 + 3;
-        // pivot block and its inverse (every thread, from the broadcast panel)
-        double D[9], Di[9], pv[3];
-#pragma unroll
-        for (int l = 0; l < 3; ++l)
-#pragma unroll
-            for (int m = 0; m < 3; ++m)
-                D[3 * l + m] = RP[bf][l][c0 + m];
-        double Cm[T][3], Rp[3][T];
-#pragma unroll
-        for (int a = 0; a < T; ++a)
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-                Cm[a][l] = CP[bf][ri[a] < 0 ? 0 : ri[a]][l];
-                Rp[l][a] = RP[bf][l][cj[a] < 0 ? 0 : cj[a]];
-            }
-        inv3_pivots(D, Di, pv);
-        singular |= !(pv[0] > tol) || !(pv[1] > tol) || !(pv[2] > tol);
-        // normalised pivot rows for the owned columns
-        double R[3][T];
-#pragma unroll
-        for (int l = 0; l < 3; ++l)
-#pragma unroll
-            for (int b = 0; b < T; ++b)
-                R[l][b] = fma(Di[3 * l], Rp[0][b], fma(Di[3 * l + 1], Rp[1][b], Di[3 * l + 2] * Rp[2][b]));
-        // Update.  Entries of rows beyond n and of eliminated columns are never
-        // read again (publishing takes live columns and rows only), so they
-        // are updated like the others instead of being masked; only the pivot
-        // rows, which can sit in two row slots at most, take R instead.
-        const int ap0 = c0 / G, ap1 = (c0 + 2) / G;   // uniform
-#pragma unroll
-        for (int b = 0; b < T; ++b) {
-            if (G * b + G - 1 < c1)   // every column of this slot is eliminated (uniform)
-                continue;
-#pragma unroll
-            for (int a = 0; a < T; ++a) {
-                const double upd = fma(-Cm[a][0], R[0][b], fma(-Cm[a][1], R[1][b], fma(-Cm[a][2], R[2][b], v[a][b])));
-                if (a == ap0 || a == ap1) {   // uniform
-                    const int l = ri[a] - c0;
-                    const double piv_row = (l == 0) ? R[0][b] : (l == 1) ? R[1][b] : R[2][b];
-                    v[a][b] = (l >= 0 && l < 3) ? piv_row : upd;
-                } else {
-                    v[a][b] = upd;
-                }
-            }
-        }
-        // publish the next block's three columns and rows (their owners only)
-        if (c1 < n) {
-            const int b0 = c1 / G, b1 = (c1 + 2) / G;   // slots holding them (uniform)
-#pragma unroll
-            for (int b = 0; b < T; ++b) {
-                if (b != b0 && b != b1)
-                    continue;
-                const int jc = cj[b] - c1;   // column index within the next block
-                if (jc >= 0 && jc < 3) {
-#pragma unroll
-                    for (int a = 0; a < T; ++a)
-                        if (ri[a] >= 0)
-                            CP[bf ^ 1][ri[a]][jc] = v[a][b];
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < T; ++a) {
-                if (a != b0 && a != b1)
-                    continue;
-                const int ir = ri[a] - c1;   // row index within the next block
-                if (ir >= 0 && ir < 3) {
-#pragma unroll
-                    for (int b = 0; b < T; ++b)
-                        if (cj[b] >= 0)
-                            RP[bf ^ 1][ir][cj[b]] = v[a][b];
-                }
-            }
-        }
-        __syncthreads();
-    }
-    if (__syncthreads_or(singular)) {
-        if (tid == 0)
-            *gd.status |= kStatusSingular;
-        return;
-    }
-    // the right-hand column holds the solution
-#pragma unroll
-    for (int a = 0; a < T; ++a)
-#pragma unroll
-        for (int b = 0; b < T; ++b)
-            if (ri[a] >= 0 && cj[b] == n)
-                xs[ri[a]] = v[a][b];
-    bool bad = false;
-    __syncthreads();
-    for (int a = tid; a < n; a += kThreads)
-        bad |= !isfinite(xs[a]);
-    if (__syncthreads_or(bad)) {
-        if (tid == 0)
-            *gd.status |= kStatusNonFinite;
-        return;
-    }
-    for (int a = tid; a < gd.n_free; a += kThreads) {
-        const int node = sfree[a];
-        double E[16], Tn[16];
-        se3_exp(xs + 6 * a, E);
-        mat4_mul(E, Ts + 16 * node, Tn);
-        for (int k = 0; k < 16; ++k) {
-            Ts[16 * node + k] = Tn[k];
-            gd.poses[16 * node + k] = Tn[k];
-        }
-    }
-    __syncthreads();
-    if (tid == 0)
-        *gd.iters_done = it + 1;
-    compute_transforms(gd, Ts);
-}
-
-// ------------------------------------------------- matrix-core Gauss-Jordan
-
 typedef double gj_d4 __attribute__((ext_vector_type(4)));
 
-// The same block Gauss-Jordan elimination (3 x 3 pivot blocks, no pivoting,
-// Schur-pivot singularity test, solution left in the right-hand column) with
-// the rank-3 update of each block step on the FP64 matrix cores.  The
+// One Gauss-Newton solve by block Gauss-Jordan elimination without pivoting
+// of the augmented system [H_ff | -g_f] (n = 6 x free nodes, a multiple of 3),
+// with 3 x 3 pivot blocks.  H_ff is symmetric positive definite: the LU pivots
+// of each pivot block are the Schur-complement pivots of the Cholesky
+// factorisation, so the usual singularity test applies, and at the end the
+// right-hand column holds the solution (no back substitution).  The rank-3
+// update of each block step runs on the FP64 matrix cores.  The
 // augmented n x (n+1) system is padded with zeros to NT x NT tiles of 16 x 16;
 // wave w of the four owns the tiles (tr, tc) with (tr + tc) mod 4 = w, so the
 // tile columns that elimination retires drop out of every wave alike.  A tile
@@ -2049,7 +1834,7 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
     constexpr int kM = 16 * NT;        // padded side
     const GraphDev& gd = gds[blockIdx.x];
     const int N = gd.n_frames;
-    const int n = 6 * gd.n_free, n6 = 6 * N;
+    const int n = 6 * gd.n_free;
     __shared__ double CP[2][3][kM];    // column panel v(i, 3K + m), by column
     __shared__ double RPn[2][3];       // right-hand side of the pivot rows v(3K + m, n)
     __shared__ double sink[256];       // publish target of the lanes that own nothing to publish
