@@ -30,6 +30,9 @@ HBM_PEAK_GBS = 8000.0
 # ordered pair, one float4 per target pixel read
 SRC_BYTES = 20
 TGT_BYTES = 16
+# the feature match sets run in the same launch: two float4 point records per
+# feature match
+FEAT_BYTES = 32
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assoc_paper_window_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2108_00516_amd", "csrc", "pg_kernels.hip")
 
@@ -242,7 +245,8 @@ def main():
     if ev is not None:
         el_ev, _, ms_phase, n_launch, _ = ev
         avg_s = assoc_ms / 1000.0
-        bytes_alg = SRC_BYTES * src + TGT_BYTES * reads0
+        n_feat = sum(len(m.uv_i) for m in g.matches)
+        bytes_alg = SRC_BYTES * src + TGT_BYTES * reads0 + FEAT_BYTES * n_feat
         achieved = bytes_alg / avg_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(),
@@ -399,7 +403,8 @@ def run_batch(args, graphs):
         for pg in pgs:
             pg.close()
         avg_s = ms[0] / launches / 1000.0
-        bytes_alg = SRC_BYTES * src + TGT_BYTES * reads
+        n_feat = sum(len(m.uv_i) for g in graphs for m in g.matches)
+        bytes_alg = SRC_BYTES * src + TGT_BYTES * reads + FEAT_BYTES * n_feat
         achieved = bytes_alg / avg_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "assoc_kernel",

@@ -66,6 +66,7 @@ struct GraphDev {
     const int* set_of;        // N*N: feature set of node pair, or -1
     float* xf32;              // per ordered pair: A (12) then B (12), rows of [R|t]
     double* xf64;             // per ordered pair: A (12)
+    double* tinv64;           // per node: T^-1 = [R^T | -R^T t] (12)
     double* poses;            // N * 16
     double* Hm;               // 6N * 6N normal matrix, row-major
     double* grad;             // 6N

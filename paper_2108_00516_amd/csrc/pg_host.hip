@@ -25,13 +25,12 @@ void launch_match_points(const float* di, const uint8_t* mi, const float* dj, co
                          const float* uvi, const float* uvj, int n, float4* out, hipStream_t st);
 int assoc_ppt_supported(int ppt);
 void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision, bool learned,
-                  int iteration, hipStream_t st);
+                  int iteration, const int2* fitems, int n_fitems, hipStream_t st);
 void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int iteration, int* target, float* r,
                         float* uv, float* feat, float* sigma, hipStream_t st);
 void launch_prune(const GraphDev* gds, const WorkItem* pitems, int n_pitems, const int2* pframes, int n_pframes,
                   hipStream_t st);
 void launch_mlp_to_float(const __half* p16, float* p32, hipStream_t st);
-void launch_feature(const GraphDev* gds, const int2* fitems, int n, hipStream_t st);
 void launch_assemble(const GraphDev* gds, const int2* nbs, int n, hipStream_t st);
 size_t solve_lds_bytes(int n_free, int n_frames);
 int gj_slots(int n_free);   // columns of the Gauss-Jordan system
@@ -124,7 +123,7 @@ struct pg_graph {
 
     // per-optimize device state
     DevBuf d_partials, d_fpartials, d_fpts, d_fsets, d_set_of, d_xf32, d_xf64, d_H, d_grad, d_node_stats,
-        d_free_ids, d_free_pos, d_Hff, d_n_src, d_pair_base, d_mlp;
+        d_free_ids, d_free_pos, d_Hff, d_tinv64, d_n_src, d_pair_base, d_mlp;
     // results of an optimize, one block read back with one copy (same layout
     // as the pinned host mirror): status, iterations done, per-iteration
     // records (kMaxIters), poses (max_frames)
@@ -343,6 +342,7 @@ pg_status prepare_graph(pg_graph* g)
     HIP_OR_FAIL(g, g->d_set_of.ensure(sizeof(int) * N * N));
     HIP_OR_FAIL(g, g->d_xf32.ensure(sizeof(float) * 24 * std::max(P, 1)));
     HIP_OR_FAIL(g, g->d_xf64.ensure(sizeof(double) * 12 * std::max(P, 1)));
+    HIP_OR_FAIL(g, g->d_tinv64.ensure(sizeof(double) * 12 * N));
     HIP_OR_FAIL(g, g->d_H.ensure(sizeof(double) * 36 * N * N));
     HIP_OR_FAIL(g, g->d_grad.ensure(sizeof(double) * 6 * N));
     HIP_OR_FAIL(g, g->d_node_stats.ensure(sizeof(double) * kNodeStats * N));
@@ -427,6 +427,7 @@ GraphDev make_dev(pg_graph* g)
     d.set_of = g->d_set_of.as<int>();
     d.xf32 = g->d_xf32.as<float>();
     d.xf64 = g->d_xf64.as<double>();
+    d.tinv64 = g->d_tinv64.as<double>();
     d.poses = g->dev_poses();
     d.Hm = g->d_H.as<double>();
     d.grad = g->d_grad.as<double>();
@@ -589,10 +590,12 @@ hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std
         const hipEvent_t* m = ev ? ev->data() + 1 + 5 * it : nullptr;
         if (m && (e = hipEventRecord(m[0], st)) != hipSuccess)
             return e;
-        launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
+        // the feature match sets run in the first blocks of the association
+        // launch (the timing slot of the features stays empty)
         if (m && (e = hipEventRecord(m[1], st)) != hipSuccess)
             return e;
-        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, it, st);
+        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, it,
+                     s.fitems.as<int2>(), s.n_fitems, st);
         if (m && (e = hipEventRecord(m[2], st)) != hipSuccess)
             return e;
         launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
@@ -1036,8 +1039,8 @@ pg_status pose_graph_linearize(pg_graph* g, double* H, double* grad, pg_stats* s
     hipStream_t st = g->stream;
     launch_solve(gds, 1, s.lds, 1, st);
     launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, st);
-    launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, st);
-    launch_feature(gds, s.fitems.as<int2>(), s.n_fitems, st);
+    launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, s.fitems.as<int2>(),
+                 s.n_fitems, st);
     launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
     HIP_OR_FAIL(g, hipGetLastError());
     const int N = g->n_frames;
@@ -1184,14 +1187,16 @@ pg_status pose_graph_time_assoc(pg_graph* g, int reps, double* ms_per_launch)
     const GraphDev* gds = s.gds.as<GraphDev>();
     launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, g->stream);
     // one untimed launch, then reps back-to-back launches between two events
-    launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, g->stream);
+    launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, s.fitems.as<int2>(),
+                 s.n_fitems, g->stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OR_FAIL(g, hipEventCreate(&e0));
     hipError_t e = hipEventCreate(&e1);
     if (e == hipSuccess)
         e = hipEventRecord(e0, g->stream);
     for (int k = 0; k < reps && e == hipSuccess; ++k) {
-        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, g->stream);
+        launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, s.fitems.as<int2>(),
+                     s.n_fitems, g->stream);
         e = hipGetLastError();
     }
     if (e == hipSuccess)

@@ -5,9 +5,10 @@
 //   assoc_kernel     dense projective association, point-to-plane residual of
 //                    Eq. (3), Jacobian, Huber IRLS weight and the per-item sum of
 //                    w J_i^T J_i, w r J_i, energy, count and target reads (30 values);
-//   feature_kernel   feature residual of Eq. (2): weighted second moments of
+//   feature_set      feature residual of Eq. (2): weighted second moments of
 //                    (1, p_m, p_n) per match set, expanded exactly into the
-//                    12x12 block and gradient of its 3x12 Jacobian (FP64);
+//                    12x12 block and gradient of its 3x12 Jacobian (FP64), in
+//                    the first blocks of the association launch;
 //   assemble_kernel  FP64 expansion of the per-pair sums into the 6x6 node
 //                    blocks of J^T W J and J^T W r, in a fixed order (also
 //                    written as the free-node system [H_ff | -g_f]);
@@ -234,6 +235,10 @@ __global__ void match_points_kernel(const float* __restrict__ depth_i, const uin
     out[2 * k + 1] = pn;
 }
 
+// one feature match set by one block (defined with the feature residuals);
+// the association kernels run it in their first blocks
+__device__ __forceinline__ void feature_set(const GraphDev* __restrict__ gds, int2 fi);
+
 // ------------------------------------------------------ dense association
 
 // Project source point p (frame-i camera) into frame j with B = T_j T_i^-1:
@@ -344,9 +349,17 @@ __device__ __forceinline__ void halve(float (&acc)[32], int lane)
 template <int PPT, bool LEARNED>
 __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __restrict__ gds,
                                                               const WorkItem* __restrict__ items, int n_items,
-                                                              int per_xcd, int iteration)
+                                                              int per_xcd, int iteration,
+                                                              const int2* __restrict__ fitems, int n_fitems)
 {
-    const int b = blockIdx.x;
+    // the first blocks (a multiple of 8) take the feature match sets
+    const int nf8 = (n_fitems + 7) & ~7;
+    if ((int)blockIdx.x < nf8) {
+        if ((int)blockIdx.x < n_fitems)
+            feature_set(gds, fitems[blockIdx.x]);
+        return;
+    }
+    const int b = blockIdx.x - nf8;
     const int L = (b & 7) * per_xcd + (b >> 3);
     if (L >= n_items)
         return;
@@ -486,9 +499,17 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <int PPT, bool LEARNED>
 __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const GraphDev* __restrict__ gds,
                                                                      const WorkItem* __restrict__ items,
-                                                                     int n_items, int per_xcd, int iteration)
+                                                                     int n_items, int per_xcd, int iteration,
+                                                                     const int2* __restrict__ fitems, int n_fitems)
 {
-    const int b = blockIdx.x;
+    // the first blocks (a multiple of 8) take the feature match sets
+    const int nf8 = (n_fitems + 7) & ~7;
+    if ((int)blockIdx.x < nf8) {
+        if ((int)blockIdx.x < n_fitems)
+            feature_set(gds, fitems[blockIdx.x]);
+        return;
+    }
+    const int b = blockIdx.x - nf8;
     const int L = (b & 7) * per_xcd + (b >> 3);
     if (L >= n_items)
         return;
@@ -963,6 +984,7 @@ __global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const Grap
 // the 12x12 upper triangle, the 12 gradient entries, energy and count
 // expanded from S in FP64, one output per thread.
 constexpr int kFeatThreads = 256;
+static_assert(kFeatThreads == kAssocThreads, "feature sets run in association blocks");
 
 template <int HALF, int OFF, typename T, int L>
 __device__ __forceinline__ void halve_at(T (&acc)[L], int lane)
@@ -1067,10 +1089,82 @@ __device__ __forceinline__ void feat_jac_sparse(const double* __restrict__ rho, 
     }
 }
 
-__global__ __launch_bounds__(kFeatThreads) void feature_kernel(const GraphDev* __restrict__ gds,
-                                                               const int2* __restrict__ fitems)
+// Sum 16 values acc[0..15] over the wave: on return acc[0] of lane l < 16
+// holds the total of value wave_sum16_index(l).
+template <int L>
+__device__ __forceinline__ void wave_sum16(double (&acc)[L], int lane)
 {
-    const int2 fi = fitems[blockIdx.x];
+    halve_bit<8, 0>(acc, lane);
+    halve_bit<4, 1>(acc, lane);
+    halve_bit<2, 3>(acc, lane);
+    halve_bit<1, 2>(acc, lane);
+    acc[0] += lane_swap<4>(acc[0]);
+    acc[0] += lane_swap<5>(acc[0]);
+}
+
+__device__ __forceinline__ int wave_sum16_index(int lane)
+{
+    return 8 * (lane & 1) + 4 * ((lane >> 1) & 1) + 2 * ((lane >> 3) & 1) + ((lane >> 2) & 1);
+}
+
+// Values 16 PASS .. 16 PASS + 15 of one match's 30 (the 28 weighted moments
+// w u_a u_c, a <= c, row-major, then the Huber energy and the count) added to
+// acc; false when the match is invalid.
+// a value equal on every lane, moved to scalar registers
+__device__ __forceinline__ double uniform_f64(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int PASS>
+__device__ __forceinline__ bool feature_match_values(const GraphDev& gd, const double (&A)[12], float4 qm,
+                                                     float4 qn, double ifx, double ify, double (&acc)[16])
+{
+    if (!(qm.w > 0.f))
+        return false;
+    const double huber = (double)gd.huber_f;
+    const double zm = qm.z, zn = qn.z;
+    const double u[7] = {1.0,
+                         zm * (((double)qm.x - gd.cx64) * ifx), zm * (((double)qm.y - gd.cy64) * ify), zm,
+                         zn * (((double)qn.x - gd.cx64) * ifx), zn * (((double)qn.y - gd.cy64) * ify), zn};
+    // |e| = |R_i^T (p_m - A p_n)| = |p_m - A p_n| with A = T_i T_j^-1
+    double ne2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const double d = u[1 + r] - (A[4 * r] * u[4] + A[4 * r + 1] * u[5] + A[4 * r + 2] * u[6] + A[4 * r + 3]);
+        ne2 = fma(d, d, ne2);
+    }
+    // |e| and the Huber weight through 1/|e| (hardware reciprocal square root
+    // and two Newton steps)
+    const double x = fmax(ne2, 1e-300);
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    const double ne = ne2 * y;
+    const double w = (ne <= huber) ? 1.0 : huber * y;
+    int q = 0;
+#pragma unroll
+    for (int a = 0; a < 7; ++a)
+#pragma unroll
+        for (int c = a; c < 7; ++c, ++q)
+            if (q >= 16 * PASS && q < 16 * PASS + 16)
+                acc[q - 16 * PASS] += (w * u[a]) * u[c];
+    if (PASS == 1) {
+        acc[28 - 16] += (ne <= huber) ? 0.5 * ne * ne : huber * (ne - 0.5 * huber);
+        acc[29 - 16] += 1.0;
+    }
+    return true;
+}
+
+// One match set (fi = {graph, set}) by one block of kFeatThreads threads: the
+// 30 sums in two passes of 16 (few registers, so the association kernels can
+// run it in some of their blocks), fixed-order wave and cross-wave sums, then
+// the expansion to the 92 outputs.
+__device__ __forceinline__ void feature_set(const GraphDev* __restrict__ gds, int2 fi)
+{
     const GraphDev& gd = gds[fi.x];
     if (*gd.status)
         return;
@@ -1078,54 +1172,40 @@ __global__ __launch_bounds__(kFeatThreads) void feature_kernel(const GraphDev* _
     __shared__ double Tinv[2][12];
     __shared__ double red[kFeatThreads / 64][32];
     __shared__ double Sm[7][8];  // the moments as a full symmetric matrix; [0][7], [1][7]: energy, count
-    if (threadIdx.x < 24) {
-        const int side = threadIdx.x / 12, e = threadIdx.x % 12, r = e / 4, c = e % 4;
-        const double* T = gd.poses + 16 * (side == 0 ? S.x : S.y);
-        // [R^T | -R^T t]
-        Tinv[side][e] = (c < 3) ? T[4 * c + r] : -(T[r] * T[3] + T[4 + r] * T[7] + T[8 + r] * T[11]);
-    }
-    __syncthreads();
-    const double huber = (double)gd.huber_f;
+    // T^-1 of both frames: uniform reads (scalar registers) in the match loop,
+    // an LDS copy for the expansion
+    const double* __restrict__ Ti_g = gd.tinv64 + 12 * S.x;
+    const double* __restrict__ Tj_g = gd.tinv64 + 12 * S.y;
+    if (threadIdx.x < 24)
+        Tinv[threadIdx.x / 12][threadIdx.x % 12] = (threadIdx.x < 12 ? Ti_g : Tj_g)[threadIdx.x % 12];
+    // A = T_i T_j^-1 of the ordered pair (i, j), in scalar registers
+    const double* __restrict__ A_g = gd.xf64 + 12 * pair_index(S.x, S.y, gd.n_frames);
+    double A[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        A[k] = uniform_f64(A_g[k]);
     const double ifx = 1.0 / gd.fx64, ify = 1.0 / gd.fy64;
-    double acc[32];
-#pragma unroll
-    for (int q = 0; q < 32; ++q)
-        acc[q] = 0.0;
-#pragma unroll 1
-    for (int k = threadIdx.x; k < S.w; k += kFeatThreads) {
-        const float4 qm = gd.fpts[2 * (S.z + k)];
-        const float4 qn = gd.fpts[2 * (S.z + k) + 1];
-        if (!(qm.w > 0.f))
-            continue;
-        const double zm = qm.z, zn = qn.z;
-        const double u[7] = {1.0,
-                             zm * (((double)qm.x - gd.cx64) * ifx), zm * (((double)qm.y - gd.cy64) * ify), zm,
-                             zn * (((double)qn.x - gd.cx64) * ifx), zn * (((double)qn.y - gd.cy64) * ify), zn};
-        double e[3];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const double* Ti = Tinv[0] + 4 * r;
-            const double* Tj = Tinv[1] + 4 * r;
-            e[r] = (Ti[0] * u[1] + Ti[1] * u[2] + Ti[2] * u[3] + Ti[3]) -
-                   (Tj[0] * u[4] + Tj[1] * u[5] + Tj[2] * u[6] + Tj[3]);
-        }
-        const double ne = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
-        const double w = (ne <= huber) ? 1.0 : huber / ne;
-        int q = 0;
-#pragma unroll
-        for (int a = 0; a < 7; ++a) {
-            const double wa = w * u[a];
-#pragma unroll
-            for (int c = a; c < 7; ++c)
-                acc[q++] += wa * u[c];
-        }
-        acc[28] += (ne <= huber) ? 0.5 * ne * ne : huber * (ne - 0.5 * huber);
-        acc[29] += 1.0;
-    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    wave_sum32(acc, lane);
-    if (lane < 32)
-        red[wave][wave_sum32_index(lane)] = acc[0];
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        double acc[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            acc[q] = 0.0;
+#pragma unroll 1
+        for (int k = threadIdx.x; k < S.w; k += kFeatThreads) {
+            const float4 qm = gd.fpts[2 * (S.z + k)];
+            const float4 qn = gd.fpts[2 * (S.z + k) + 1];
+            if (pass == 0)
+                feature_match_values<0>(gd, A, qm, qn, ifx, ify, acc);
+            else
+                feature_match_values<1>(gd, A, qm, qn, ifx, ify, acc);
+        }
+        wave_sum16(acc, lane);
+        if (lane < 16)
+            red[wave][16 * pass + wave_sum16_index(lane)] = acc[0];
+        __builtin_amdgcn_sched_barrier(0);   // the passes do not overlap (registers)
+    }
     __syncthreads();
     if (threadIdx.x < 30) {
         double v = red[0][threadIdx.x];
@@ -1503,10 +1583,15 @@ __device__ void mat4_mul(const double* A, const double* B, double* C)
 }
 
 // A = T_i T_j^-1, B = T_j T_i^-1 per ordered pair (FP64, stored FP32 and
-// FP64), from the poses in LDS.
+// FP64), and T^-1 per node (FP64), from the poses in LDS.
 __device__ void compute_transforms(const GraphDev& gd, const double* __restrict__ Ts)
 {
     const int N = gd.n_frames;
+    for (int q = threadIdx.x; q < 12 * N; q += blockDim.x) {
+        const double* T = Ts + 16 * (q / 12);
+        const int e = q % 12, r = e / 4, c = e % 4;
+        gd.tinv64[q] = (c < 3) ? T[4 * c + r] : -(T[r] * T[3] + T[4 + r] * T[7] + T[8 + r] * T[11]);
+    }
     for (int p = threadIdx.x; p < N * (N - 1); p += blockDim.x) {
         const int i = p / (N - 1), jj = p % (N - 1), j = (jj < i) ? jj : jj + 1;
         const double* Ti = Ts + 16 * i;
@@ -2067,16 +2152,16 @@ int assoc_ppt_supported(int ppt) { return ppt == 1 || ppt == 2 || ppt == 4 || pp
 
 template <bool LEARNED>
 static void launch_assoc_t(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision,
-                           int iteration, hipStream_t st)
+                           int iteration, const int2* fitems, int n_fitems, hipStream_t st)
 {
     const int per_xcd = (n_items + 7) / 8;
-    const int grid = 8 * per_xcd;
+    const int grid = ((n_fitems + 7) & ~7) + 8 * per_xcd;
 #define PG_ASSOC_LAUNCH(K)                                                                                  \
     switch (ppt) {                                                                                          \
-    case 1: K<1, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration); break;  \
-    case 2: K<2, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration); break;  \
-    case 8: K<8, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration); break;  \
-    default: K<4, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration); break; \
+    case 1: K<1, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration, fitems, n_fitems); break;  \
+    case 2: K<2, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration, fitems, n_fitems); break;  \
+    case 8: K<8, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration, fitems, n_fitems); break;  \
+    default: K<4, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration, fitems, n_fitems); break; \
     }
     if (precision == 1) {
         PG_ASSOC_LAUNCH(assoc_bf16x3_kernel)
@@ -2087,14 +2172,14 @@ static void launch_assoc_t(const GraphDev* gds, const WorkItem* items, int n_ite
 }
 
 void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision, bool learned,
-                  int iteration, hipStream_t st)
+                  int iteration, const int2* fitems, int n_fitems, hipStream_t st)
 {
-    if (n_items <= 0)
+    if (n_items <= 0 && n_fitems <= 0)
         return;
     if (learned)
-        launch_assoc_t<true>(gds, items, n_items, ppt, precision, iteration, st);
+        launch_assoc_t<true>(gds, items, n_items, ppt, precision, iteration, fitems, n_fitems, st);
     else
-        launch_assoc_t<false>(gds, items, n_items, ppt, precision, iteration, st);
+        launch_assoc_t<false>(gds, items, n_items, ppt, precision, iteration, fitems, n_fitems, st);
 }
 
 void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int iteration, int* target, float* r,
@@ -2122,12 +2207,6 @@ void launch_prune(const GraphDev* gds, const WorkItem* pitems, int n_pitems, con
         prune_score_kernel<<<n_pitems, kPruneThreads, 0, st>>>(gds, pitems);
     if (n_pframes > 0)
         prune_select_kernel<<<n_pframes * kSelectBlocks, kSelectThreads, 0, st>>>(gds, pframes);
-}
-
-void launch_feature(const GraphDev* gds, const int2* fitems, int n, hipStream_t st)
-{
-    if (n > 0)
-        feature_kernel<<<n, kFeatThreads, 0, st>>>(gds, fitems);
 }
 
 void launch_assemble(const GraphDev* gds, const int2* nbs, int n, hipStream_t st)
