@@ -242,8 +242,8 @@ __device__ __forceinline__ void feature_set(const GraphDev* __restrict__ gds, in
 // ------------------------------------------------------ dense association
 
 // Project source point p (frame-i camera) into frame j with B = T_j T_i^-1:
-// returns the nearest target pixel index, or -2 (behind the camera) / -3
-// (outside the image); (uf, vf) is the continuous projection.
+// returns the nearest target pixel packed as u | v << 16, or -2 (behind the
+// camera) / -3 (outside the image); (uf, vf) is the continuous projection.
 __device__ __forceinline__ int project_px(const float (&B)[12], float px, float py, float pz, const GraphDev& gd,
                                           float& uf, float& vf)
 {
@@ -260,19 +260,22 @@ __device__ __forceinline__ int project_px(const float (&B)[12], float px, float 
     const float ui = round_half_up(uf), vi = round_half_up(vf);
     if (!(ui >= 0.0f && ui < (float)gd.W && vi >= 0.0f && vi < (float)gd.H))
         return -3;
-    return (int)vi * gd.W + (int)ui;
+    return (int)ui | ((int)vi << 16);
 }
 
-// Finish the association with the gathered target t = {n_q, z_q} of pixel y:
-// -4 invalid target, -5 distance gate, -6 normal gate; else returns y with the
-// residual r = n . (A q - p) and J_i = [n, s x n] (s = A q).
+// row-major index of a packed pixel (u | v << 16)
+__device__ __forceinline__ int px_index(int pk, int W) { return (pk >> 16) * W + (pk & 0xffff); }
+
+// Finish the association with the gathered target t = {n_q, z_q} of the
+// packed pixel pk: -4 invalid target, -5 distance gate, -6 normal gate; else
+// returns pk with the residual r = n . (A q - p) and J_i = [n, s x n] (s = A q).
 __device__ __forceinline__ int finish_px(const float (&A)[12], float px, float py, float pz, float nx, float ny,
-                                         float nz, int y, float4 t, const GraphDev& gd, float& r,
+                                         float nz, int pk, float4 t, const GraphDev& gd, float& r,
                                          float (&J)[6], float& d2_out, float& c_out, float& sn_out)
 {
     if (!(t.w > 0.0f))
         return -4;
-    const int ui = y % gd.W, vi = y / gd.W;
+    const int ui = pk & 0xffff, vi = pk >> 16;
     const float qz = t.w;
     const float qx = qz * (((float)ui - gd.cx) * gd.ifx);
     const float qy = qz * (((float)vi - gd.cy) * gd.ify);
@@ -306,7 +309,7 @@ __device__ __forceinline__ int finish_px(const float (&A)[12], float px, float p
     J[3] = sy * nz - sz * ny;
     J[4] = sz * nx - sx * nz;
     J[5] = sx * ny - sy * nx;
-    return y;
+    return pk;
 }
 
 // ------------------------------------------------ learned weighting network
@@ -327,19 +330,50 @@ __device__ __forceinline__ void learned_features(const GraphDev& gd, float r, fl
 }
 
 
-// recursive-halving step of the wave reduction: lanes differing in bit
-// log2(2*HALF) exchange half of their values, each keeping the half its bit
-// selects, so 32 values reduce with 31 shuffles
-template <int HALF>
-__device__ __forceinline__ void halve(float (&acc)[32], int lane)
+// Value of v held by the partner lane across lane bit B (partner = lane ^
+// (1 << B)): DPP quad permutations for bits 0 and 1, a row rotation by 8 for
+// bit 3, bit-mask swizzles for bits 2 and 4, a permute for bit 5.
+template <int B>
+__device__ __forceinline__ float lane_swap_f32(float v)
 {
-    const bool up = (lane & (2 * HALF)) != 0;
+    const int x = __float_as_int(v);
+    if constexpr (B == 0)
+        return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false));    // quad_perm [1, 0, 3, 2]
+    else if constexpr (B == 1)
+        return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false));    // quad_perm [2, 3, 0, 1]
+    else if constexpr (B == 3)
+        return __int_as_float(__builtin_amdgcn_mov_dpp(x, 0x128, 0xF, 0xF, false));   // row_ror 8
+    else if constexpr (B == 2 || B == 4)
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(x, 0x1F | ((1 << B) << 10)));
+    else
+        return __shfl_xor(v, 1 << B);
+}
+
+// One recursive-halving level over lane bit B (lanes with the bit clear keep
+// values [0, HALF), the others [HALF, 2 HALF), moved to acc[0, HALF)).
+template <int HALF, int B>
+__device__ __forceinline__ void halve_bit_f32(float (&acc)[32], int lane)
+{
+    const bool up = (lane >> B) & 1;
 #pragma unroll
     for (int q = 0; q < HALF; ++q) {
         const float send = up ? acc[q] : acc[q + HALF];
         const float keep = up ? acc[q + HALF] : acc[q];
-        acc[q] = keep + __shfl_xor(send, 2 * HALF);
+        acc[q] = keep + lane_swap_f32<B>(send);
     }
+}
+
+// Sum acc[0..31] over the wave: lane l < 32 ends with the total of value
+// 16 b0 + 8 b1 + 4 b3 + 2 b2 + b4 (b the bits of l) in acc[0].
+__device__ __forceinline__ int wave_sum32_f32(float (&acc)[32], int lane)
+{
+    halve_bit_f32<16, 0>(acc, lane);
+    halve_bit_f32<8, 1>(acc, lane);
+    halve_bit_f32<4, 3>(acc, lane);
+    halve_bit_f32<2, 2>(acc, lane);
+    halve_bit_f32<1, 4>(acc, lane);
+    acc[0] += lane_swap_f32<5>(acc[0]);
+    return 16 * (lane & 1) + 8 * ((lane >> 1) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 2) & 1) + ((lane >> 4) & 1);
 }
 
 // One work item per block: PPT source pixels per thread of one frame-i tile,
@@ -422,7 +456,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     float4 t[PPT];
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-        t[m] = (y[m] >= 0) ? tmap[y[m]] : make_float4(0.f, 0.f, 0.f, 0.f);
+        t[m] = (y[m] >= 0) ? tmap[px_index(y[m], gd.W)] : make_float4(0.f, 0.f, 0.f, 0.f);
         acc[29] += (y[m] >= 0) ? 1.0f : 0.0f;
     }
 #pragma unroll
@@ -443,7 +477,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
         if (!gated)
             continue;
         const float ar = fabsf(r);
-        const float w = ((ar <= huber) ? 1.0f : huber / ar) * sg;
+        const float w = ((ar <= huber) ? 1.0f : huber * __builtin_amdgcn_rcpf(ar)) * sg;
         const float e = ((ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber)) * sg;
         float wJ[6];
 #pragma unroll
@@ -462,15 +496,10 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
         acc[28] += 1.0f;
     }
 
-    halve<16>(acc, lane);
-    halve<8>(acc, lane);
-    halve<4>(acc, lane);
-    halve<2>(acc, lane);
-    halve<1>(acc, lane);
-    acc[0] += __shfl_xor(acc[0], 1);   // lane l now holds value (l >> 1)
+    const int vidx = wave_sum32_f32(acc, lane);
     __shared__ float red[kAssocThreads / 64][32];
-    if ((lane & 1) == 0)
-        red[wave][lane >> 1] = acc[0];
+    if (lane < 32)
+        red[wave][vidx] = acc[0];
     __syncthreads();
     if (threadIdx.x < 32) {
         float v = red[0][threadIdx.x];
@@ -569,7 +598,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
     float4 t[PPT];
 #pragma unroll
     for (int m = 0; m < PPT; ++m)
-        t[m] = (y[m] >= 0) ? tmap[y[m]] : make_float4(0.f, 0.f, 0.f, 0.f);
+        t[m] = (y[m] >= 0) ? tmap[px_index(y[m], gd.W)] : make_float4(0.f, 0.f, 0.f, 0.f);
 
     float energy = 0.f, count = 0.f, reads = 0.f;
     f32x4 C = {0.f, 0.f, 0.f, 0.f};
@@ -593,7 +622,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
         }
         if (gated) {
             const float ar = fabsf(r);
-            const float w = ((ar <= huber) ? 1.0f : huber / ar) * sg;
+            const float w = ((ar <= huber) ? 1.0f : huber * __builtin_amdgcn_rcpf(ar)) * sg;
             energy += ((ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber)) * sg;
             count += 1.0f;
             const float sw = sqrtf(w);
@@ -687,8 +716,11 @@ __global__ __launch_bounds__(256) void assoc_debug_kernel(const GraphDev* __rest
         code = project_px(B, px, py, s.w, gd, uf, vf);
         if (code >= 0) {
             float J[6], rr, d2, c, sn;
-            const float4 t = gd.maps[(size_t)j * gd.HW + code];
+            const int yi = px_index(code, gd.W);
+            const float4 t = gd.maps[(size_t)j * gd.HW + yi];
             code = finish_px(A, px, py, s.w, s.x, s.y, s.z, code, t, gd, rr, J, d2, c, sn);
+            if (code >= 0)
+                code = yi;   // the target pixel's row-major index
             if (code >= 0) {
                 r = rr;
                 learned_features(gd, rr, d2, c, sn, s.w, (uint32_t)u | ((uint32_t)v << 16), iteration, f);
@@ -763,7 +795,7 @@ __global__ __launch_bounds__(kPruneThreads) void prune_score_kernel(const GraphD
             float uf, vf;
             const int y = project_px(B, px, py, s.w, gd, uf, vf);
             if (y >= 0) {
-                const float4 t = gd.maps[(size_t)j * gd.HW + y];
+                const float4 t = gd.maps[(size_t)j * gd.HW + px_index(y, gd.W)];
                 float r, J[6], d2, c, sn;
                 if (finish_px(A, px, py, s.w, s.x, s.y, s.z, y, t, gd, r, J, d2, c, sn) >= 0) {
                     gated = true;
