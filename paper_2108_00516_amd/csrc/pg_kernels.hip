@@ -263,6 +263,21 @@ __device__ __forceinline__ int project_px(const float (&B)[12], float px, float 
     return (int)ui | ((int)vi << 16);
 }
 
+// loads through the global address space (global_load instead of flat_load)
+template <typename T>
+__device__ __forceinline__ T ld_global(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
+typedef float pg_f4v __attribute__((ext_vector_type(4)));
+template <>
+__device__ __forceinline__ float4 ld_global<float4>(const float4* p)
+{
+    const pg_f4v v = *(const __attribute__((address_space(1))) pg_f4v*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // row-major index of a packed pixel (u | v << 16)
 __device__ __forceinline__ int px_index(int pk, int W) { return (pk >> 16) * W + (pk & 0xffff); }
 
@@ -443,8 +458,8 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
         px[m] = py[m] = 0.f;
         uvs[m] = 0;
         if (k < end) {
-            s[m] = src_nz[k];
-            const uint32_t uv = src_uv[k];
+            s[m] = ld_global(src_nz + k);
+            const uint32_t uv = ld_global(src_uv + k);
             uvs[m] = uv;
             const float z = s[m].w;
             px[m] = z * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
@@ -456,7 +471,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     float4 t[PPT];
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-        t[m] = (y[m] >= 0) ? tmap[px_index(y[m], gd.W)] : make_float4(0.f, 0.f, 0.f, 0.f);
+        t[m] = (y[m] >= 0) ? ld_global(tmap + px_index(y[m], gd.W)) : make_float4(0.f, 0.f, 0.f, 0.f);
         acc[29] += (y[m] >= 0) ? 1.0f : 0.0f;
     }
 #pragma unroll
@@ -585,8 +600,8 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
         px[m] = py[m] = 0.f;
         uvs[m] = 0;
         if (k < end) {
-            s[m] = src_nz[k];
-            const uint32_t uv = src_uv[k];
+            s[m] = ld_global(src_nz + k);
+            const uint32_t uv = ld_global(src_uv + k);
             uvs[m] = uv;
             const float z = s[m].w;
             px[m] = z * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
@@ -598,7 +613,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
     float4 t[PPT];
 #pragma unroll
     for (int m = 0; m < PPT; ++m)
-        t[m] = (y[m] >= 0) ? tmap[px_index(y[m], gd.W)] : make_float4(0.f, 0.f, 0.f, 0.f);
+        t[m] = (y[m] >= 0) ? ld_global(tmap + px_index(y[m], gd.W)) : make_float4(0.f, 0.f, 0.f, 0.f);
 
     float energy = 0.f, count = 0.f, reads = 0.f;
     f32x4 C = {0.f, 0.f, 0.f, 0.f};
@@ -1339,22 +1354,30 @@ constexpr int kMaxPairsPerBlock = 2 * (kMaxFrames - 1);
 constexpr int kMaxTgtPairs = kMaxFrames - 1;
 constexpr int kAsmChunks = 8;   // tile-sum chunks per field of an off-diagonal block
 
-// Sum of the partial records [t0, t1) of one field, in order, with four
-// interleaved accumulators (loads of a chunk are independent and in flight
-// together).
+constexpr int kSumBatch = 32;   // partial records of one field loaded together
+
+// Sum of the partial records [t0, t1) of one field in a fixed order: batches of
+// kSumBatch loads issued together (the tail of a batch reads an in-bounds
+// record and drops it), each summed as a pairwise tree, batches in order.
 __device__ __forceinline__ double sum_records(const float* __restrict__ src, int t0, int t1)
 {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int t = t0;
-    for (; t + 4 <= t1; t += 4) {
-        s0 += (double)src[(size_t)t * kDenseStride];
-        s1 += (double)src[(size_t)(t + 1) * kDenseStride];
-        s2 += (double)src[(size_t)(t + 2) * kDenseStride];
-        s3 += (double)src[(size_t)(t + 3) * kDenseStride];
+    double s = 0.0;
+    for (int t = t0; t < t1; t += kSumBatch) {
+        double v[kSumBatch];
+#pragma unroll
+        for (int k = 0; k < kSumBatch; ++k) {
+            const int tk = (t + k < t1) ? t + k : t1 - 1;
+            const float x = src[(size_t)tk * kDenseStride];
+            v[k] = (t + k < t1) ? (double)x : 0.0;
+        }
+#pragma unroll
+        for (int w = kSumBatch / 2; w > 0; w /= 2)
+#pragma unroll
+            for (int k = 0; k < w; ++k)
+                v[k] += v[k + w];
+        s += v[0];
     }
-    for (; t < t1; ++t)
-        s0 += (double)src[(size_t)t * kDenseStride];
-    return (s0 + s1) + (s2 + s3);
+    return s;
 }
 
 // One block per node block (I, J), I >= J, of the 6N x 6N system.  A diagonal
@@ -1374,8 +1397,9 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
 {
     const int2 nb = nbs[blockIdx.x];
     const GraphDev& gd = gds[nb.x];
-    if (*gd.status)
-        return;
+    // the reads of phase 1 are in bounds whatever the status holds: it is
+    // loaded with them and tested before anything is written
+    const int status = *gd.status;
     const int I = nb.y & 0xff, J = (nb.y >> 8) & 0xff;
     const int N = gd.n_frames, n6 = 6 * N;
     const int fI = gd.free_pos[I], fJ = gd.free_pos[J];   // free-node positions (-1: fixed)
@@ -1464,6 +1488,8 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
         }
     }
     __syncthreads();
+    if (status)
+        return;
     if (!diag) {
         // chunk sums of the two pairs, in chunk order
         if (threadIdx.x < 2 * kDenseFields) {
@@ -1944,6 +1970,10 @@ typedef double gj_d4 __attribute__((ext_vector_type(4)));
 // block's columns (and right-hand side) publish them to double-buffered LDS
 // panels: one barrier per block step.  Then the update T <- Exp(x) T and the next
 // iteration's transforms.
+// one block of 256 threads: two pose entries, a node-statistics entry and a
+// free-node id per thread at most
+static_assert(16 * kMaxFrames <= 2 * 256 && kNodeStats * kMaxFrames <= 256 && kMaxFrames <= 256, "GJ prologue");
+
 template <int NT>
 __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict__ gds)
 {
@@ -1982,15 +2012,27 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
                 acc[tr][s][v] = Hff[in ? (size_t)i * (n + 1) + j : 0];
             }
         }
+    // the poses, node statistics and free-node ids, loaded with the system
+    double tv[2], nv = 0.0;
+    int fv = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+        tv[u] = (tid + 256 * u < 16 * N) ? gd.poses[tid + 256 * u] : 0.0;
+    if (tid < kNodeStats * N)
+        nv = gd.node_stats[tid];
+    if (tid < gd.n_free)
+        fv = gd.free_ids[tid];
+    const int it = *gd.iters_done;
     if (*gd.status)
         return;
-    const int it = *gd.iters_done;
-    for (int k = tid; k < 16 * N; k += 256)
-        Ts[k] = gd.poses[k];
-    for (int k = tid; k < kNodeStats * N; k += 256)
-        ns[k] = gd.node_stats[k];
-    for (int k = tid; k < gd.n_free; k += 256)
-        sfree[k] = gd.free_ids[k];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+        if (tid + 256 * u < 16 * N)
+            Ts[tid + 256 * u] = tv[u];
+    if (tid < kNodeStats * N)
+        ns[tid] = nv;
+    if (tid < gd.n_free)
+        sfree[tid] = fv;
     if (tid == 0)
         sflags = 0;
     __syncthreads();
