@@ -1433,7 +1433,7 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
     // ---- phase 1: all global reads
     const int n_sum = diag ? np * kDenseFields : kAsmChunks * 2 * kDenseFields;
     const int n_ax = nt * 12;
-    const int n_fs = diag ? N * 44 : 36;
+    const int n_fs = diag ? N * 22 : 36;          // diagonal: two entries per task
     for (int task = threadIdx.x; task < n_sum + n_ax + n_fs; task += kAsmThreads) {
         if (task < n_sum) {
             int k, f, c;
@@ -1465,26 +1465,33 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
             AX[pk][q % 12] = gd.xf64[12 * pair_index(i, j, N) + q % 12];
         } else {
             const int q = task - n_sum - n_ax;
-            const int K = diag ? q / 44 : J, e = diag ? q % 44 : q;
-            double v = 0.0;
+            const int K = diag ? q / 22 : J, e0 = diag ? q % 22 : q;
+            double v0 = 0.0, v1 = 0.0;
             const int s = (K != I) ? gd.set_of[I * N + K] : -1;
             if (s >= 0) {
                 const double* F = gd.fpartials + (size_t)s * kFeatStride;
                 const bool first = gd.fsets[s].x == I;
                 if (diag) {
+                    // entry e of the neighbour's oriented block: H (36), g (6),
+                    // energy and count (once per set)
                     const int o = first ? 0 : 6;
-                    if (e < 36)
-                        v = sym12(F, o + e / 6, o + e % 6);
-                    else if (e < 42)
-                        v = F[78 + o + (e - 36)];
-                    else
-                        v = first ? F[90 + (e - 42)] : 0.0;   // energy and count once per set
+                    auto entry = [&](int e) {
+                        if (e < 36)
+                            return sym12(F, o + e / 6, o + e % 6);
+                        if (e < 42)
+                            return F[78 + o + (e - 36)];
+                        return first ? F[90 + (e - 42)] : 0.0;
+                    };
+                    v0 = entry(e0);
+                    v1 = entry(e0 + 22);
                 } else {
-                    const int a = e / 6, c = e % 6;
-                    v = first ? sym12(F, a, 6 + c) : sym12(F, 6 + a, c);
+                    const int a = e0 / 6, c = e0 % 6;
+                    v0 = first ? sym12(F, a, 6 + c) : sym12(F, 6 + a, c);
                 }
             }
-            FS[K][e] = v;
+            FS[K][e0] = v0;
+            if (diag)
+                FS[K][e0 + 22] = v1;
         }
     }
     __syncthreads();
