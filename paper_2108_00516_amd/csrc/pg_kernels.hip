@@ -449,18 +449,28 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     float px[PPT], py[PPT];
     int y[PPT];
     uint32_t uvs[PPT];
-    const int end = it.start + it.count;
+    const int end = it.start + it.count;   // count >= 1
+    // every source load in flight before the first projection: unconditional
+    // loads from a clamped (in-bounds) index, the pixels past the end dropped
+    // afterwards (a load under the per-pixel branch would wait for the
+    // previous pixel's projection)
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int k = it.start + threadIdx.x + m * kAssocThreads;
+        const int kc = (k < end) ? k : end - 1;
+        s[m] = ld_global(src_nz + kc);
+        uvs[m] = ld_global(src_uv + kc);
+    }
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         const int k = it.start + threadIdx.x + m * kAssocThreads;
         y[m] = -1;
-        s[m] = make_float4(0.f, 0.f, 0.f, 0.f);
         px[m] = py[m] = 0.f;
-        uvs[m] = 0;
-        if (k < end) {
-            s[m] = ld_global(src_nz + k);
-            const uint32_t uv = ld_global(src_uv + k);
-            uvs[m] = uv;
+        if (k >= end) {
+            s[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+            uvs[m] = 0;
+        } else {
+            const uint32_t uv = uvs[m];
             const float z = s[m].w;
             px[m] = z * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
             py[m] = z * (((float)(uv >> 16) - gd.cy) * gd.ify);
@@ -591,18 +601,28 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
     float px[PPT], py[PPT];
     int y[PPT];
     uint32_t uvs[PPT];
-    const int end = it.start + it.count;
+    const int end = it.start + it.count;   // count >= 1
+    // every source load in flight before the first projection: unconditional
+    // loads from a clamped (in-bounds) index, the pixels past the end dropped
+    // afterwards (a load under the per-pixel branch would wait for the
+    // previous pixel's projection)
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int k = it.start + threadIdx.x + m * kAssocThreads;
+        const int kc = (k < end) ? k : end - 1;
+        s[m] = ld_global(src_nz + kc);
+        uvs[m] = ld_global(src_uv + kc);
+    }
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         const int k = it.start + threadIdx.x + m * kAssocThreads;
         y[m] = -1;
-        s[m] = make_float4(0.f, 0.f, 0.f, 0.f);
         px[m] = py[m] = 0.f;
-        uvs[m] = 0;
-        if (k < end) {
-            s[m] = ld_global(src_nz + k);
-            const uint32_t uv = ld_global(src_uv + k);
-            uvs[m] = uv;
+        if (k >= end) {
+            s[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+            uvs[m] = 0;
+        } else {
+            const uint32_t uv = uvs[m];
             const float z = s[m].w;
             px[m] = z * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
             py[m] = z * (((float)(uv >> 16) - gd.cy) * gd.ify);
