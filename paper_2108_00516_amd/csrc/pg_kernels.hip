@@ -918,9 +918,26 @@ __global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const Grap
                 for (int q = 0; q < kSelectPer; ++q)
                     kk[q] = key[min(k0 + q, V - 1)];
 #pragma unroll
-                for (int q = 0; q < kSelectPer; ++q)
-                    if (k0 + q < V && (kk[q] & mask) == prefix)
-                        atomicAdd(&hist16[((kk[q] >> shift) & 255u) * kHistCopies + (lane & (kHistCopies - 1))], 1);
+                for (int q = 0; q < kSelectPer; ++q) {
+                    // wave-aggregated when every counted lane of the wave hits
+                    // one bin (the common case in the high passes, where the
+                    // scores share their exponent bits): one atomic with the
+                    // lane count instead of up to 64 on one address
+                    const bool in = k0 + q < V && (kk[q] & mask) == prefix;
+                    const unsigned int bin = (kk[q] >> shift) & 255u;
+                    const unsigned long long act = __ballot(in);
+                    if (act == 0ull)
+                        continue;
+                    const int fl = __ffsll((long long)act) - 1;
+                    const unsigned int b0 = (unsigned int)__shfl((int)bin, fl);
+                    const unsigned long long same = __ballot(in && bin == b0);
+                    if (same == act) {
+                        if (lane == fl)
+                            atomicAdd(&hist16[b0 * kHistCopies + (lane & (kHistCopies - 1))], (int)__popcll(act));
+                    } else if (in) {
+                        atomicAdd(&hist16[bin * kHistCopies + (lane & (kHistCopies - 1))], 1);
+                    }
+                }
             }
             __syncthreads();
             if (tid < 256) {
