@@ -244,7 +244,8 @@ __device__ __forceinline__ void feature_set(const GraphDev* __restrict__ gds, in
 // Project source point p (frame-i camera) into frame j with B = T_j T_i^-1:
 // returns the nearest target pixel packed as u | v << 16, or -2 (behind the
 // camera) / -3 (outside the image); (uf, vf) is the continuous projection.
-__device__ __forceinline__ int project_px(const float (&B)[12], float px, float py, float pz, const GraphDev& gd,
+template <typename Cam>
+__device__ __forceinline__ int project_px(const float (&B)[12], float px, float py, float pz, const Cam& gd,
                                           float& uf, float& vf)
 {
     const float qx = fmaf(B[0], px, fmaf(B[1], py, fmaf(B[2], pz, B[3])));
@@ -278,14 +279,32 @@ __device__ __forceinline__ float4 ld_global<float4>(const float4* p)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// The graph constants of the per-pixel projection and gating, read once into
+// scalar registers (the same names as in GraphDev, so the helpers above take
+// either): kept as opaque values, they are not reloaded under every pixel's
+// branch.
+struct PixelConsts {
+    float fx, fy, cx, cy, ifx, ify, gate_cos, gate_d2;
+    int W, H;
+};
+
+__device__ __forceinline__ PixelConsts pixel_consts(const GraphDev& gd)
+{
+    PixelConsts c{gd.fx, gd.fy, gd.cx, gd.cy, gd.ifx, gd.ify, gd.gate_cos, gd.gate_d2, gd.W, gd.H};
+    asm volatile("" : "+s"(c.fx), "+s"(c.fy), "+s"(c.cx), "+s"(c.cy), "+s"(c.ifx), "+s"(c.ify));
+    asm volatile("" : "+s"(c.gate_cos), "+s"(c.gate_d2), "+s"(c.W), "+s"(c.H));
+    return c;
+}
+
 // row-major index of a packed pixel (u | v << 16)
 __device__ __forceinline__ int px_index(int pk, int W) { return (pk >> 16) * W + (pk & 0xffff); }
 
 // Finish the association with the gathered target t = {n_q, z_q} of the
 // packed pixel pk: -4 invalid target, -5 distance gate, -6 normal gate; else
 // returns pk with the residual r = n . (A q - p) and J_i = [n, s x n] (s = A q).
+template <typename Cam>
 __device__ __forceinline__ int finish_px(const float (&A)[12], float px, float py, float pz, float nx, float ny,
-                                         float nz, int pk, float4 t, const GraphDev& gd, float& r,
+                                         float nz, int pk, float4 t, const Cam& gd, float& r,
                                          float (&J)[6], float& d2_out, float& c_out, float& sn_out)
 {
     if (!(t.w > 0.0f))
@@ -415,8 +434,10 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     const WorkItem it = items[L];
     const int gid = it.gij >> 16, i = it.gij & 0xff, j = (it.gij >> 8) & 0xff;
     const GraphDev& gd = gds[gid];
-    if (*gd.status)
-        return;
+    // the graph status is loaded with the first reads and tested before the
+    // sums are reduced (one memory round trip fewer ahead of the source
+    // loads); every read below is in bounds whatever it holds
+    const int status = *gd.status;
     const int p = pair_index(i, j, gd.n_frames);
     float A[12], B[12];
 #pragma unroll
@@ -461,6 +482,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
         s[m] = ld_global(src_nz + kc);
         uvs[m] = ld_global(src_uv + kc);
     }
+    const PixelConsts pc = pixel_consts(gd);   // after the loads are issued
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         const int k = it.start + threadIdx.x + m * kAssocThreads;
@@ -472,16 +494,16 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
         } else {
             const uint32_t uv = uvs[m];
             const float z = s[m].w;
-            px[m] = z * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
-            py[m] = z * (((float)(uv >> 16) - gd.cy) * gd.ify);
+            px[m] = z * (((float)(uv & 0xffffu) - pc.cx) * pc.ifx);
+            py[m] = z * (((float)(uv >> 16) - pc.cy) * pc.ify);
             float uf, vf;
-            y[m] = project_px(B, px[m], py[m], z, gd, uf, vf);
+            y[m] = project_px(B, px[m], py[m], z, pc, uf, vf);
         }
     }
     float4 t[PPT];
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
-        t[m] = (y[m] >= 0) ? ld_global(tmap + px_index(y[m], gd.W)) : make_float4(0.f, 0.f, 0.f, 0.f);
+        t[m] = (y[m] >= 0) ? ld_global(tmap + px_index(y[m], pc.W)) : make_float4(0.f, 0.f, 0.f, 0.f);
         acc[29] += (y[m] >= 0) ? 1.0f : 0.0f;
     }
 #pragma unroll
@@ -489,7 +511,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
         float r = 0.f, J[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, d2 = 0.f, cg = 0.f, sn = 0.f;
         bool gated = false;
         if (y[m] >= 0)
-            gated = finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J, d2, cg, sn) >= 0;
+            gated = finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], pc, r, J, d2, cg, sn) >= 0;
         float sg = 1.0f;
         if (LEARNED) {
             // the network runs wave-wide: every lane takes part, gated in or not
@@ -520,6 +542,8 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
         acc[27] += e;
         acc[28] += 1.0f;
     }
+    if (status)   // uniform over the block
+        return;
 
     const int vidx = wave_sum32_f32(acc, lane);
     __shared__ float red[kAssocThreads / 64][32];
@@ -570,8 +594,10 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
     const WorkItem it = items[L];
     const int gid = it.gij >> 16, i = it.gij & 0xff, j = (it.gij >> 8) & 0xff;
     const GraphDev& gd = gds[gid];
-    if (*gd.status)
-        return;
+    // the graph status is loaded with the first reads and tested before the
+    // sums are reduced (one memory round trip fewer ahead of the source
+    // loads); every read below is in bounds whatever it holds
+    const int status = *gd.status;
     const int p = pair_index(i, j, gd.n_frames);
     float A[12], B[12];
 #pragma unroll
@@ -613,6 +639,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
         s[m] = ld_global(src_nz + kc);
         uvs[m] = ld_global(src_uv + kc);
     }
+    const PixelConsts pc = pixel_consts(gd);   // after the loads are issued
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         const int k = it.start + threadIdx.x + m * kAssocThreads;
@@ -624,16 +651,16 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
         } else {
             const uint32_t uv = uvs[m];
             const float z = s[m].w;
-            px[m] = z * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
-            py[m] = z * (((float)(uv >> 16) - gd.cy) * gd.ify);
+            px[m] = z * (((float)(uv & 0xffffu) - pc.cx) * pc.ifx);
+            py[m] = z * (((float)(uv >> 16) - pc.cy) * pc.ify);
             float uf, vf;
-            y[m] = project_px(B, px[m], py[m], z, gd, uf, vf);
+            y[m] = project_px(B, px[m], py[m], z, pc, uf, vf);
         }
     }
     float4 t[PPT];
 #pragma unroll
     for (int m = 0; m < PPT; ++m)
-        t[m] = (y[m] >= 0) ? ld_global(tmap + px_index(y[m], gd.W)) : make_float4(0.f, 0.f, 0.f, 0.f);
+        t[m] = (y[m] >= 0) ? ld_global(tmap + px_index(y[m], pc.W)) : make_float4(0.f, 0.f, 0.f, 0.f);
 
     float energy = 0.f, count = 0.f, reads = 0.f;
     f32x4 C = {0.f, 0.f, 0.f, 0.f};
@@ -644,7 +671,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
         bool gated = false;
         if (y[m] >= 0) {
             reads += 1.0f;
-            gated = finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], gd, r, J, d2, cg, sn) >= 0;
+            gated = finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], pc, r, J, d2, cg, sn) >= 0;
         }
         float sg = 1.0f;
         if (LEARNED) {
@@ -683,6 +710,8 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
             C = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, ah, C, 0, 0, 0);
         }
     }
+    if (status)   // uniform over the block
+        return;
     for (int o = 32; o > 0; o >>= 1) {
         energy += __shfl_xor(energy, o);
         count += __shfl_xor(count, o);
