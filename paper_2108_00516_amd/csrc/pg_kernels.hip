@@ -1410,6 +1410,11 @@ __device__ __forceinline__ double sym6(const double* M, int a, int b)
     return (a <= b) ? M[upper_index(a, b, 6)] : M[upper_index(b, a, 6)];
 }
 
+__device__ __forceinline__ int sym12_index(int a, int b)
+{
+    return (a <= b) ? upper_index(a, b, 12) : upper_index(b, a, 12);
+}
+
 __device__ __forceinline__ double sym12(const double* F, int a, int b)
 {
     return (a <= b) ? F[upper_index(a, b, 12)] : F[upper_index(b, a, 12)];
@@ -1535,25 +1540,23 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
             double v0 = 0.0, v1 = 0.0;
             const int s = (K != I) ? gd.set_of[I * N + K] : -1;
             if (s >= 0) {
+                // the entries of both orientations depend only on the set: all
+                // loaded at once from computed (in-bounds) indices, the one of
+                // node I chosen when the set's first node is known
                 const double* F = gd.fpartials + (size_t)s * kFeatStride;
-                const bool first = gd.fsets[s].x == I;
-                if (diag) {
-                    // entry e of the neighbour's oriented block: H (36), g (6),
-                    // energy and count (once per set)
-                    const int o = first ? 0 : 6;
-                    auto entry = [&](int e) {
-                        if (e < 36)
-                            return sym12(F, o + e / 6, o + e % 6);
-                        if (e < 42)
-                            return F[78 + o + (e - 36)];
-                        return first ? F[90 + (e - 42)] : 0.0;
-                    };
-                    v0 = entry(e0);
-                    v1 = entry(e0 + 22);
-                } else {
-                    const int a = e0 / 6, c = e0 % 6;
-                    v0 = first ? sym12(F, a, 6 + c) : sym12(F, 6 + a, c);
-                }
+                // entry e of the neighbour's oriented block: H (36), g (6),
+                // energy and count (once per set, with the first node)
+                auto index = [&](int e, int o) {
+                    if (!diag)
+                        return sym12_index(e / 6 + o, e % 6 + 6 - o);
+                    return (e < 36) ? sym12_index(o + e / 6, o + e % 6) : (e < 42) ? 78 + o + (e - 36) : 90 + (e - 42);
+                };
+                const int e1 = diag ? e0 + 22 : e0;
+                const double a0 = F[index(e0, 0)], b0 = F[index(e0, 6)];
+                const double a1 = F[index(e1, 0)], b1 = F[index(e1, 6)];
+                const bool first = gd.fsets[s].x == I;   // loaded after the entries
+                v0 = first ? a0 : b0;                        // diagonal e0 < 22: an H entry
+                v1 = first ? a1 : ((e1 < 42) ? b1 : 0.0);
             }
             FS[K][e0] = v0;
             if (diag)
