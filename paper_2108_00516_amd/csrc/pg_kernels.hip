@@ -1848,10 +1848,12 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
     }
     // iteration record: one field per thread, nodes summed in order
     if (tid < kNodeStats) {
-        const int src[kNodeStats] = {1, 0, 2, 3, 4};   // E_f, E_g, n_g, n_f, target reads
+        // record fields E_f, E_g, n_g, n_f, target reads from node fields
+        // 1, 0, 2, 3, 4 (arithmetic, not a table in memory)
+        const int src = (tid < 2) ? 1 - tid : tid;
         double s = 0.0;
         for (int k = 0; k < N; ++k)
-            s += ns[kNodeStats * k + src[tid]];
+            s += ns[kNodeStats * k + src];
         gd.iter_stats[kIterRecord * it + tid] = s;
     }
     if (n == 0) {                                   // every node fixed
@@ -2099,7 +2101,11 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
     if (tid < gd.n_free)
         fv = gd.free_ids[tid];
     const int it = *gd.iters_done;
-    if (*gd.status)
+    const int status = *gd.status;
+    // both values in hand before the branch (the iteration counter is not
+    // loaded after it, one memory round trip later)
+    asm volatile("" ::"v"(it), "v"(status));
+    if (status)
         return;
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -2113,10 +2119,12 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
         sflags = 0;
     __syncthreads();
     if (tid < kNodeStats) {
-        const int src[kNodeStats] = {1, 0, 2, 3, 4};   // E_f, E_g, n_g, n_f, target reads
+        // record fields E_f, E_g, n_g, n_f, target reads from node fields
+        // 1, 0, 2, 3, 4 (arithmetic, not a table in memory)
+        const int src = (tid < 2) ? 1 - tid : tid;
         double s = 0.0;
         for (int k = 0; k < N; ++k)
-            s += ns[kNodeStats * k + src[tid]];
+            s += ns[kNodeStats * k + src];
         gd.iter_stats[kIterRecord * it + tid] = s;
     }
     if (n == 0) {
