@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--window", choices=["P", "X"], default="P",
                     help="paper workload window: P = 10 keyframes 640x480 (the headline), X = 20 keyframes 640x480")
     ap.add_argument("--tile", type=int, default=0, help="association tile (pixels); 0 = library choice")
+    ap.add_argument("--graph", type=int, default=0, choices=[0, 1],
+                    help="1: replay the timed steps from a captured hipGraph (default: direct launches)")
     ap.add_argument("--autotune", metavar="JSON", default="",
                     help="time every association tile for the workload, write the table to JSON and exit")
     ap.add_argument("--tune-table", default="", metavar="JSON",
@@ -171,7 +173,7 @@ def main():
         autotune.save(table, args.autotune)
         print(json.dumps(table), flush=True)
         return
-    cfg = Config(max_frames=g.n_frames, gn_iters=iters, use_graph=1, timing=0, tile_pixels=args.tile)
+    cfg = Config(max_frames=g.n_frames, gn_iters=iters, use_graph=args.graph, timing=0, tile_pixels=args.tile)
     pg = from_synth(g, cfg, device_inputs=True)
 
     def run(steps, timing):
@@ -344,7 +346,7 @@ def run_batch(args, graphs):
         tile = autotune.load(args.tune_table).get(autotune.BATCH_KEY, {}).get("tile", 0)
 
     def build(timing):
-        return [from_synth(g, Config(max_frames=g.n_frames, gn_iters=iters, use_graph=0 if timing else 1,
+        return [from_synth(g, Config(max_frames=g.n_frames, gn_iters=iters, use_graph=0 if timing else args.graph,
                                      timing=1 if timing else 0, tile_pixels=tile), device_inputs=True)
                 for g in graphs]
 

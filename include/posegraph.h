@@ -83,7 +83,7 @@ typedef struct {
     double pcg_rel_tol;         /* PCG stop: |r| <= tol |b| (default 1e-12)                  */
     int weighting;              /* PG_WEIGHT_HUBER (default) or PG_WEIGHT_LEARNED            */
     int precision;              /* PG_PREC_FP32 (default) or PG_PREC_BF16X3                  */
-    int use_graph;              /* 1 = replay the iteration loop as a captured hipGraph (1)  */
+    int use_graph;              /* 1 = replay the iteration loop as a captured hipGraph (0)  */
     int timing;                 /* 1 = HIP events around each kernel, launched directly (0)  */
     int tile_pixels;            /* source pixels per association work item, 0 = library pick */
     double prune_frac;          /* learned weighting: fraction of source pixels dropped (0.25) */

@@ -38,7 +38,7 @@ class Config:
     pcg_rel_tol: float = 1e-12
     weighting: int = L.PG_WEIGHT_HUBER
     precision: int = L.PG_PREC_FP32
-    use_graph: int = 1
+    use_graph: int = 0
     timing: int = 0
     tile_pixels: int = 0
     prune_frac: float = 0.25
