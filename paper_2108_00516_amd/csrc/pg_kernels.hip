@@ -2000,28 +2000,6 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
 
 // ------------------------------------------------- Gauss-Jordan solve
 
-// 3x3 inverse by cofactors of a block expected symmetric positive definite,
-// all nine entries materialised; returns whether its LU (Schur) pivots M00,
-// c22 / M00 and det / c22 all exceed tol, tested by products (no divisions).
-// 1/det: hardware reciprocal and two Newton steps.
-__device__ __forceinline__ bool inv3_spd(const double (&M)[9], double (&Mi)[9], double tol)
-{
-    const double c00 = M[4] * M[8] - M[5] * M[7], c01 = M[2] * M[7] - M[1] * M[8], c02 = M[1] * M[5] - M[2] * M[4];
-    const double c10 = M[5] * M[6] - M[3] * M[8], c11 = M[0] * M[8] - M[2] * M[6], c12 = M[2] * M[3] - M[0] * M[5];
-    const double c20 = M[3] * M[7] - M[4] * M[6], c21 = M[1] * M[6] - M[0] * M[7], c22 = M[0] * M[4] - M[1] * M[3];
-    const double det = M[0] * c00 + M[1] * c10 + M[2] * c20;
-    double id = __builtin_amdgcn_rcp(det);
-    id = fma(id, fma(-det, id, 1.0), id);
-    id = fma(id, fma(-det, id, 1.0), id);
-    Mi[0] = c00 * id; Mi[1] = c01 * id; Mi[2] = c02 * id;
-    Mi[3] = c10 * id; Mi[4] = c11 * id; Mi[5] = c12 * id;
-    Mi[6] = c20 * id; Mi[7] = c21 * id; Mi[8] = c22 * id;
-#pragma unroll
-    for (int k = 0; k < 9; ++k)
-        asm volatile("" : "+v"(Mi[k]));   // keep all nine (a lane selects its row afterwards)
-    return (M[0] > tol) && (c22 > tol * M[0]) && (det > tol * c22);
-}
-
 typedef double gj_d4 __attribute__((ext_vector_type(4)));
 
 // One Gauss-Newton solve by block Gauss-Jordan elimination without pivoting
@@ -2156,19 +2134,24 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
     const double maxdiag = block_max(md, scratch);   // includes barriers
     const double tol = 1e-12 * maxdiag;
     bool singular = !(maxdiag > 0.0);
-    // weights selecting row lr of D^-1 (all zero for the padding row k = 3)
-    const double w0 = (lr == 0) ? 1.0 : 0.0, w1 = (lr == 1) ? 1.0 : 0.0, w2 = (lr == 2) ? 1.0 : 0.0;
+    // the lane's row r of each pivot block's inverse (the padding row lr = 3
+    // computes row 0 and drops it) and the other two columns, cyclically
+    const int r0 = (lr < 3) ? lr : 0;
+    const int r1 = (r0 == 2) ? 0 : r0 + 1, r2 = (r0 == 0) ? 2 : r0 - 1;
     for (int K = 0; 3 * K < n; ++K) {
         const int bf = K & 1, c0 = 3 * K, c1 = c0 + 3;
         // pivot block and row panel from the column panel: the trailing part of
         // the system stays symmetric under elimination, so row c0 + m of it is
-        // column c0 + m; only the right-hand side of the pivot rows is separate
-        double D[9], Di[9];
+        // column c0 + m; only the right-hand side of the pivot rows is separate.
+        // Pivot block D, entry (l, m) = v(c0 + l, c0 + m) at CP[m][c0 + l]:
+        // the lane reads its columns r0, r1, r2
+        double d0[3], d1[3], d2[3];
 #pragma unroll
-        for (int l = 0; l < 3; ++l)
-#pragma unroll
-            for (int m = 0; m < 3; ++m)
-                D[3 * l + m] = CP[bf][m][c0 + l];
+        for (int l = 0; l < 3; ++l) {
+            d0[l] = CP[bf][r0][c0 + l];
+            d1[l] = CP[bf][r1][c0 + l];
+            d2[l] = CP[bf][r2][c0 + l];
+        }
         // operands of every owned tile, read together: A from the column panel,
         // the three panel entries of the lane's column for B
         double ca[NT], rb[NT][kS][3];
@@ -2184,12 +2167,28 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
                     rb[tr][s][m] = (j == n) ? RPn[bf][m] : CP[bf][m][j];
             }
         }
-        singular |= !inv3_spd(D, Di, tol);
-        // row lr of D^-1 (zero for the padding row k = 3)
+        // row r0 of D^-1 = cofactors (m, r0) / det, det expanded along column
+        // r0 (no full inverse per lane); 1/det by the hardware reciprocal and
+        // two Newton steps.  cof(m, r0) = D(m+1, r1) D(m+2, r2) - D(m+1, r2) D(m+2, r1)
+        double cf[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int m1 = (m + 1) % 3, m2 = (m + 2) % 3;
+            cf[m] = d1[m1] * d2[m2] - d2[m1] * d1[m2];
+        }
+        const double det = d0[0] * cf[0] + d0[1] * cf[1] + d0[2] * cf[2];
+        double id = __builtin_amdgcn_rcp(det);
+        id = fma(id, fma(-det, id, 1.0), id);
+        id = fma(id, fma(-det, id, 1.0), id);
+        // the LU (Schur) pivots D00, c22 / D00 and det / c22 of an SPD block all
+        // exceed tol (tested by products); lanes of row 2 hold D00 = d1[0] and
+        // c22 = cf[2]
+        if (lr == 2)
+            singular |= !((d1[0] > tol) && (cf[2] > tol * d1[0]) && (det > tol * cf[2]));
         double Dl[3];
 #pragma unroll
         for (int m = 0; m < 3; ++m)
-            Dl[m] = fma(w0, Di[m], fma(w1, Di[3 + m], w2 * Di[6 + m]));
+            Dl[m] = (lr < 3) ? cf[m] * id : 0.0;
         // A operand: -(C - E)(16 tr + lc, lr), E the unit entries of the pivot
         // rows, so the update leaves R in the pivot rows: V - C R + E R
         double a[NT];
