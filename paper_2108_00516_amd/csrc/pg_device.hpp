@@ -68,6 +68,7 @@ struct GraphDev {
     double* xf64;             // per ordered pair: A (12)
     double* tinv64;           // per node: T^-1 = [R^T | -R^T t] (12)
     double* poses;            // N * 16
+    const double* poses_in;   // N * 16, pinned host memory: the poses an optimize starts from
     double* Hm;               // 6N * 6N normal matrix, row-major
     double* grad;             // 6N
     double* node_stats;       // N * kNodeStats

@@ -429,6 +429,7 @@ GraphDev make_dev(pg_graph* g)
     d.xf64 = g->d_xf64.as<double>();
     d.tinv64 = g->d_tinv64.as<double>();
     d.poses = g->dev_poses();
+    d.poses_in = g->h_up;
     d.Hm = g->d_H.as<double>();
     d.grad = g->d_grad.as<double>();
     d.node_stats = g->d_node_stats.as<double>();
@@ -454,16 +455,14 @@ GraphDev make_dev(pg_graph* g)
 
 pg_status upload_poses(pg_graph* g)
 {
-    if (!g->poses_dirty)
-        return PG_OK;
-    // staged through pinned memory: the copy is truly asynchronous, ordered
-    // before the work that follows on the stream; the staging buffer is
-    // reused only once the previous upload from it has completed
+    // the start kernel (solve_kernel, mode 1) reads the poses straight from
+    // this pinned staging buffer (no copy launch).  The host mirror equals
+    // the device poses after every optimize, so the buffer always gets the
+    // mirror; it is rewritten only once the previous start kernel reading it
+    // has completed (the entry points synchronise their stream, the one that
+    // does not records up_done)
     HIP_OR_FAIL(g, hipEventSynchronize(g->up_done));
     memcpy(g->h_up, g->poses.data(), sizeof(double) * 16 * g->n_frames);
-    HIP_OR_FAIL(g, hipMemcpyAsync(g->dev_poses(), g->h_up, sizeof(double) * 16 * g->n_frames,
-                                  hipMemcpyHostToDevice, g->stream));
-    HIP_OR_FAIL(g, hipEventRecord(g->up_done, g->stream));
     g->poses_dirty = false;
     return PG_OK;
 }
@@ -1135,6 +1134,7 @@ static pg_status ready_single(pg_graph* g)
         return rc;
     launch_solve(g->sched->gds.as<GraphDev>(), 1, g->sched->lds, 1, g->stream);
     HIP_OR_FAIL(g, hipGetLastError());
+    HIP_OR_FAIL(g, hipEventRecord(g->up_done, g->stream));   // the staging buffer is read until then
     return PG_OK;
 }
 

@@ -1817,8 +1817,13 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
     __shared__ int sfree[kMaxFrames];
     const int tid = threadIdx.x;
 
-    for (int k = tid; k < 16 * N; k += blockDim.x)
-        Ts[k] = gd.poses[k];
+    // mode 1 takes the poses from the pinned staging buffer of the host
+    for (int k = tid; k < 16 * N; k += blockDim.x) {
+        const double v = (mode == 1) ? gd.poses_in[k] : gd.poses[k];
+        Ts[k] = v;
+        if (mode == 1)
+            gd.poses[k] = v;
+    }
     if (mode == 1) {
         if (tid == 0) {
             *gd.status = 0;
