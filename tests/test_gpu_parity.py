@@ -368,3 +368,30 @@ def test_abi_errors_on_gpu():
     assert e.value.status == _lib.PG_ERR_INVALID_ARG
     pg.close()
     pg.close()  # destroy is NULL-safe / idempotent in the binding
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_zero_iterations_and_continuation(use_graph):
+    """Zero iterations return the start poses (no solve runs, the result block
+    is copied back); a second optimize without set_poses starts from the
+    first one's result (the start kernel reads the host mirror of the device
+    poses): its first record is the energy at those poses, not at the start."""
+    g = graph("T")
+    say(f"zero iterations and continuation T, use_graph={use_graph}")
+    pg0 = gpu_graph(g, gn_iters=0, use_graph=use_graph)
+    st0 = pg0.optimize()
+    assert st0["iters_done"] == 0
+    assert np.array_equal(pg0.poses, g.poses_init)
+    pg0.close()
+    pg = gpu_graph(g, gn_iters=3, use_graph=use_graph)
+    st1 = pg.optimize()
+    P1 = pg.poses
+    st2 = pg.optimize()
+    assert st1["iters_done"] == 3 and st2["iters_done"] == 3
+    ob = oracle.OracleProblem.from_synth(g)
+    _, s_at_p1 = ob.optimize(P1, 1)
+    say(f"  first energy: first optimize {st1['energy_g'][0]:.6e}, second {st2['energy_g'][0]:.6e}, "
+        f"oracle at the first result {s_at_p1['energy_g'][0]:.6e}")
+    assert np.isclose(st2["energy_g"][0], s_at_p1["energy_g"][0], rtol=1e-3)
+    assert not np.isclose(st2["energy_g"][0], st1["energy_g"][0], rtol=1e-3)
+    pg.close()
