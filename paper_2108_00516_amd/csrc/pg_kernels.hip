@@ -1484,6 +1484,7 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
     __shared__ double X[kMaxTgtPairs][42];       // off-diagonal blocks: chunk sums
     __shared__ double AX[kMaxTgtPairs][12];      // A = T_i T_j^-1 of the expanded pairs (FP64)
     __shared__ double FS[kMaxFrames][44];        // oriented feature entries per neighbour
+    __shared__ double ADJ[kMaxTgtPairs][36];     // the adjoints Ad of the expanded pairs
     double* const chunk = &X[0][0];
 
     // pair k: diagonal: k < N-1 (I, j), else (i, I); off-diagonal: (I, J), (J, I)
@@ -1566,24 +1567,29 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
     __syncthreads();
     if (status)
         return;
+    // the adjoints of the expanded pairs, once (phases 2 and 3 read them),
+    // and on off-diagonal blocks the chunk sums of the two pairs, in chunk
+    // order, by other threads (the adjoints take the first 72 there)
+    for (int task = threadIdx.x; task < nt * 36; task += kAsmThreads)
+        ADJ[task / 36][task % 36] = adj(AX[task / 36], (task % 36) / 6, task % 6);
     if (!diag) {
-        // chunk sums of the two pairs, in chunk order
-        if (threadIdx.x < 2 * kDenseFields) {
-            const int k = threadIdx.x / kDenseFields, f = threadIdx.x % kDenseFields;
+        const int t = (int)threadIdx.x - kAsmThreads / 2;
+        if (t >= 0 && t < 2 * kDenseFields) {
+            const int k = t / kDenseFields, f = t % kDenseFields;
             double v = 0.0;
             for (int c = 0; c < kAsmChunks; ++c)
                 v += chunk[c * 2 * kDenseFields + k * kDenseFields + f];
             S[k][f] = v;
         }
-        __syncthreads();
     }
+    __syncthreads();
     // ---- phase 2: P = M Ad of the expanded pairs
     for (int task = threadIdx.x; task < nt * 36; task += kAsmThreads) {
         const int pk = task / 36, e = task % 36, a = e / 6, c = e % 6;
         const double* Sk = S[kt0 + pk];
         double v = 0.0;
         for (int l = 0; l < 6; ++l)
-            v += sym6(Sk, a, l) * adj(AX[pk], l, c);
+            v += sym6(Sk, a, l) * ADJ[pk][6 * l + c];
         P[pk][e] = v;
     }
     __syncthreads();
@@ -1606,17 +1612,16 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
     // ---- phase 3 (diagonal): target-role terms Ad^T M Ad (upper) and -Ad^T v
     for (int task = threadIdx.x; task < nt * 42; task += kAsmThreads) {
         const int pk = task / 42, e = task % 42;
-        const double* Xa = AX[pk];
         double v = 0.0;
         if (e < 36) {
             const int a = e / 6, c = e % 6;
             if (a <= c)
                 for (int l = 0; l < 6; ++l)
-                    v += adj(Xa, l, a) * P[pk][6 * l + c];
+                    v += ADJ[pk][6 * l + a] * P[pk][6 * l + c];
         } else {
             const int a = e - 36;
             for (int l = 0; l < 6; ++l)
-                v -= adj(Xa, l, a) * S[kt0 + pk][21 + l];
+                v -= ADJ[pk][6 * l + a] * S[kt0 + pk][21 + l];
         }
         X[pk][e] = v;
     }
