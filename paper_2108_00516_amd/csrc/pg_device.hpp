@@ -67,6 +67,8 @@ struct GraphDev {
     float* xf32;              // per ordered pair: A (12) then B (12), rows of [R|t]
     double* xf64;             // per ordered pair: A (12)
     double* tinv64;           // per node: T^-1 = [R^T | -R^T t] (12)
+    unsigned long long* maxdiag;  // bits of the largest positive diagonal entry of H_ff (an atomic
+                                  // maximum by the assembly; cleared by the start and by each solve)
     double* poses;            // N * 16
     const double* poses_in;   // N * 16, pinned host memory: the poses an optimize starts from
     double* Hm;               // 6N * 6N normal matrix, row-major

@@ -123,7 +123,7 @@ struct pg_graph {
 
     // per-optimize device state
     DevBuf d_partials, d_fpartials, d_fpts, d_fsets, d_set_of, d_xf32, d_xf64, d_H, d_grad, d_node_stats,
-        d_free_ids, d_free_pos, d_Hff, d_tinv64, d_n_src, d_pair_base, d_mlp;
+        d_free_ids, d_free_pos, d_Hff, d_tinv64, d_maxdiag, d_n_src, d_pair_base, d_mlp;
     // results of an optimize, one block read back with one copy (same layout
     // as the pinned host mirror): status, iterations done, per-iteration
     // records (kMaxIters), poses (max_frames)
@@ -343,6 +343,7 @@ pg_status prepare_graph(pg_graph* g)
     HIP_OR_FAIL(g, g->d_xf32.ensure(sizeof(float) * 24 * std::max(P, 1)));
     HIP_OR_FAIL(g, g->d_xf64.ensure(sizeof(double) * 12 * std::max(P, 1)));
     HIP_OR_FAIL(g, g->d_tinv64.ensure(sizeof(double) * 12 * N));
+    HIP_OR_FAIL(g, g->d_maxdiag.ensure(sizeof(unsigned long long)));
     HIP_OR_FAIL(g, g->d_H.ensure(sizeof(double) * 36 * N * N));
     HIP_OR_FAIL(g, g->d_grad.ensure(sizeof(double) * 6 * N));
     HIP_OR_FAIL(g, g->d_node_stats.ensure(sizeof(double) * kNodeStats * N));
@@ -428,6 +429,7 @@ GraphDev make_dev(pg_graph* g)
     d.xf32 = g->d_xf32.as<float>();
     d.xf64 = g->d_xf64.as<double>();
     d.tinv64 = g->d_tinv64.as<double>();
+    d.maxdiag = g->d_maxdiag.as<unsigned long long>();
     d.poses = g->dev_poses();
     d.poses_in = g->h_up;
     d.Hm = g->d_H.as<double>();

@@ -1644,6 +1644,11 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
             if (fI >= 0) {
                 gd.Hff[(size_t)(6 * fI + e / 6) * nf1 + 6 * fI + e % 6] = h;
                 gd.Hff[(size_t)(6 * fI + e % 6) * nf1 + 6 * fI + e / 6] = h;
+                // the largest positive diagonal entry of H_ff for the solve's
+                // singularity tolerance: an atomic maximum of the bit patterns,
+                // which order like the values for positive doubles
+                if (e / 6 == e % 6 && h > 0.0)
+                    atomicMax(gd.maxdiag, (unsigned long long)__double_as_longlong(h));
             }
         } else {
             gd.grad[6 * I + (e - 36)] = h;
@@ -1833,6 +1838,7 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
         if (tid == 0) {
             *gd.status = 0;
             *gd.iters_done = 0;
+            *gd.maxdiag = 0ull;
         }
         __syncthreads();
         compute_transforms(gd, Ts);
@@ -2054,7 +2060,6 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
     __shared__ double xs[kM];
     __shared__ double Ts[16 * kMaxFrames];
     __shared__ double ns[kMaxFrames * kNodeStats];
-    __shared__ double scratch[4];
     __shared__ int sfree[kMaxFrames];
     __shared__ int sflags;             // 1: singular pivot, 2: non-finite solution
     const int tid = threadIdx.x, lane = tid & 63;
@@ -2063,7 +2068,6 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
     // the owned tiles of [H_ff | -g_f], every load issued first, from clamped
     // addresses (padding applied once the system size is checked)
     gj_d4 acc[NT][kS];
-    double md = 0.0;
     const double* __restrict__ Hff = gd.Hff;
 #pragma unroll
     for (int tr = 0; tr < NT; ++tr)
@@ -2090,6 +2094,7 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
         fv = gd.free_ids[tid];
     const int it = *gd.iters_done;
     const int status = *gd.status;
+    const double maxdiag = __longlong_as_double((long long)*gd.maxdiag);   // written by the assembly
     // both values in hand before the branch (the iteration counter is not
     // loaded after it, one memory round trip later)
     asm volatile("" ::"v"(it), "v"(status));
@@ -2133,15 +2138,13 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
                 const bool in = tc < NT && i < n && j <= n;
                 const double h = in ? acc[tr][s][v] : 0.0;
                 acc[tr][s][v] = h;
-                if (in && i == j)
-                    md = fmax(md, h);
                 if (tc < NT && j < 3)
                     CP[0][j][i] = h;
                 if (in && i < 3 && j == n)
                     RPn[0][i] = h;
             }
         }
-    const double maxdiag = block_max(md, scratch);   // includes barriers
+    __syncthreads();   // padding and first panels
     const double tol = 1e-12 * maxdiag;
     bool singular = !(maxdiag > 0.0);
     // the lane's row r of each pivot block's inverse (the padding row lr = 3
@@ -2274,6 +2277,10 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
         atomicOr(&sflags, (singular ? 1 : 0) | (bad ? 2 : 0));
     __syncthreads();
     const int flags = sflags;
+    // every thread has used the diagonal maximum by now: cleared for the
+    // next iteration's assembly
+    if (tid == 0)
+        *gd.maxdiag = 0ull;
     if (flags) {
         if (tid == 0)
             *gd.status |= (flags & 1) ? kStatusSingular : kStatusNonFinite;
