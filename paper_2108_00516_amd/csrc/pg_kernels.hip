@@ -941,18 +941,20 @@ __global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const Grap
             for (int q = tid; q < 256 * kHistCopies; q += kSelectThreads)
                 hist16[q] = 0;
             __syncthreads();
-            for (int k0 = tid * kSelectPer; k0 < V; k0 += kSelectThreads * kSelectPer) {
+            // coalesced: entry k0 + q kSelectThreads + tid (a histogram does
+            // not depend on which thread counts an entry)
+            for (int k0 = 0; k0 < V; k0 += kSelectThreads * kSelectPer) {
                 unsigned int kk[kSelectPer];
 #pragma unroll
                 for (int q = 0; q < kSelectPer; ++q)
-                    kk[q] = key[min(k0 + q, V - 1)];
+                    kk[q] = key[min(k0 + q * kSelectThreads + tid, V - 1)];
 #pragma unroll
                 for (int q = 0; q < kSelectPer; ++q) {
                     // wave-aggregated when every counted lane of the wave hits
                     // one bin (the common case in the high passes, where the
                     // scores share their exponent bits): one atomic with the
                     // lane count instead of up to 64 on one address
-                    const bool in = k0 + q < V && (kk[q] & mask) == prefix;
+                    const bool in = k0 + q * kSelectThreads + tid < V && (kk[q] & mask) == prefix;
                     const unsigned int bin = (kk[q] >> shift) & 255u;
                     const unsigned long long act = __ballot(in);
                     if (act == 0ull)
@@ -1023,15 +1025,16 @@ __global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const Grap
     const int s1 = (int)(((long long)V * (seg + 1)) / kSelectBlocks);
     int n_lt = 0, n_eq = 0;
     if (drop > 0)
-        for (int k0 = tid * kSelectPer; k0 < s0; k0 += kSelectThreads * kSelectPer) {
+        for (int k0 = 0; k0 < s0; k0 += kSelectThreads * kSelectPer) {   // coalesced, as above
             unsigned int kk[kSelectPer];
 #pragma unroll
             for (int q = 0; q < kSelectPer; ++q)
-                kk[q] = key[min(k0 + q, V - 1)];
+                kk[q] = key[min(k0 + q * kSelectThreads + tid, V - 1)];
 #pragma unroll
             for (int q = 0; q < kSelectPer; ++q) {
-                n_lt += (k0 + q < s0 && kk[q] < tau) ? 1 : 0;
-                n_eq += (k0 + q < s0 && kk[q] == tau) ? 1 : 0;
+                const bool in = k0 + q * kSelectThreads + tid < s0;
+                n_lt += (in && kk[q] < tau) ? 1 : 0;
+                n_eq += (in && kk[q] == tau) ? 1 : 0;
             }
         }
     int lt_before, eq_seen;
