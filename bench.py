@@ -192,7 +192,7 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0, st, ms, launches, reads
 
-    # graph-replayed schedule: the timed steps of 'value'
+    # the timed steps of 'value' (direct launches, or the graph replay with --graph 1)
     for _ in range(args.warmup):
         pg.set_poses(g.poses_init)
         pg.optimize()
@@ -275,7 +275,7 @@ WEIGHTS = os.path.join(ROOT, "paper_2108_00516_amd", "weights", "weightnet.npy")
 
 def other_forms(g, iters, P_plain, steps, tile):
     """The learned (25% of source pixels pruned), BF16x3 and combined forms on
-    the same window: GN iterations/s over graph-replayed steps and the largest
+    the same window: GN iterations/s over the same kind of steps and the largest
     pose difference to the plain FP32 result; pose error of each against the
     generator's ground truth."""
     import numpy as np
@@ -331,8 +331,8 @@ def _make_batch_graph(k):
 
 def run_batch(args, graphs):
     """64 independent windows of uneven node counts (4-20) and resolutions in
-    one batched schedule: one launch per phase for all graphs, the 7
-    iterations replayed as one hipGraph.  value = graph-iterations per second
+    one batched schedule: one launch per phase for all graphs, 7 iterations
+    per step (direct launches, or one hipGraph with --graph 1).  value = graph-iterations per second
     (GN iterations summed over the graphs)."""
     import numpy as np
     import torch
