@@ -123,7 +123,7 @@ def main():
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (to scale HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported "
               "(independent windows shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
