@@ -452,12 +452,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // learned weighting: network operands (registers) and output-layer constants (LDS)
     __shared__ __attribute__((aligned(16))) float s_tail[kMlpTail];
-    MlpFrags M;
-    if (LEARNED) {
-        mlp_tail_load(gd.mlp32, s_tail);
-        mlp_frags_load(gd.mlp32, M, lane);
-        __syncthreads();
-    }
+    MlpFrags M;   // loaded after the source records are in flight (one memory round trip)
 
     float acc[32];
 #pragma unroll
@@ -481,6 +476,11 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
         const int kc = (k < end) ? k : end - 1;
         s[m] = ld_global(src_nz + kc);
         uvs[m] = ld_global(src_uv + kc);
+    }
+    if (LEARNED) {
+        mlp_tail_load(gd.mlp32, s_tail);
+        mlp_frags_load(gd.mlp32, M, lane);
+        __syncthreads();
     }
     const PixelConsts pc = pixel_consts(gd);   // after the loads are issued
 #pragma unroll
@@ -612,12 +612,7 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // learned weighting: network operands (registers) and output-layer constants (LDS)
     __shared__ __attribute__((aligned(16))) float s_tail[kMlpTail];
-    MlpFrags M;
-    if (LEARNED) {
-        mlp_tail_load(gd.mlp32, s_tail);
-        mlp_frags_load(gd.mlp32, M, lane);
-        __syncthreads();
-    }
+    MlpFrags M;   // loaded after the source records are in flight (one memory round trip)
     // per wave: [hi, lo][16 features][64 pixels]
     __shared__ __attribute__((aligned(16))) __bf16 stage[kAssocThreads / 64][2][16][64];
     for (int e = lane; e < 2 * 9 * 64; e += 64)
@@ -638,6 +633,11 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
         const int kc = (k < end) ? k : end - 1;
         s[m] = ld_global(src_nz + kc);
         uvs[m] = ld_global(src_uv + kc);
+    }
+    if (LEARNED) {
+        mlp_tail_load(gd.mlp32, s_tail);
+        mlp_frags_load(gd.mlp32, M, lane);
+        __syncthreads();
     }
     const PixelConsts pc = pixel_consts(gd);   // after the loads are issued
 #pragma unroll
@@ -831,15 +831,16 @@ __global__ __launch_bounds__(kPruneThreads) void prune_score_kernel(const GraphD
     const int i = it.gij & 0xff;
     const int lane = threadIdx.x & 63;
     __shared__ __attribute__((aligned(16))) float s_tail[kMlpTail];
-    MlpFrags M;
-    mlp_tail_load(gd.mlp32, s_tail);
-    mlp_frags_load(gd.mlp32, M, lane);
-    __syncthreads();
     // every lane stays to the end: the network runs wave-wide
     const bool live = (int)threadIdx.x < it.count;
     const size_t e = (size_t)i * gd.HW + it.start + (live ? threadIdx.x : 0);
     const float4 s = gd.src_nz[e];
     const uint32_t uv = gd.src_uv[e];
+    // the network parameters, loaded while the source record is in flight
+    MlpFrags M;
+    mlp_tail_load(gd.mlp32, s_tail);
+    mlp_frags_load(gd.mlp32, M, lane);
+    __syncthreads();
     const float px = s.w * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
     const float py = s.w * (((float)(uv >> 16) - gd.cy) * gd.ify);
     float best = 0.0f;
