@@ -90,11 +90,20 @@ def lib():
         L.orc_cholesky_solve.argtypes = [C.c_int, dp, dp, dp]
         L.orc_mlp_forward.argtypes = [dp, C.c_int, dp, dp]
         L.orc_mlp_forward_half.argtypes = [dp, C.c_int, dp, dp]
+        L.orc_mlp_trace_half.argtypes = [dp, C.c_int, dp, dp, dp, dp]
         L.orc_round_half.argtypes = [C.c_double]
         L.orc_round_half.restype = C.c_double
         L.orc_pair_features.argtypes = [P(Problem), dp, C.c_int, C.c_int, C.c_int, P(C.c_int), dp]
+        L.orc_pairs_features.argtypes = [P(Problem), dp, C.c_int, P(C.c_int), P(C.c_int), C.c_int, P(C.c_int), dp]
         L.orc_prune_scores.argtypes = [P(Problem), dp, dp]
         L.orc_prune_select.argtypes = [P(Problem), dp, C.c_double, P(C.c_ubyte)]
+        L.orc_arun.argtypes = [C.c_int, dp, dp, dp]
+        L.orc_ransac_score.restype = C.c_int
+        L.orc_ransac_score.argtypes = [C.c_int, dp, dp, dp, dp, P(C.c_ubyte), P(C.c_int), C.c_double, C.c_double,
+                                       dp, P(C.c_ubyte)]
+        L.orc_ransac_pairs.argtypes = [P(Problem), C.c_int, P(C.c_int), P(C.c_int), P(C.c_int), P(C.c_float),
+                                       P(C.c_float), C.c_int, P(C.c_int), C.c_double, C.c_double, P(C.c_int),
+                                       P(C.c_int), dp, P(C.c_ubyte)]
         L.orc_mlp_bce.argtypes = [dp, C.c_int, dp, dp, dp]
         L.orc_mlp_bce.restype = C.c_double
         _lib = L
@@ -193,6 +202,51 @@ class OracleProblem:
                                      _ptr(tgt, C.c_int), _ptr(f, C.c_double))
         assert rc == OK
         return tgt, f
+
+    def pairs_features(self, poses, pairs, iteration=0):
+        """(targets (n, H*W), features (n, H*W, 6)) of the ordered pairs."""
+        poses = np.ascontiguousarray(poses, np.float64)
+        hw = self.width * self.height
+        pi = np.ascontiguousarray([p[0] for p in pairs], np.int32)
+        pj = np.ascontiguousarray([p[1] for p in pairs], np.int32)
+        tgt = np.zeros((len(pairs), hw), np.int32)
+        f = np.zeros((len(pairs), hw, 6))
+        rc = lib().orc_pairs_features(C.byref(self.c), _ptr(poses, C.c_double), len(pairs), _ptr(pi, C.c_int),
+                                      _ptr(pj, C.c_int), iteration, _ptr(tgt, C.c_int), _ptr(f, C.c_double))
+        assert rc == OK
+        return tgt, f
+
+    def ransac(self, pairs, uv_i, uv_j, samples, delta=0.005, alpha=float(np.deg2rad(45.0)), scores=False):
+        """RANSAC registration of each ordered pair (i, j) in pairs from its
+        matches: uv_i / uv_j are lists (one (n_q, 2) array per pair), samples an
+        (n_pairs, n_hyp, 3) array of match indices.  Returns dict(best (n_pairs,),
+        T (n_pairs, 4, 4) frame-j camera -> frame-i camera, inliers (list of
+        (n_q,) bools), and score (n_pairs, n_hyp) when asked)."""
+        npairs = len(pairs)
+        samples = np.ascontiguousarray(samples, np.int32).reshape(npairs, -1, 3)
+        n_hyp = samples.shape[1]
+        counts = [len(np.asarray(u).reshape(-1, 2)) for u in uv_i]
+        off = np.ascontiguousarray(np.concatenate([[0], np.cumsum(counts)]), np.int32)
+        ui = np.ascontiguousarray(np.concatenate([np.asarray(u, np.float32).reshape(-1, 2) for u in uv_i]
+                                                 + [np.zeros((1, 2), np.float32)]))
+        uj = np.ascontiguousarray(np.concatenate([np.asarray(u, np.float32).reshape(-1, 2) for u in uv_j]
+                                                 + [np.zeros((1, 2), np.float32)]))
+        pi = np.ascontiguousarray([p[0] for p in pairs], np.int32)
+        pj = np.ascontiguousarray([p[1] for p in pairs], np.int32)
+        best = np.zeros(npairs, np.int32)
+        T = np.zeros((npairs, 4, 4))
+        inl = np.zeros(max(int(off[-1]), 1), np.uint8)
+        sc = np.zeros((npairs, n_hyp), np.int32) if scores else None
+        rc = lib().orc_ransac_pairs(C.byref(self.c), npairs, _ptr(pi, C.c_int), _ptr(pj, C.c_int),
+                                    _ptr(off, C.c_int), _ptr(ui, C.c_float), _ptr(uj, C.c_float), n_hyp,
+                                    _ptr(samples, C.c_int), float(delta), float(alpha), _ptr(best, C.c_int),
+                                    _ptr(sc, C.c_int) if scores else None, _ptr(T, C.c_double),
+                                    _ptr(inl, C.c_ubyte))
+        assert rc == OK
+        out = dict(best=best, T=T, inliers=[inl[off[q]:off[q + 1]].astype(bool) for q in range(npairs)])
+        if scores:
+            out["score"] = sc
+        return out
 
     def prune_scores(self, poses):
         poses = np.ascontiguousarray(poses, np.float64)
@@ -346,13 +400,51 @@ def mlp_forward(params, x):
 
 
 def mlp_forward_half(params, x):
-    """Outputs of the network as the dense term evaluates it: binary16 inputs
-    and first-layer activations, exact products and sums."""
+    """Outputs of the network as the dense term evaluates it, "in FP16":
+    binary16 parameters, every layer's input (features, both hidden layers'
+    activations) rounded to binary16, exact products and sums."""
     p = np.ascontiguousarray(params, np.float64)
     x = np.ascontiguousarray(x, np.float64).reshape(-1, 6)
     y = np.zeros(len(x))
     lib().orc_mlp_forward_half(_ptr(p, C.c_double), len(x), _ptr(x, C.c_double), _ptr(y, C.c_double))
     return y
+
+
+def mlp_trace_half(params, x):
+    """(s1, s2, z) of the FP16 evaluation: the exact pre-activations (n, 32)
+    of the two hidden layers, each from its layer's binary16 inputs, and the
+    logits (n,)."""
+    p = np.ascontiguousarray(params, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 6)
+    s1 = np.zeros((len(x), 32))
+    s2 = np.zeros((len(x), 32))
+    z = np.zeros(len(x))
+    lib().orc_mlp_trace_half(_ptr(p, C.c_double), len(x), _ptr(x, C.c_double), _ptr(s1, C.c_double),
+                             _ptr(s2, C.c_double), _ptr(z, C.c_double))
+    return s1, s2, z
+
+
+def arun(a, b):
+    """(rc, T): least-squares rigid transform with R b + t ~ a for (k, 3)
+    point arrays (Arun et al.)."""
+    a = np.ascontiguousarray(a, np.float64).reshape(-1, 3)
+    b = np.ascontiguousarray(b, np.float64).reshape(-1, 3)
+    T = np.zeros((4, 4))
+    rc = lib().orc_arun(len(a), _ptr(a, C.c_double), _ptr(b, C.c_double), _ptr(T, C.c_double))
+    return rc, T
+
+
+def ransac_score(a, na, b, nb, valid, sample, delta=0.005, alpha=float(np.deg2rad(45.0))):
+    """(score, T, inlier flags) of one hypothesis on explicit geometry."""
+    arrs = [np.ascontiguousarray(v, np.float64).reshape(-1, 3) for v in (a, na, b, nb)]
+    n = len(arrs[0])
+    valid = np.ascontiguousarray(valid, np.uint8)
+    smp = np.ascontiguousarray(sample, np.int32)
+    T = np.zeros((4, 4))
+    inl = np.zeros(max(n, 1), np.uint8)
+    s = lib().orc_ransac_score(n, *[_ptr(v, C.c_double) for v in arrs], _ptr(valid, C.c_ubyte), _ptr(smp, C.c_int),
+                               float(delta), float(alpha), _ptr(T, C.c_double), _ptr(inl, C.c_ubyte))
+    return s, T, inl[:n].astype(bool)
 
 
 def round_half(x):

@@ -881,8 +881,13 @@ double orc_round_half(double x)
     return r;
 }
 
-/* network evaluation with binary16 inputs and first-layer activations */
-static double mlp_eval_half(const double *P, const double *f)
+/* The network "in FP16" (6-32-32-1): the parameters are binary16 values, and
+ * the input of every layer (the features, then each hidden layer's
+ * activations) is rounded to binary16 (nearest, ties to even) before it is
+ * multiplied; products and sums are exact here (FP64).  s1, s2 (may be NULL)
+ * receive the exact pre-activations of the two hidden layers, from the
+ * rounded inputs of their layer. */
+static double mlp_eval_half_trace(const double *P, const double *f, double *s1, double *s2)
 {
     double x[ORC_MLP_IN], h1[ORC_MLP_HID];
     for (int k = 0; k < ORC_MLP_IN; ++k)
@@ -891,6 +896,8 @@ static double mlp_eval_half(const double *P, const double *f)
         double s = P[MLP_B1 + o];
         for (int k = 0; k < ORC_MLP_IN; ++k)
             s += P[MLP_W1 + ORC_MLP_IN * o + k] * x[k];
+        if (s1)
+            s1[o] = s;
         h1[o] = orc_round_half(s > 0.0 ? s : 0.0);
     }
     double z = P[MLP_B3];
@@ -898,9 +905,28 @@ static double mlp_eval_half(const double *P, const double *f)
         double s = P[MLP_B2 + o];
         for (int k = 0; k < ORC_MLP_HID; ++k)
             s += P[MLP_W2 + ORC_MLP_HID * o + k] * h1[k];
-        z += P[MLP_W3 + o] * (s > 0.0 ? s : 0.0);
+        if (s2)
+            s2[o] = s;
+        z += P[MLP_W3 + o] * orc_round_half(s > 0.0 ? s : 0.0);
     }
     return z;
+}
+
+static double mlp_eval_half(const double *P, const double *f)
+{
+    return mlp_eval_half_trace(P, f, NULL, NULL);
+}
+
+void orc_mlp_trace_half(const double *params, int n, const double *x, double *s1, double *s2,
+                        double *z)
+{
+    for (int i = 0; i < n; ++i) {
+        const double zi = mlp_eval_half_trace(params, x + ORC_MLP_IN * (size_t)i,
+                                              s1 ? s1 + ORC_MLP_HID * (size_t)i : NULL,
+                                              s2 ? s2 + ORC_MLP_HID * (size_t)i : NULL);
+        if (z)
+            z[i] = zi;
+    }
 }
 
 void orc_mlp_forward_half(const double *params, int n, const double *x, double *y)
@@ -930,29 +956,44 @@ static void mlp_features(const orc_problem *pb, const frame_maps *fm, int i, siz
     f[5] = (double)iteration / den;
 }
 
-int orc_pair_features(const orc_problem *pb, const double *poses, int i, int j, int iteration,
-                      int *target, double *features)
+int orc_pairs_features(const orc_problem *pb, const double *poses, int n_pairs, const int *pi,
+                       const int *pj, int iteration, int *target, double *features)
 {
-    if (check_problem(pb) != ORC_OK || !poses || i == j || i < 0 || j < 0 || i >= pb->n_frames ||
-        j >= pb->n_frames)
+    if (check_problem(pb) != ORC_OK || !poses || n_pairs < 0 || (n_pairs > 0 && (!pi || !pj)))
         return ORC_ERR_ARG;
+    for (int q = 0; q < n_pairs; ++q)
+        if (pi[q] == pj[q] || pi[q] < 0 || pj[q] < 0 || pi[q] >= pb->n_frames || pj[q] >= pb->n_frames)
+            return ORC_ERR_ARG;
     frame_maps *fm = build_frames(pb);
-    double A[16], B[16];
-    pair_transforms(poses, i, j, A, B);
     const size_t hw = (size_t)pb->width * pb->height;
-    for (size_t x = 0; x < hw; ++x) {
-        double r = 0.0, gate[2] = {0.0, 0.0};
-        int y = associate_pixel(pb, fm, i, j, A, B, x, NULL, &r, NULL, gate);
-        if (target)
-            target[x] = y;
-        double *f = features + 6 * x;
-        if (y >= 0)
-            mlp_features(pb, fm, i, x, r, gate[0], gate[1], iteration, f);
-        else
-            f[0] = f[1] = f[2] = f[3] = f[4] = f[5] = 0.0;
+    for (int q = 0; q < n_pairs; ++q) {
+        const int i = pi[q], j = pj[q];
+        double A[16], B[16];
+        pair_transforms(poses, i, j, A, B);
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+        for (long long xx = 0; xx < (long long)hw; ++xx) {
+            const size_t x = (size_t)xx;
+            double r = 0.0, gate[2] = {0.0, 0.0};
+            int y = associate_pixel(pb, fm, i, j, A, B, x, NULL, &r, NULL, gate);
+            if (target)
+                target[(size_t)q * hw + x] = y;
+            if (!features)
+                continue;
+            double *f = features + 6 * ((size_t)q * hw + x);
+            if (y >= 0)
+                mlp_features(pb, fm, i, x, r, gate[0], gate[1], iteration, f);
+            else
+                f[0] = f[1] = f[2] = f[3] = f[4] = f[5] = 0.0;
+        }
     }
     free_frames(pb, fm);
     return ORC_OK;
+}
+
+int orc_pair_features(const orc_problem *pb, const double *poses, int i, int j, int iteration,
+                      int *target, double *features)
+{
+    return orc_pairs_features(pb, poses, 1, &i, &j, iteration, target, features);
 }
 
 int orc_prune_scores(const orc_problem *pb, const double *poses, double *score)
@@ -1028,5 +1069,242 @@ int orc_prune_select(const orc_problem *pb, const double *score, double frac, un
             kp[buf[k].pos] = 0;
     }
     free(buf);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Coarse registration by RANSAC (Sec. IV-B): each hypothesis is the
+ * least-squares rigid transform of a sample of three matched keypoint pairs
+ * (Arun et al.), scored by the matches it brings within delta of their
+ * partner with normals within alpha; the best sampled hypothesis is the
+ * registration.  The random samples are an input. */
+
+/* Singular value decomposition of a 3x3 matrix by one-sided Jacobi
+ * rotations: M V = W with orthogonal columns; columns of W (and of V) sorted
+ * by decreasing norm. */
+static void svd3_jacobi(const double *M, double *W, double *V)
+{
+    memcpy(W, M, 9 * sizeof(double));
+    for (int r = 0; r < 9; ++r)
+        V[r] = (r % 4 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                double a = 0.0, b = 0.0, c = 0.0;   /* |w_p|^2, |w_q|^2, w_p . w_q */
+                for (int r = 0; r < 3; ++r) {
+                    a += W[3 * r + p] * W[3 * r + p];
+                    b += W[3 * r + q] * W[3 * r + q];
+                    c += W[3 * r + p] * W[3 * r + q];
+                }
+                if (c == 0.0 || fabs(c) <= 1e-300)
+                    continue;
+                const double rel = fabs(c) / sqrt(a * b);
+                if (rel > off)
+                    off = rel;
+                /* rotation that makes columns p and q orthogonal */
+                const double zeta = (b - a) / (2.0 * c);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+                for (int r = 0; r < 3; ++r) {
+                    const double wp = W[3 * r + p], wq = W[3 * r + q];
+                    W[3 * r + p] = cs * wp - sn * wq;
+                    W[3 * r + q] = sn * wp + cs * wq;
+                    const double vp = V[3 * r + p], vq = V[3 * r + q];
+                    V[3 * r + p] = cs * vp - sn * vq;
+                    V[3 * r + q] = sn * vp + cs * vq;
+                }
+            }
+        if (off <= 1e-15)
+            break;
+    }
+    /* sort the columns by decreasing norm */
+    for (int p = 0; p < 2; ++p)
+        for (int q = p + 1; q < 3; ++q) {
+            double a = 0.0, b = 0.0;
+            for (int r = 0; r < 3; ++r) {
+                a += W[3 * r + p] * W[3 * r + p];
+                b += W[3 * r + q] * W[3 * r + q];
+            }
+            if (b > a)
+                for (int r = 0; r < 3; ++r) {
+                    double t = W[3 * r + p];
+                    W[3 * r + p] = W[3 * r + q];
+                    W[3 * r + q] = t;
+                    t = V[3 * r + p];
+                    V[3 * r + p] = V[3 * r + q];
+                    V[3 * r + q] = t;
+                }
+        }
+}
+
+static double det3(const double *M)
+{
+    return M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
+           M[2] * (M[3] * M[7] - M[4] * M[6]);
+}
+
+int orc_arun(int k, const double *a, const double *b, double *T)
+{
+    if (k < 3 || !a || !b || !T)
+        return ORC_ERR_ARG;
+    double ca[3] = {0, 0, 0}, cb[3] = {0, 0, 0};
+    for (int m = 0; m < k; ++m)
+        for (int r = 0; r < 3; ++r) {
+            ca[r] += a[3 * m + r] / k;
+            cb[r] += b[3 * m + r] / k;
+        }
+    /* cross-covariance S = sum (a - ca)(b - cb)^T; S = U D V^T; the rotation
+     * mapping b onto a is R = U diag(1, 1, det(U) det(V)) V^T */
+    double S[9] = {0};
+    for (int m = 0; m < k; ++m)
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                S[3 * r + c] += (a[3 * m + r] - ca[r]) * (b[3 * m + c] - cb[c]);
+    double W[9], V[9], U[9];
+    svd3_jacobi(S, W, V);
+    double n0 = 0.0, n1 = 0.0;
+    for (int r = 0; r < 3; ++r) {
+        n0 += W[3 * r] * W[3 * r];
+        n1 += W[3 * r + 1] * W[3 * r + 1];
+    }
+    n0 = sqrt(n0);
+    n1 = sqrt(n1);
+    if (!(n1 > 1e-12 * n0))
+        return ORC_ERR_SINGULAR;   /* collinear points: the rotation about their line is free */
+    for (int r = 0; r < 3; ++r) {
+        U[3 * r] = W[3 * r] / n0;
+        U[3 * r + 1] = W[3 * r + 1] / n1;
+    }
+    /* third left vector completes a right-handed basis (the third singular
+     * value may be zero); the sign choice cancels in R */
+    const double u0[3] = {U[0], U[3], U[6]}, u1[3] = {U[1], U[4], U[7]};
+    double u2[3];
+    cross3(u0, u1, u2);
+    for (int r = 0; r < 3; ++r)
+        U[3 * r + 2] = u2[r];
+    const double d = det3(V) < 0.0 ? -1.0 : 1.0;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            T[4 * r + c] = U[3 * r] * V[3 * c] + U[3 * r + 1] * V[3 * c + 1] + d * U[3 * r + 2] * V[3 * c + 2];
+    for (int r = 0; r < 3; ++r)
+        T[4 * r + 3] = ca[r] - (T[4 * r] * cb[0] + T[4 * r + 1] * cb[1] + T[4 * r + 2] * cb[2]);
+    T[12] = T[13] = T[14] = 0.0;
+    T[15] = 1.0;
+    return ORC_OK;
+}
+
+/* 3-D point and normal of a keypoint at the nearest pixel; valid when the
+ * pixel is inside the image, has depth and mask and a valid normal */
+static int keypoint_geometry(const orc_problem *pb, const frame_maps *fm, int f, const float *uv, double *p,
+                             double *n)
+{
+    double u = round_half_up((double)uv[0]), v = round_half_up((double)uv[1]);
+    if (!(u >= 0.0 && u < pb->width && v >= 0.0 && v < pb->height))
+        return 0;
+    size_t x = (size_t)v * pb->width + (size_t)u;
+    if ((fm[f].valid[x] & 3) != 3)
+        return 0;
+    memcpy(p, fm[f].vertex + 3 * x, 3 * sizeof(double));
+    memcpy(n, fm[f].normal + 3 * x, 3 * sizeof(double));
+    return 1;
+}
+
+int orc_ransac_score(int n, const double *a, const double *na, const double *b, const double *nb,
+                     const unsigned char *valid, const int *sample, double delta, double alpha,
+                     double *T, unsigned char *inlier)
+{
+    double sa[9], sb[9];
+    for (int q = 0; q < 3; ++q) {
+        const int m = sample[q];
+        if (m < 0 || m >= n || !valid[m])
+            return -1;
+        for (int r = 0; r < q; ++r)
+            if (sample[r] == m)
+                return -1;
+        memcpy(sa + 3 * q, a + 3 * m, 3 * sizeof(double));
+        memcpy(sb + 3 * q, b + 3 * m, 3 * sizeof(double));
+    }
+    /* a sample whose triangle is (nearly) degenerate in either frame fixes no
+     * rotation: area below 1e-8 m^2 (sides of 0.1 mm) */
+    for (int s = 0; s < 2; ++s) {
+        const double *P = s ? sb : sa;
+        double e1[3], e2[3], c[3];
+        for (int r = 0; r < 3; ++r) {
+            e1[r] = P[3 + r] - P[r];
+            e2[r] = P[6 + r] - P[r];
+        }
+        cross3(e1, e2, c);
+        if (!(0.5 * sqrt(dot3(c, c)) >= 1e-8))
+            return -1;
+    }
+    double Th[16];
+    if (orc_arun(3, sa, sb, Th) != ORC_OK)
+        return -1;
+    const double cos_a = cos(alpha);
+    int count = 0;
+    for (int m = 0; m < n; ++m) {
+        int in = 0;
+        if (valid[m]) {
+            double y[3], rn[3];
+            apply_T(Th, b + 3 * m, y);
+            apply_R(Th, nb + 3 * m, rn);
+            const double d[3] = {y[0] - a[3 * m], y[1] - a[3 * m + 1], y[2] - a[3 * m + 2]};
+            in = sqrt(dot3(d, d)) < delta && dot3(rn, na + 3 * m) > cos_a;
+        }
+        count += in;
+        if (inlier)
+            inlier[m] = (unsigned char)in;
+    }
+    if (T)
+        memcpy(T, Th, sizeof(Th));
+    return count;
+}
+
+int orc_ransac_pairs(const orc_problem *pb, int n_pairs, const int *pi, const int *pj, const int *match_off,
+                     const float *uv_i, const float *uv_j, int n_hyp, const int *samples, double delta,
+                     double alpha, int *best, int *score, double *T, unsigned char *inlier)
+{
+    if (check_problem(pb) != ORC_OK || n_pairs < 0 || n_hyp < 1 || !match_off || !samples || !best || !T)
+        return ORC_ERR_ARG;
+    for (int q = 0; q < n_pairs; ++q)
+        if (pi[q] < 0 || pj[q] < 0 || pi[q] >= pb->n_frames || pj[q] >= pb->n_frames || pi[q] == pj[q] ||
+            match_off[q + 1] < match_off[q])
+            return ORC_ERR_ARG;
+    frame_maps *fm = build_frames(pb);
+    for (int q = 0; q < n_pairs; ++q) {
+        const int n = match_off[q + 1] - match_off[q], o = match_off[q];
+        double *a = (double *)malloc(sizeof(double) * 12 * (size_t)(n > 0 ? n : 1));
+        double *na = a + 3 * n, *b = a + 6 * n, *nb = a + 9 * n;
+        unsigned char *valid = (unsigned char *)malloc((size_t)(n > 0 ? n : 1));
+        for (int m = 0; m < n; ++m)
+            valid[m] = (unsigned char)(keypoint_geometry(pb, fm, pi[q], uv_i + 2 * (size_t)(o + m), a + 3 * m,
+                                                         na + 3 * m) &&
+                                       keypoint_geometry(pb, fm, pj[q], uv_j + 2 * (size_t)(o + m), b + 3 * m,
+                                                         nb + 3 * m));
+        int bh = -1, bs = -1;
+        for (int h = 0; h < n_hyp; ++h) {
+            const int s = orc_ransac_score(n, a, na, b, nb, valid, samples + 3 * ((size_t)q * n_hyp + h), delta,
+                                           alpha, NULL, NULL);
+            if (score)
+                score[(size_t)q * n_hyp + h] = s;
+            if (s > bs) {
+                bs = s;
+                bh = h;
+            }
+        }
+        best[q] = bs >= 0 ? bh : -1;
+        double *Tq = T + 16 * (size_t)q;
+        for (int r = 0; r < 16; ++r)
+            Tq[r] = (r % 5 == 0) ? 1.0 : 0.0;
+        if (inlier)
+            memset(inlier + o, 0, (size_t)n);
+        if (bs >= 0)
+            orc_ransac_score(n, a, na, b, nb, valid, samples + 3 * ((size_t)q * n_hyp + bh), delta, alpha, Tq,
+                             inlier ? inlier + o : NULL);
+        free(a);
+        free(valid);
+    }
+    free_frames(pb, fm);
     return ORC_OK;
 }

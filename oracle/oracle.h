@@ -142,6 +142,12 @@ int orc_cholesky_solve(int n, const double *A, const double *b, double *x);
 int orc_pair_features(const orc_problem *pb, const double *poses, int i, int j, int iteration,
                       int *target, double *features);
 
+/* orc_pair_features for n_pairs ordered pairs (pi[q], pj[q]) at once:
+ * target holds n_pairs*H*W codes and features n_pairs*H*W*6 values (either
+ * may be NULL), pair q's block after pair q-1's. */
+int orc_pairs_features(const orc_problem *pb, const double *poses, int n_pairs, const int *pi,
+                       const int *pj, int iteration, int *target, double *features);
+
 /* Pruning scores at the given poses (iteration feature 0): for every source
  * pixel the largest network output over its gated-in pairs (0 if none), -1
  * where the pixel is not a valid source; n_frames*H*W doubles. */
@@ -155,13 +161,21 @@ int orc_prune_select(const orc_problem *pb, const double *score, double frac, un
 /* Output of the network for each of n inputs (n x 6, row-major). */
 void orc_mlp_forward(const double *params, int n, const double *x, double *y);
 
-/* The network as the dense term evaluates it, in the FP16 arithmetic of the
- * learned-weighting design (6-32-32-1 "in FP16"): the inputs and the first
- * hidden layer's activations are rounded to binary16 (nearest, ties to even)
- * before they enter the two products; products and sums are exact here
- * (FP64).  Used by the dense term, orc_pair_features' consumers and
- * orc_prune_scores whenever pb->mlp is set. */
+/* The network as the dense term evaluates it, "in FP16" (the learned
+ * weighting's 6-32-32-1 network): the parameters are binary16 values and the
+ * input of every layer (the features and both hidden layers' activations) is
+ * rounded to binary16 (nearest, ties to even) before it enters that layer's
+ * products; products and sums are exact here (FP64).  Used by the dense term,
+ * orc_pair_features' consumers and orc_prune_scores whenever pb->mlp is set. */
 void orc_mlp_forward_half(const double *params, int n, const double *x, double *y);
+
+/* The same evaluation, returning for each of the n inputs the exact
+ * pre-activations of the two hidden layers (s1, s2: n x 32, each from its
+ * layer's rounded inputs; either may be NULL) and the logit z (n, may be
+ * NULL).  Lets a caller find activations that lie next to a binary16 rounding
+ * boundary. */
+void orc_mlp_trace_half(const double *params, int n, const double *x, double *s1, double *s2,
+                        double *z);
 
 /* x rounded to the nearest IEEE binary16 value (ties to even; overflow to
  * +-inf; subnormals kept), returned as a double. */
@@ -171,6 +185,38 @@ double orc_round_half(double x);
  * gradient with respect to the parameters (1313 doubles; grad may be NULL). */
 double orc_mlp_bce(const double *params, int n, const double *x, const double *labels,
                    double *grad);
+
+/* ---- coarse registration by RANSAC (Sec. IV-B) ----
+ * Least-squares rigid transform of k >= 3 point pairs (Arun et al.): T (4x4
+ * row-major) minimising sum |R b_m + t - a_m|^2, from the SVD of the
+ * cross-covariance with the reflection correction.  ORC_ERR_SINGULAR when the
+ * points are collinear. */
+int orc_arun(int k, const double *a, const double *b, double *T);
+
+/* Score of one hypothesis: sample holds three match indices; the hypothesis
+ * is orc_arun of those three pairs.  Returns -1 for an unusable sample (an
+ * index out of range, repeated or of an invalid match, or a triangle of area
+ * below 1e-8 m^2 in either frame), else the number of valid matches m with
+ * |R b_m + t - a_m| < delta and (R nb_m) . na_m > cos(alpha).  T (16) and
+ * inlier (n) receive the hypothesis and its inlier flags (either may be
+ * NULL). */
+int orc_ransac_score(int n, const double *a, const double *na, const double *b, const double *nb,
+                     const unsigned char *valid, const int *sample, double delta, double alpha,
+                     double *T, unsigned char *inlier);
+
+/* RANSAC over the matches of n_pairs ordered node pairs (pi[q], pj[q]): pair
+ * q's matches are uv_i/uv_j entries match_off[q] .. match_off[q+1]-1 (pixel
+ * coordinates in frames pi[q] and pj[q]); a match's points a (frame pi) and b
+ * (frame pj) and their normals are taken at the nearest pixels and the match
+ * is valid when both are valid sources (depth, mask, normal).  samples holds
+ * n_pairs * n_hyp triples of match indices (local to the pair).  best[q] =
+ * the hypothesis with the most inliers (lowest index among equals; -1 when no
+ * sample is usable), T[16q..] = its transform (frame pj camera -> frame pi
+ * camera; identity when best is -1), inlier[match_off[q] + m] = its inlier
+ * flags; score (may be NULL) = every hypothesis' score. */
+int orc_ransac_pairs(const orc_problem *pb, int n_pairs, const int *pi, const int *pj, const int *match_off,
+                     const float *uv_i, const float *uv_j, int n_hyp, const int *samples, double delta,
+                     double alpha, int *best, int *score, double *T, unsigned char *inlier);
 
 #ifdef __cplusplus
 }

@@ -348,3 +348,23 @@ def plane_frames(n_frames=2, width=64, height=48, fx=60.0, fy=60.0, cx=32.0, cy=
     z = -offset / denom
     depth = np.where(z > 0, z, 0.0)
     return np.broadcast_to(depth, (n_frames, height, width)).astype(np.float32).copy(), n
+
+
+def ransac_samples(seed: int, n_matches: int, n_hyp: int, pair: int = 0) -> np.ndarray:
+    """The random draws of RANSAC for one pair: n_hyp samples of three
+    distinct match indices in [0, n_matches), (n_hyp, 3) int32, from a seeded
+    generator (seed, pair).  Fewer than three matches give all -1 rows."""
+    rng = np.random.default_rng([seed, pair, 7])
+    out = np.full((n_hyp, 3), -1, np.int32)
+    if n_matches < 3:
+        return out
+    # three distinct indices: i0 uniform, i1 != i0, i2 not in {i0, i1}
+    i0 = rng.integers(0, n_matches, n_hyp)
+    i1 = rng.integers(0, n_matches - 1, n_hyp)
+    i1 = i1 + (i1 >= i0)
+    i2 = rng.integers(0, n_matches - 2, n_hyp)
+    lo, hi = np.minimum(i0, i1), np.maximum(i0, i1)
+    i2 = i2 + (i2 >= lo)
+    i2 = i2 + (i2 >= hi)
+    out[:, 0], out[:, 1], out[:, 2] = i0, i1, i2
+    return out

@@ -119,6 +119,16 @@ def test_features_follow_their_definition(oracle_lib):
     assert np.all(f[tgt < 0] == 0.0)
 
 
+def test_pairs_features_equal_single_pair_calls(oracle_lib):
+    g = synth.make_graph("T")
+    pb = oracle.OracleProblem.from_synth(g)
+    pairs = [(0, 1), (2, 1), (3, 0)]
+    T, F = pb.pairs_features(g.poses_init, pairs, iteration=2)
+    for q, (i, j) in enumerate(pairs):
+        t, f = pb.pair_features(g.poses_init, i, j, iteration=2)
+        assert np.array_equal(T[q], t) and np.array_equal(F[q], f)
+
+
 def test_prune_scores_and_selection_brute_force(oracle_lib):
     g = synth.make_graph("T", width=80, height=60)
     rng = np.random.default_rng(4)
@@ -179,24 +189,27 @@ def test_round_half_matches_numpy_binary16(oracle_lib):
 
 
 def test_half_network_matches_exact_network_on_binary16_values(oracle_lib):
-    """With inputs, weights and every first-layer activation exactly
-    representable in binary16, the FP16 evaluation equals the exact one."""
+    """With inputs, weights and every hidden activation exactly representable
+    in binary16, the FP16 evaluation equals the exact one."""
     rng = np.random.default_rng(12)
     p = np.zeros(oracle.MLP_PARAMS)
-    # small dyadic weights and inputs: products and sums of a few terms stay
-    # within binary16's 11 significant bits
-    p[0:192] = rng.integers(-4, 5, 192) / 8.0
-    p[192:224] = rng.integers(-4, 5, 32) / 8.0
-    p[224:1248] = rng.normal(size=1024)
+    # integer inputs and hidden weights in {-1, 0, 1}: both hidden layers'
+    # activations are integers below 2^11, exact in binary16
+    p[0:224] = rng.integers(-1, 2, 224)
+    p[224:1280] = rng.integers(-1, 2, 1056)
     p[1280:1313] = rng.normal(size=33)
-    x = rng.integers(-8, 9, size=(300, 6)) / 4.0
+    x = rng.integers(-2, 3, size=(300, 6)).astype(np.float64)
     assert np.array_equal(oracle.mlp_forward_half(p, x), oracle.mlp_forward(p, x))
+    s1, s2, z = oracle.mlp_trace_half(p, x)
+    assert np.all(s1 == np.round(s1)) and np.all(np.abs(s2) < 2048)
+    assert np.allclose(1.0 / (1.0 + np.exp(-z)), oracle.mlp_forward(p, x), rtol=1e-15, atol=0)
 
 
-def test_half_network_rounds_inputs_and_first_activations(oracle_lib):
+def test_half_network_rounds_every_layer_input(oracle_lib):
     """A one-path network y = sigmoid(w3 relu(w2 relu(w1 x0))) : the FP16
-    evaluation equals the exact network applied to x0 rounded to binary16 and
-    the first activation rounded to binary16."""
+    evaluation equals the exact network applied to x0 rounded to binary16, the
+    first activation rounded to binary16 and the second activation rounded to
+    binary16; the trace returns the two exact pre-activations."""
     p = np.zeros(oracle.MLP_PARAMS)
     w1, w2, w3 = 1.0 / 3.0, 0.7, 1.3
     p[0] = w1            # W1[0][0]
@@ -207,6 +220,15 @@ def test_half_network_rounds_inputs_and_first_activations(oracle_lib):
         x[0, 0] = x0
         xh = float(np.float16(x0))
         h1 = float(np.float16(w1 * xh))
-        want = 1.0 / (1.0 + np.exp(-(w3 * (w2 * h1))))
+        h2 = float(np.float16(w2 * h1))
+        want = 1.0 / (1.0 + np.exp(-(w3 * h2)))
         assert oracle.mlp_forward_half(p, x)[0] == pytest.approx(want, rel=1e-15)
         assert oracle.mlp_forward_half(p, x)[0] != oracle.mlp_forward(p, x)[0]
+        # h2 rounding alone moves the output (the value without it differs)
+        without_h2 = 1.0 / (1.0 + np.exp(-(w3 * (w2 * h1))))
+        assert want != without_h2
+        s1, s2, z = oracle.mlp_trace_half(p, x)
+        assert s1[0, 0] == w1 * xh and s2[0, 0] == w2 * h1 and z[0] == w3 * h2
+        # a negative pre-activation is clipped before rounding
+        x[0, 0] = -x0
+        assert oracle.mlp_forward_half(p, x)[0] == 0.5
