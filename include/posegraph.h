@@ -180,7 +180,11 @@ pg_status pose_graph_frame_info(pg_graph *g, int id, float *map, int *n_valid);
  * Sec. IV-D; the paper itself weights every residual by the M-estimator
  * only): parameters of a 6-32-32-1 perceptron (ReLU hidden layers, sigmoid
  * output) as fp16, layout W1[32x6] b1[32] W2[32x32] b2[32] W3[1x32] b3[1]
- * (row-major, 1313 values); evaluated in FP32 from these values.  With
+ * (row-major, 1313 values).  The network is evaluated "in FP16": these
+ * binary16 parameters, and every layer's input (the features and both hidden
+ * layers' activations) rounded to binary16 (nearest, ties to even), with each
+ * layer's products summed in FP32 (the hidden layers on the fp16 matrix
+ * cores) and the logistic in FP32.  With
  * cfg.weighting == PG_WEIGHT_LEARNED every gated-in dense residual's IRLS
  * weight and energy are multiplied by the network output sigma(f) of its
  * features f (pose_graph_pair_features), and, when cfg.prune_frac > 0, each

@@ -51,9 +51,12 @@ __device__ __forceinline__ float mlp_sigma(const float* __restrict__ P, const fl
 
 // ---------------------------------------------------------------------------
 // The network on the matrix cores, one wave = 64 samples (one per lane), as
-// the dense term evaluates it: inputs and first-layer activations in fp16,
-// products on v_mfma_f32_32x32x16_f16 with FP32 sums, the output layer in
-// FP32.  Both layers are computed transposed (hidden units as rows, samples
+// the dense term evaluates it, "in FP16": every layer's input (the features
+// and both hidden layers' activations) is a binary16 value, rounded to
+// nearest with ties to even, the parameters are binary16, and each layer's
+// products are summed in FP32 (the two hidden layers on
+// v_mfma_f32_32x32x16_f16, the 32-term output layer on the vector units).
+// Both hidden layers are computed transposed (hidden units as rows, samples
 // as columns), so the first layer's output registers are already the second
 // layer's B operand: a 32x32x16 product leaves row 8j + 4(lane/32) + i,
 // column lane%32 in c[4j + i], and the two K steps of the second layer take
@@ -99,6 +102,9 @@ __device__ __forceinline__ void mlp_frags_load(const float* __restrict__ P, MlpF
         }
 }
 
+// max(x, 0) rounded to binary16 (nearest, ties to even), widened exactly
+__device__ __forceinline__ float half_relu(float x) { return (float)(_Float16)fmaxf(x, 0.0f); }
+
 __device__ __forceinline__ float mlp_sigma_wave(const MlpFrags& M, const float* __restrict__ tail,
                                                 const float (&f)[kMlpIn], int lane)
 {
@@ -138,14 +144,14 @@ __device__ __forceinline__ float mlp_sigma_wave(const MlpFrags& M, const float* 
     for (int j = 0; j < 4; ++j) {
         const float4 b2 = reinterpret_cast<const float4*>(tail)[2 * j + g];
         const float4 w3 = reinterpret_cast<const float4*>(tail + 32)[2 * j + g];
-        p0 = fmaf(w3.x, fmaxf(d0[4 * j + 0] + b2.x, 0.0f), p0);
-        p0 = fmaf(w3.y, fmaxf(d0[4 * j + 1] + b2.y, 0.0f), p0);
-        p0 = fmaf(w3.z, fmaxf(d0[4 * j + 2] + b2.z, 0.0f), p0);
-        p0 = fmaf(w3.w, fmaxf(d0[4 * j + 3] + b2.w, 0.0f), p0);
-        p1 = fmaf(w3.x, fmaxf(d1[4 * j + 0] + b2.x, 0.0f), p1);
-        p1 = fmaf(w3.y, fmaxf(d1[4 * j + 1] + b2.y, 0.0f), p1);
-        p1 = fmaf(w3.z, fmaxf(d1[4 * j + 2] + b2.z, 0.0f), p1);
-        p1 = fmaf(w3.w, fmaxf(d1[4 * j + 3] + b2.w, 0.0f), p1);
+        p0 = fmaf(w3.x, half_relu(d0[4 * j + 0] + b2.x), p0);
+        p0 = fmaf(w3.y, half_relu(d0[4 * j + 1] + b2.y), p0);
+        p0 = fmaf(w3.z, half_relu(d0[4 * j + 2] + b2.z), p0);
+        p0 = fmaf(w3.w, half_relu(d0[4 * j + 3] + b2.w), p0);
+        p1 = fmaf(w3.x, half_relu(d1[4 * j + 0] + b2.x), p1);
+        p1 = fmaf(w3.y, half_relu(d1[4 * j + 1] + b2.y), p1);
+        p1 = fmaf(w3.z, half_relu(d1[4 * j + 2] + b2.z), p1);
+        p1 = fmaf(w3.w, half_relu(d1[4 * j + 3] + b2.w), p1);
     }
     p0 += __shfl_xor(p0, 32);
     p1 += __shfl_xor(p1, 32);

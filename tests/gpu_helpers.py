@@ -41,3 +41,96 @@ def check_normal_equations(H_gpu, g_gpu, lin, tol_h=H_REL_TOL, tol_g=G_REL_TOL):
 
 def near_half_integer(x, tol):
     return np.abs((x - np.floor(x)) - 0.5) <= tol
+
+
+# ------------------------------------------------------------------------
+# Learned weighting: bounds for a network evaluated "in FP16" (binary16
+# parameters; every layer's input rounded to binary16, nearest-even) whose
+# sums run in FP32 in any order on the GPU and exactly in the oracle.
+
+U32 = 2.0 ** -24            # FP32 unit roundoff
+SIGMA_ROUND = 3e-7          # FP32 logistic (exp, add, divide): a few units of 2^-24 on values <= 1
+
+
+def r16(v):
+    """Round to binary16 (nearest, ties to even) and widen to float64."""
+    return np.asarray(v, np.float64).astype(np.float16).astype(np.float64)
+
+
+def _rounded_relu_interval(s, e):
+    """Any value within e of s, clipped at 0 and rounded to binary16, lies in
+    [lo, hi] (rounding is monotone); returns (r16(relu(s)), the largest
+    distance of the interval's ends from it)."""
+    h = r16(np.maximum(s, 0.0))
+    lo = r16(np.maximum(s - e, 0.0))
+    hi = r16(np.maximum(s + e, 0.0))
+    return h, np.maximum(hi - h, h - lo)
+
+
+def net_sigma_bound(p16, x_gpu, x_orc):
+    """Per sample, a bound on |sigma_gpu(x_gpu) - sigma_oracle(x_orc)|.
+
+    Layer by layer: the binary16 inputs of the two sides differ by a known
+    amount (zero when x_gpu == x_orc); a layer's FP32 sum of n exact
+    products (binary16 x binary16 fits FP32) is within 2 n u sum|terms| of the
+    exact sum, u = 2^-24, in any order and under either rounding of the
+    partial sums; an activation can differ only if the interval of its
+    possible pre-activations contains a binary16 rounding boundary, and then
+    by at most the interval's rounded width.  The logistic has slope <= 1/4.
+    Returns (bound, flips): flips marks samples where some activation may
+    round to a neighbouring binary16 value."""
+    P = np.asarray(p16, np.float64)
+    W1, b1 = np.abs(P[0:192].reshape(32, 6)), np.abs(P[192:224])
+    W2, b2 = np.abs(P[224:1248].reshape(32, 32)), np.abs(P[1248:1280])
+    w3, b3 = np.abs(P[1280:1312]), abs(P[1312])
+    s1, s2, _ = oracle.mlp_trace_half(P, x_orc)
+    xo, xg = r16(x_orc), r16(x_gpu)
+    dx = np.abs(xg - xo)
+    e1 = dx @ W1.T + 2 * 7 * U32 * ((np.abs(xo) + dx) @ W1.T + b1)
+    h1, dh1 = _rounded_relu_interval(s1, e1)
+    e2 = dh1 @ W2.T + 2 * 33 * U32 * ((h1 + dh1) @ W2.T + b2)
+    h2, dh2 = _rounded_relu_interval(s2, e2)
+    dz = dh2 @ w3 + 2 * 34 * U32 * ((h2 + dh2) @ w3 + b3)
+    flips = (dh1 > 0).any(axis=1) | (dh2 > 0).any(axis=1)
+    return 0.25 * dz + SIGMA_ROUND, flips
+
+
+def certify_pruning(score_g, keep_g, score_o, keep_o, t_pix, uncertain, frac):
+    """Certify the GPU's pruning decisions against the oracle's own.
+
+    Per frame, k = floor(frac V) sources are dropped, lowest (score, position)
+    first.  Sources in 'uncertain' (some target association decided
+    differently, a certified near-tie elsewhere) may score anything on the
+    GPU; every other source has |S_gpu - S_oracle| <= t_pix (checked here).
+    With m uncertain sources and t the largest t_pix of a frame, the GPU's k-th
+    score lies within t of the oracle's (k-m)-th .. (k+m)-th, so a certain
+    source that one side keeps and the other drops has an oracle score in
+    [S_(k-m) - 2t, S_(k+m) + 2t].  Returns (differing sources, certain ones
+    among them)."""
+    n_diff = n_cert = 0
+    for f in range(score_o.shape[0]):
+        so, sg = score_o[f], score_g[f]
+        valid = so >= 0
+        assert np.array_equal(valid, sg >= 0)
+        cert = valid & ~uncertain[f]
+        d = np.abs(sg - so)
+        assert np.all(d[cert] <= t_pix[f][cert]), \
+            f"frame {f}: score difference {d[cert].max():.3e} over its bound"
+        V = int(valid.sum())
+        k = int(np.floor(frac * V))
+        m = int((valid & uncertain[f]).sum())
+        diff = keep_g[f].astype(bool) != keep_o[f].astype(bool)
+        assert not (diff & ~valid).any()
+        n_diff += int(diff.sum())
+        dc = diff & cert
+        n_cert += int(dc.sum())
+        if not dc.any():
+            continue
+        srt = np.sort(so[valid])
+        t = float(t_pix[f][cert].max())
+        lo = srt[max(k - m - 1, 0)] - 2 * t        # S_(k-m), 1-based order statistics
+        hi = srt[min(k + m - 1, V - 1)] + 2 * t    # S_(k+m)
+        bad = dc & ((so < lo) | (so > hi))
+        assert not bad.any(), (f"frame {f}: pruning decision of {np.flatnonzero(bad)} differs with oracle "
+                               f"scores {so[bad]} outside [{lo:.6e}, {hi:.6e}] (k={k}, m={m}, t={t:.2e})")
+    return n_diff, n_cert

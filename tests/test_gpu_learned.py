@@ -1,15 +1,18 @@
 """GPU: learned correspondence weighting — the trainer kernels (forward,
 loss/gradient, Adam) against the FP64 oracle, the association features and
 network weights, the pruning pass, and whole learned optimisations against the
-oracle taking the same pruning decisions; then the gain of a trained network
-on windows whose masks leak onto the background.
+oracle; then the gain of a trained network on windows whose masks leak onto
+the background.
 
-Readings shared with the oracle: the network runs on the fp16 parameters
-widened exactly to FP32 (GPU) / FP64 (oracle); float-decided integers (which
-pixels are pruned) are compared on one decision set: the oracle is given the
-GPU's kept pixels, and the GPU's choice is checked to be exactly the lowest
-scores by (score, position) of its own scores, and its scores against the
-oracle's."""
+The network runs "in FP16" on both sides: binary16 parameters, every layer's
+input (features, both hidden layers' activations) rounded to binary16; the GPU
+sums in FP32, the oracle exactly.  Each network output is checked against a
+bound derived per sample from that rule (a rounding-boundary flip is allowed
+only where the FP32 sums or the feature differences reach a binary16
+boundary).  Pruning decisions are integers decided in floating point: the
+GPU's kept pixels are compared with the oracle's own selection, and every
+differing pixel is certified to lie at the threshold within the score bound;
+the end-to-end comparison then gives the oracle the certified GPU set."""
 import math
 
 import numpy as np
@@ -17,7 +20,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import max_pose_diff
+from gpu_helpers import certify_pruning, max_pose_diff, net_sigma_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -167,20 +170,19 @@ def test_pair_features_and_weights_match_oracle():
         # r / huber and |s - p| / gate carry FP32 rounding of millimetre
         # differences; the others are O(1e-6)
         assert np.all(df.max(axis=0) <= np.array([2e-4, 2e-5, 1e-6, 1e-6, 2e-4, 0.0]))
-        # the association evaluates the network with fp16 inputs and first
-        # activations (matrix cores); the oracle rounds the same values.  On
-        # the GPU's own features the outputs agree to FP32 summation error,
-        # except where a first-layer activation sits on a binary16 rounding
-        # boundary (one fp16 ulp moves sigma by < 1e-3); on the oracle's
-        # features (within 2e-4 of the GPU's), an input itself may round to
-        # the neighbouring binary16 value
+        # every output within its derived bound, on the GPU's own features and
+        # on the oracle's (whose binary16 inputs may differ from the GPU's)
         net = p16.astype(np.float64)
+        b, flips = net_sigma_bound(net, f[same], f[same])
         d = np.abs(sg[same] - oracle.mlp_forward_half(net, f[same].astype(np.float64)))
-        say(f"  sigma on the GPU features: {100 * np.mean(d <= 2e-6):.3f}% within 2e-6, max {d.max():.2e}")
-        assert np.mean(d <= 2e-6) >= 0.999 and d.max() <= 2e-3
+        say(f"  sigma on the GPU features: max {d.max():.2e}, max/bound {np.max(d / b):.3f}, "
+            f"{int(flips.sum())} samples near a binary16 boundary")
+        assert np.all(d <= b)
+        b, flips = net_sigma_bound(net, f[same], fo[same])
         d = np.abs(sg[same] - oracle.mlp_forward_half(net, fo[same]))
-        say(f"  sigma on the oracle features: {100 * np.mean(d <= 2e-5):.3f}% within 2e-5, max {d.max():.2e}")
-        assert np.mean(d <= 2e-5) >= 0.95 and d.max() <= 2e-3
+        say(f"  sigma on the oracle features: max {d.max():.2e}, max/bound {np.max(d / b):.3f}, "
+            f"{int(flips.sum())} samples with a possible flip")
+        assert np.all(d <= b)
         assert np.all(f[t < 0] == 0) and np.all(sg[t < 0] == 0)
     pg.close()
 
@@ -201,21 +203,51 @@ def check_selection(score, keep, frac):
         assert keep[f].sum() == V - drop
 
 
+def certified_keep(g, pg, pb, p16, frac, label):
+    """The GPU's pruning pass against the oracle's own at the starting poses:
+    every network output of the iteration-0 association within its derived
+    bound, every source score within the largest bound over its targets (where
+    all target decisions agree), and every differing keep decision certified at
+    the threshold (certify_pruning).  Returns the GPU's keep mask."""
+    N, hw = g.n_frames, g.width * g.height
+    net = p16.astype(np.float64)
+    score_g, keep_g = pg.prune()
+    check_selection(score_g, keep_g, frac)
+    score_o = pb.prune_scores(g.poses_init).reshape(N, hw)
+    keep_o = pb.prune_select(score_o.reshape(N, g.height, g.width), frac).reshape(N, hw)
+    t_pix = np.zeros((N, hw))
+    uncertain = np.zeros((N, hw), bool)
+    n_flip = n_pp = 0
+    for i in range(N):
+        pairs = [(i, j) for j in range(N) if j != i]
+        To, Fo = pb.pairs_features(g.poses_init, pairs, 0)
+        for q, (_, j) in enumerate(pairs):
+            fg, sg, tg = pg.pair_features(i, j, 0, sigma=True)
+            to = To[q]
+            uncertain[i] |= ((tg >= 0) != (to >= 0)) | ((tg >= 0) & (tg != to))
+            both = (tg >= 0) & (tg == to)
+            b, flips = net_sigma_bound(net, fg[both], Fo[q][both])
+            d = np.abs(sg[both] - oracle.mlp_forward_half(net, Fo[q][both]))
+            assert np.all(d <= b), f"pair ({i},{j}): network output off its bound"
+            t_pix[i][both] = np.maximum(t_pix[i][both], b)
+            n_flip += int(flips.sum())
+            n_pp += int(both.sum())
+    n_diff, n_cert = certify_pruning(score_g, keep_g, score_o, keep_o, t_pix, uncertain, frac)
+    say(f"{label}: {n_pp} gated-in pixel-pairs ({n_flip} with a possible binary16 flip), "
+        f"{int(uncertain.sum())} sources with a differing association; keep differs at {n_diff} of "
+        f"{int((score_o >= 0).sum())} sources ({n_cert} certified at the threshold, the rest uncertain)")
+    return keep_g
+
+
 @pytest.mark.parametrize("frac", [0.25, 0.5])
 def test_prune_scores_and_selection(frac):
     g = synth.make_graph("T")
     p16 = rand_params(5)
     pg = gpu_graph(g, learned_cfg(g, prune_frac=frac), p16)
-    score, keep = pg.prune()
-    check_selection(score, keep, frac)
     pb = oracle.OracleProblem.from_synth(g, oracle.Params(mlp=p16.astype(np.float64)))
-    so = pb.prune_scores(g.poses_init).reshape(g.n_frames, -1)
-    assert np.array_equal(score < 0, so < 0)
-    d = np.abs(score - so)[so >= 0]
-    frac_close = np.mean(d <= 5e-5)
-    say(f"frac {frac}: scores within 5e-5 for {100 * frac_close:.3f}% of sources (max {d.max():.2e})")
-    # a source whose best target flips at a pixel-rounding tie may score differently
-    assert frac_close >= 0.995
+    keep = certified_keep(g, pg, pb, p16, frac, f"T frac {frac}")
+    score, keep2 = pg.prune()
+    assert np.array_equal(keep, keep2)
     # the oracle's own selection from the GPU scores is the GPU's selection
     ko = pb.prune_select(score.reshape(g.n_frames, g.height, g.width).astype(np.float64), frac)
     assert np.array_equal(ko.reshape(g.n_frames, -1).astype(bool), keep)
@@ -260,18 +292,32 @@ def test_prune_edge_cases():
 
 # ---------------------------------------------------------- learned optimise
 
-@pytest.mark.parametrize("name,frac", [("T", 0.25), ("T", 0.0), ("P", 0.25)])
-def test_learned_optimize_matches_oracle(name, frac):
+def shipped_weights():
+    import os
+    from paper_2108_00516_amd import learn
+    path = os.path.join(os.path.dirname(learn.__file__), "weights", "weightnet.npy")
+    return np.load(path).astype(np.float16)
+
+
+@pytest.mark.parametrize("name,frac,weights", [("T", 0.25, "rand"), ("T", 0.0, "rand"), ("P", 0.25, "rand"),
+                                               ("P", 0.25, "shipped"), ("L", 0.25, "shipped")])
+def test_learned_optimize_matches_oracle(name, frac, weights):
+    """Seven learned iterations against the oracle: the pruning decisions are
+    certified against the oracle's own (certified_keep) and the oracle is then
+    given the GPU's kept pixels; each side takes its own association decisions
+    in every iteration.  L is the learned-weighting workload: 20 keyframes at
+    640x480, 25 % pruned, the shipped network."""
     g = synth.make_graph(name)
-    p16 = rand_params(7)
-    say(f"learned optimise {name} ({g.n_frames} keyframes), prune {frac}")
+    p16 = rand_params(7) if weights == "rand" else shipped_weights()
+    say(f"learned optimise {name} ({g.n_frames} keyframes), prune {frac}, {weights} weights")
     pg = gpu_graph(g, learned_cfg(g, prune_frac=frac), p16)
-    keep = None
-    if frac > 0:
-        _, keep = pg.prune()          # the pass optimize runs at the same starting poses
-    st = pg.optimize()
     P = oracle.Params(mlp=p16.astype(np.float64), mlp_iters=7)
     pb = oracle.OracleProblem.from_synth(g, P)
+    keep = None
+    if frac > 0:
+        # the pass optimize runs at the same starting poses
+        keep = certified_keep(g, pg, pb, p16, frac, name)
+    st = pg.optimize()
     if keep is not None:
         pb.set_keep(keep.reshape(g.n_frames, g.height, g.width))
     Po, so = pb.optimize(g.poses_init, 7)
@@ -284,7 +330,8 @@ def test_learned_optimize_matches_oracle(name, frac):
         assert st["src_pixels"] == (g.n_frames - 1) * int(keep.sum())
         assert int(keep.sum()) == V - sum(math.floor(frac * pg.frame_info(f, with_map=False)[1])
                                           for f in range(g.n_frames))
-    # a graph replay reproduces the result bit for bit
+    # a second optimisation from the same poses and a fresh graph reproduce
+    # the result bit for bit
     pg.set_poses(g.poses_init)
     P1 = pg.poses
     pg.optimize()
@@ -303,10 +350,10 @@ def test_learned_linearize_matches_oracle():
     g = synth.make_graph("T")
     p16 = rand_params(8)
     pg = gpu_graph(g, learned_cfg(g, prune_frac=0.25), p16)
-    _, keep = pg.prune()
-    H, gv, st = pg.linearize()
     P = oracle.Params(mlp=p16.astype(np.float64), mlp_iters=7)
     pb = oracle.OracleProblem.from_synth(g, P)
+    keep = certified_keep(g, pg, pb, p16, 0.25, "T linearize")
+    H, gv, st = pg.linearize()
     pb.set_keep(keep.reshape(g.n_frames, g.height, g.width))
     dec = np.stack([pg.associate(i, j)[0] for (i, j) in pb.ordered_pairs()])
     lin = pb.linearize_given(g.poses_init, dec)
