@@ -104,6 +104,8 @@ def lib():
         L.orc_ransac_pairs.argtypes = [P(Problem), C.c_int, P(C.c_int), P(C.c_int), P(C.c_int), P(C.c_float),
                                        P(C.c_float), C.c_int, P(C.c_int), C.c_double, C.c_double, P(C.c_int),
                                        P(C.c_int), dp, P(C.c_ubyte)]
+        L.orc_match_descriptors.argtypes = [C.c_int, P(C.c_float), C.c_int, P(C.c_float), C.c_int, C.c_double,
+                                            P(C.c_int), dp, dp]
         L.orc_mlp_bce.argtypes = [dp, C.c_int, dp, dp, dp]
         L.orc_mlp_bce.restype = C.c_double
         _lib = L
@@ -445,6 +447,23 @@ def ransac_score(a, na, b, nb, valid, sample, delta=0.005, alpha=float(np.deg2ra
     s = lib().orc_ransac_score(n, *[_ptr(v, C.c_double) for v in arrs], _ptr(valid, C.c_ubyte), _ptr(smp, C.c_int),
                                float(delta), float(alpha), _ptr(T, C.c_double), _ptr(inl, C.c_ubyte))
     return s, T, inl[:n].astype(bool)
+
+
+def match_descriptors(A, B, ratio=1.0):
+    """(match (na,), d1 (na,), d2 (na,)): mutual nearest neighbours of the
+    FP32 descriptor rows of A in B (squared Euclidean distances, FP64), with
+    the ratio test when ratio < 1."""
+    A = np.ascontiguousarray(A, np.float32)
+    B = np.ascontiguousarray(B, np.float32)
+    na, nb = len(A), len(B)
+    dim = A.shape[1] if A.ndim == 2 else B.shape[1]
+    m = np.zeros(max(na, 1), np.int32)
+    d1 = np.zeros(max(na, 1))
+    d2 = np.zeros(max(na, 1))
+    rc = lib().orc_match_descriptors(na, _ptr(A, C.c_float), nb, _ptr(B, C.c_float), int(dim), float(ratio),
+                                     _ptr(m, C.c_int), _ptr(d1, C.c_double), _ptr(d2, C.c_double))
+    assert rc == OK
+    return m[:na], d1[:na], d2[:na]
 
 
 def round_half(x):

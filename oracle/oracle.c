@@ -1308,3 +1308,65 @@ int orc_ransac_pairs(const orc_problem *pb, int n_pairs, const int *pi, const in
     free_frames(pb, fm);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Keypoint matching (Sec. IV-B): nearest neighbours of descriptors in
+ * Euclidean distance, kept when mutual and, with ratio < 1, when the nearest
+ * is closer than ratio times the second nearest (squared distances exact in
+ * FP64 from the FP32 descriptors). */
+int orc_match_descriptors(int na, const float *A, int nb, const float *B, int dim, double ratio, int *match,
+                          double *d1_out, double *d2_out)
+{
+    if (na < 0 || nb < 0 || dim < 1 || (na > 0 && (!A || !match)) || (nb > 0 && !B))
+        return ORC_ERR_ARG;
+    int *best_b = (int *)malloc(sizeof(int) * (size_t)(nb > 0 ? nb : 1));
+    double *best_bd = (double *)malloc(sizeof(double) * (size_t)(nb > 0 ? nb : 1));
+    for (int b = 0; b < nb; ++b) {
+        best_b[b] = -1;
+        best_bd[b] = INFINITY;
+    }
+    int *best_a = (int *)malloc(sizeof(int) * (size_t)(na > 0 ? na : 1));
+    double *d1 = (double *)malloc(sizeof(double) * (size_t)(na > 0 ? na : 1));
+    double *d2 = (double *)malloc(sizeof(double) * (size_t)(na > 0 ? na : 1));
+    for (int a = 0; a < na; ++a) {
+        best_a[a] = -1;
+        d1[a] = d2[a] = INFINITY;
+        for (int b = 0; b < nb; ++b) {
+            double d = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                const double e = (double)A[(size_t)a * dim + k] - (double)B[(size_t)b * dim + k];
+                d += e * e;
+            }
+            /* nearest (lowest index among equals) and second nearest of a */
+            if (d < d1[a]) {
+                d2[a] = d1[a];
+                d1[a] = d;
+                best_a[a] = b;
+            } else if (d < d2[a]) {
+                d2[a] = d;
+            }
+            /* nearest of b (lowest index among equals) */
+            if (d < best_bd[b]) {
+                best_bd[b] = d;
+                best_b[b] = a;
+            }
+        }
+    }
+    for (int a = 0; a < na; ++a) {
+        const int b = best_a[a];
+        int m = (b >= 0 && best_b[b] == a) ? b : -1;
+        if (m >= 0 && ratio < 1.0 && !(d1[a] < ratio * ratio * d2[a]))
+            m = -1;
+        match[a] = m;
+        if (d1_out)
+            d1_out[a] = d1[a];
+        if (d2_out)
+            d2_out[a] = d2[a];
+    }
+    free(best_b);
+    free(best_bd);
+    free(best_a);
+    free(d1);
+    free(d2);
+    return ORC_OK;
+}

@@ -218,6 +218,17 @@ int orc_ransac_pairs(const orc_problem *pb, int n_pairs, const int *pi, const in
                      const float *uv_i, const float *uv_j, int n_hyp, const int *samples, double delta,
                      double alpha, int *best, int *score, double *T, unsigned char *inlier);
 
+/* ---- keypoint matching (Sec. IV-B) ----
+ * Descriptors A (na x dim) of frame a and B (nb x dim) of frame b, FP32
+ * row-major.  match[x] = the nearest descriptor of B to A[x] (squared
+ * Euclidean distance, exact in FP64; lowest index among equals) when A[x] is
+ * also the nearest of A to it (lowest index among equals) and, for ratio < 1,
+ * when d1 < ratio^2 d2 (d1, d2: the squared distances to the nearest and the
+ * second nearest); else -1.  d1_out, d2_out (na, may be NULL) receive d1 and
+ * d2 (infinity where undefined). */
+int orc_match_descriptors(int na, const float *A, int nb, const float *B, int dim, double ratio, int *match,
+                          double *d1_out, double *d2_out);
+
 #ifdef __cplusplus
 }
 #endif

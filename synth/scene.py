@@ -368,3 +368,61 @@ def ransac_samples(seed: int, n_matches: int, n_hyp: int, pair: int = 0) -> np.n
     i2 = i2 + (i2 >= hi)
     out[:, 0], out[:, 1], out[:, 2] = i0, i1, i2
     return out
+
+
+@dataclasses.dataclass
+class KeypointFrame:
+    uv: np.ndarray         # (n, 2) float32 pixel coordinates (u, v)
+    desc: np.ndarray       # (n, dim) float32 unit descriptors
+    landmark: np.ndarray   # (n,) int32 landmark id, -1 for a clutter keypoint
+
+
+def make_keypoints(g: SynthGraph, n: int = 500, dim: int = 128, n_landmarks: int = 600,
+                   clutter_frac: float = 0.3, desc_noise: float = 0.15, seed: int = 0) -> List[KeypointFrame]:
+    """Keypoints with descriptors for every frame of a window, standing in for
+    the learned detector's n = 500 keypoints and 128-D descriptors: landmarks
+    are object surface points (drawn from frame 0's clean render and kept in
+    the object frame); a frame's keypoints are the landmarks visible in it
+    (projected at its ground-truth pose, depth-consistent), each with its
+    landmark's random unit descriptor plus N(0, desc_noise^2 / dim) noise per
+    component, renormalised, then clutter keypoints (random object pixels with
+    random descriptors) up to clutter_frac of n; at most n per frame, in
+    random order."""
+    rng = np.random.default_rng([seed, 4242])
+    K = (g.fx, g.fy, g.cx, g.cy, g.width, g.height)
+    fx, fy, cx, cy, width, height = K
+    # landmarks: object points of frame 0 (object frame)
+    m0 = np.flatnonzero(g.mask[0].ravel())
+    pick = rng.choice(m0, size=min(n_landmarks, m0.size), replace=False)
+    u = (pick % width).astype(np.float64)
+    v = (pick // width).astype(np.float64)
+    X0 = _backproject(u, v, g.depth_clean[0].ravel()[pick].astype(np.float64), fx, fy, cx, cy)
+    T0inv = np.linalg.inv(g.poses_gt[0])
+    Lobj = X0 @ T0inv[:3, :3].T + T0inv[:3, 3]
+    base = rng.normal(size=(len(Lobj), dim))
+    base /= np.linalg.norm(base, axis=1, keepdims=True)
+    frames = []
+    n_clutter = int(round(clutter_frac * n))
+    for f in range(g.n_frames):
+        T = g.poses_gt[f]
+        Xc = Lobj @ T[:3, :3].T + T[:3, 3]
+        uv = _project(np.where(Xc[:, 2:3] > 1e-6, Xc, 1.0), fx, fy, cx, cy)
+        p = np.floor(uv + 0.5).astype(np.int64)
+        inb = (Xc[:, 2] > 1e-6) & (p[:, 0] >= 1) & (p[:, 0] < width - 1) & (p[:, 1] >= 1) & (p[:, 1] < height - 1)
+        idx = np.where(inb, p[:, 1] * width + p[:, 0], 0)
+        vis = inb & (g.mask[f].ravel()[idx] > 0) & (np.abs(g.depth_clean[f].ravel()[idx] - Xc[:, 2]) < VISIBLE_TOL)
+        lm = np.flatnonzero(vis)
+        lm = lm[rng.permutation(lm.size)][:n - n_clutter]
+        d = base[lm] + rng.normal(scale=desc_noise / np.sqrt(dim), size=(lm.size, dim))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        mf = np.flatnonzero(g.mask[f].ravel())
+        cl = rng.choice(mf, size=min(n_clutter, mf.size), replace=False)
+        cd = rng.normal(size=(cl.size, dim))
+        cd /= np.linalg.norm(cd, axis=1, keepdims=True)
+        uv_all = np.concatenate([uv[lm], np.stack([cl % width, cl // width], axis=-1).astype(np.float64)])
+        d_all = np.concatenate([d, cd])
+        ids = np.concatenate([lm, np.full(cl.size, -1)])
+        perm = rng.permutation(ids.size)
+        frames.append(KeypointFrame(uv_all[perm].astype(np.float32), d_all[perm].astype(np.float32),
+                                    ids[perm].astype(np.int32)))
+    return frames
