@@ -52,11 +52,15 @@ typedef enum {
 } pg_status;
 
 /* Solvers of the Gauss-Newton step (all exact up to rounding):
- * AUTO picks Gauss-Jordan (3x3 pivot blocks, rank-3 updates on the FP64 matrix
- * cores, one workgroup per graph) when the system has at most 126 unknowns
- * (21 free nodes), else Cholesky; PCG is the Jacobi-preconditioned conjugate
- * gradient the paper names (Sec. IV-D). */
-enum { PG_SOLVER_AUTO = 0, PG_SOLVER_PCG = 1, PG_SOLVER_CHOLESKY = 2, PG_SOLVER_GAUSS_JORDAN = 3 };
+ * AUTO picks LDL (block LDL^T with 4x4 pivot blocks on one wavefront, the
+ * system held in registers, rank-4 updates on the FP64 matrix cores) when the
+ * system has at most 60 unknowns (10 free nodes), else Gauss-Jordan (3x3 pivot
+ * blocks, rank-3 updates on the matrix cores, one workgroup per graph) up to
+ * 126 unknowns (21 free nodes), else Cholesky; PCG is the Jacobi-preconditioned
+ * conjugate gradient the paper names (Sec. IV-D).  Choosing LDL for a graph
+ * that may hold more than 10 free nodes fails (PG_ERR_CAPACITY at create). */
+enum { PG_SOLVER_AUTO = 0, PG_SOLVER_PCG = 1, PG_SOLVER_CHOLESKY = 2, PG_SOLVER_GAUSS_JORDAN = 3,
+       PG_SOLVER_LDL = 4 };
 enum { PG_WEIGHT_HUBER = 0, PG_WEIGHT_LEARNED = 1 };
 enum { PG_PREC_FP32 = 0, PG_PREC_BF16X3 = 1 };
 
@@ -78,7 +82,7 @@ typedef struct {
     double huber_g_m;           /* Huber threshold of the dense term, metres (0.005)        */
     double gate_dist_m;         /* dense association distance gate, metres (0.01)           */
     double gate_normal_rad;     /* dense association normal-angle gate, radians (30 deg)    */
-    int solver;                 /* PG_SOLVER_AUTO (default), _PCG, _CHOLESKY, _GAUSS_JORDAN */
+    int solver;                 /* PG_SOLVER_AUTO (default), _PCG, _CHOLESKY, _GAUSS_JORDAN, _LDL */
     int pcg_max_iters;          /* PCG iteration cap (default 500)                           */
     double pcg_rel_tol;         /* PCG stop: |r| <= tol |b| (default 1e-12)                  */
     int weighting;              /* PG_WEIGHT_HUBER (default) or PG_WEIGHT_LEARNED            */

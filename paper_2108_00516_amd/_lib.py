@@ -22,7 +22,7 @@ PG_ERR_HIP = -7
 STATUS_NAMES = {0: "PG_OK", -1: "PG_ERR_INVALID_ARG", -2: "PG_ERR_NO_DEVICE", -3: "PG_ERR_OUT_OF_MEMORY",
                 -4: "PG_ERR_CAPACITY", -5: "PG_ERR_SINGULAR", -6: "PG_ERR_NONFINITE", -7: "PG_ERR_HIP"}
 
-PG_SOLVER_AUTO, PG_SOLVER_PCG, PG_SOLVER_CHOLESKY, PG_SOLVER_GAUSS_JORDAN = 0, 1, 2, 3
+PG_SOLVER_AUTO, PG_SOLVER_PCG, PG_SOLVER_CHOLESKY, PG_SOLVER_GAUSS_JORDAN, PG_SOLVER_LDL = 0, 1, 2, 3, 4
 PG_WEIGHT_HUBER, PG_WEIGHT_LEARNED = 0, 1
 PG_PREC_FP32, PG_PREC_BF16X3 = 0, 1
 PG_MAX_FRAMES_LIMIT = 32

@@ -22,7 +22,10 @@ constexpr int kIterRecord = 8;       // per iteration: E_f, E_g, n_g, n_f, targe
 constexpr int kSolverPCG = 1;
 constexpr int kSolverCholesky = 2;
 constexpr int kSolverGaussJordan = 3;
+constexpr int kSolverLDL = 4;
 constexpr int kGjMaxN = 126;
+constexpr int kLdlMaxN = 60;     // single-wavefront LDL^T: 4 x 4 tiles of 16, rows padded to 4, one column for -g
+constexpr int kLdlMaxN2 = 28;    //   2 x 2 tiles up to this size
 constexpr int kSolveStaticLds = 4096;  // static LDS of the solve kernel (upper bound)         // Gauss-Jordan: at most 21 free nodes (n x (n+1) doubles in LDS)
 
 // status bits (sticky, per graph)

@@ -34,7 +34,7 @@ void launch_mlp_to_float(const __half* p16, float* p32, hipStream_t st);
 void launch_assemble(const GraphDev* gds, const int2* nbs, int n, hipStream_t st);
 size_t solve_lds_bytes(int n_free, int n_frames);
 int gj_slots(int n_free);   // columns of the Gauss-Jordan system
-void launch_gj_solve(const GraphDev* gds, int n_graphs, int cols, hipStream_t st);
+void launch_mfma_solve(const GraphDev* gds, int n_graphs, int cols, hipStream_t st);
 hipError_t solve_set_max_lds(size_t bytes);
 void launch_solve(const GraphDev* gds, int n_graphs, size_t lds, int mode, hipStream_t st);
 }  // namespace pg
@@ -86,9 +86,9 @@ struct Schedule {
     size_t lds = 0;
     int ppt = 4;
     int iters = 0;
-    bool gj = false;      // every graph solved by the register Gauss-Jordan kernel
+    bool gj = false;      // every graph solved on the matrix cores (LDL^T or Gauss-Jordan)
     int precision = 0;    // PG_PREC_* of every graph of the schedule
-    int gj_slots = 1;   // widest Gauss-Jordan system (columns) of the schedule
+    int gj_slots = 1;   // widest Gauss-Jordan system (columns) of the schedule (1 if none)
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> events;   // timing: start, then 5 per iteration
     ~Schedule()
@@ -258,7 +258,7 @@ pg_status prepare_graph(pg_graph* g)
     g->n_free = (int)free_ids.size();
     {
         const int nf = 6 * g->n_free;
-        const bool gj_fits = nf <= kGjMaxN;
+        const bool gj_fits = nf <= kGjMaxN, ldl_fits = nf <= kLdlMaxN;
         switch (g->cfg.solver) {
         case PG_SOLVER_PCG: g->solver = kSolverPCG; break;
         case PG_SOLVER_CHOLESKY: g->solver = kSolverCholesky; break;
@@ -267,7 +267,12 @@ pg_status prepare_graph(pg_graph* g)
                 return fail(g, PG_ERR_CAPACITY, "Gauss-Jordan solve of %d unknowns exceeds %d", nf, kGjMaxN);
             g->solver = kSolverGaussJordan;
             break;
-        default: g->solver = gj_fits ? kSolverGaussJordan : kSolverCholesky; break;
+        case PG_SOLVER_LDL:
+            if (!ldl_fits)
+                return fail(g, PG_ERR_CAPACITY, "LDL^T solve of %d unknowns exceeds %d", nf, kLdlMaxN);
+            g->solver = kSolverLDL;
+            break;
+        default: g->solver = ldl_fits ? kSolverLDL : gj_fits ? kSolverGaussJordan : kSolverCholesky; break;
         }
     }
     // learned weighting: each frame keeps its n_src - floor(frac * n_src)
@@ -521,18 +526,21 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
                 nbs.push_back(make_int2((int)k, I | (J << 8)));
         lds = std::max(lds, solve_lds_bytes(g->n_free, g->n_frames));
     }
-    // one solve kernel for the whole schedule: Gauss-Jordan when every graph
-    // resolved to it, else the LDS Cholesky/PCG kernel (Gauss-Jordan graphs
-    // then use Cholesky, which gives the same step)
+    // one solve kernel for the whole schedule: the matrix-core kernel when
+    // every graph resolved to LDL^T or Gauss-Jordan (each graph keeps its own,
+    // so a batched graph's step is its single run's bit for bit), else the
+    // LDS Cholesky/PCG kernel (those graphs then use Cholesky, which gives the
+    // same step up to rounding)
     s.gj = true;
     s.gj_slots = 1;
     for (pg_graph* g : gs) {
-        s.gj = s.gj && g->solver == kSolverGaussJordan;
-        s.gj_slots = std::max(s.gj_slots, gj_slots(g->n_free));
+        s.gj = s.gj && (g->solver == kSolverGaussJordan || g->solver == kSolverLDL);
+        if (g->solver == kSolverGaussJordan)
+            s.gj_slots = std::max(s.gj_slots, gj_slots(g->n_free));
     }
     if (!s.gj)
         for (GraphDev& d : devs)
-            if (d.solver == kSolverGaussJordan)
+            if (d.solver == kSolverGaussJordan || d.solver == kSolverLDL)
                 d.solver = kSolverCholesky;
     // items of all graphs are concatenated; the XCD mapping of the association
     // kernel hands each XCD a contiguous run of them
@@ -603,7 +611,7 @@ hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std
         if (m && (e = hipEventRecord(m[3], st)) != hipSuccess)
             return e;
         if (s.gj)
-            launch_gj_solve(gds, ng, s.gj_slots, st);
+            launch_mfma_solve(gds, ng, s.gj_slots, st);
         else
             launch_solve(gds, ng, s.lds, 0, st);
         if (m && (e = hipEventRecord(m[4], st)) != hipSuccess)
@@ -768,7 +776,7 @@ pg_status pose_graph_create(const pg_config* cfg, const pg_camera* cam, void* hi
     if (!(cfg->huber_f_m > 0 && cfg->huber_g_m > 0 && cfg->gate_dist_m > 0 && cfg->gate_normal_rad > 0 &&
           cfg->gate_normal_rad <= M_PI && cfg->lambda_f >= 0 && cfg->lambda_g >= 0))
         return fail(nullptr, PG_ERR_INVALID_ARG, "bad method parameters");
-    if (cfg->solver < PG_SOLVER_AUTO || cfg->solver > PG_SOLVER_GAUSS_JORDAN)
+    if (cfg->solver < PG_SOLVER_AUTO || cfg->solver > PG_SOLVER_LDL)
         return fail(nullptr, PG_ERR_INVALID_ARG, "unknown solver");
     if (cfg->weighting != PG_WEIGHT_HUBER && cfg->weighting != PG_WEIGHT_LEARNED)
         return fail(nullptr, PG_ERR_INVALID_ARG, "unknown weighting");
@@ -799,7 +807,8 @@ pg_status pose_graph_create(const pg_config* cfg, const pg_camera* cam, void* hi
     g->lds_limit = lds_max - kSolveStaticLds;
     const size_t need = solve_lds_bytes(cfg->max_frames - 1, cfg->max_frames);
     if (need > (size_t)g->lds_limit ||
-        (cfg->solver == PG_SOLVER_GAUSS_JORDAN && 6 * (cfg->max_frames - 1) > kGjMaxN)) {
+        (cfg->solver == PG_SOLVER_GAUSS_JORDAN && 6 * (cfg->max_frames - 1) > kGjMaxN) ||
+        (cfg->solver == PG_SOLVER_LDL && 6 * (cfg->max_frames - 1) > kLdlMaxN)) {
         delete g;
         return fail(nullptr, PG_ERR_CAPACITY, "max_frames %d needs %zu B of LDS for the solve, device has %d",
                     cfg->max_frames, need, lds_max);

@@ -2051,11 +2051,10 @@ typedef double gj_d4 __attribute__((ext_vector_type(4)));
 static_assert(16 * kMaxFrames <= 2 * 256 && kNodeStats * kMaxFrames <= 256 && kMaxFrames <= 256, "GJ prologue");
 
 template <int NT>
-__global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict__ gds)
+__device__ __forceinline__ void gj_solve(const GraphDev& gd)
 {
     constexpr int kS = (NT + 3) / 4;   // tile slots per tile row and wave
     constexpr int kM = 16 * NT;        // padded side
-    const GraphDev& gd = gds[blockIdx.x];
     const int N = gd.n_frames;
     const int n = 6 * gd.n_free;
     __shared__ double CP[2][3][kM];    // column panel v(i, 3K + m), by column
@@ -2306,6 +2305,321 @@ __global__ __launch_bounds__(256) void gj_mfma_kernel(const GraphDev* __restrict
     compute_transforms(gd, Ts);
 }
 
+// ------------------------------------------------- single-wavefront block LDL^T solve
+
+// Value of v at lane l ^ (16 T) (the same position in another row of 16 lanes).
+template <int T>
+__device__ __forceinline__ double row_xor(double v)
+{
+    static_assert(T >= 0 && T < 4, "row_xor");
+    if constexpr (T == 0)
+        return v;
+    else
+        return __shfl_xor(v, 16 * T);
+}
+
+// v summed over the 16 lanes of each row (every lane of the row gets the sum):
+// rotations by 8, 4, 2, 1 within the row (DPP row_ror), a fixed order per lane.
+__device__ __forceinline__ double row_sum16(double v)
+{
+#define PG_ROR_ADD(N)                                                                    \
+    {                                                                                    \
+        const long long x = __double_as_longlong(v);                                     \
+        const int lo = __builtin_amdgcn_mov_dpp((int)x, 0x120 + (N), 0xF, 0xF, false);   \
+        const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), 0x120 + (N), 0xF, 0xF, false); \
+        v += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);             \
+    }
+    PG_ROR_ADD(8)
+    PG_ROR_ADD(4)
+    PG_ROR_ADD(2)
+    PG_ROR_ADD(1)
+#undef PG_ROR_ADD
+    return v;
+}
+
+// v of lane L (a constant), in scalar registers
+__device__ __forceinline__ double lane_f64(double v, int L)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, L);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), L);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double rcp_f64(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
+// One Gauss-Newton solve on one wavefront: block LDL^T factorisation without
+// pivoting of the symmetric positive definite H_ff with 4 x 4 pivot blocks,
+// the right-hand side -g_f carried as the last column of the padded system,
+// then block back substitution.  Only the upper NT(NT+1)/2 tiles of 16 x 16
+// are kept, each in one v_mfma_f64_16x16x4f64 accumulator in registers (lane l
+// holds entries (16 I + 4 v + l / 16, 16 J + l % 16), v < 4).  At pivot rows
+// k..k+3 (k = 16 J + 4 v) the row panel P = rows k..k+3 sits in register v of
+// tiles (J, I >= J) in exactly the matrix cores' operand layout: lane l holds
+// P(l / 16, 16 I + l % 16), which is the A operand entry (row l % 16, column
+// l / 16) of the 16 x 4 block P^T of tile row I (the trailing system is
+// symmetric) and the B operand entry of the 4 x 16 block of tile column I.  So
+// the rank-4 update of the trailing system, V <- V - P^T D^-1 P, is one matrix
+// instruction per upper tile, with A = -P^T (rows at or above the pivot rows
+// zeroed, which leaves them unchanged) and B = R = D^-1 P (the lane's row of
+// D^-1 times P's column, gathered from the four rows of lanes).  R replaces P
+// in register v, for the back substitution x_k = R(., rhs) - R(., > k) x.
+// D^-1 comes from the 2 x 2 blocks of D (two Schur steps) in every lane, from
+// D's entries read into scalar registers.  Padding rows n..npiv-1 (npiv = n
+// rounded up to 4) are unit rows; the right-hand side is column 16 NT - 1.
+// No barrier and no shared memory until the solution is written; the other
+// three waves load the poses and node statistics meanwhile.  Then
+// T <- Exp(x) T and the next iteration's transforms, as the other solves.
+template <int NT>
+__device__ __forceinline__ void ldl_solve(const GraphDev& gd)
+{
+    constexpr int kM = 16 * NT;   // padded side; the right-hand side is column kM - 1
+    const int N = gd.n_frames;
+    const int n = 6 * gd.n_free;
+    const int npiv = (n + 3) & ~3;
+    __shared__ double xs[kM];
+    __shared__ double Ts[16 * kMaxFrames];
+    __shared__ int sfree[kMaxFrames];
+    __shared__ int sflags;   // 1: singular pivot, 2: non-finite solution
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int m = lane >> 4, c = lane & 15;
+    const int it = *gd.iters_done;
+    const int status = *gd.status;
+    const double maxdiag = __longlong_as_double((long long)*gd.maxdiag);   // written by the assembly
+    if (wave == 0) {
+        // the upper tiles of the padded system, every load issued first;
+        // padding pivots equal the largest diagonal entry (decoupled rows
+        // that pass the pivot test at any scale)
+        const double pad = (maxdiag > 0.0) ? maxdiag : 1.0;
+        gj_d4 t[NT][NT];
+        const double* __restrict__ Hff = gd.Hff;
+#pragma unroll
+        for (int I = 0; I < NT; ++I)
+#pragma unroll
+            for (int K = I; K < NT; ++K)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * I + 4 * v + m;
+                    const int j = 16 * K + c;
+                    const int col = (j == kM - 1) ? n : j;
+                    const bool in = i < n && (j == kM - 1 || j < n);
+                    const double h = Hff[in ? (size_t)i * (n + 1) + col : 0];
+                    t[I][K][v] = in ? h : ((i == j && i < npiv) ? pad : 0.0);
+                }
+        asm volatile("" ::"v"(it), "v"(status));
+        if (status == 0 && n > 0 && npiv < kM) {
+            const double tol = 1e-12 * maxdiag;
+            bool singular = !(maxdiag > 0.0);
+#pragma unroll
+            for (int J = 0; J < NT; ++J)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int k = 16 * J + 4 * v;
+                    if (k < npiv) {
+                        // pivot block D (rows and columns k..k+3) into scalar registers
+                        const double d00 = lane_f64(t[J][J][v], 4 * v + 0);
+                        const double d01 = lane_f64(t[J][J][v], 4 * v + 1);
+                        const double d02 = lane_f64(t[J][J][v], 4 * v + 2);
+                        const double d03 = lane_f64(t[J][J][v], 4 * v + 3);
+                        const double d11 = lane_f64(t[J][J][v], 16 + 4 * v + 1);
+                        const double d12 = lane_f64(t[J][J][v], 16 + 4 * v + 2);
+                        const double d13 = lane_f64(t[J][J][v], 16 + 4 * v + 3);
+                        const double d22 = lane_f64(t[J][J][v], 32 + 4 * v + 2);
+                        const double d23 = lane_f64(t[J][J][v], 32 + 4 * v + 3);
+                        const double d33 = lane_f64(t[J][J][v], 48 + 4 * v + 3);
+                        // the row panel's four rows of each column, from the other rows of lanes
+                        double x1[NT], x2[NT], x3[NT];
+#pragma unroll
+                        for (int I = J; I < NT; ++I) {
+                            x1[I] = row_xor<1>(t[J][I][v]);
+                            x2[I] = row_xor<2>(t[J][I][v]);
+                            x3[I] = row_xor<3>(t[J][I][v]);
+                        }
+                        // D^-1 by two 2 x 2 Schur steps: D = [[P, Q], [Q^T, S]]
+                        const double detP = fma(d00, d11, -d01 * d01);
+                        const double ip = rcp_f64(detP);
+                        const double p00 = d11 * ip, p01 = -d01 * ip, p11 = d00 * ip;
+                        const double w00 = fma(p00, d02, p01 * d12), w01 = fma(p00, d03, p01 * d13);
+                        const double w10 = fma(p01, d02, p11 * d12), w11 = fma(p01, d03, p11 * d13);
+                        const double s00 = d22 - fma(d02, w00, d12 * w10);
+                        const double s01 = d23 - fma(d02, w01, d12 * w11);
+                        const double s11 = d33 - fma(d03, w01, d13 * w11);
+                        const double detS = fma(s00, s11, -s01 * s01);
+                        const double is = rcp_f64(detS);
+                        const double q00 = s11 * is, q01 = -s01 * is, q11 = s00 * is;
+                        // X12 = -W S^-1, X11 = P^-1 - X12 W^T
+                        const double e00 = -fma(w00, q00, w01 * q01), e01 = -fma(w00, q01, w01 * q11);
+                        const double e10 = -fma(w10, q00, w11 * q01), e11 = -fma(w10, q01, w11 * q11);
+                        const double f00 = p00 - fma(e00, w00, e01 * w01);
+                        const double f01 = p01 - fma(e00, w10, e01 * w11);
+                        const double f11 = p11 - fma(e10, w10, e11 * w11);
+                        // the scalar pivots d00, detP / d00, s00, detS / s00 all exceed tol
+                        singular |= !((d00 > tol) && (detP > tol * d00) && (s00 > tol) && (detS > tol * s00));
+                        // row m of D^-1, column m ^ q in slot q
+                        double dq[4];
+                        {
+                            // rows of D^-1 = [[F, E], [E^T, Q]]
+                            const double r0[4] = {f00, f01, e00, e01};
+                            const double r1[4] = {f01, f11, e10, e11};
+                            const double r2[4] = {e00, e10, q00, q01};
+                            const double r3[4] = {e01, e11, q01, q11};
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                dq[q] = (m == 0) ? r0[q] : (m == 1) ? r1[q ^ 1] : (m == 2) ? r2[q ^ 2] : r3[q ^ 3];
+                        }
+                        // operands: A = -P^T, B = R = D^-1 P; the pivot rows' own
+                        // columns and those left of them give zero (masked)
+                        double a[NT], b[NT];
+#pragma unroll
+                        for (int I = J; I < NT; ++I) {
+                            const double p = t[J][I][v];
+                            const bool left = (I == J) && (c <= 4 * v + 3);
+                            const bool rhs = (I == NT - 1) && (c == 15);
+                            const double r = fma(dq[0], p, fma(dq[1], x1[I], fma(dq[2], x2[I], dq[3] * x3[I])));
+                            a[I] = (left || rhs) ? 0.0 : -p;
+                            b[I] = left ? 0.0 : r;
+                            t[J][I][v] = b[I];
+                        }
+                        // the next pivot rows' tiles first
+                        const int Jn = (v < 3) ? J : J + 1;
+#pragma unroll
+                        for (int I = Jn; I < NT; ++I)
+                            t[Jn][I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[Jn], b[I], t[Jn][I], 0, 0, 0);
+#pragma unroll
+                        for (int Ir = J; Ir < NT; ++Ir) {
+                            if (Ir == Jn)
+                                continue;
+#pragma unroll
+                            for (int I = Ir; I < NT; ++I)
+                                t[Ir][I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[Ir], b[I], t[Ir][I], 0, 0, 0);
+                        }
+                    }
+                }
+            // back substitution: lane (m, c) holds x(16 I + c) in xv[I]; the
+            // right-hand side column's slot holds -1, so each block's
+            // x = R(., rhs) - R(., > k) x is minus the row sum of R x
+            double xv[NT];
+#pragma unroll
+            for (int I = 0; I < NT; ++I)
+                xv[I] = (I == NT - 1 && c == 15) ? -1.0 : 0.0;
+#pragma unroll
+            for (int J = NT - 1; J >= 0; --J)
+#pragma unroll
+                for (int v = 3; v >= 0; --v) {
+                    const int k = 16 * J + 4 * v;
+                    if (k < npiv) {
+                        double p = 0.0;
+#pragma unroll
+                        for (int I = NT - 1; I >= J; --I)
+                            p = fma(t[J][I][v], xv[I], p);
+                        const double xk = -row_sum16(p);   // x(k + m) on every lane of row m
+                        const double y1 = row_xor<1>(xk), y2 = row_xor<2>(xk), y3 = row_xor<3>(xk);
+                        const int d = c - 4 * v;   // lanes of columns k..k+3 take x(k + d)
+                        const int q = d ^ m;
+                        const double y = (q == 0) ? xk : (q == 1) ? y1 : (q == 2) ? y2 : y3;
+                        if (d >= 0 && d < 4)
+                            xv[J] = y;
+                    }
+                }
+            bool bad = false;
+            if (m == 0) {
+#pragma unroll
+                for (int I = 0; I < NT; ++I)
+                    if (16 * I + c < n) {
+                        xs[16 * I + c] = xv[I];
+                        bad |= !isfinite(xv[I]);
+                    }
+            }
+            bad = __any(bad);
+            if (lane == 0)
+                sflags = (singular ? 1 : 0) | (bad ? 2 : 0);
+        } else if (lane == 0) {
+            // nothing to solve (every node fixed); a system too large for the
+            // tiles is refused on the host
+            sflags = (n > 0) ? 1 : 0;
+        }
+    } else {
+        // the poses, the free-node ids and this iteration's statistics
+        // (record fields E_f, E_g, n_g, n_f, target reads from node fields
+        // 1, 0, 2, 3, 4), while wave 0 solves
+        const int u = tid - 64;
+        double tv[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            tv[r] = (u + 192 * r < 16 * N) ? gd.poses[u + 192 * r] : 0.0;
+        const int fv = (u < gd.n_free) ? gd.free_ids[u] : 0;
+        double s = 0.0;
+        if (u < kNodeStats && status == 0) {
+            const int src = (u < 2) ? 1 - u : u;
+            for (int k = 0; k < N; ++k)
+                s += gd.node_stats[kNodeStats * k + src];
+            gd.iter_stats[kIterRecord * it + u] = s;
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            if (u + 192 * r < 16 * N)
+                Ts[u + 192 * r] = tv[r];
+        if (u < gd.n_free)
+            sfree[u] = fv;
+    }
+    if (status)
+        return;   // uniform: every wave read the same status
+    __syncthreads();
+    const int flags = sflags;
+    // every thread has used the diagonal maximum by now: cleared for the
+    // next iteration's assembly
+    if (tid == 0)
+        *gd.maxdiag = 0ull;
+    if (n == 0) {
+        if (tid == 0)
+            *gd.iters_done = it + 1;
+        return;
+    }
+    if (flags) {
+        if (tid == 0)
+            *gd.status |= (flags & 1) ? kStatusSingular : kStatusNonFinite;
+        return;
+    }
+    for (int q = tid; q < gd.n_free; q += 256) {
+        const int node = sfree[q];
+        double E[16], Tn[16];
+        se3_exp(xs + 6 * q, E);
+        mat4_mul(E, Ts + 16 * node, Tn);
+        for (int k = 0; k < 16; ++k) {
+            Ts[16 * node + k] = Tn[k];
+            gd.poses[16 * node + k] = Tn[k];
+        }
+    }
+    __syncthreads();
+    if (tid == 0)
+        *gd.iters_done = it + 1;
+    compute_transforms(gd, Ts);
+}
+
+// One block of 256 threads per graph: the single-wavefront block LDL^T for
+// graphs resolved to it (16 x 16 tiles: 2 x 2 up to 28 unknowns, else 4 x 4),
+// else block Gauss-Jordan on GNT x GNT tiles.
+template <int GNT>
+__global__ __launch_bounds__(256) void solve_mfma_kernel(const GraphDev* __restrict__ gds)
+{
+    const GraphDev& gd = gds[blockIdx.x];
+    if (gd.solver == kSolverLDL) {
+        if (6 * gd.n_free <= kLdlMaxN2)
+            ldl_solve<2>(gd);
+        else
+            ldl_solve<4>(gd);
+    } else {
+        gj_solve<GNT>(gd);
+    }
+}
+
 // ------------------------------------------------------------ launchers
 
 void launch_preprocess(const float* depth, const uint8_t* mask, int W, int H, float cx, float cy, float ifx,
@@ -2402,16 +2716,18 @@ size_t solve_lds_bytes(int n_free, int n_frames)
 // columns (n + 1) of the Gauss-Jordan system of n_free free nodes
 int gj_slots(int n_free) { return 6 * n_free + 1; }
 
-// Matrix-core variant: NT x NT tiles of 16 x 16, 16 NT >= n + 1.
-void launch_gj_solve(const GraphDev* gds, int n_graphs, int cols, hipStream_t st)
+// Matrix-core solves: LDL^T graphs on their own tiles, Gauss-Jordan graphs on
+// NT x NT tiles of 16 x 16, 16 NT >= cols (the widest Gauss-Jordan system).
+void launch_mfma_solve(const GraphDev* gds, int n_graphs, int cols, hipStream_t st)
 {
     static_assert(kGjMaxN + 1 <= 16 * 8, "Gauss-Jordan tiles too few for kGjMaxN");
+    static_assert(((kLdlMaxN + 3) & ~3) < 16 * 4 && ((kLdlMaxN2 + 3) & ~3) < 16 * 2, "LDL tiles too few");
     if (cols <= 32)
-        gj_mfma_kernel<2><<<n_graphs, 256, 0, st>>>(gds);
+        solve_mfma_kernel<2><<<n_graphs, 256, 0, st>>>(gds);
     else if (cols <= 64)
-        gj_mfma_kernel<4><<<n_graphs, 256, 0, st>>>(gds);
+        solve_mfma_kernel<4><<<n_graphs, 256, 0, st>>>(gds);
     else
-        gj_mfma_kernel<8><<<n_graphs, 256, 0, st>>>(gds);
+        solve_mfma_kernel<8><<<n_graphs, 256, 0, st>>>(gds);
 }
 
 hipError_t solve_set_max_lds(size_t bytes)

@@ -180,7 +180,8 @@ def test_optimize_parity(name):
 
 
 @pytest.mark.parametrize("name,fixed,solver", [("T", (0, 2), "GAUSS_JORDAN"), ("P", (0, 4, 7), "GAUSS_JORDAN"),
-                                                ("P", (0, 4, 7), "CHOLESKY")])
+                                                ("P", (0, 4, 7), "CHOLESKY"), ("T", (0, 2), "LDL"),
+                                                ("P", (0, 4, 7), "LDL")])
 def test_interior_fixed_nodes(name, fixed, solver):
     """Fixed nodes inside the window: the free-node system skips their rows and
     columns (node -> free position table), the poses of fixed nodes stay put."""
@@ -238,7 +239,7 @@ def test_tile_sizes(tile):
     pg.close()
 
 
-@pytest.mark.parametrize("solver", ["PCG", "CHOLESKY", "GAUSS_JORDAN"])
+@pytest.mark.parametrize("solver", ["PCG", "CHOLESKY", "GAUSS_JORDAN", "LDL"])
 def test_solvers_match(solver):
     from paper_2108_00516_amd import _lib
     g = graph("T")
