@@ -23,15 +23,25 @@ OK, ERR_ARG, ERR_SINGULAR = 0, -1, -5
 MAX_ITERS = 64
 
 
-def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP)."""
-    if force or not os.path.exists(_SO):
-        tmp = _SO + ".tmp"
+# A sanitized build (AddressSanitizer + UndefinedBehaviorSanitizer, every
+# finding fatal) for the checker's own tests; ORACLE_LIB selects the library
+# this module loads (the process must then preload the ASan runtime).
+_SAN_SO = os.path.join(_HERE, "liboracle_san.so")
+
+
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP), or with
+    sanitize=True into liboracle_san.so with -fsanitize=address,undefined."""
+    so = _SAN_SO if sanitize else _SO
+    if force or not os.path.exists(so):
+        tmp = so + ".tmp"
+        san = (["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+               if sanitize else [])
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
-               "-Wno-unused-parameter", _SRC, "-o", tmp, "-lm"]
+               "-Wno-unused-parameter", *san, _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True, cwd=_HERE)
-        os.replace(tmp, _SO)
-    return _SO
+        os.replace(tmp, so)
+    return so
 
 
 class Problem(C.Structure):
@@ -68,9 +78,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
+        path = os.environ.get("ORACLE_LIB") or _SO
+        if path == _SO and not os.path.exists(_SO):
             build()
-        L = C.CDLL(_SO)
+        L = C.CDLL(path)
         P = C.POINTER
         dp = P(C.c_double)
         L.orc_set_threads.argtypes = [C.c_int]

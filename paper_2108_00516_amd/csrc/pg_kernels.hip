@@ -1723,44 +1723,106 @@ __device__ void se3_exp(const double* xi, double* T)
     T[15] = 1.0;
 }
 
-__device__ void mat4_mul(const double* A, const double* B, double* C)
+// Block barrier that orders LDS only: waits for the thread's own LDS (and
+// scalar) accesses, not for its global stores, which nothing in the block
+// reads back.
+__device__ __forceinline__ void lds_barrier()
 {
-    for (int r = 0; r < 4; ++r)
-        for (int c = 0; c < 4; ++c)
-            C[4 * r + c] = A[4 * r] * B[c] + A[4 * r + 1] * B[4 + c] + A[4 * r + 2] * B[8 + c] + A[4 * r + 3] * B[12 + c];
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 }
 
 // A = T_i T_j^-1, B = T_j T_i^-1 per ordered pair (FP64, stored FP32 and
-// FP64), and T^-1 per node (FP64), from the poses in LDS.
+// FP64), and T^-1 = [R^T | -R^T t] per node (FP64), from the poses in LDS:
+// one thread per row of a node's inverse, then one per row of A or B.  The
+// translation of A is t_i + R_i (-R_j^T t_j), from the nodes' inverse
+// translations of the first pass.  Every thread of the block takes part (one
+// barrier).
 __device__ void compute_transforms(const GraphDev& gd, const double* __restrict__ Ts)
 {
+    __shared__ double su[3 * kMaxFrames];   // -R^T t per node
     const int N = gd.n_frames;
-    for (int q = threadIdx.x; q < 12 * N; q += blockDim.x) {
-        const double* T = Ts + 16 * (q / 12);
-        const int e = q % 12, r = e / 4, c = e % 4;
-        gd.tinv64[q] = (c < 3) ? T[4 * c + r] : -(T[r] * T[3] + T[4 + r] * T[7] + T[8 + r] * T[11]);
+    for (int q = threadIdx.x; q < 3 * N; q += blockDim.x) {
+        const int node = q / 3, r = q - 3 * node;
+        const double* T = Ts + 16 * node;
+        const double u = -(T[r] * T[3] + T[4 + r] * T[7] + T[8 + r] * T[11]);
+        double* dst = gd.tinv64 + 12 * node + 4 * r;
+        dst[0] = T[r];
+        dst[1] = T[4 + r];
+        dst[2] = T[8 + r];
+        dst[3] = u;
+        su[q] = u;
     }
-    for (int p = threadIdx.x; p < N * (N - 1); p += blockDim.x) {
-        const int i = p / (N - 1), jj = p % (N - 1), j = (jj < i) ? jj : jj + 1;
-        const double* Ti = Ts + 16 * i;
-        const double* Tj = Ts + 16 * j;
-        double A[12], B[12];
-        for (int r = 0; r < 3; ++r) {
-            for (int c = 0; c < 3; ++c) {
-                A[4 * r + c] = Ti[4 * r] * Tj[4 * c] + Ti[4 * r + 1] * Tj[4 * c + 1] + Ti[4 * r + 2] * Tj[4 * c + 2];
-                B[4 * r + c] = Tj[4 * r] * Ti[4 * c] + Tj[4 * r + 1] * Ti[4 * c + 1] + Tj[4 * r + 2] * Ti[4 * c + 2];
-            }
-        }
-        for (int r = 0; r < 3; ++r) {
-            A[4 * r + 3] = Ti[4 * r + 3] - (A[4 * r] * Tj[3] + A[4 * r + 1] * Tj[7] + A[4 * r + 2] * Tj[11]);
-            B[4 * r + 3] = Tj[4 * r + 3] - (B[4 * r] * Ti[3] + B[4 * r + 1] * Ti[7] + B[4 * r + 2] * Ti[11]);
-        }
-        for (int k = 0; k < 12; ++k) {
-            gd.xf32[p * 24 + k] = (float)A[k];
-            gd.xf32[p * 24 + 12 + k] = (float)B[k];
-            gd.xf64[p * 12 + k] = A[k];
+    lds_barrier();
+    // pair p = i (N - 1) + jj: i from a float reciprocal (exact: the
+    // fraction (jj + 1/2) / (N - 1) stays at least 1/62 from an integer)
+    const float inv = 1.0f / (float)max(N - 1, 1);
+    const int np = N * (N - 1);
+    for (int e = threadIdx.x; e < 6 * np; e += blockDim.x) {
+        const int p = e / 6, w = e - 6 * p;
+        const int i = (int)(((float)p + 0.5f) * inv), jj = p - i * (N - 1), j = (jj < i) ? jj : jj + 1;
+        const bool isA = w < 3;   // rows of A, then of B = T_j T_i^-1
+        const int r = isA ? w : w - 3;
+        const double* Ta = Ts + 16 * (isA ? i : j);
+        const int nb = isA ? j : i;
+        const double* Tb = Ts + 16 * nb;
+        const double a0 = Ta[4 * r], a1 = Ta[4 * r + 1], a2 = Ta[4 * r + 2];
+        double v[4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            v[c] = a0 * Tb[4 * c] + a1 * Tb[4 * c + 1] + a2 * Tb[4 * c + 2];
+        v[3] = Ta[4 * r + 3] + (a0 * su[3 * nb] + a1 * su[3 * nb + 1] + a2 * su[3 * nb + 2]);
+        float* d32 = gd.xf32 + 24 * p + (isA ? 0 : 12) + 4 * r;
+        *(float4*)d32 = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+        if (isA) {
+            double* d64 = gd.xf64 + 12 * p + 4 * r;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                d64[c] = v[c];
         }
     }
+}
+
+// T_q <- Exp(x_q) T_q for the free nodes q (x: 6 per free node, Ts: the
+// poses, both in LDS), 16 threads per node, one entry each; then the new
+// poses in LDS and in the graph.  Every thread of the block takes part (two
+// barriers); at least 256 threads.
+__device__ void update_poses(const GraphDev& gd, const double* __restrict__ xs, const int* __restrict__ sfree,
+                             double* __restrict__ Ts)
+{
+    static_assert(16 * kMaxFrames <= 2 * 256, "pose update: two entries per thread");
+    const int nf = gd.n_free;
+    double tn[2];
+    int at[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int e = threadIdx.x + u * blockDim.x;
+        at[u] = -1;
+        tn[u] = 0.0;
+        if (e < 16 * nf) {
+            const int q = e >> 4, r = (e >> 2) & 3, c = e & 3;
+            const int node = sfree[q];
+            double E[16];
+            se3_exp(xs + 6 * q, E);
+            const double* T = Ts + 16 * node;
+            const double t0 = T[c], t1 = T[4 + c], t2 = T[8 + c], t3 = T[12 + c];
+            double row[4];   // entry (rr, c) of E T for every row rr (constant register indices)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+                row[rr] = E[4 * rr] * t0 + E[4 * rr + 1] * t1 + E[4 * rr + 2] * t2 + E[4 * rr + 3] * t3;
+            tn[u] = (r & 2) ? ((r & 1) ? row[3] : row[2]) : ((r & 1) ? row[1] : row[0]);
+            at[u] = 16 * node + (e & 15);
+        }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+        if (at[u] >= 0) {
+            Ts[at[u]] = tn[u];
+            gd.poses[at[u]] = tn[u];
+        }
+    lds_barrier();
 }
 
 __device__ double block_sum(double v, double* scratch)
@@ -2002,17 +2064,7 @@ __global__ __launch_bounds__(kSolveThreads) void solve_kernel(const GraphDev* __
         return;
     }
     // T <- Exp(delta) T for the free nodes
-    for (int a = tid; a < gd.n_free; a += blockDim.x) {
-        const int node = sfree[a];
-        double E[16], Tn[16];
-        se3_exp(xv + 6 * a, E);
-        mat4_mul(E, Ts + 16 * node, Tn);
-        for (int k = 0; k < 16; ++k) {
-            Ts[16 * node + k] = Tn[k];
-            gd.poses[16 * node + k] = Tn[k];
-        }
-    }
-    __syncthreads();
+    update_poses(gd, xv, sfree, Ts);
     if (tid == 0)
         *gd.iters_done = it + 1;
     compute_transforms(gd, Ts);
@@ -2289,53 +2341,13 @@ __device__ __forceinline__ void gj_solve(const GraphDev& gd)
             *gd.status |= (flags & 1) ? kStatusSingular : kStatusNonFinite;
         return;
     }
-    for (int a = tid; a < gd.n_free; a += 256) {
-        const int node = sfree[a];
-        double E[16], Tn[16];
-        se3_exp(xs + 6 * a, E);
-        mat4_mul(E, Ts + 16 * node, Tn);
-        for (int k = 0; k < 16; ++k) {
-            Ts[16 * node + k] = Tn[k];
-            gd.poses[16 * node + k] = Tn[k];
-        }
-    }
-    __syncthreads();
+    update_poses(gd, xs, sfree, Ts);
     if (tid == 0)
         *gd.iters_done = it + 1;
     compute_transforms(gd, Ts);
 }
 
 // ------------------------------------------------- single-wavefront block LDL^T solve
-
-// Value of v at lane l ^ (16 T) (the same position in another row of 16 lanes).
-template <int T>
-__device__ __forceinline__ double row_xor(double v)
-{
-    static_assert(T >= 0 && T < 4, "row_xor");
-    if constexpr (T == 0)
-        return v;
-    else
-        return __shfl_xor(v, 16 * T);
-}
-
-// v summed over the 16 lanes of each row (every lane of the row gets the sum):
-// rotations by 8, 4, 2, 1 within the row (DPP row_ror), a fixed order per lane.
-__device__ __forceinline__ double row_sum16(double v)
-{
-#define PG_ROR_ADD(N)                                                                    \
-    {                                                                                    \
-        const long long x = __double_as_longlong(v);                                     \
-        const int lo = __builtin_amdgcn_mov_dpp((int)x, 0x120 + (N), 0xF, 0xF, false);   \
-        const int hi = __builtin_amdgcn_mov_dpp((int)(x >> 32), 0x120 + (N), 0xF, 0xF, false); \
-        v += __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);             \
-    }
-    PG_ROR_ADD(8)
-    PG_ROR_ADD(4)
-    PG_ROR_ADD(2)
-    PG_ROR_ADD(1)
-#undef PG_ROR_ADD
-    return v;
-}
 
 // v of lane L (a constant), in scalar registers
 __device__ __forceinline__ double lane_f64(double v, int L)
@@ -2371,18 +2383,25 @@ __device__ __forceinline__ double rcp_f64(double d)
 // D^-1 times P's column, gathered from the four rows of lanes).  R replaces P
 // in register v, for the back substitution x_k = R(., rhs) - R(., > k) x.
 // D^-1 comes from the 2 x 2 blocks of D (two Schur steps) in every lane, from
-// D's entries read into scalar registers.  Padding rows n..npiv-1 (npiv = n
-// rounded up to 4) are unit rows; the right-hand side is column 16 NT - 1.
-// No barrier and no shared memory until the solution is written; the other
-// three waves load the poses and node statistics meanwhile.  Then
-// T <- Exp(x) T and the next iteration's transforms, as the other solves.
+// D's entries read into scalar registers.  Every size runs the same 4 NT - 1
+// block steps (rows 0 .. 16 NT - 5, n <= 16 NT - 4): rows n and up to there are
+// decoupled padding rows with a diagonal equal to the largest diagonal entry of
+// H_ff, so the steps are straight-line code the compiler can overlap (the
+// next step's pivot work with this step's matrix instructions).  The
+// right-hand side is column 16 NT - 1.  No barrier and no shared memory until
+// the solution is written; the other three waves load the poses and node
+// statistics meanwhile.  Then T <- Exp(x) T and the next iteration's
+// transforms, as the other solves.
+constexpr int kLdlStride = 66;   // doubles per row of the R rows in LDS (16-byte aligned rows)
+
 template <int NT>
-__device__ __forceinline__ void ldl_solve(const GraphDev& gd)
+__device__ __forceinline__ void ldl_solve(const GraphDev& gd, double* __restrict__ Rl)
 {
-    constexpr int kM = 16 * NT;   // padded side; the right-hand side is column kM - 1
+    constexpr int kM = 16 * NT;          // padded side; the right-hand side is column kM - 1
+    constexpr int kSteps = 4 * NT - 1;   // pivot rows 0 .. kM - 5
+    static_assert(kM + 2 <= kLdlStride, "LDL row stride");
     const int N = gd.n_frames;
     const int n = 6 * gd.n_free;
-    const int npiv = (n + 3) & ~3;
     __shared__ double xs[kM];
     __shared__ double Ts[16 * kMaxFrames];
     __shared__ int sfree[kMaxFrames];
@@ -2394,10 +2413,11 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd)
     const int status = *gd.status;
     const double maxdiag = __longlong_as_double((long long)*gd.maxdiag);   // written by the assembly
     if (wave == 0) {
-        // the upper tiles of the padded system, every load issued first;
-        // padding pivots equal the largest diagonal entry (decoupled rows
-        // that pass the pivot test at any scale)
+        // the upper tiles of the padded system, every load issued first from
+        // a clamped (always valid) address; padding pivots equal the largest
+        // diagonal entry (decoupled rows that pass the pivot test at any scale)
         const double pad = (maxdiag > 0.0) ? maxdiag : 1.0;
+        const int ilast = (n > 0) ? n - 1 : 0;
         gj_d4 t[NT][NT];
         const double* __restrict__ Hff = gd.Hff;
 #pragma unroll
@@ -2408,134 +2428,130 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd)
                 for (int v = 0; v < 4; ++v) {
                     const int i = 16 * I + 4 * v + m;
                     const int j = 16 * K + c;
-                    const int col = (j == kM - 1) ? n : j;
-                    const bool in = i < n && (j == kM - 1 || j < n);
-                    const double h = Hff[in ? (size_t)i * (n + 1) + col : 0];
-                    t[I][K][v] = in ? h : ((i == j && i < npiv) ? pad : 0.0);
+                    const int col = (j == kM - 1) ? n : min(j, n);
+                    t[I][K][v] = ld_global(Hff + (min(i, ilast) * (n + 1) + col));
                 }
-        asm volatile("" ::"v"(it), "v"(status));
-        if (status == 0 && n > 0 && npiv < kM) {
-            const double tol = 1e-12 * maxdiag;
-            bool singular = !(maxdiag > 0.0);
 #pragma unroll
-            for (int J = 0; J < NT; ++J)
+        for (int I = 0; I < NT; ++I)
+#pragma unroll
+            for (int K = I; K < NT; ++K)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int k = 16 * J + 4 * v;
-                    if (k < npiv) {
-                        // pivot block D (rows and columns k..k+3) into scalar registers
-                        const double d00 = lane_f64(t[J][J][v], 4 * v + 0);
-                        const double d01 = lane_f64(t[J][J][v], 4 * v + 1);
-                        const double d02 = lane_f64(t[J][J][v], 4 * v + 2);
-                        const double d03 = lane_f64(t[J][J][v], 4 * v + 3);
-                        const double d11 = lane_f64(t[J][J][v], 16 + 4 * v + 1);
-                        const double d12 = lane_f64(t[J][J][v], 16 + 4 * v + 2);
-                        const double d13 = lane_f64(t[J][J][v], 16 + 4 * v + 3);
-                        const double d22 = lane_f64(t[J][J][v], 32 + 4 * v + 2);
-                        const double d23 = lane_f64(t[J][J][v], 32 + 4 * v + 3);
-                        const double d33 = lane_f64(t[J][J][v], 48 + 4 * v + 3);
-                        // the row panel's four rows of each column, from the other rows of lanes
-                        double x1[NT], x2[NT], x3[NT];
-#pragma unroll
-                        for (int I = J; I < NT; ++I) {
-                            x1[I] = row_xor<1>(t[J][I][v]);
-                            x2[I] = row_xor<2>(t[J][I][v]);
-                            x3[I] = row_xor<3>(t[J][I][v]);
-                        }
-                        // D^-1 by two 2 x 2 Schur steps: D = [[P, Q], [Q^T, S]]
-                        const double detP = fma(d00, d11, -d01 * d01);
-                        const double ip = rcp_f64(detP);
-                        const double p00 = d11 * ip, p01 = -d01 * ip, p11 = d00 * ip;
-                        const double w00 = fma(p00, d02, p01 * d12), w01 = fma(p00, d03, p01 * d13);
-                        const double w10 = fma(p01, d02, p11 * d12), w11 = fma(p01, d03, p11 * d13);
-                        const double s00 = d22 - fma(d02, w00, d12 * w10);
-                        const double s01 = d23 - fma(d02, w01, d12 * w11);
-                        const double s11 = d33 - fma(d03, w01, d13 * w11);
-                        const double detS = fma(s00, s11, -s01 * s01);
-                        const double is = rcp_f64(detS);
-                        const double q00 = s11 * is, q01 = -s01 * is, q11 = s00 * is;
-                        // X12 = -W S^-1, X11 = P^-1 - X12 W^T
-                        const double e00 = -fma(w00, q00, w01 * q01), e01 = -fma(w00, q01, w01 * q11);
-                        const double e10 = -fma(w10, q00, w11 * q01), e11 = -fma(w10, q01, w11 * q11);
-                        const double f00 = p00 - fma(e00, w00, e01 * w01);
-                        const double f01 = p01 - fma(e00, w10, e01 * w11);
-                        const double f11 = p11 - fma(e10, w10, e11 * w11);
-                        // the scalar pivots d00, detP / d00, s00, detS / s00 all exceed tol
-                        singular |= !((d00 > tol) && (detP > tol * d00) && (s00 > tol) && (detS > tol * s00));
-                        // row m of D^-1, column m ^ q in slot q
-                        double dq[4];
-                        {
-                            // rows of D^-1 = [[F, E], [E^T, Q]]
-                            const double r0[4] = {f00, f01, e00, e01};
-                            const double r1[4] = {f01, f11, e10, e11};
-                            const double r2[4] = {e00, e10, q00, q01};
-                            const double r3[4] = {e01, e11, q01, q11};
-#pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                dq[q] = (m == 0) ? r0[q] : (m == 1) ? r1[q ^ 1] : (m == 2) ? r2[q ^ 2] : r3[q ^ 3];
-                        }
-                        // operands: A = -P^T, B = R = D^-1 P; the pivot rows' own
-                        // columns and those left of them give zero (masked)
-                        double a[NT], b[NT];
-#pragma unroll
-                        for (int I = J; I < NT; ++I) {
-                            const double p = t[J][I][v];
-                            const bool left = (I == J) && (c <= 4 * v + 3);
-                            const bool rhs = (I == NT - 1) && (c == 15);
-                            const double r = fma(dq[0], p, fma(dq[1], x1[I], fma(dq[2], x2[I], dq[3] * x3[I])));
-                            a[I] = (left || rhs) ? 0.0 : -p;
-                            b[I] = left ? 0.0 : r;
-                            t[J][I][v] = b[I];
-                        }
-                        // the next pivot rows' tiles first
-                        const int Jn = (v < 3) ? J : J + 1;
-#pragma unroll
-                        for (int I = Jn; I < NT; ++I)
-                            t[Jn][I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[Jn], b[I], t[Jn][I], 0, 0, 0);
-#pragma unroll
-                        for (int Ir = J; Ir < NT; ++Ir) {
-                            if (Ir == Jn)
-                                continue;
-#pragma unroll
-                            for (int I = Ir; I < NT; ++I)
-                                t[Ir][I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[Ir], b[I], t[Ir][I], 0, 0, 0);
-                        }
-                    }
+                    const int i = 16 * I + 4 * v + m;
+                    const int j = 16 * K + c;
+                    const bool in = i < n && (j == kM - 1 || j < n);
+                    t[I][K][v] = in ? t[I][K][v] : ((i == j && i < kM - 4) ? pad : 0.0);
                 }
-            // back substitution: lane (m, c) holds x(16 I + c) in xv[I]; the
-            // right-hand side column's slot holds -1, so each block's
-            // x = R(., rhs) - R(., > k) x is minus the row sum of R x
-            double xv[NT];
+        if (status == 0 && n > 0 && n <= kM - 4) {
+            const double tol = 1e-12 * maxdiag;
+            bool singular = !(maxdiag > 0.0);
+            const bool odd = (m & 1) != 0, hi2 = (m & 2) != 0, mid = (m == 1) || (m == 2);
 #pragma unroll
-            for (int I = 0; I < NT; ++I)
-                xv[I] = (I == NT - 1 && c == 15) ? -1.0 : 0.0;
+            for (int s = 0; s < kSteps; ++s) {
+                const int J = s >> 2, v = s & 3;
+                // pivot block D (rows and columns k..k+3, k = 16 J + 4 v) into scalar registers
+                const double d00 = lane_f64(t[J][J][v], 4 * v + 0);
+                const double d01 = lane_f64(t[J][J][v], 4 * v + 1);
+                const double d02 = lane_f64(t[J][J][v], 4 * v + 2);
+                const double d03 = lane_f64(t[J][J][v], 4 * v + 3);
+                const double d11 = lane_f64(t[J][J][v], 16 + 4 * v + 1);
+                const double d12 = lane_f64(t[J][J][v], 16 + 4 * v + 2);
+                const double d13 = lane_f64(t[J][J][v], 16 + 4 * v + 3);
+                const double d22 = lane_f64(t[J][J][v], 32 + 4 * v + 2);
+                const double d23 = lane_f64(t[J][J][v], 32 + 4 * v + 3);
+                const double d33 = lane_f64(t[J][J][v], 48 + 4 * v + 3);
+                // the row panel's four rows of each column, from the other rows of lanes
+                double x1[NT], x2[NT], x3[NT];
 #pragma unroll
-            for (int J = NT - 1; J >= 0; --J)
-#pragma unroll
-                for (int v = 3; v >= 0; --v) {
-                    const int k = 16 * J + 4 * v;
-                    if (k < npiv) {
-                        double p = 0.0;
-#pragma unroll
-                        for (int I = NT - 1; I >= J; --I)
-                            p = fma(t[J][I][v], xv[I], p);
-                        const double xk = -row_sum16(p);   // x(k + m) on every lane of row m
-                        const double y1 = row_xor<1>(xk), y2 = row_xor<2>(xk), y3 = row_xor<3>(xk);
-                        const int d = c - 4 * v;   // lanes of columns k..k+3 take x(k + d)
-                        const int q = d ^ m;
-                        const double y = (q == 0) ? xk : (q == 1) ? y1 : (q == 2) ? y2 : y3;
-                        if (d >= 0 && d < 4)
-                            xv[J] = y;
-                    }
+                for (int I = J; I < NT; ++I) {
+                    x1[I] = __shfl_xor(t[J][I][v], 16);
+                    x2[I] = __shfl_xor(t[J][I][v], 32);
+                    x3[I] = __shfl_xor(t[J][I][v], 48);
                 }
+                // D^-1 by two 2 x 2 Schur steps: D = [[P, Q], [Q^T, S]],
+                // D^-1 = [[F, E], [E^T, Z]], Z = (S - Q^T P^-1 Q)^-1,
+                // E = -P^-1 Q Z, F = P^-1 - E (P^-1 Q)^T
+                const double detP = fma(d00, d11, -d01 * d01);
+                const double ip = rcp_f64(detP);
+                const double p00 = d11 * ip, p01 = -d01 * ip, p11 = d00 * ip;
+                const double w00 = fma(p00, d02, p01 * d12), w01 = fma(p00, d03, p01 * d13);
+                const double w10 = fma(p01, d02, p11 * d12), w11 = fma(p01, d03, p11 * d13);
+                const double s00 = d22 - fma(d02, w00, d12 * w10);
+                const double s01 = d23 - fma(d02, w01, d12 * w11);
+                const double s11 = d33 - fma(d03, w01, d13 * w11);
+                const double detS = fma(s00, s11, -s01 * s01);
+                const double is = rcp_f64(detS);
+                const double z00 = s11 * is, z01 = -s01 * is, z11 = s00 * is;
+                const double e00 = -fma(w00, z00, w01 * z01), e01 = -fma(w00, z01, w01 * z11);
+                const double e10 = -fma(w10, z00, w11 * z01), e11 = -fma(w10, z01, w11 * z11);
+                const double f00 = p00 - fma(e00, w00, e01 * w01);
+                const double f01 = p01 - fma(e00, w10, e01 * w11);
+                const double f11 = p11 - fma(e10, w10, e11 * w11);
+                // the scalar pivots d00, detP / d00, s00, detS / s00 all exceed tol
+                singular |= !((d00 > tol) && (detP > tol * d00) && (s00 > tol) && (detS > tol * s00));
+                // row m of D^-1 at columns m, m ^ 1, m ^ 2, m ^ 3 (D^-1 symmetric)
+                const double dq0 = hi2 ? (odd ? z11 : z00) : (odd ? f11 : f00);
+                const double dq1 = hi2 ? z01 : f01;
+                const double dq2 = odd ? e11 : e00;
+                const double dq3 = mid ? e10 : e01;
+                // operands: A = -P^T, B = R = D^-1 P; the pivot rows' own
+                // columns and those left of them give zero (masked)
+                double a[NT], b[NT];
+#pragma unroll
+                for (int I = J; I < NT; ++I) {
+                    const double p = t[J][I][v];
+                    const bool left = (I == J) && (c <= 4 * v + 3);
+                    const bool rhs = (I == NT - 1) && (c == 15);
+                    const double r = fma(dq0, p, fma(dq1, x1[I], fma(dq2, x2[I], dq3 * x3[I])));
+                    a[I] = (left || rhs) ? 0.0 : -p;
+                    b[I] = left ? 0.0 : r;
+                    t[J][I][v] = b[I];
+                    // the row panel of R, row-major in LDS, for the back substitution
+                    Rl[(16 * J + 4 * v + m) * kLdlStride + 16 * I + c] = b[I];
+                }
+                // the next pivot rows' tiles first
+                const int Jn = (v < 3) ? J : J + 1;
+#pragma unroll
+                for (int I = Jn; I < NT; ++I)
+                    t[Jn][I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[Jn], b[I], t[Jn][I], 0, 0, 0);
+#pragma unroll
+                for (int Ir = J; Ir < NT; ++Ir) {
+                    if (Ir == Jn)
+                        continue;
+#pragma unroll
+                    for (int I = Ir; I < NT; ++I)
+                        t[Ir][I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[Ir], b[I], t[Ir][I], 0, 0, 0);
+                }
+            }
+            // back substitution, one row per lane: lane i loads row i of R
+            // (its own 4 x 4 block and everything left of it are zero or never
+            // read), y starts as R(i, rhs) = (D^-1 z)_i; going up the blocks,
+            // the block's four x are the y of its lanes (every later block
+            // already subtracted), read into scalar registers, and every lane
+            // subtracts R(i, block) x
+            double Rrow[kM];
+            {
+                const double* __restrict__ src = Rl + min(lane, kM - 5) * kLdlStride;
+#pragma unroll
+                for (int j = 0; j < kM; j += 2) {
+                    const double2 w = *(const double2*)(src + j);
+                    Rrow[j] = w.x;
+                    Rrow[j + 1] = w.y;
+                }
+            }
+            double y = Rrow[kM - 1], xf = 0.0;
+#pragma unroll
+            for (int s = kSteps - 1; s >= 0; --s) {
+                const int k = 4 * s;
+                const double x0 = lane_f64(y, k), x1 = lane_f64(y, k + 1);
+                const double x2 = lane_f64(y, k + 2), x3 = lane_f64(y, k + 3);
+                xf = (lane >= k && lane < k + 4) ? y : xf;
+                y -= fma(Rrow[k], x0, Rrow[k + 1] * x1) + fma(Rrow[k + 2], x2, Rrow[k + 3] * x3);
+            }
             bool bad = false;
-            if (m == 0) {
-#pragma unroll
-                for (int I = 0; I < NT; ++I)
-                    if (16 * I + c < n) {
-                        xs[16 * I + c] = xv[I];
-                        bad |= !isfinite(xv[I]);
-                    }
+            if (lane < n) {
+                xs[lane] = xf;
+                bad = !isfinite(xf);
             }
             bad = __any(bad);
             if (lane == 0)
@@ -2555,9 +2571,9 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd)
         for (int r = 0; r < 3; ++r)
             tv[r] = (u + 192 * r < 16 * N) ? gd.poses[u + 192 * r] : 0.0;
         const int fv = (u < gd.n_free) ? gd.free_ids[u] : 0;
-        double s = 0.0;
         if (u < kNodeStats && status == 0) {
             const int src = (u < 2) ? 1 - u : u;
+            double s = 0.0;
             for (int k = 0; k < N; ++k)
                 s += gd.node_stats[kNodeStats * k + src];
             gd.iter_stats[kIterRecord * it + u] = s;
@@ -2571,7 +2587,7 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd)
     }
     if (status)
         return;   // uniform: every wave read the same status
-    __syncthreads();
+    lds_barrier();
     const int flags = sflags;
     // every thread has used the diagonal maximum by now: cleared for the
     // next iteration's assembly
@@ -2587,17 +2603,7 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd)
             *gd.status |= (flags & 1) ? kStatusSingular : kStatusNonFinite;
         return;
     }
-    for (int q = tid; q < gd.n_free; q += 256) {
-        const int node = sfree[q];
-        double E[16], Tn[16];
-        se3_exp(xs + 6 * q, E);
-        mat4_mul(E, Ts + 16 * node, Tn);
-        for (int k = 0; k < 16; ++k) {
-            Ts[16 * node + k] = Tn[k];
-            gd.poses[16 * node + k] = Tn[k];
-        }
-    }
-    __syncthreads();
+    update_poses(gd, xs, sfree, Ts);
     if (tid == 0)
         *gd.iters_done = it + 1;
     compute_transforms(gd, Ts);
@@ -2609,12 +2615,13 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd)
 template <int GNT>
 __global__ __launch_bounds__(256) void solve_mfma_kernel(const GraphDev* __restrict__ gds)
 {
+    __shared__ __attribute__((aligned(16))) double Rl[64 * kLdlStride];   // R rows of the LDL^T solve
     const GraphDev& gd = gds[blockIdx.x];
     if (gd.solver == kSolverLDL) {
         if (6 * gd.n_free <= kLdlMaxN2)
-            ldl_solve<2>(gd);
+            ldl_solve<2>(gd, Rl);
         else
-            ldl_solve<4>(gd);
+            ldl_solve<4>(gd, Rl);
     } else {
         gj_solve<GNT>(gd);
     }
@@ -2721,7 +2728,7 @@ int gj_slots(int n_free) { return 6 * n_free + 1; }
 void launch_mfma_solve(const GraphDev* gds, int n_graphs, int cols, hipStream_t st)
 {
     static_assert(kGjMaxN + 1 <= 16 * 8, "Gauss-Jordan tiles too few for kGjMaxN");
-    static_assert(((kLdlMaxN + 3) & ~3) < 16 * 4 && ((kLdlMaxN2 + 3) & ~3) < 16 * 2, "LDL tiles too few");
+    static_assert(kLdlMaxN <= 16 * 4 - 4 && kLdlMaxN2 <= 16 * 2 - 4, "LDL tiles too few");
     if (cols <= 32)
         solve_mfma_kernel<2><<<n_graphs, 256, 0, st>>>(gds);
     else if (cols <= 64)
