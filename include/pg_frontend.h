@@ -1,0 +1,57 @@
+/* C ABI of the front end of the pose-graph library: keypoint descriptor
+ * matching of BundleTrack (Wen & Bekris, IROS 2021), Sec. IV-B, on the GPU.
+ * Same library and status codes as posegraph.h. */
+#ifndef PG_FRONTEND_H
+#define PG_FRONTEND_H
+
+#include "posegraph.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PG_MATCH_MAX_PAIRS 96       /* descriptor-set pairs per call                   */
+#define PG_MATCH_MAX_ROWS 4096      /* descriptors per set                             */
+
+/* Mutual nearest-neighbour matching of keypoint descriptors (Sec. IV-B: the
+ * keypoints of the current frame are matched against those of the keyframes
+ * on the GPU, several pairs at once).  For pair q, with A = descriptor set
+ * pair_a[q] (na rows) and B = set pair_b[q] (nb rows): row x of A is matched
+ * to the row y of B nearest to it in squared Euclidean distance (lowest y
+ * among equal distances) when x is also the row of A nearest to y (lowest x
+ * among equals) and, for ratio < 1, when d1 < ratio^2 d2 (d1, d2: the
+ * squared distances from x to its nearest and second-nearest rows of B, the
+ * second equal to the first when two rows of B tie); else -1.  Distances are
+ * FP64, |a|^2 + |b|^2 - 2 a.b with the dot products on the FP64 matrix cores
+ * (rounding-level differences from the difference form can change a decision
+ * only between near-equal distances).
+ *
+ *   desc      device memory, FP32, row-major: set s is rows set_off[s] ..
+ *             set_off[s + 1] - 1, dim values per row
+ *   set_off   host array of n_sets + 1 non-decreasing row offsets (set_off[0]
+ *             is the first row used), each set at most PG_MATCH_MAX_ROWS rows
+ *   dim       32, 64, 128 or 256
+ *   pair_a, pair_b   host arrays of n_pairs set indices (1..PG_MATCH_MAX_PAIRS
+ *             pairs; a set may be matched against itself)
+ *   ratio     ratio test threshold; >= 1 disables the test
+ *   match     device memory, int32: pair q's na results at out_off(q) = sum of
+ *             the na of pairs before q (local row indices of B, or -1)
+ *   d1, d2    device memory, FP64, same layout; may be NULL; infinity where
+ *             B is empty (and d2 where B has one row)
+ *   hip_stream   the stream the work is ordered on (NULL: the null stream);
+ *             the call returns once the work is enqueued
+ * Ownership stays with the caller; nothing is kept after the call.  Errors:
+ * PG_ERR_INVALID_ARG (null, host or out-of-range pointers and sizes),
+ * PG_ERR_CAPACITY (limits above), PG_ERR_OUT_OF_MEMORY / PG_ERR_HIP.
+ * The scratch of the column minima is allocated and freed on the stream. */
+pg_status pg_match_descriptors(const float* desc, const int* set_off, int n_sets, int dim, const int* pair_a,
+                               const int* pair_b, int n_pairs, double ratio, int* match, double* d1, double* d2,
+                               void* hip_stream);
+
+/* Message of the last failed front-end call on this thread ("" if none). */
+const char* pg_frontend_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PG_FRONTEND_H */

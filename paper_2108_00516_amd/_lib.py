@@ -86,6 +86,9 @@ SIGNATURES = {
     "pose_graph_num_frames": (C.c_int, [_vp]),
     "pose_graph_last_error": (C.c_char_p, [_vp]),
     "pose_graph_destroy": (None, [_vp]),
+    "pg_match_descriptors": (C.c_int, [_vp, _vp, C.c_int, C.c_int, _vp, _vp, C.c_int, C.c_double, _vp, _vp, _vp,
+                                       _vp]),
+    "pg_frontend_last_error": (C.c_char_p, []),
 }
 
 _lib = None

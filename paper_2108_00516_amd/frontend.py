@@ -1,0 +1,51 @@
+"""Python binding of the front-end entry points (include/pg_frontend.h):
+keypoint descriptor matching on the GPU (Sec. IV-B).  Argument marshalling
+only; torch supplies the device memory and the stream."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Sequence, Tuple
+
+import numpy as np
+
+from . import _lib as L
+
+
+class FrontendError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != L.PG_OK:
+        msg = L.load().pg_frontend_last_error().decode()
+        raise FrontendError(f"{what}: {L.STATUS_NAMES.get(rc, rc)}: {msg}")
+
+
+def match_descriptors(desc, set_off: Sequence[int], pairs: Sequence[Tuple[int, int]], ratio: float = 1.0,
+                      stream=None, with_distances: bool = True):
+    """Mutual nearest-neighbour matching of descriptor sets on the GPU.
+
+    desc: (rows, dim) float32 CUDA tensor; set s is rows set_off[s] ..
+    set_off[s + 1] - 1.  pairs: (set a, set b) per pair.  Returns (match, d1,
+    d2) CUDA tensors laid out pair after pair (na entries each; d1 / d2 None
+    when with_distances is False)."""
+    import torch
+    lib = L.load()
+    if not (desc.is_cuda and desc.dtype == torch.float32 and desc.dim() == 2 and desc.is_contiguous()):
+        raise FrontendError("desc must be a contiguous (rows, dim) float32 CUDA tensor")
+    off = np.ascontiguousarray(set_off, np.int32)
+    pa = np.ascontiguousarray([p[0] for p in pairs], np.int32)
+    pb = np.ascontiguousarray([p[1] for p in pairs], np.int32)
+    n_out = int(sum(off[a + 1] - off[a] for a in pa)) if len(pa) else 0
+    dev = desc.device
+    match = torch.empty(max(n_out, 1), dtype=torch.int32, device=dev)
+    d1 = torch.empty(max(n_out, 1), dtype=torch.float64, device=dev) if with_distances else None
+    d2 = torch.empty(max(n_out, 1), dtype=torch.float64, device=dev) if with_distances else None
+    st = (stream or torch.cuda.current_stream(dev)).cuda_stream
+    rc = lib.pg_match_descriptors(
+        C.c_void_p(desc.data_ptr()), off.ctypes.data_as(C.c_void_p), len(off) - 1, desc.shape[1],
+        pa.ctypes.data_as(C.c_void_p), pb.ctypes.data_as(C.c_void_p), len(pa), float(ratio),
+        C.c_void_p(match.data_ptr()), C.c_void_p(d1.data_ptr()) if d1 is not None else None,
+        C.c_void_p(d2.data_ptr()) if d2 is not None else None, C.c_void_p(st))
+    _check(rc, "pg_match_descriptors")
+    return match[:n_out], (d1[:n_out] if d1 is not None else None), (d2[:n_out] if d2 is not None else None)

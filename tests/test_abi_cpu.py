@@ -11,6 +11,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "posegraph.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 
 
 @pytest.fixture(scope="module")
@@ -23,9 +25,11 @@ def lib():
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b((?:pose_graph|pg)_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b((?:pose_graph|pg)_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol(lib):
@@ -108,3 +112,17 @@ def test_no_device_reported(lib):
     cam = _lib.pg_camera(64, 48, 60.0, 60.0, 32.0, 24.0)
     out = C.c_void_p()
     assert lib.pose_graph_create(C.byref(cfg), C.byref(cam), None, C.byref(out)) == _lib.PG_ERR_NO_DEVICE
+
+
+def test_match_argument_errors_without_a_device(lib):
+    """pg_match_descriptors checks sizes before it touches the device."""
+    from paper_2108_00516_amd import _lib
+    off = (C.c_int * 3)(0, 5, 10)
+    pa = (C.c_int * 97)(*([0] * 97))
+    pb = (C.c_int * 97)(*([1] * 97))
+    args = lambda n_pairs, dim, ratio: (None, off, 2, dim, pa, pb, n_pairs, ratio, None, None, None, None)
+    assert lib.pg_match_descriptors(*args(0, 128, 1.0)) == _lib.PG_ERR_INVALID_ARG
+    assert lib.pg_match_descriptors(*args(97, 128, 1.0)) == _lib.PG_ERR_CAPACITY
+    assert lib.pg_match_descriptors(*args(1, 100, 1.0)) == _lib.PG_ERR_INVALID_ARG
+    assert lib.pg_match_descriptors(*args(1, 128, -1.0)) == _lib.PG_ERR_INVALID_ARG
+    assert lib.pg_frontend_last_error()
