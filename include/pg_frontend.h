@@ -12,6 +12,11 @@ extern "C" {
 
 #define PG_MATCH_MAX_PAIRS 96       /* descriptor-set pairs per call                   */
 #define PG_MATCH_MAX_ROWS 4096      /* descriptors per set                             */
+/* partial column minima the allocation-free variant holds: sum over the pairs
+ * of ceil(rows of set a / 64) x rows of set b */
+#define PG_MATCH_SCRATCH_PARTIALS (1 << 19)
+/* rows the allocation-free variant holds: sum over the pairs of rows of set a */
+#define PG_MATCH_SCRATCH_ROWS (1 << 16)
 
 /* Mutual nearest-neighbour matching of keypoint descriptors (Sec. IV-B: the
  * keypoints of the current frame are matched against those of the keyframes
@@ -47,6 +52,17 @@ extern "C" {
 pg_status pg_match_descriptors(const float* desc, const int* set_off, int n_sets, int dim, const int* pair_a,
                                const int* pair_b, int n_pairs, double ratio, int* match, double* d1, double* d2,
                                void* hip_stream);
+
+/* pg_match_descriptors for callers that cannot allocate device memory (code
+ * under stream capture, serving loops): the same results from the same
+ * kernels, with the scratch in a fixed array of the library on each device
+ * (PG_MATCH_SCRATCH_PARTIALS column minima, PG_MATCH_SCRATCH_ROWS rows; about
+ * 9.5 MB, held until the process ends).  Larger calls fail with
+ * PG_ERR_CAPACITY.  Calls that overlap on one device share that array and
+ * race: order them on one stream. */
+pg_status pg_match_descriptors_noalloc(const float* desc, const int* set_off, int n_sets, int dim,
+                                       const int* pair_a, const int* pair_b, int n_pairs, double ratio, int* match,
+                                       double* d1, double* d2, void* hip_stream);
 
 /* Message of the last failed front-end call on this thread ("" if none). */
 const char* pg_frontend_last_error(void);

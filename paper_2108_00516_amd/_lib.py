@@ -88,6 +88,8 @@ SIGNATURES = {
     "pose_graph_destroy": (None, [_vp]),
     "pg_match_descriptors": (C.c_int, [_vp, _vp, C.c_int, C.c_int, _vp, _vp, C.c_int, C.c_double, _vp, _vp, _vp,
                                        _vp]),
+    "pg_match_descriptors_noalloc": (C.c_int, [_vp, _vp, C.c_int, C.c_int, _vp, _vp, C.c_int, C.c_double, _vp,
+                                               _vp, _vp, _vp]),
     "pg_frontend_last_error": (C.c_char_p, []),
 }
 

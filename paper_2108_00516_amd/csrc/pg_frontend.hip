@@ -19,6 +19,7 @@
 #include <stdint.h>
 #include <stdio.h>
 
+#include <mutex>
 #include <string>
 
 namespace pg {
@@ -303,6 +304,18 @@ __global__ __launch_bounds__(kMatchThreads) void match_resolve_kernel(MatchArgs 
     }
 }
 
+// Scratch of the allocation-free entry point: the partial records, then the
+// row records, in one fixed array per device.  Host code never uses the
+// array's name as an address: each device's address comes from
+// hipGetSymbolAddress (scratch_on_device), taken once with that device current.
+constexpr size_t kScratchPartBytes = sizeof(MatchPart) * (size_t)PG_MATCH_SCRATCH_PARTIALS;
+constexpr size_t kScratchBytes = kScratchPartBytes + sizeof(MatchRow) * (size_t)PG_MATCH_SCRATCH_ROWS;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 thread_local std::string g_frontend_error;
 
 pg_status ffail(pg_status s, const char* fmt, ...)
@@ -451,6 +464,44 @@ pg_status pg_match_descriptors(const float* desc, const int* set_off, int n_sets
         return ffail(PG_ERR_HIP, "match launch: %s", hipGetErrorString(e));
     if (ef != hipSuccess)
         return ffail(PG_ERR_HIP, "hipFreeAsync: %s", hipGetErrorString(ef));
+    return PG_OK;
+}
+
+pg_status pg_match_descriptors_noalloc(const float* desc, const int* set_off, int n_sets, int dim,
+                                       const int* pair_a, const int* pair_b, int n_pairs, double ratio, int* match,
+                                       double* d1, double* d2, void* hip_stream)
+{
+    MatchArgs a;
+    size_t n_part = 0, n_rows = 0;
+    int n_blocks = 0;
+    pg_status s = match_setup(desc, set_off, n_sets, dim, pair_a, pair_b, n_pairs, ratio, match, d1, d2, a, n_part,
+                              n_rows, n_blocks);
+    if (s != PG_OK)
+        return s;
+    if (n_part > (size_t)PG_MATCH_SCRATCH_PARTIALS || n_rows > (size_t)PG_MATCH_SCRATCH_ROWS)
+        return ffail(PG_ERR_CAPACITY, "%zu partial records / %zu rows exceed the fixed scratch (%d / %d)", n_part,
+                     n_rows, PG_MATCH_SCRATCH_PARTIALS, PG_MATCH_SCRATCH_ROWS);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return ffail(PG_ERR_NO_DEVICE, "no current device");
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (!g_scratch_ptr[dev]) {
+            void* p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return ffail(PG_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+            g_scratch_ptr[dev] = p;
+        }
+        base = g_scratch_ptr[dev];
+    }
+    a.part = (MatchPart*)base;
+    a.rows = (MatchRow*)((char*)base + kScratchPartBytes);
+    e = launch_match(a, dim, n_blocks, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+        return ffail(PG_ERR_HIP, "match launch: %s", hipGetErrorString(e));
     return PG_OK;
 }
 

@@ -22,13 +22,14 @@ def _check(rc: int, what: str):
 
 
 def match_descriptors(desc, set_off: Sequence[int], pairs: Sequence[Tuple[int, int]], ratio: float = 1.0,
-                      stream=None, with_distances: bool = True):
+                      stream=None, with_distances: bool = True, noalloc: bool = False):
     """Mutual nearest-neighbour matching of descriptor sets on the GPU.
 
     desc: (rows, dim) float32 CUDA tensor; set s is rows set_off[s] ..
     set_off[s + 1] - 1.  pairs: (set a, set b) per pair.  Returns (match, d1,
     d2) CUDA tensors laid out pair after pair (na entries each; d1 / d2 None
-    when with_distances is False)."""
+    when with_distances is False).  noalloc selects the entry point whose
+    scratch is the library's fixed array (no device allocation in the call)."""
     import torch
     lib = L.load()
     if not (desc.is_cuda and desc.dtype == torch.float32 and desc.dim() == 2 and desc.is_contiguous()):
@@ -42,10 +43,11 @@ def match_descriptors(desc, set_off: Sequence[int], pairs: Sequence[Tuple[int, i
     d1 = torch.empty(max(n_out, 1), dtype=torch.float64, device=dev) if with_distances else None
     d2 = torch.empty(max(n_out, 1), dtype=torch.float64, device=dev) if with_distances else None
     st = (stream or torch.cuda.current_stream(dev)).cuda_stream
-    rc = lib.pg_match_descriptors(
+    fn = lib.pg_match_descriptors_noalloc if noalloc else lib.pg_match_descriptors
+    rc = fn(
         C.c_void_p(desc.data_ptr()), off.ctypes.data_as(C.c_void_p), len(off) - 1, desc.shape[1],
         pa.ctypes.data_as(C.c_void_p), pb.ctypes.data_as(C.c_void_p), len(pa), float(ratio),
         C.c_void_p(match.data_ptr()), C.c_void_p(d1.data_ptr()) if d1 is not None else None,
         C.c_void_p(d2.data_ptr()) if d2 is not None else None, C.c_void_p(st))
-    _check(rc, "pg_match_descriptors")
+    _check(rc, "pg_match_descriptors_noalloc" if noalloc else "pg_match_descriptors")
     return match[:n_out], (d1[:n_out] if d1 is not None else None), (d2[:n_out] if d2 is not None else None)
