@@ -1,5 +1,6 @@
 /* C ABI of the front end of the pose-graph library: keypoint descriptor
- * matching of BundleTrack (Wen & Bekris, IROS 2021), Sec. IV-B, on the GPU.
+ * matching and coarse registration by RANSAC of BundleTrack (Wen & Bekris,
+ * IROS 2021), Sec. IV-B, on the GPU.
  * Same library and status codes as posegraph.h. */
 #ifndef PG_FRONTEND_H
 #define PG_FRONTEND_H
@@ -63,6 +64,40 @@ pg_status pg_match_descriptors(const float* desc, const int* set_off, int n_sets
 pg_status pg_match_descriptors_noalloc(const float* desc, const int* set_off, int n_sets, int dim,
                                        const int* pair_a, const int* pair_b, int n_pairs, double ratio, int* match,
                                        double* d1, double* d2, void* hip_stream);
+
+#define PG_RANSAC_MAX_MATCHES 512   /* matches of one pair                              */
+#define PG_RANSAC_MAX_HYP 8192      /* hypotheses per pair                              */
+
+/* Coarse registration by RANSAC (Sec. IV-B): for each of n_pairs ordered node
+ * pairs (pi[q], pj[q]) of graph g, its matched keypoints (pixel coordinates
+ * uv_i in frame pi[q], uv_j in frame pj[q], entries match_off[q] ..
+ * match_off[q + 1] - 1, at most PG_RANSAC_MAX_MATCHES) are lifted to 3-D
+ * points and normals at their nearest pixels (pi_D^-1 of Eq. 3; a match is
+ * valid when both pixels hold a valid point).  Hypothesis h of pair q is the
+ * least-squares rigid transform (Arun et al.) of the three matches
+ * samples[3 (q n_hyp + h) ..] (indices local to the pair; the random draws are
+ * the caller's), unusable (score -1) when a match is invalid or repeated or
+ * either triangle has an area below 1e-8 m^2; its score is the number of
+ * valid matches m with |R b_m + t - a_m| < delta_m and
+ * (R n_b) . n_a > cos(alpha_rad) (a: point in frame pi, b: in frame pj).
+ *   best[q]    the hypothesis with the highest score (lowest index among
+ *              equals), -1 when none is usable
+ *   T[16 q..]  its transform, frame pj camera -> frame pi camera, row-major
+ *              4 x 4 FP64 (the identity when best[q] is -1)
+ *   score      n_pairs x n_hyp scores, may be NULL
+ *   inlier     one byte per match (match_off layout), the best hypothesis'
+ *              inlier flags, may be NULL
+ *   install    nonzero: each pair with a usable hypothesis gets its inliers
+ *              as the feature matches of the pair (Eq. 2; the C_ij the
+ *              optimisation reuses), replacing earlier ones (none: removed)
+ * All arrays are host memory, copied; the call is synchronous on the graph's
+ * stream.  Rounding-level differences from an FP64 reference can change a
+ * decision only for matches at the delta or alpha boundary.  Errors:
+ * PG_ERR_INVALID_ARG, PG_ERR_CAPACITY (limits above), PG_ERR_OUT_OF_MEMORY,
+ * PG_ERR_HIP; the message is pose_graph_last_error(g). */
+pg_status pose_graph_ransac(pg_graph* g, int n_pairs, const int* pi, const int* pj, const int* match_off,
+                            const float* uv_i, const float* uv_j, int n_hyp, const int* samples, double delta_m,
+                            double alpha_rad, int install, int* best, int* score, double* T, uint8_t* inlier);
 
 /* Message of the last failed front-end call on this thread ("" if none). */
 const char* pg_frontend_last_error(void);

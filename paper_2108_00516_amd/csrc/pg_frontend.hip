@@ -11,7 +11,21 @@
 //   match_resolve_kernel  one block per pair: each row of B's nearest row of A
 //                         from the partial records, then the mutual and ratio
 //                         tests per row of A
+//
+// and the coarse registration by RANSAC of Sec. IV-B over the frames a pose
+// graph holds:
+//
+//   ransac_hyp_kernel     one wavefront per (pair, 64 hypotheses): the pair's
+//                         matched keypoints (3-D point and normal at the
+//                         nearest pixel of each frame) in LDS, one hypothesis
+//                         per lane: the least-squares rigid transform of its
+//                         three matches (Arun et al.; SVD by one-sided Jacobi
+//                         rotations) and its inlier count
+//   ransac_best_kernel    one block per pair: the best hypothesis (most
+//                         inliers, lowest index among equals), its transform
+//                         and inlier flags
 #include "pg_frontend.h"
+#include "pg_device.hpp"
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -316,6 +330,296 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mutex;
 void* g_scratch_ptr[kMaxDevices] = {};
 
+// ------------------------------------------------------------ RANSAC
+
+constexpr int kRansacHyp = 64;   // hypotheses per wavefront block
+
+struct RansacArgs {
+    const float4* maps;     // n_frames x H x W packed {normal, z}; z = 0: no valid point
+    int W, H;
+    double fx, fy, cx, cy;
+    const int4* pairs;      // per pair: frame i, frame j, first match, match count
+    const float* uv_i;      // per match: (u, v) in frame i
+    const float* uv_j;      // per match: (u, v) in frame j
+    const int* samples;     // per pair and hypothesis: three match indices
+    int n_hyp, hyp_blocks;
+    double delta, cos_alpha;
+    int* score;             // per pair and hypothesis; -1: unusable sample
+    double* T;              // per pair and hypothesis: [R | t] (12)
+    int* best;              // per pair
+    double* T_best;         // per pair: 16, row-major
+    unsigned char* inlier;  // per match
+};
+
+// 3-D point (pi_D^-1 at the nearest pixel, ties up) and normal of a keypoint;
+// false outside the image or where the frame has no valid point
+__device__ bool keypoint_point(const RansacArgs& a, int f, float uf, float vf, double* p, double* nrm)
+{
+    const double x = (double)uf, y = (double)vf;
+    double u = floor(x), v = floor(y);
+    u += (x - u >= 0.5) ? 1.0 : 0.0;
+    v += (y - v >= 0.5) ? 1.0 : 0.0;
+    if (!(u >= 0.0 && u < (double)a.W && v >= 0.0 && v < (double)a.H))
+        return false;
+    const float4 e = a.maps[(size_t)f * a.W * a.H + (size_t)v * a.W + (size_t)u];
+    if (!(e.w > 0.0f))
+        return false;
+    const double z = e.w;
+    p[0] = (z * (u - a.cx)) / a.fx;
+    p[1] = (z * (v - a.cy)) / a.fy;
+    p[2] = z;
+    nrm[0] = e.x;
+    nrm[1] = e.y;
+    nrm[2] = e.z;
+    return true;
+}
+
+// Rotation and translation minimising sum |R b_k + t - a_k|^2 over three
+// point pairs (Arun et al.): S = sum (a_k - ca)(b_k - cb)^T = U D V^T,
+// R = U diag(1, 1, det V) V^T with U's third column the cross product of its
+// first two (right-handed; the third singular value of three points is 0),
+// t = ca - R cb.  The SVD by one-sided Jacobi rotations: columns p, q of
+// W = S V are rotated until orthogonal, then sorted by decreasing length.
+// False for collinear points (second singular value below 1e-12 of the first).
+__device__ bool arun3(const double (&A)[9], const double (&B)[9], double (&T)[12])
+{
+    double ca[3], cb[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        ca[r] = (A[r] + A[3 + r] + A[6 + r]) / 3.0;
+        cb[r] = (B[r] + B[3 + r] + B[6 + r]) / 3.0;
+    }
+    double W[9], V[9];   // row-major 3 x 3
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                s = fma(A[3 * k + r] - ca[r], B[3 * k + c] - cb[c], s);
+            W[3 * r + c] = s;
+            V[3 * r + c] = (r == c) ? 1.0 : 0.0;
+        }
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        bool turned = false;
+#pragma unroll
+        for (int pq = 0; pq < 3; ++pq) {
+            const int p = (pq == 2) ? 1 : 0, q = (pq == 0) ? 1 : 2;
+            double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                al = fma(W[3 * r + p], W[3 * r + p], al);
+                be = fma(W[3 * r + q], W[3 * r + q], be);
+                ga = fma(W[3 * r + p], W[3 * r + q], ga);
+            }
+            if (!(fabs(ga) > 1e-15 * sqrt(al * be)))
+                continue;
+            turned = true;
+            const double zeta = (be - al) / (2.0 * ga);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const double wp = W[3 * r + p], wq = W[3 * r + q];
+                W[3 * r + p] = cs * wp - sn * wq;
+                W[3 * r + q] = sn * wp + cs * wq;
+                const double vp = V[3 * r + p], vq = V[3 * r + q];
+                V[3 * r + p] = cs * vp - sn * vq;
+                V[3 * r + q] = sn * vp + cs * vq;
+            }
+        }
+        if (!turned)
+            break;
+    }
+    double nn[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        nn[c] = W[c] * W[c] + W[3 + c] * W[3 + c] + W[6 + c] * W[6 + c];
+    // the two longest columns, in order (the third is not needed)
+    int c0 = 0, c1 = 1, c2 = 2;
+    if (nn[c1] > nn[c0]) { const int x = c0; c0 = c1; c1 = x; }
+    if (nn[c2] > nn[c0]) { const int x = c0; c0 = c2; c2 = x; }
+    if (nn[c2] > nn[c1]) { const int x = c1; c1 = c2; c2 = x; }
+    const double n0 = sqrt(nn[c0]), n1 = sqrt(nn[c1]);
+    if (!(n1 > 1e-12 * n0))
+        return false;
+    double u0[3], u1[3], u2[3], v0[3], v1[3], v2[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        u0[r] = W[3 * r + c0] / n0;
+        u1[r] = W[3 * r + c1] / n1;
+        v0[r] = V[3 * r + c0];
+        v1[r] = V[3 * r + c1];
+        v2[r] = V[3 * r + c2];
+    }
+    u2[0] = u0[1] * u1[2] - u0[2] * u1[1];
+    u2[1] = u0[2] * u1[0] - u0[0] * u1[2];
+    u2[2] = u0[0] * u1[1] - u0[1] * u1[0];
+    // det of V with its columns in sorted order
+    const double detv = v0[0] * (v1[1] * v2[2] - v1[2] * v2[1]) - v1[0] * (v0[1] * v2[2] - v0[2] * v2[1]) +
+                        v2[0] * (v0[1] * v1[2] - v0[2] * v1[1]);
+    const double d = detv < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            T[4 * r + c] = u0[r] * v0[c] + u1[r] * v1[c] + d * u2[r] * v2[c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        T[4 * r + 3] = ca[r] - (T[4 * r] * cb[0] + T[4 * r + 1] * cb[1] + T[4 * r + 2] * cb[2]);
+    return true;
+}
+
+// inlier test of one match under [R | t]: |R b + t - a| < delta and
+// (R n_b) . n_a > cos alpha
+__device__ __forceinline__ bool ransac_inlier(const double (&T)[12], const double* a, const double* na,
+                                              const double* b, const double* nb, double delta, double cos_alpha)
+{
+    double d2 = 0.0, c = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const double y = T[4 * r] * b[0] + T[4 * r + 1] * b[1] + T[4 * r + 2] * b[2] + T[4 * r + 3] - a[r];
+        const double rn = T[4 * r] * nb[0] + T[4 * r + 1] * nb[1] + T[4 * r + 2] * nb[2];
+        d2 = fma(y, y, d2);
+        c = fma(rn, na[r], c);
+    }
+    return sqrt(d2) < delta && c > cos_alpha;
+}
+
+__global__ __launch_bounds__(kRansacHyp) void ransac_hyp_kernel(RansacArgs args)
+{
+    __shared__ double sg[12 * PG_RANSAC_MAX_MATCHES];   // per match: a, n_a, b, n_b
+    __shared__ unsigned char sv[PG_RANSAC_MAX_MATCHES];
+    const int q = blockIdx.x / args.hyp_blocks;
+    const int hb = blockIdx.x - q * args.hyp_blocks;
+    const int4 pr = args.pairs[q];
+    const int n = pr.w;
+    for (int m = threadIdx.x; m < n; m += kRansacHyp) {
+        const int k = pr.z + m;
+        double* g = sg + 12 * m;
+        const bool ok = keypoint_point(args, pr.x, args.uv_i[2 * k], args.uv_i[2 * k + 1], g, g + 3) &&
+                        keypoint_point(args, pr.y, args.uv_j[2 * k], args.uv_j[2 * k + 1], g + 6, g + 9);
+        sv[m] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    const int h = hb * kRansacHyp + threadIdx.x;
+    if (h >= args.n_hyp)
+        return;
+    const size_t o = (size_t)q * args.n_hyp + h;
+    int s[3];
+    bool usable = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        s[k] = args.samples[3 * o + k];
+        usable = usable && s[k] >= 0 && s[k] < n;
+    }
+    usable = usable && s[0] != s[1] && s[0] != s[2] && s[1] != s[2];
+    double A[9], B[9], T[12];
+    if (usable) {
+        usable = sv[s[0]] && sv[s[1]] && sv[s[2]];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                A[3 * k + r] = sg[12 * s[k] + r];
+                B[3 * k + r] = sg[12 * s[k] + 6 + r];
+            }
+    }
+    // a triangle of area below 1e-8 m^2 in either frame fixes no rotation
+    if (usable) {
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            const double* P = f ? B : A;
+            const double e1[3] = {P[3] - P[0], P[4] - P[1], P[5] - P[2]};
+            const double e2[3] = {P[6] - P[0], P[7] - P[1], P[8] - P[2]};
+            const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                         cz = e1[0] * e2[1] - e1[1] * e2[0];
+            usable = usable && (0.5 * sqrt(cx * cx + cy * cy + cz * cz) >= 1e-8);
+        }
+    }
+    if (usable)
+        usable = arun3(A, B, T);
+    int count = -1;
+    if (usable) {
+        count = 0;
+        for (int m = 0; m < n; ++m)
+            count += (sv[m] && ransac_inlier(T, sg + 12 * m, sg + 12 * m + 3, sg + 12 * m + 6, sg + 12 * m + 9,
+                                             args.delta, args.cos_alpha))
+                         ? 1
+                         : 0;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            T[k] = 0.0;
+    }
+    args.score[o] = count;
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        args.T[12 * o + k] = T[k];
+}
+
+__global__ __launch_bounds__(256) void ransac_best_kernel(RansacArgs args)
+{
+    __shared__ int ws[4], wh[4];
+    __shared__ double sT[12];
+    __shared__ int sbest;
+    const int q = blockIdx.x;
+    const int4 pr = args.pairs[q];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // most inliers, lowest index among equals
+    int bs = -1, bh = 0x7fffffff;
+    for (int h = tid; h < args.n_hyp; h += 256) {
+        const int sc = args.score[(size_t)q * args.n_hyp + h];
+        if (sc > bs) {
+            bs = sc;
+            bh = h;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const int os = __shfl_xor(bs, o), oh = __shfl_xor(bh, o);
+        if (os > bs || (os == bs && oh < bh)) {
+            bs = os;
+            bh = oh;
+        }
+    }
+    if (lane == 0) {
+        ws[wave] = bs;
+        wh[wave] = bh;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int s = ws[0], hh = wh[0];
+        for (int w = 1; w < 4; ++w)
+            if (ws[w] > s || (ws[w] == s && wh[w] < hh)) {
+                s = ws[w];
+                hh = wh[w];
+            }
+        sbest = (s >= 0) ? hh : -1;
+        args.best[q] = sbest;
+    }
+    __syncthreads();
+    const int b = sbest;
+    if (tid < 12)
+        sT[tid] = (b >= 0) ? args.T[12 * ((size_t)q * args.n_hyp + b) + tid] : ((tid % 5 == 0) ? 1.0 : 0.0);
+    __syncthreads();
+    if (tid < 16)
+        args.T_best[16 * q + tid] = (tid < 12) ? sT[tid] : (tid == 15 ? 1.0 : 0.0);
+    double T[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        T[k] = sT[k];
+    for (int m = tid; m < pr.w; m += 256) {
+        const int k = pr.z + m;
+        double g[12];
+        bool in = false;
+        if (b >= 0 && keypoint_point(args, pr.x, args.uv_i[2 * k], args.uv_i[2 * k + 1], g, g + 3) &&
+            keypoint_point(args, pr.y, args.uv_j[2 * k], args.uv_j[2 * k + 1], g + 6, g + 9))
+            in = ransac_inlier(T, g, g + 3, g + 6, g + 9, args.delta, args.cos_alpha);
+        args.inlier[k] = in ? 1 : 0;
+    }
+}
+
 thread_local std::string g_frontend_error;
 
 pg_status ffail(pg_status s, const char* fmt, ...)
@@ -432,6 +736,42 @@ hipError_t launch_match(const MatchArgs& a, int dim, int n_blocks, hipStream_t s
 }
 
 }  // namespace
+
+// RANSAC over the pairs of a graph's frames (arrays in device memory; the
+// counts were checked by the caller)
+hipError_t launch_ransac(const float4* maps, int W, int H, double fx, double fy, double cx, double cy,
+                         const int4* pairs, int n_pairs, const float* uv_i, const float* uv_j, const int* samples,
+                         int n_hyp, double delta, double cos_alpha, int* score, double* T, int* best, double* T_best,
+                         unsigned char* inlier, hipStream_t st)
+{
+    RansacArgs a;
+    a.maps = maps;
+    a.W = W;
+    a.H = H;
+    a.fx = fx;
+    a.fy = fy;
+    a.cx = cx;
+    a.cy = cy;
+    a.pairs = pairs;
+    a.uv_i = uv_i;
+    a.uv_j = uv_j;
+    a.samples = samples;
+    a.n_hyp = n_hyp;
+    a.hyp_blocks = (n_hyp + kRansacHyp - 1) / kRansacHyp;
+    a.delta = delta;
+    a.cos_alpha = cos_alpha;
+    a.score = score;
+    a.T = T;
+    a.best = best;
+    a.T_best = T_best;
+    a.inlier = inlier;
+    if (n_pairs <= 0)
+        return hipSuccess;
+    ransac_hyp_kernel<<<n_pairs * a.hyp_blocks, kRansacHyp, 0, st>>>(a);
+    ransac_best_kernel<<<n_pairs, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
 }  // namespace pg
 
 using namespace pg;

@@ -3,6 +3,7 @@
 // launches or a captured hipGraph) and the batched path.
 #include "pg_device.hpp"
 #include "posegraph.h"
+#include "pg_frontend.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -37,6 +38,10 @@ int gj_slots(int n_free);   // columns of the Gauss-Jordan system
 void launch_mfma_solve(const GraphDev* gds, int n_graphs, int cols, hipStream_t st);
 hipError_t solve_set_max_lds(size_t bytes);
 void launch_solve(const GraphDev* gds, int n_graphs, size_t lds, int mode, hipStream_t st);
+hipError_t launch_ransac(const float4* maps, int W, int H, double fx, double fy, double cx, double cy,
+                         const int4* pairs, int n_pairs, const float* uv_i, const float* uv_j, const int* samples,
+                         int n_hyp, double delta, double cos_alpha, int* score, double* T, int* best, double* T_best,
+                         unsigned char* inlier, hipStream_t st);
 }  // namespace pg
 
 using namespace pg;
@@ -1303,6 +1308,91 @@ pg_status pose_graph_set_mlp(pg_graph* g, const void* params, size_t n_bytes)
     if (!g->has_mlp)
         g->version++;   // the parameter pointer enters the schedule's tables
     g->has_mlp = true;
+    return PG_OK;
+}
+
+pg_status pose_graph_ransac(pg_graph* g, int n_pairs, const int* pi, const int* pj, const int* match_off,
+                            const float* uv_i, const float* uv_j, int n_hyp, const int* samples, double delta_m,
+                            double alpha_rad, int install, int* best, int* score, double* T, uint8_t* inlier)
+{
+    if (!g)
+        return PG_ERR_INVALID_ARG;
+    if (n_pairs < 1 || !pi || !pj || !match_off || !samples || !best || !T)
+        return fail(g, PG_ERR_INVALID_ARG, "pairs, match offsets, samples, best and T are required");
+    if (n_hyp < 1 || n_hyp > PG_RANSAC_MAX_HYP)
+        return fail(g, n_hyp < 1 ? PG_ERR_INVALID_ARG : PG_ERR_CAPACITY, "n_hyp %d outside 1..%d", n_hyp,
+                    PG_RANSAC_MAX_HYP);
+    if (!(delta_m > 0.0) || !isfinite(delta_m) || !(alpha_rad > 0.0) || !(alpha_rad < M_PI))
+        return fail(g, PG_ERR_INVALID_ARG, "delta must be positive and alpha in (0, pi)");
+    std::vector<int4> pairs(n_pairs);
+    for (int q = 0; q < n_pairs; ++q) {
+        if (pi[q] < 0 || pj[q] < 0 || pi[q] >= g->n_frames || pj[q] >= g->n_frames || pi[q] == pj[q])
+            return fail(g, PG_ERR_INVALID_ARG, "pair %d: bad node pair (%d, %d)", q, pi[q], pj[q]);
+        const int n = match_off[q + 1] - match_off[q];
+        if (match_off[q] < 0 || n < 0)
+            return fail(g, PG_ERR_INVALID_ARG, "match offsets must be non-negative and non-decreasing");
+        if (n > PG_RANSAC_MAX_MATCHES)
+            return fail(g, PG_ERR_CAPACITY, "pair %d has %d matches, more than %d", q, n, PG_RANSAC_MAX_MATCHES);
+        pairs[q] = make_int4(pi[q], pj[q], match_off[q], n);
+    }
+    const int total = match_off[n_pairs];
+    if (total > 0 && (!uv_i || !uv_j))
+        return fail(g, PG_ERR_INVALID_ARG, "match coordinates are required");
+    const size_t nh = (size_t)n_pairs * n_hyp;
+    DevBuf d_pairs, d_uv, d_samples, d_score, d_T, d_best, d_Tbest, d_inl;
+    HIP_OR_FAIL(g, d_pairs.ensure(sizeof(int4) * n_pairs));
+    HIP_OR_FAIL(g, d_uv.ensure(sizeof(float) * 4 * (size_t)std::max(total, 1)));
+    HIP_OR_FAIL(g, d_samples.ensure(sizeof(int) * 3 * nh));
+    HIP_OR_FAIL(g, d_score.ensure(sizeof(int) * nh));
+    HIP_OR_FAIL(g, d_T.ensure(sizeof(double) * 12 * nh));
+    HIP_OR_FAIL(g, d_best.ensure(sizeof(int) * n_pairs));
+    HIP_OR_FAIL(g, d_Tbest.ensure(sizeof(double) * 16 * n_pairs));
+    HIP_OR_FAIL(g, d_inl.ensure((size_t)std::max(total, 1)));
+    hipStream_t st = g->stream;
+    float* ui = d_uv.as<float>();
+    float* uj = ui + 2 * (size_t)std::max(total, 1);
+    HIP_OR_FAIL(g, hipMemcpyAsync(d_pairs.p, pairs.data(), sizeof(int4) * n_pairs, hipMemcpyHostToDevice, st));
+    if (total > 0) {
+        HIP_OR_FAIL(g, copy_in(ui, uv_i, sizeof(float) * 2 * total, st));
+        HIP_OR_FAIL(g, copy_in(uj, uv_j, sizeof(float) * 2 * total, st));
+    }
+    HIP_OR_FAIL(g, copy_in(d_samples.p, samples, sizeof(int) * 3 * nh, st));
+    HIP_OR_FAIL(g, launch_ransac(g->maps.as<float4>(), g->cam.width, g->cam.height, g->cam.fx, g->cam.fy,
+                                 g->cam.cx, g->cam.cy, d_pairs.as<int4>(), n_pairs, ui, uj, d_samples.as<int>(),
+                                 n_hyp, delta_m, cos(alpha_rad), d_score.as<int>(), d_T.as<double>(),
+                                 d_best.as<int>(), d_Tbest.as<double>(), d_inl.as<unsigned char>(), st));
+    std::vector<uint8_t> inl((size_t)std::max(total, 1));
+    HIP_OR_FAIL(g, hipMemcpyAsync(best, d_best.p, sizeof(int) * n_pairs, hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(g, hipMemcpyAsync(T, d_Tbest.p, sizeof(double) * 16 * n_pairs, hipMemcpyDeviceToHost, st));
+    if (score)
+        HIP_OR_FAIL(g, hipMemcpyAsync(score, d_score.p, sizeof(int) * nh, hipMemcpyDeviceToHost, st));
+    if (total > 0)
+        HIP_OR_FAIL(g, hipMemcpyAsync(inl.data(), d_inl.p, total, hipMemcpyDeviceToHost, st));
+    HIP_OR_FAIL(g, hipStreamSynchronize(st));
+    if (inlier && total > 0)
+        memcpy(inlier, inl.data(), total);
+    if (install) {
+        // the inlier coordinates, read back from the device copies (the
+        // caller's arrays may be device memory)
+        std::vector<float> hu(2 * (size_t)std::max(total, 1)), hv(2 * (size_t)std::max(total, 1));
+        if (total > 0) {
+            HIP_OR_FAIL(g, hipMemcpy(hu.data(), ui, sizeof(float) * 2 * total, hipMemcpyDeviceToHost));
+            HIP_OR_FAIL(g, hipMemcpy(hv.data(), uj, sizeof(float) * 2 * total, hipMemcpyDeviceToHost));
+        }
+        for (int q = 0; q < n_pairs; ++q) {
+            if (best[q] < 0)
+                continue;
+            std::vector<float> a, b;
+            for (int m = match_off[q]; m < match_off[q + 1]; ++m)
+                if (inl[m]) {
+                    a.insert(a.end(), {hu[2 * m], hu[2 * m + 1]});
+                    b.insert(b.end(), {hv[2 * m], hv[2 * m + 1]});
+                }
+            const pg_status r = pose_graph_add_matches(g, pi[q], pj[q], a.data(), b.data(), (int)(a.size() / 2));
+            if (r != PG_OK)
+                return r;
+        }
+    }
     return PG_OK;
 }
 

@@ -262,6 +262,39 @@ class PoseGraph:
         self._check(self.lib.pose_graph_time_assoc(self.h, int(reps), C.byref(ms)))
         return ms.value
 
+    def ransac(self, pairs, uv_i, uv_j, samples, delta: float = 0.005, alpha: float = float(np.deg2rad(45.0)),
+               install: bool = False, scores: bool = False):
+        """Coarse registration by RANSAC of ordered node pairs (Sec. IV-B) on
+        the GPU: uv_i / uv_j are lists (one (n_q, 2) array per pair),
+        samples an (n_pairs, n_hyp, 3) array of match indices.  Returns
+        dict(best (n_pairs,), T (n_pairs, 4, 4) frame-j camera -> frame-i
+        camera, inliers (list of (n_q,) bools), and score (n_pairs, n_hyp)
+        when asked); install=True makes the inliers the pairs' feature
+        matches."""
+        npairs = len(pairs)
+        samples = np.ascontiguousarray(samples, np.int32).reshape(npairs, -1, 3)
+        n_hyp = samples.shape[1]
+        counts = [len(np.asarray(u).reshape(-1, 2)) for u in uv_i]
+        off = np.ascontiguousarray(np.concatenate([[0], np.cumsum(counts)]), np.int32)
+        ui = np.ascontiguousarray(np.concatenate([np.asarray(u, np.float32).reshape(-1, 2) for u in uv_i]
+                                                 + [np.zeros((1, 2), np.float32)]))
+        uj = np.ascontiguousarray(np.concatenate([np.asarray(u, np.float32).reshape(-1, 2) for u in uv_j]
+                                                 + [np.zeros((1, 2), np.float32)]))
+        pi = np.ascontiguousarray([p[0] for p in pairs], np.int32)
+        pj = np.ascontiguousarray([p[1] for p in pairs], np.int32)
+        best = np.zeros(npairs, np.int32)
+        T = np.zeros((npairs, 4, 4))
+        inl = np.zeros(max(int(off[-1]), 1), np.uint8)
+        sc = np.zeros((npairs, n_hyp), np.int32) if scores else None
+        vp = lambda a: a.ctypes.data_as(C.c_void_p)
+        self._check(self.lib.pose_graph_ransac(self.h, npairs, vp(pi), vp(pj), vp(off), vp(ui), vp(uj), n_hyp,
+                                               vp(samples), float(delta), float(alpha), int(bool(install)),
+                                               vp(best), vp(sc) if scores else None, vp(T), vp(inl)))
+        out = dict(best=best, T=T, inliers=[inl[off[q]:off[q + 1]].astype(bool) for q in range(npairs)])
+        if scores:
+            out["score"] = sc
+        return out
+
     def prune(self):
         """Pruning pass at the current poses: (score (N, H*W), keep (N, H*W))."""
         n = self.n_frames * self.camera.width * self.camera.height

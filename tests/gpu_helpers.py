@@ -13,12 +13,37 @@ H_REL_TOL = 1e-5
 G_REL_TOL = 1e-5
 
 
+def gpu_graph(g, **cfg):
+    """The library's pose graph holding synthetic window g (inputs passed as
+    device memory)."""
+    from paper_2108_00516_amd import Config, from_synth
+    c = Config(max_frames=max(g.n_frames, 2), **cfg)
+    return from_synth(g, c, device_inputs=True)
+
+
 def max_pose_diff(Pa, Pb):
     worst_r, worst_t = 0.0, 0.0
     for a, b in zip(Pa, Pb):
         r, t = oracle.pose_error(a, b)
         worst_r, worst_t = max(worst_r, r), max(worst_t, t)
     return worst_r, worst_t
+
+
+def gpu_decisions(pg, pb):
+    """The GPU's association target of every source pixel of every ordered pair."""
+    return np.stack([pg.associate(i, j)[0] for (i, j) in pb.ordered_pairs()])
+
+
+def oracle_step(lin, P, fixed):
+    """One Gauss-Newton update of the oracle from given normal equations."""
+    free = [k for k in range(len(P)) if not fixed[k]]
+    idx = np.concatenate([np.arange(6 * k, 6 * k + 6) for k in free])
+    rc, d = oracle.cholesky_solve(lin["H"][np.ix_(idx, idx)], -lin["g"][idx])
+    assert rc == oracle.OK
+    Q = P.copy()
+    for a, k in enumerate(free):
+        Q[k] = oracle.se3_exp(d[6 * a:6 * a + 6]) @ P[k]
+    return Q
 
 
 def check_normal_equations(H_gpu, g_gpu, lin, tol_h=H_REL_TOL, tol_g=G_REL_TOL):

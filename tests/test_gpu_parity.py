@@ -10,8 +10,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import (G_REL_TOL, H_REL_TOL, POSE_TOL_M, POSE_TOL_RAD, check_normal_equations,
-                         max_pose_diff, near_half_integer)
+from gpu_helpers import (G_REL_TOL, H_REL_TOL, POSE_TOL_M, POSE_TOL_RAD, check_normal_equations, gpu_decisions,
+                         max_pose_diff, near_half_integer, oracle_step)
 
 pytestmark = pytest.mark.gpu
 
@@ -97,9 +97,6 @@ def test_association_parity(name, pairs):
     pg.close()
 
 
-def gpu_decisions(pg, pb):
-    return np.stack([pg.associate(i, j)[0] for (i, j) in pb.ordered_pairs()])
-
 
 @pytest.mark.parametrize("name", ["T", "P"])
 def test_linearize_parity(name):
@@ -123,17 +120,6 @@ def test_linearize_parity(name):
     assert st["energy_g"] == pytest.approx(lin["energy_g"], rel=1e-5)
     pg.close()
 
-
-def oracle_step(lin, P, fixed):
-    """One Gauss-Newton update of the oracle from given normal equations."""
-    free = [k for k in range(len(P)) if not fixed[k]]
-    idx = np.concatenate([np.arange(6 * k, 6 * k + 6) for k in free])
-    rc, d = oracle.cholesky_solve(lin["H"][np.ix_(idx, idx)], -lin["g"][idx])
-    assert rc == oracle.OK
-    Q = P.copy()
-    for a, k in enumerate(free):
-        Q[k] = oracle.se3_exp(d[6 * a:6 * a + 6]) @ P[k]
-    return Q
 
 
 @pytest.mark.parametrize("name,lf,lg,iters", [("T", 1.0, 1.0, 7), ("T", 0.5, 2.0, 7), ("T", 1.0, 0.0, 4),
