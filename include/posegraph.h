@@ -57,10 +57,15 @@ typedef enum {
  * system has at most 60 unknowns (10 free nodes), else Gauss-Jordan (3x3 pivot
  * blocks, rank-3 updates on the matrix cores, one workgroup per graph) up to
  * 126 unknowns (21 free nodes), else Cholesky; PCG is the Jacobi-preconditioned
- * conjugate gradient the paper names (Sec. IV-D).  Choosing LDL for a graph
- * that may hold more than 10 free nodes fails (PG_ERR_CAPACITY at create). */
+ * conjugate gradient the paper names (Sec. IV-D) on the assembled normal
+ * equations.  PCG_MATRIX_FREE is that PCG without forming the normal
+ * equations: J^T W J p is applied from per-pair Gram blocks of the
+ * association pass and the feature blocks (up to 14 keyframes); it stops at
+ * |r| <= pcg_rel_tol |b|.  Choosing LDL for a graph that may hold more than 10
+ * free nodes, or PCG_MATRIX_FREE with max_frames above 14, fails
+ * (PG_ERR_CAPACITY at create). */
 enum { PG_SOLVER_AUTO = 0, PG_SOLVER_PCG = 1, PG_SOLVER_CHOLESKY = 2, PG_SOLVER_GAUSS_JORDAN = 3,
-       PG_SOLVER_LDL = 4 };
+       PG_SOLVER_LDL = 4, PG_SOLVER_PCG_MATRIX_FREE = 5 };
 enum { PG_WEIGHT_HUBER = 0, PG_WEIGHT_LEARNED = 1 };
 enum { PG_PREC_FP32 = 0, PG_PREC_BF16X3 = 1 };
 
@@ -82,7 +87,7 @@ typedef struct {
     double huber_g_m;           /* Huber threshold of the dense term, metres (0.005)        */
     double gate_dist_m;         /* dense association distance gate, metres (0.01)           */
     double gate_normal_rad;     /* dense association normal-angle gate, radians (30 deg)    */
-    int solver;                 /* PG_SOLVER_AUTO (default), _PCG, _CHOLESKY, _GAUSS_JORDAN, _LDL */
+    int solver;                 /* PG_SOLVER_AUTO (default), _PCG, _CHOLESKY, _GAUSS_JORDAN, _LDL, _PCG_MATRIX_FREE */
     int pcg_max_iters;          /* PCG iteration cap (default 500)                           */
     double pcg_rel_tol;         /* PCG stop: |r| <= tol |b| (default 1e-12)                  */
     int weighting;              /* PG_WEIGHT_HUBER (default) or PG_WEIGHT_LEARNED            */
@@ -105,6 +110,7 @@ typedef struct {
     int n_assoc_launches;                    /* association kernel launches (timing = 1)   */
     float ms_assoc, ms_feature, ms_reduce, ms_solve, ms_total; /* kernel time (timing = 1) */
     long long n_target_reads[PG_MAX_ITERS];  /* dense association: target pixels read   */
+    int pcg_iters[PG_MAX_ITERS];             /* PCG iterations per Gauss-Newton iteration (PCG solvers; else 0) */
 } pg_stats;
 
 /* Defaults listed in pg_config. */

@@ -22,7 +22,8 @@ PG_ERR_HIP = -7
 STATUS_NAMES = {0: "PG_OK", -1: "PG_ERR_INVALID_ARG", -2: "PG_ERR_NO_DEVICE", -3: "PG_ERR_OUT_OF_MEMORY",
                 -4: "PG_ERR_CAPACITY", -5: "PG_ERR_SINGULAR", -6: "PG_ERR_NONFINITE", -7: "PG_ERR_HIP"}
 
-PG_SOLVER_AUTO, PG_SOLVER_PCG, PG_SOLVER_CHOLESKY, PG_SOLVER_GAUSS_JORDAN, PG_SOLVER_LDL = 0, 1, 2, 3, 4
+(PG_SOLVER_AUTO, PG_SOLVER_PCG, PG_SOLVER_CHOLESKY, PG_SOLVER_GAUSS_JORDAN, PG_SOLVER_LDL,
+ PG_SOLVER_PCG_MATRIX_FREE) = 0, 1, 2, 3, 4, 5
 PG_WEIGHT_HUBER, PG_WEIGHT_LEARNED = 0, 1
 PG_PREC_FP32, PG_PREC_BF16X3 = 0, 1
 PG_MAX_FRAMES_LIMIT = 32
@@ -51,7 +52,7 @@ class pg_stats(C.Structure):
                 ("status_bits", C.c_int), ("src_pixels", C.c_longlong), ("n_assoc_launches", C.c_int),
                 ("ms_assoc", C.c_float), ("ms_feature", C.c_float), ("ms_reduce", C.c_float),
                 ("ms_solve", C.c_float), ("ms_total", C.c_float),
-                ("n_target_reads", C.c_longlong * PG_MAX_ITERS)]
+                ("n_target_reads", C.c_longlong * PG_MAX_ITERS), ("pcg_iters", C.c_int * PG_MAX_ITERS)]
 
 
 # entry point -> (restype, argtypes)

@@ -23,6 +23,8 @@ constexpr int kSolverPCG = 1;
 constexpr int kSolverCholesky = 2;
 constexpr int kSolverGaussJordan = 3;
 constexpr int kSolverLDL = 4;
+constexpr int kSolverPcgMatrixFree = 5;
+constexpr int kMfMaxFrames = 14;   // matrix-free PCG: per-pair Gram blocks and feature blocks in LDS
 constexpr int kGjMaxN = 126;
 constexpr int kLdlMaxN = 60;     // single-wavefront LDL^T: 4 x 4 tiles of 16, rows padded to 4, one column for -g
 constexpr int kLdlMaxN2 = 28;    //   2 x 2 tiles up to this size

@@ -38,6 +38,9 @@ int gj_slots(int n_free);   // columns of the Gauss-Jordan system
 void launch_mfma_solve(const GraphDev* gds, int n_graphs, int cols, hipStream_t st);
 hipError_t solve_set_max_lds(size_t bytes);
 void launch_solve(const GraphDev* gds, int n_graphs, size_t lds, int mode, hipStream_t st);
+size_t mf_lds_bytes(int n_frames, int n_sets);
+hipError_t mf_set_max_lds(size_t bytes);
+void launch_mf_pcg(const GraphDev* gds, int n_graphs, size_t lds, hipStream_t st);
 hipError_t launch_ransac(const float4* maps, int W, int H, double fx, double fy, double cx, double cy,
                          const int4* pairs, int n_pairs, const float* uv_i, const float* uv_j, const int* samples,
                          int n_hyp, double delta, double cos_alpha, int* score, double* T, int* best, double* T_best,
@@ -92,6 +95,8 @@ struct Schedule {
     int ppt = 4;
     int iters = 0;
     bool gj = false;      // every graph solved on the matrix cores (LDL^T or Gauss-Jordan)
+    bool mf = false;      // every graph solved by matrix-free PCG (no assembly)
+    size_t mf_lds = 0;    // dynamic LDS of the matrix-free solve
     int precision = 0;    // PG_PREC_* of every graph of the schedule
     int gj_slots = 1;   // widest Gauss-Jordan system (columns) of the schedule (1 if none)
     hipGraphExec_t exec = nullptr;
@@ -276,6 +281,11 @@ pg_status prepare_graph(pg_graph* g)
             if (!ldl_fits)
                 return fail(g, PG_ERR_CAPACITY, "LDL^T solve of %d unknowns exceeds %d", nf, kLdlMaxN);
             g->solver = kSolverLDL;
+            break;
+        case PG_SOLVER_PCG_MATRIX_FREE:
+            if (N > kMfMaxFrames)
+                return fail(g, PG_ERR_CAPACITY, "matrix-free PCG holds at most %d frames", kMfMaxFrames);
+            g->solver = kSolverPcgMatrixFree;
             break;
         default: g->solver = ldl_fits ? kSolverLDL : gj_fits ? kSolverGaussJordan : kSolverCholesky; break;
         }
@@ -537,15 +547,24 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
     // LDS Cholesky/PCG kernel (those graphs then use Cholesky, which gives the
     // same step up to rounding)
     s.gj = true;
+    s.mf = true;
     s.gj_slots = 1;
+    s.mf_lds = 0;
     for (pg_graph* g : gs) {
         s.gj = s.gj && (g->solver == kSolverGaussJordan || g->solver == kSolverLDL);
+        s.mf = s.mf && g->solver == kSolverPcgMatrixFree;
         if (g->solver == kSolverGaussJordan)
             s.gj_slots = std::max(s.gj_slots, gj_slots(g->n_free));
+        s.mf_lds = std::max(s.mf_lds, mf_lds_bytes(g->n_frames, g->n_sets));
     }
-    if (!s.gj)
+    if (s.mf) {
+        if (s.mf_lds > (size_t)g0->lds_limit)
+            return fail(g0, PG_ERR_CAPACITY, "matrix-free PCG needs %zu B of LDS", s.mf_lds);
+        HIP_OR_FAIL(g0, mf_set_max_lds(s.mf_lds));
+    }
+    if (!s.gj && !s.mf)
         for (GraphDev& d : devs)
-            if (d.solver == kSolverGaussJordan || d.solver == kSolverLDL)
+            if (d.solver == kSolverGaussJordan || d.solver == kSolverLDL || d.solver == kSolverPcgMatrixFree)
                 d.solver = kSolverCholesky;
     // items of all graphs are concatenated; the XCD mapping of the association
     // kernel hands each XCD a contiguous run of them
@@ -612,10 +631,13 @@ hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std
                      s.fitems.as<int2>(), s.n_fitems, st);
         if (m && (e = hipEventRecord(m[2], st)) != hipSuccess)
             return e;
-        launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
+        if (!s.mf)
+            launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
         if (m && (e = hipEventRecord(m[3], st)) != hipSuccess)
             return e;
-        if (s.gj)
+        if (s.mf)
+            launch_mf_pcg(gds, ng, s.mf_lds, st);
+        else if (s.gj)
             launch_mfma_solve(gds, ng, s.gj_slots, st);
         else
             launch_solve(gds, ng, s.lds, 0, st);
@@ -713,6 +735,9 @@ pg_status run_schedule(Schedule& s, int iters, bool use_graph, bool timing, std:
                 out->n_valid_g[it] = (long long)g->h_iter_stats[kIterRecord * it + 2];
                 out->n_valid_f[it] = (long long)g->h_iter_stats[kIterRecord * it + 3];
                 out->n_target_reads[it] = (long long)g->h_iter_stats[kIterRecord * it + 4];
+                out->pcg_iters[it] = (g->solver == kSolverPCG || g->solver == kSolverPcgMatrixFree)
+                                         ? (int)g->h_iter_stats[kIterRecord * it + 5]
+                                         : 0;
             }
             out->status_bits = *g->h_status;
             long long sp = 0;
@@ -781,7 +806,7 @@ pg_status pose_graph_create(const pg_config* cfg, const pg_camera* cam, void* hi
     if (!(cfg->huber_f_m > 0 && cfg->huber_g_m > 0 && cfg->gate_dist_m > 0 && cfg->gate_normal_rad > 0 &&
           cfg->gate_normal_rad <= M_PI && cfg->lambda_f >= 0 && cfg->lambda_g >= 0))
         return fail(nullptr, PG_ERR_INVALID_ARG, "bad method parameters");
-    if (cfg->solver < PG_SOLVER_AUTO || cfg->solver > PG_SOLVER_LDL)
+    if (cfg->solver < PG_SOLVER_AUTO || cfg->solver > PG_SOLVER_PCG_MATRIX_FREE)
         return fail(nullptr, PG_ERR_INVALID_ARG, "unknown solver");
     if (cfg->weighting != PG_WEIGHT_HUBER && cfg->weighting != PG_WEIGHT_LEARNED)
         return fail(nullptr, PG_ERR_INVALID_ARG, "unknown weighting");
@@ -813,7 +838,8 @@ pg_status pose_graph_create(const pg_config* cfg, const pg_camera* cam, void* hi
     const size_t need = solve_lds_bytes(cfg->max_frames - 1, cfg->max_frames);
     if (need > (size_t)g->lds_limit ||
         (cfg->solver == PG_SOLVER_GAUSS_JORDAN && 6 * (cfg->max_frames - 1) > kGjMaxN) ||
-        (cfg->solver == PG_SOLVER_LDL && 6 * (cfg->max_frames - 1) > kLdlMaxN)) {
+        (cfg->solver == PG_SOLVER_LDL && 6 * (cfg->max_frames - 1) > kLdlMaxN) ||
+        (cfg->solver == PG_SOLVER_PCG_MATRIX_FREE && cfg->max_frames > kMfMaxFrames)) {
         delete g;
         return fail(nullptr, PG_ERR_CAPACITY, "max_frames %d needs %zu B of LDS for the solve, device has %d",
                     cfg->max_frames, need, lds_max);

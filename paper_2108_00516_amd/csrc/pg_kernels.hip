@@ -2609,6 +2609,351 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd, double* __restrict
     compute_transforms(gd, Ts);
 }
 
+// ------------------------------------------------- matrix-free PCG
+
+constexpr int kMfThreads = 256;
+
+// Dynamic LDS of the matrix-free solve (doubles): per ordered pair the Gram
+// block M = sum w J_i^T J_i (21), the pair transform A (12) and a product slot
+// (12); per feature set its 12 x 12 block (78) and a product slot (12); six
+// 6N vectors; a reduction scratch.
+__host__ __device__ inline size_t mf_lds_doubles(int n_frames, int n_sets)
+{
+    const size_t P = (size_t)n_frames * (n_frames - 1);
+    return 45 * P + 90 * (size_t)n_sets + 6 * 6 * (size_t)n_frames + 16;
+}
+
+// (Ad^T y) for the adjoint of A = [R | t] (xi = [v; w]): [R^T y_v; R^T (y_w - t x y_v)]
+__device__ __forceinline__ void adjT_apply(const double* __restrict__ A, const double* y, double* out)
+{
+    const double t0 = A[3], t1 = A[7], t2 = A[11];
+    const double w0 = y[3] - (t1 * y[2] - t2 * y[1]);
+    const double w1 = y[4] - (t2 * y[0] - t0 * y[2]);
+    const double w2 = y[5] - (t0 * y[1] - t1 * y[0]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        out[c] = A[c] * y[0] + A[4 + c] * y[1] + A[8 + c] * y[2];
+        out[3 + c] = A[c] * w0 + A[4 + c] * w1 + A[8 + c] * w2;
+    }
+}
+
+// (Ad x) for the adjoint of A: [R x_v + t x (R x_w); R x_w]
+__device__ __forceinline__ void adj_apply(const double* __restrict__ A, const double* x, double* out)
+{
+    double rw[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        rw[r] = A[4 * r] * x[3] + A[4 * r + 1] * x[4] + A[4 * r + 2] * x[5];
+    const double t0 = A[3], t1 = A[7], t2 = A[11];
+    out[0] = A[0] * x[0] + A[1] * x[1] + A[2] * x[2] + (t1 * rw[2] - t2 * rw[1]);
+    out[1] = A[4] * x[0] + A[5] * x[1] + A[6] * x[2] + (t2 * rw[0] - t0 * rw[2]);
+    out[2] = A[8] * x[0] + A[9] * x[1] + A[10] * x[2] + (t0 * rw[1] - t1 * rw[0]);
+    out[3] = rw[0];
+    out[4] = rw[1];
+    out[5] = rw[2];
+}
+
+// Sum of two values over the block (fixed order over the waves); every thread
+// gets both.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    lds_barrier();
+    if (lane == 0) {
+        red[2 * wave] = a;
+        red[2 * wave + 1] = b;
+    }
+    lds_barrier();
+    a = 0.0;
+    b = 0.0;
+    for (int w = 0; w < kMfThreads / 64; ++w) {
+        a += red[2 * w];
+        b += red[2 * w + 1];
+    }
+}
+
+// One Gauss-Newton step by preconditioned conjugate gradients on the normal
+// equations without forming them (the solver Sec. IV-D names: PCG with the
+// preconditioner diag(J^T W J)).  The association pass left per work item the
+// sums of w J_i^T J_i, w r J_i, energy, count and target reads; this block
+// reduces them per ordered pair (fixed order) to M and v.  A dense residual
+// row's Jacobian is [J_i | -J_i Ad_A], so J^T W J p = sum over pairs of
+// [M u; -Ad^T M u] with u = p_i - Ad_A p_j; the feature term (Eq. 2) adds each
+// set's 12 x 12 block times [p_i; p_j] (both orderings of Eq. 1: factor 2).
+// Gradient and preconditioner come from the same pieces.  x = 0 start,
+// stopped at |r| <= pcg_rel_tol |b| or pcg_max_iters; a non-positive curvature
+// p^T H p is a singular system.  Then T <- Exp(x) T and the next iteration's
+// transforms, as the other solves.  One block of 256 threads per graph; the
+// per-pair data lives in LDS (mf_lds_doubles).
+__global__ __launch_bounds__(kMfThreads) void mf_pcg_kernel(const GraphDev* __restrict__ gds)
+{
+    const GraphDev& gd = gds[blockIdx.x];
+    const int N = gd.n_frames, P = N * (N - 1), NS = gd.n_sets, n6 = 6 * N;
+    extern __shared__ double sm[];
+    double* Mg = sm;              // P x 21
+    double* Ax = Mg + 21 * P;     // P x 12
+    double* Yp = Ax + 12 * P;     // P x 12: M u, then -Ad^T M u
+    double* Fb = Yp + 12 * P;     // NS x 78
+    double* Fy = Fb + 78 * NS;    // NS x 12
+    double* xv = Fy + 12 * NS;    // six 6N vectors
+    double* rv = xv + n6;
+    double* zv = rv + n6;
+    double* pv = zv + n6;
+    double* dg = pv + n6;
+    double* gv = dg + n6;
+    double* red = gv + n6;        // 16
+    __shared__ double Ts[16 * kMaxFrames];
+    __shared__ double xs[6 * kMaxFrames];
+    __shared__ int sfree[kMaxFrames];
+    __shared__ int sflags;
+    const int tid = threadIdx.x;
+    const int status = *gd.status;
+    const int it = *gd.iters_done;
+    if (status)
+        return;
+    // per-pair sums of the association records, transforms, feature blocks
+    for (int task = tid; task < 30 * P; task += kMfThreads) {
+        const int p = task / 30, f = task - 30 * p;
+        const double v = sum_records(gd.partials + f, gd.pair_base[p], gd.pair_base[p + 1]);
+        if (f < 21)
+            Mg[21 * p + f] = v;
+        else
+            Yp[12 * p + (f - 21)] = v;   // v (6), energy, count, target reads
+    }
+    for (int task = tid; task < 12 * P; task += kMfThreads)
+        Ax[task] = gd.xf64[task];
+    for (int task = tid; task < 78 * NS; task += kMfThreads)
+        Fb[task] = gd.fpartials[(size_t)(task / 78) * kFeatStride + task % 78];
+    for (int task = tid; task < 16 * N; task += kMfThreads)
+        Ts[task] = gd.poses[task];
+    if (tid < gd.n_free)
+        sfree[tid] = gd.free_ids[tid];
+    if (tid == 0)
+        sflags = 0;
+    __syncthreads();
+    const double lg = (double)gd.lambda_g, lf2 = 2.0 * (double)gd.lambda_f;
+    // iteration record: E_f, E_g, n_g, n_f, target reads
+    if (tid < kNodeStats) {
+        double s = 0.0;
+        if (tid == 0 || tid == 3)
+            for (int q = 0; q < NS; ++q)
+                s += gd.fpartials[(size_t)q * kFeatStride + (tid == 0 ? 90 : 91)];
+        else
+            for (int p = 0; p < P; ++p)
+                s += Yp[12 * p + (tid == 1 ? 6 : tid == 2 ? 7 : 8)];
+        gd.iter_stats[kIterRecord * it + tid] = (tid == 0) ? lf2 * s : (tid == 1) ? lg * s : s;
+    }
+    // gradient and the diagonal of J^T W J per node entry (fixed order)
+    const int n = 6 * gd.n_free;
+    for (int e = tid; e < n6; e += kMfThreads) {
+        const int k = e / 6, c = e - 6 * k;
+        double g = 0.0, d = 0.0;
+        for (int j = 0; j < N; ++j) {
+            if (j == k)
+                continue;
+            const int ps = pair_index(k, j, N), pt = pair_index(j, k, N);   // k as source, as target
+            g += Yp[12 * ps + c];
+            d += sym6(Mg + 21 * ps, c, c);
+            // target role: -Ad^T v and (Ad^T M Ad)_cc = a^T M a, a = column c of Ad
+            double y[6], tv[6], col[6], ec[6];
+#pragma unroll
+            for (int l = 0; l < 6; ++l) {
+                y[l] = Yp[12 * pt + l];
+                ec[l] = (l == c) ? 1.0 : 0.0;
+            }
+            adjT_apply(Ax + 12 * pt, y, tv);
+            g -= tv[c];
+            adj_apply(Ax + 12 * pt, ec, col);
+            double q = 0.0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {
+                double ma = 0.0;
+#pragma unroll
+                for (int b = 0; b < 6; ++b)
+                    ma += sym6(Mg + 21 * pt, a, b) * col[b];
+                q += col[a] * ma;
+            }
+            d += q;
+        }
+        g *= lg;
+        d *= lg;
+        for (int j = 0; j < N; ++j) {
+            const int q = (j != k) ? gd.set_of[k * N + j] : -1;
+            if (q < 0)
+                continue;
+            const int o = (gd.fsets[q].x == k) ? 0 : 6;
+            g += lf2 * gd.fpartials[(size_t)q * kFeatStride + 78 + o + c];
+            d += lf2 * Fb[78 * q + sym12_index(o + c, o + c)];
+        }
+        const bool fr = gd.free_pos[k] >= 0;
+        gv[e] = g;
+        dg[e] = d;
+        xv[e] = 0.0;
+        rv[e] = fr ? -g : 0.0;
+        zv[e] = (fr && d > 0.0) ? -g / d : 0.0;
+        pv[e] = zv[e];
+    }
+    double bb = 0.0, rz = 0.0, nbad = 0.0, unused = 0.0;
+    for (int e = tid; e < n6; e += kMfThreads) {
+        bb += rv[e] * rv[e];
+        rz += rv[e] * zv[e];
+        nbad += (gd.free_pos[e / 6] >= 0 && !(dg[e] > 0.0)) ? 1.0 : 0.0;
+    }
+    block_sum2(bb, rz, red);
+    block_sum2(nbad, unused, red);
+    bool singular = nbad > 0.0;   // a free unknown without curvature
+    int iters = 0;
+    if (n > 0 && bb > 0.0 && !singular) {
+        const double tol2 = gd.pcg_rel_tol * gd.pcg_rel_tol * bb;
+        for (iters = 0; iters < gd.pcg_max_iters;) {
+            // q = J^T W J p: per pair M u and -Ad^T M u, per set F [p_i; p_j]
+            for (int p = tid; p < P + NS; p += kMfThreads) {
+                if (p < P) {
+                    const int i = p / (N - 1), jj = p - i * (N - 1), j = (jj < i) ? jj : jj + 1;
+                    double pj[6], ap[6], u[6], y[6], w[6];
+#pragma unroll
+                    for (int l = 0; l < 6; ++l)
+                        pj[l] = pv[6 * j + l];
+                    adj_apply(Ax + 12 * p, pj, ap);
+#pragma unroll
+                    for (int l = 0; l < 6; ++l)
+                        u[l] = pv[6 * i + l] - ap[l];
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int b = 0; b < 6; ++b)
+                            s += sym6(Mg + 21 * p, a, b) * u[b];
+                        y[a] = s;
+                    }
+                    adjT_apply(Ax + 12 * p, y, w);
+#pragma unroll
+                    for (int l = 0; l < 6; ++l) {
+                        Yp[12 * p + l] = y[l];
+                        Yp[12 * p + 6 + l] = -w[l];
+                    }
+                } else {
+                    const int q = p - P;
+                    const int4 fs = gd.fsets[q];
+                    double v[12];
+#pragma unroll
+                    for (int l = 0; l < 6; ++l) {
+                        v[l] = pv[6 * fs.x + l];
+                        v[6 + l] = pv[6 * fs.y + l];
+                    }
+#pragma unroll
+                    for (int a = 0; a < 12; ++a) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int b = 0; b < 12; ++b)
+                            s += Fb[78 * q + sym12_index(a, b)] * v[b];
+                        Fy[12 * q + a] = s;
+                    }
+                }
+            }
+            lds_barrier();
+            double pq = 0.0, dummy = 0.0;
+            double qv[(6 * kMaxFrames + kMfThreads - 1) / kMfThreads];
+#pragma unroll
+            for (int u = 0; u < (6 * kMaxFrames + kMfThreads - 1) / kMfThreads; ++u) {
+                const int e = tid + u * kMfThreads;
+                qv[u] = 0.0;
+                if (e >= n6)
+                    continue;
+                const int k = e / 6, c = e - 6 * k;
+                if (gd.free_pos[k] < 0)
+                    continue;
+                double h = 0.0;
+                for (int j = 0; j < N; ++j)
+                    if (j != k)
+                        h += Yp[12 * pair_index(k, j, N) + c] + Yp[12 * pair_index(j, k, N) + 6 + c];
+                h *= lg;
+                double f = 0.0;
+                for (int j = 0; j < N; ++j) {
+                    const int q = (j != k) ? gd.set_of[k * N + j] : -1;
+                    if (q >= 0)
+                        f += Fy[12 * q + ((gd.fsets[q].x == k) ? 0 : 6) + c];
+                }
+                qv[u] = h + lf2 * f;
+                pq += pv[e] * qv[u];
+            }
+            block_sum2(pq, dummy, red);
+            if (!(pq > 0.0)) {
+                singular = true;
+                break;
+            }
+            const double alpha = rz / pq;
+            double rr = 0.0, rzn = 0.0;
+#pragma unroll
+            for (int u = 0; u < (6 * kMaxFrames + kMfThreads - 1) / kMfThreads; ++u) {
+                const int e = tid + u * kMfThreads;
+                if (e >= n6 || gd.free_pos[e / 6] < 0)
+                    continue;
+                xv[e] += alpha * pv[e];
+                rv[e] -= alpha * qv[u];
+                zv[e] = rv[e] / dg[e];
+                rr += rv[e] * rv[e];
+                rzn += rv[e] * zv[e];
+            }
+            block_sum2(rr, rzn, red);
+            ++iters;
+            if (rr <= tol2)
+                break;
+            const double beta = rzn / rz;
+            rz = rzn;
+            for (int e = tid; e < n6; e += kMfThreads)
+                if (gd.free_pos[e / 6] >= 0)
+                    pv[e] = zv[e] + beta * pv[e];
+            lds_barrier();
+        }
+    }
+    // solution in free-node order, flags
+    bool bad = false;
+    for (int e = tid; e < n6; e += kMfThreads) {
+        const int fp = gd.free_pos[e / 6];
+        if (fp >= 0) {
+            xs[6 * fp + e % 6] = xv[e];
+            bad |= !isfinite(xv[e]);
+        }
+    }
+    if (singular || bad)
+        atomicOr(&sflags, (singular ? 1 : 0) | (bad ? 2 : 0));
+    if (tid == 0)
+        gd.iter_stats[kIterRecord * it + 5] = (double)iters;
+    __syncthreads();
+    const int flags = sflags;
+    if (n == 0) {
+        if (tid == 0)
+            *gd.iters_done = it + 1;
+        return;
+    }
+    if (flags) {
+        if (tid == 0)
+            *gd.status |= (flags & 1) ? kStatusSingular : kStatusNonFinite;
+        return;
+    }
+    update_poses(gd, xs, sfree, Ts);
+    if (tid == 0)
+        *gd.iters_done = it + 1;
+    compute_transforms(gd, Ts);
+}
+
+hipError_t mf_set_max_lds(size_t bytes)
+{
+    return hipFuncSetAttribute((const void*)mf_pcg_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+size_t mf_lds_bytes(int n_frames, int n_sets) { return sizeof(double) * mf_lds_doubles(n_frames, n_sets); }
+
+void launch_mf_pcg(const GraphDev* gds, int n_graphs, size_t lds, hipStream_t st)
+{
+    mf_pcg_kernel<<<n_graphs, kMfThreads, lds, st>>>(gds);
+}
+
 // One block of 256 threads per graph: the single-wavefront block LDL^T for
 // graphs resolved to it (16 x 16 tiles: 2 x 2 up to 28 unknowns, else 4 x 4),
 // else block Gauss-Jordan on GNT x GNT tiles.

@@ -67,7 +67,7 @@ def stats_to_dict(s: L.pg_stats, iters: int) -> dict:
     k = max(0, min(iters, L.PG_MAX_ITERS))
     return dict(iters_done=s.iters_done, energy_f=np.array(s.energy_f[:k]), energy_g=np.array(s.energy_g[:k]),
                 n_valid_g=np.array(s.n_valid_g[:k]), n_valid_f=np.array(s.n_valid_f[:k]),
-                n_target_reads=np.array(s.n_target_reads[:k]),
+                n_target_reads=np.array(s.n_target_reads[:k]), pcg_iters=np.array(s.pcg_iters[:k]),
                 status_bits=s.status_bits, src_pixels=s.src_pixels, n_assoc_launches=s.n_assoc_launches,
                 ms_assoc=s.ms_assoc, ms_feature=s.ms_feature, ms_reduce=s.ms_reduce, ms_solve=s.ms_solve,
                 ms_total=s.ms_total)

@@ -167,7 +167,7 @@ def test_optimize_parity(name):
 
 @pytest.mark.parametrize("name,fixed,solver", [("T", (0, 2), "GAUSS_JORDAN"), ("P", (0, 4, 7), "GAUSS_JORDAN"),
                                                 ("P", (0, 4, 7), "CHOLESKY"), ("T", (0, 2), "LDL"),
-                                                ("P", (0, 4, 7), "LDL")])
+                                                ("P", (0, 4, 7), "LDL"), ("P", (0, 4, 7), "PCG_MATRIX_FREE")])
 def test_interior_fixed_nodes(name, fixed, solver):
     """Fixed nodes inside the window: the free-node system skips their rows and
     columns (node -> free position table), the poses of fixed nodes stay put."""
@@ -225,7 +225,7 @@ def test_tile_sizes(tile):
     pg.close()
 
 
-@pytest.mark.parametrize("solver", ["PCG", "CHOLESKY", "GAUSS_JORDAN", "LDL"])
+@pytest.mark.parametrize("solver", ["PCG", "CHOLESKY", "GAUSS_JORDAN", "LDL", "PCG_MATRIX_FREE"])
 def test_solvers_match(solver):
     from paper_2108_00516_amd import _lib
     g = graph("T")
@@ -382,3 +382,50 @@ def test_zero_iterations_and_continuation(use_graph):
     assert np.isclose(st2["energy_g"][0], s_at_p1["energy_g"][0], rtol=1e-3)
     assert not np.isclose(st2["energy_g"][0], st1["energy_g"][0], rtol=1e-3)
     pg.close()
+
+
+def test_matrix_free_pcg_against_explicit_normal_equations():
+    """The matrix-free PCG (J^T W J applied from per-pair Gram blocks, never
+    formed) against the direct solve of the explicitly assembled equations on
+    the 10-keyframe window: the same association decisions and, with PCG
+    converged to |r| <= 1e-12 |b|, the same steps (poses within 1e-9 after
+    each of 7 iterations); the oracle within 1e-5 end to end; the PCG
+    iteration counts reported; a capped PCG (3 iterations) reports 3 and ends
+    elsewhere; a singular window fails as with the direct solve."""
+    from paper_2108_00516_amd import _lib
+    g = graph("P")
+    say("matrix-free PCG vs explicit normal equations, P")
+    mf = gpu_graph(g, solver=_lib.PG_SOLVER_PCG_MATRIX_FREE, gn_iters=1)
+    dr_ = gpu_graph(g, solver=_lib.PG_SOLVER_LDL, gn_iters=1)
+    for it in range(7):
+        s1 = mf.optimize()
+        dr_.optimize()
+        a, b = mf.poses, dr_.poses
+        d_r, d_t = max_pose_diff(a, b)
+        say(f"  iteration {it}: PCG iterations {s1['pcg_iters'][0]}, difference {d_r:.2e} rad {d_t:.2e} m")
+        assert 1 <= s1["pcg_iters"][0] < 500
+        assert d_r <= 1e-9 and d_t <= 1e-9
+        dr_.set_poses(a)          # continue both from the same poses
+    mf.close()
+    dr_.close()
+    full = gpu_graph(g, solver=_lib.PG_SOLVER_PCG_MATRIX_FREE)
+    st = full.optimize()
+    Po, so = oracle.OracleProblem.from_synth(g).optimize(g.poses_init, 7)
+    d_r, d_t = max_pose_diff(full.poses, Po)
+    say(f"  end to end vs oracle: {d_r:.2e} rad {d_t:.2e} m; PCG iterations {list(st['pcg_iters'])}")
+    assert d_r <= POSE_TOL_RAD and d_t <= POSE_TOL_M
+    assert np.array_equal(st["n_valid_f"], so["n_valid_f"])
+    full.close()
+    capped = gpu_graph(g, solver=_lib.PG_SOLVER_PCG_MATRIX_FREE, pcg_max_iters=3)
+    st = capped.optimize()
+    assert list(st["pcg_iters"]) == [3] * 7
+    assert max_pose_diff(capped.poses, Po)[0] > 1e-7
+    capped.close()
+    mask = g.mask.copy()
+    mask[2] = 0
+    gs = synth.SynthGraph(**{**g.__dict__, "mask": mask,
+                             "matches": [m for m in g.matches if 2 not in (m.i, m.j)]})
+    sing = gpu_graph(gs, solver=_lib.PG_SOLVER_PCG_MATRIX_FREE)
+    st = sing.optimize(check=False)
+    assert st["status"] == _lib.PG_ERR_SINGULAR and st["iters_done"] == 0
+    sing.close()
