@@ -85,6 +85,10 @@ def lib():
         P = C.POINTER
         dp = P(C.c_double)
         L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_rot_geodesic.restype = C.c_double
+        L.orc_rot_geodesic.argtypes = [dp, dp]
+        L.orc_select_keyframes.argtypes = [C.c_int, dp, dp, C.c_int, P(C.c_int), P(C.c_int), dp]
+        L.orc_novel_view.argtypes = [C.c_int, dp, dp, C.c_double]
         L.orc_get_threads.restype = C.c_int
         L.orc_preprocess_frame.argtypes = [P(Problem), C.c_int, dp, dp, P(C.c_ubyte)]
         L.orc_linearize.argtypes = [P(Problem), dp, dp, dp, dp, dp, P(LinStats)]
@@ -490,6 +494,32 @@ def mlp_bce(params, x, labels, with_grad=True):
     loss = lib().orc_mlp_bce(_ptr(p, C.c_double), len(x), _ptr(x, C.c_double), _ptr(t, C.c_double),
                              _ptr(g, C.c_double) if with_grad else None)
     return loss, g
+
+
+def rot_geodesic(Ta, Tb) -> float:
+    a = np.ascontiguousarray(Ta, np.float64).reshape(16)
+    b = np.ascontiguousarray(Tb, np.float64).reshape(16)
+    return float(lib().orc_rot_geodesic(_ptr(a, C.c_double), _ptr(b, C.c_double)))
+
+
+def select_keyframes(T_pool, T_cur, K):
+    """Greedy keyframe selection (Sec. IV-C): (selected indices in selection
+    order, final cost sums)."""
+    P = np.ascontiguousarray(T_pool, np.float64).reshape(-1, 16)
+    t = np.ascontiguousarray(T_cur, np.float64).reshape(16)
+    sel = np.zeros(max(K, 1), np.int32)
+    nsel = C.c_int(0)
+    cost = np.zeros(len(P))
+    rc = lib().orc_select_keyframes(len(P), _ptr(P, C.c_double), _ptr(t, C.c_double), int(K),
+                                    _ptr(sel, C.c_int), C.byref(nsel), _ptr(cost, C.c_double))
+    assert rc == OK
+    return sel[:nsel.value].copy(), cost
+
+
+def novel_view(T_pool, T_cur, thresh=float(np.deg2rad(10.0))) -> bool:
+    P = np.ascontiguousarray(T_pool, np.float64).reshape(-1, 16)
+    t = np.ascontiguousarray(T_cur, np.float64).reshape(16)
+    return bool(lib().orc_novel_view(len(P), _ptr(P, C.c_double), _ptr(t, C.c_double), float(thresh)))
 
 
 def set_threads(n: int):

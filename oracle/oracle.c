@@ -1370,3 +1370,72 @@ int orc_match_descriptors(int na, const float *A, int nb, const float *B, int di
     free(d2);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Keyframe memory pool (Sec. IV-C, IV-E): the minimum H-subgraph objective
+ * over rotation geodesic distances, solved by the paper's greedy selection,
+ * and the novelty rule that admits a frame to the pool. */
+
+double orc_rot_geodesic(const double *Ta, const double *Tb)
+{
+    /* tr(R_a^T R_b) = sum over entries of R_a .* R_b */
+    double tr = 0.0;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            tr += Ta[4 * r + c] * Tb[4 * r + c];
+    double cs = 0.5 * (tr - 1.0);
+    if (cs > 1.0)
+        cs = 1.0;
+    if (cs < -1.0)
+        cs = -1.0;
+    return acos(cs);
+}
+
+int orc_select_keyframes(int n_pool, const double *T_pool, const double *T_cur, int K, int *selected,
+                         int *n_selected, double *cost)
+{
+    if (n_pool < 1 || K < 1 || !T_pool || !T_cur || !selected || !n_selected)
+        return ORC_ERR_ARG;
+    const int want = K < n_pool ? K : n_pool;
+    double *sum = (double *)malloc(sizeof(double) * (size_t)n_pool);
+    unsigned char *taken = (unsigned char *)calloc((size_t)n_pool, 1);
+    if (!sum || !taken) {
+        free(sum);
+        free(taken);
+        return ORC_ERR_ARG;
+    }
+    /* the initial frame first; every other keyframe starts with its distance
+     * to the current frame and to the initial frame */
+    selected[0] = 0;
+    taken[0] = 1;
+    sum[0] = orc_rot_geodesic(T_pool, T_cur);
+    for (int k = 1; k < n_pool; ++k)
+        sum[k] = orc_rot_geodesic(T_pool + 16 * (size_t)k, T_cur) +
+                 orc_rot_geodesic(T_pool + 16 * (size_t)k, T_pool);
+    int n = 1;
+    while (n < want) {
+        int best = -1;
+        for (int k = 0; k < n_pool; ++k)
+            if (!taken[k] && (best < 0 || sum[k] < sum[best]))
+                best = k;
+        selected[n++] = best;
+        taken[best] = 1;
+        for (int k = 0; k < n_pool; ++k)
+            if (!taken[k])
+                sum[k] += orc_rot_geodesic(T_pool + 16 * (size_t)k, T_pool + 16 * (size_t)best);
+    }
+    *n_selected = n;
+    if (cost)
+        memcpy(cost, sum, sizeof(double) * (size_t)n_pool);
+    free(sum);
+    free(taken);
+    return ORC_OK;
+}
+
+int orc_novel_view(int n_pool, const double *T_pool, const double *T_cur, double thresh)
+{
+    for (int k = 0; k < n_pool; ++k)
+        if (!(orc_rot_geodesic(T_pool + 16 * (size_t)k, T_cur) > thresh))
+            return 0;
+    return 1;
+}

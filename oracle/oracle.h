@@ -229,6 +229,26 @@ int orc_ransac_pairs(const orc_problem *pb, int n_pairs, const int *pi, const in
 int orc_match_descriptors(int na, const float *A, int nb, const float *B, int dim, double ratio, int *match,
                           double *d1_out, double *d2_out);
 
+/* ---- keyframe memory pool (Sec. IV-C, IV-E) ----
+ * Poses are 4x4 row-major (object -> camera); only their rotations matter.
+ * Geodesic distance of two rotations: arccos((tr(R_a^T R_b) - 1) / 2), the
+ * cosine clamped to [-1, 1]. */
+double orc_rot_geodesic(const double *Ta, const double *Tb);
+
+/* Greedy keyframe selection (Sec. IV-C): starting from {pool[0]} (the initial
+ * frame), repeatedly add the keyframe with the smallest sum of geodesic
+ * distances to the current frame and to every keyframe selected so far
+ * (lowest index among equal sums), until min(K, n_pool) are selected.
+ * selected[0..*n_selected) receives the pool indices in selection order;
+ * cost (may be NULL, n_pool) the final sums (those of selected keyframes as
+ * they were when chosen). */
+int orc_select_keyframes(int n_pool, const double *T_pool, const double *T_cur, int K, int *selected,
+                         int *n_selected, double *cost);
+
+/* Novel view (Sec. IV-E): 1 when the current frame's rotation is farther
+ * than thresh (radians) from every keyframe of the pool, else 0. */
+int orc_novel_view(int n_pool, const double *T_pool, const double *T_cur, double thresh);
+
 #ifdef __cplusplus
 }
 #endif
