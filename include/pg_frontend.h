@@ -1,6 +1,7 @@
 /* C ABI of the front end of the pose-graph library: keypoint descriptor
- * matching and coarse registration by RANSAC of BundleTrack (Wen & Bekris,
- * IROS 2021), Sec. IV-B, on the GPU.
+ * matching and coarse registration by RANSAC (Sec. IV-B), keyframe selection
+ * and the novelty test of the memory pool (Sec. IV-C, IV-E) of BundleTrack
+ * (Wen & Bekris, IROS 2021), on the GPU.
  * Same library and status codes as posegraph.h. */
 #ifndef PG_FRONTEND_H
 #define PG_FRONTEND_H
@@ -98,6 +99,30 @@ pg_status pg_match_descriptors_noalloc(const float* desc, const int* set_off, in
 pg_status pose_graph_ransac(pg_graph* g, int n_pairs, const int* pi, const int* pj, const int* match_off,
                             const float* uv_i, const float* uv_j, int n_hyp, const int* samples, double delta_m,
                             double alpha_rad, int install, int* best, int* score, double* T, uint8_t* inlier);
+
+#define PG_POOL_MAX 2048            /* keyframes of a memory pool                       */
+
+/* Keyframe selection from the memory pool (Sec. IV-C) and the novelty test of
+ * its augmentation (Sec. IV-E), on the GPU.  The geodesic distance of two
+ * poses' rotations is arccos((tr(R_a^T R_b) - 1) / 2) (cosine clamped to
+ * [-1, 1]).  Starting from {keyframe 0} (the initial frame, always kept),
+ * the keyframe with the smallest sum of geodesic distances to the current
+ * frame and to every keyframe selected so far is added (lowest index among
+ * equal sums) until min(K, n_pool) are selected: the paper's greedy
+ * solution of the minimum H-subgraph problem.
+ *   T_pool     n_pool poses, 16 doubles each (row-major 4 x 4, object ->
+ *              camera), host or device memory (copied)
+ *   T_cur      the current frame's pose (16 doubles, host)
+ *   selected   host, K entries: pool indices in selection order; n_selected
+ *              receives their count
+ *   novel      host, may be NULL: 1 when every keyframe is farther than
+ *              novel_rad from the current frame (the frame joins the pool)
+ *   cost       host, may be NULL, n_pool entries: each keyframe's final sum
+ *              (a selected keyframe's as it was when chosen)
+ * Synchronous on hip_stream (NULL: the null stream).  Errors:
+ * PG_ERR_INVALID_ARG, PG_ERR_CAPACITY (n_pool > PG_POOL_MAX), PG_ERR_HIP. */
+pg_status pg_select_keyframes(const double* T_pool, int n_pool, const double* T_cur, int K, double novel_rad,
+                              int* selected, int* n_selected, int* novel, double* cost, void* hip_stream);
 
 /* Message of the last failed front-end call on this thread ("" if none). */
 const char* pg_frontend_last_error(void);

@@ -92,6 +92,7 @@ SIGNATURES = {
     "pg_match_descriptors_noalloc": (C.c_int, [_vp, _vp, C.c_int, C.c_int, _vp, _vp, C.c_int, C.c_double, _vp,
                                                _vp, _vp, _vp]),
     "pg_frontend_last_error": (C.c_char_p, []),
+    "pg_select_keyframes": (C.c_int, [_vp, C.c_int, _vp, C.c_int, C.c_double, _vp, _vp, _vp, _vp, _vp]),
     "pose_graph_ransac": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp, _vp, C.c_int, _vp, C.c_double, C.c_double,
                                     C.c_int, _vp, _vp, _vp, _vp]),
 }

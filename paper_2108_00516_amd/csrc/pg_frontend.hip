@@ -32,9 +32,11 @@
 #include <stdarg.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <string.h>
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 namespace pg {
 namespace {
@@ -620,6 +622,135 @@ __global__ __launch_bounds__(256) void ransac_best_kernel(RansacArgs args)
     }
 }
 
+// ------------------------------------------------------------ keyframe pool
+
+constexpr int kPoolThreads = 256;
+constexpr int kPoolPer = PG_POOL_MAX / kPoolThreads;   // keyframes per thread
+
+// rotation geodesic distance between pose a (global) and pose b (LDS)
+__device__ __forceinline__ double pool_geodesic(const double* __restrict__ a, const double* b)
+{
+    double tr = 0.0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            tr = fma(a[4 * r + c], b[4 * r + c], tr);
+    return acos(fmin(1.0, fmax(-1.0, 0.5 * (tr - 1.0))));
+}
+
+// One block: thread t owns keyframes t + 256 m; per greedy step a block-wide
+// argmin of (sum, index) over the keyframes not yet taken, then every sum
+// grows by its distance to the new keyframe.  Pool entry 16 n_pool .. 16
+// n_pool + 15 holds the current frame's pose.
+__global__ __launch_bounds__(kPoolThreads) void keyframe_select_kernel(const double* __restrict__ T, int n_pool, int K,
+                                                                       double novel_rad, int* out)
+{
+    __shared__ double piv[16];
+    __shared__ double cur[16];
+    __shared__ double wd[kPoolThreads / 64];
+    __shared__ int wk[kPoolThreads / 64];
+    __shared__ int spick;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 16) {
+        cur[tid] = T[16 * (size_t)n_pool + tid];
+        piv[tid] = T[tid];   // keyframe 0, selected first
+    }
+    __syncthreads();
+    double sum[kPoolPer];
+    bool taken[kPoolPer];
+    double dmin = INFINITY;
+#pragma unroll
+    for (int m = 0; m < kPoolPer; ++m) {
+        const int k = tid + kPoolThreads * m;
+        taken[m] = (k == 0) || k >= n_pool;
+        sum[m] = INFINITY;
+        if (k < n_pool) {
+            const double dc = pool_geodesic(T + 16 * (size_t)k, cur);
+            dmin = fmin(dmin, dc);
+            sum[m] = dc + (k == 0 ? 0.0 : pool_geodesic(T + 16 * (size_t)k, piv));
+        }
+    }
+    // novelty: the nearest keyframe's distance, over the block
+    for (int o = 32; o > 0; o >>= 1)
+        dmin = fmin(dmin, __shfl_xor(dmin, o));
+    if (lane == 0)
+        wd[wave] = dmin;
+    __syncthreads();
+    if (tid == 0) {
+        double d = wd[0];
+        for (int w = 1; w < kPoolThreads / 64; ++w)
+            d = fmin(d, wd[w]);
+        out[0] = d > novel_rad ? 1 : 0;
+        out[2] = 0;   // selected[0]
+    }
+    // cost of keyframe 0 as it was when chosen: its distance to the current frame
+    double* cost = (double*)(out + 2 + PG_POOL_MAX);
+    if (tid == 0)
+        cost[0] = sum[0];
+    const int want = K < n_pool ? K : n_pool;
+    for (int n = 1; n < want; ++n) {
+        double bd = INFINITY;
+        int bk = 0x7fffffff;
+#pragma unroll
+        for (int m = 0; m < kPoolPer; ++m) {
+            const int k = tid + kPoolThreads * m;
+            if (!taken[m] && (sum[m] < bd || (sum[m] == bd && k < bk))) {
+                bd = sum[m];
+                bk = k;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double od = __shfl_xor(bd, o);
+            const int ok = __shfl_xor(bk, o);
+            if (od < bd || (od == bd && ok < bk)) {
+                bd = od;
+                bk = ok;
+            }
+        }
+        __syncthreads();   // the previous step's pivot reads are done
+        if (lane == 0) {
+            wd[wave] = bd;
+            wk[wave] = bk;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double d = wd[0];
+            int k = wk[0];
+            for (int w = 1; w < kPoolThreads / 64; ++w)
+                if (wd[w] < d || (wd[w] == d && wk[w] < k)) {
+                    d = wd[w];
+                    k = wk[w];
+                }
+            spick = k;
+            out[2 + n] = k;
+        }
+        __syncthreads();
+        const int pick = spick;
+        if (tid < 16)
+            piv[tid] = T[16 * (size_t)pick + tid];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kPoolPer; ++m) {
+            const int k = tid + kPoolThreads * m;
+            if (k == pick) {
+                taken[m] = true;
+                cost[k] = sum[m];
+            } else if (!taken[m]) {
+                sum[m] += pool_geodesic(T + 16 * (size_t)k, piv);
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < kPoolPer; ++m) {
+        const int k = tid + kPoolThreads * m;
+        if (k < n_pool && !taken[m])
+            cost[k] = sum[m];
+    }
+    if (tid == 0)
+        out[1] = want;
+}
+
 thread_local std::string g_frontend_error;
 
 pg_status ffail(pg_status s, const char* fmt, ...)
@@ -842,6 +973,56 @@ pg_status pg_match_descriptors_noalloc(const float* desc, const int* set_off, in
     e = launch_match(a, dim, n_blocks, (hipStream_t)hip_stream);
     if (e != hipSuccess)
         return ffail(PG_ERR_HIP, "match launch: %s", hipGetErrorString(e));
+    return PG_OK;
+}
+
+pg_status pg_select_keyframes(const double* T_pool, int n_pool, const double* T_cur, int K, double novel_rad,
+                              int* selected, int* n_selected, int* novel, double* cost, void* hip_stream)
+{
+    g_frontend_error.clear();
+    if (!T_pool || !T_cur || !selected || !n_selected || n_pool < 1 || K < 1 || !(novel_rad >= 0.0))
+        return ffail(PG_ERR_INVALID_ARG, "pool, current pose, outputs, n_pool >= 1, K >= 1 and novel_rad >= 0 "
+                                         "are required");
+    if (n_pool > PG_POOL_MAX)
+        return ffail(PG_ERR_CAPACITY, "pool of %d keyframes exceeds %d", n_pool, PG_POOL_MAX);
+    hipStream_t st = (hipStream_t)hip_stream;
+    // device block: the pool and the current pose, then the results (novel,
+    // count, PG_POOL_MAX indices, PG_POOL_MAX costs)
+    const size_t tb = sizeof(double) * 16 * ((size_t)n_pool + 1);
+    const size_t rb = sizeof(int) * (2 + PG_POOL_MAX) + sizeof(double) * PG_POOL_MAX;
+    void* mem = nullptr;
+    hipError_t e = hipMallocAsync(&mem, tb + rb, st);
+    if (e != hipSuccess)
+        return ffail(e == hipErrorOutOfMemory ? PG_ERR_OUT_OF_MEMORY : PG_ERR_HIP, "hipMallocAsync: %s",
+                     hipGetErrorString(e));
+    double* dT = (double*)mem;
+    int* dout = (int*)((char*)mem + tb);
+    e = hipMemcpyAsync(dT, T_pool, sizeof(double) * 16 * n_pool,
+                       on_device(T_pool) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dT + 16 * (size_t)n_pool, T_cur, sizeof(double) * 16,
+                           on_device(T_cur) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        keyframe_select_kernel<<<1, kPoolThreads, 0, st>>>(dT, n_pool, K, novel_rad, dout);
+        e = hipGetLastError();
+    }
+    std::vector<char> res(rb);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(res.data(), dout, rb, hipMemcpyDeviceToHost, st);
+    const hipError_t ef = hipFreeAsync(mem, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess || ef != hipSuccess)
+        return ffail(PG_ERR_HIP, "keyframe selection: %s", hipGetErrorString(e != hipSuccess ? e : ef));
+    const int* ri = (const int*)res.data();
+    const int n = ri[1];
+    if (novel)
+        *novel = ri[0];
+    *n_selected = n;
+    for (int k = 0; k < n && k < K; ++k)
+        selected[k] = ri[2 + k];
+    if (cost)
+        memcpy(cost, res.data() + sizeof(int) * (2 + PG_POOL_MAX), sizeof(double) * n_pool);
     return PG_OK;
 }
 

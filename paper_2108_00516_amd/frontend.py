@@ -51,3 +51,31 @@ def match_descriptors(desc, set_off: Sequence[int], pairs: Sequence[Tuple[int, i
         C.c_void_p(d2.data_ptr()) if d2 is not None else None, C.c_void_p(st))
     _check(rc, "pg_match_descriptors_noalloc" if noalloc else "pg_match_descriptors")
     return match[:n_out], (d1[:n_out] if d1 is not None else None), (d2[:n_out] if d2 is not None else None)
+
+
+def select_keyframes(T_pool, T_cur, K: int = 15, novel_deg: float = 10.0, stream=None):
+    """Greedy keyframe selection and novelty test of the memory pool
+    (Sec. IV-C, IV-E) on the GPU.  T_pool: (n, 4, 4) poses (NumPy, or a CUDA
+    float64 tensor); T_cur: (4, 4).  Returns (selected pool indices in
+    selection order, novel flag, per-keyframe cost sums)."""
+    lib = L.load()
+    Tc = np.ascontiguousarray(T_cur, np.float64).reshape(16)
+    if hasattr(T_pool, "data_ptr"):
+        n = int(T_pool.shape[0])
+        ptr = C.c_void_p(T_pool.data_ptr())
+    else:
+        Tp = np.ascontiguousarray(T_pool, np.float64).reshape(-1, 16)
+        n = Tp.shape[0]
+        ptr = Tp.ctypes.data_as(C.c_void_p)
+    sel = np.zeros(max(K, 1), np.int32)
+    nsel = C.c_int(0)
+    novel = C.c_int(0)
+    cost = np.zeros(max(n, 1))
+    st = None
+    if stream is not None:
+        st = C.c_void_p(stream.cuda_stream)
+    rc = lib.pg_select_keyframes(ptr, n, Tc.ctypes.data_as(C.c_void_p), int(K), float(np.deg2rad(novel_deg)),
+                                 sel.ctypes.data_as(C.c_void_p), C.byref(nsel), C.byref(novel),
+                                 cost.ctypes.data_as(C.c_void_p), st)
+    _check(rc, "pg_select_keyframes")
+    return sel[:nsel.value].copy(), bool(novel.value), cost[:n]
