@@ -46,6 +46,59 @@ def oracle_step(lin, P, fixed):
     return Q
 
 
+def certify_association(name, pg, pb, pairs, poses):
+    """Every GPU/oracle association decision difference at the given poses
+    must be a near-tie of FP32 vs FP64 rounding: a projection within 1e-3 px
+    of a rounding boundary or the image edge, a distance within 1e-6 m of the
+    gate, a normal cosine within 1e-5 of the gate.  Returns the number of
+    differences."""
+    import math
+    cos_gate = math.cos(pb.params.gate_angle)
+    total_diff = 0
+    for (i, j) in pairs:
+        tg, rg, uvg = pg.associate(i, j)
+        to, ro, proj, gate = pb.associate(poses, i, j)
+        diff = tg != to
+        total_diff += int(diff.sum())
+        for x in np.flatnonzero(diff):
+            u, v = proj[x]
+            ok = near_half_integer(u, 1e-3) or near_half_integer(v, 1e-3)
+            ok |= abs(gate[x, 0] - pb.params.gate_dist) <= 1e-6 if np.isfinite(gate[x, 0]) else False
+            ok |= abs(gate[x, 1] - cos_gate) <= 1e-5 if np.isfinite(gate[x, 1]) else False
+            assert ok, f"{name} pair {(i, j)} pixel {x}: gpu {tg[x]} oracle {to[x]} proj {proj[x]} gate {gate[x]}"
+        same = (tg >= 0) & (to >= 0) & ~diff
+        if same.any():
+            assert np.abs(rg[same] - ro[same]).max() < 2e-6
+        both = np.isfinite(uvg[:, 0]) & np.isfinite(proj[:, 0])
+        if both.any():
+            assert np.abs(uvg[both] - proj[both]).max() < 2e-3
+    return total_diff
+
+
+def per_iteration_certified(g, iters=7, **cfg):
+    """The window's Gauss-Newton iterations one at a time: at each iteration's
+    GPU poses every association decision differing from the oracle's is a
+    certified near-tie, the normal equations on the GPU's decisions match the
+    oracle's, and the GPU's step matches the oracle's step from them within
+    1e-6 rad / m.  Returns the total number of certified differences."""
+    pg = gpu_graph(g, gn_iters=1, **cfg)
+    pb = oracle.OracleProblem.from_synth(g)
+    P = pg.poses
+    n_diff = 0
+    for it in range(iters):
+        n_diff += certify_association(f"{g.name} iteration {it}", pg, pb, pb.ordered_pairs(), P)
+        lin = pb.linearize_given(P, gpu_decisions(pg, pb))
+        H, gv, _ = pg.linearize()
+        check_normal_equations(H, gv, lin)
+        Q = oracle_step(lin, P, g.fixed)
+        pg.optimize()
+        P = pg.poses
+        dr, dt = max_pose_diff(P, Q)
+        assert dr <= 1e-6 and dt <= 1e-6, (g.name, it, dr, dt)
+    pg.close()
+    return n_diff
+
+
 def check_normal_equations(H_gpu, g_gpu, lin, tol_h=H_REL_TOL, tol_g=G_REL_TOL):
     H, g = lin["H"], lin["g"]
     rel = np.linalg.norm(H_gpu - H) / np.linalg.norm(H)

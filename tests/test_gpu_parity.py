@@ -10,8 +10,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_helpers import (G_REL_TOL, H_REL_TOL, POSE_TOL_M, POSE_TOL_RAD, check_normal_equations, gpu_decisions,
-                         max_pose_diff, near_half_integer, oracle_step)
+from gpu_helpers import (G_REL_TOL, H_REL_TOL, POSE_TOL_M, POSE_TOL_RAD, certify_association,
+                         check_normal_equations, gpu_decisions, max_pose_diff, near_half_integer, oracle_step)
 
 pytestmark = pytest.mark.gpu
 
@@ -61,29 +61,7 @@ def test_preprocess_parity(name):
 
 
 def certify_assoc(name, g, pg, pb, pairs):
-    """Every GPU/oracle decision difference must be a near-tie of FP32 vs FP64
-    rounding: a projection within 1e-3 px of a rounding boundary or the image
-    edge, a distance within 1e-6 m of the gate, a normal cosine within 1e-5 of
-    the gate."""
-    cos_gate = math.cos(pb.params.gate_angle)
-    total_diff = 0
-    for (i, j) in pairs:
-        tg, rg, uvg = pg.associate(i, j)
-        to, ro, proj, gate = pb.associate(g.poses_init, i, j)
-        diff = tg != to
-        total_diff += int(diff.sum())
-        for x in np.flatnonzero(diff):
-            u, v = proj[x]
-            ok = near_half_integer(u, 1e-3) or near_half_integer(v, 1e-3)
-            ok |= abs(gate[x, 0] - pb.params.gate_dist) <= 1e-6 if np.isfinite(gate[x, 0]) else False
-            ok |= abs(gate[x, 1] - cos_gate) <= 1e-5 if np.isfinite(gate[x, 1]) else False
-            assert ok, f"{name} pair {(i, j)} pixel {x}: gpu {tg[x]} oracle {to[x]} proj {proj[x]} gate {gate[x]}"
-        same = (tg >= 0) & (to >= 0) & ~diff
-        assert np.abs(rg[same] - ro[same]).max() < 2e-6
-        both = np.isfinite(uvg[:, 0]) & np.isfinite(proj[:, 0])
-        assert np.abs(uvg[both] - proj[both]).max() < 2e-3
-        assert (to >= 0).sum() > 0
-    return total_diff
+    return certify_association(name, pg, pb, pairs, g.poses_init)
 
 
 @pytest.mark.parametrize("name,pairs", [("T", [(0, 1), (1, 0), (3, 1)]), ("P", [(0, 1), (3, 7), (9, 2)])])
