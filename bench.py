@@ -33,12 +33,17 @@ TGT_BYTES = 16
 # the feature match sets run in the same launch: two float4 point records per
 # feature match
 FEAT_BYTES = 32
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assoc_paper_window_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2108_00516_amd", "csrc", "pg_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assoc_traffic.json")
+# the association kernel's translation unit and the headers it includes
+ASSOC_SOURCES = [os.path.join(ROOT, "paper_2108_00516_amd", "csrc", f)
+                 for f in ("pg_assoc.hip", "pg_device.hpp", "pg_mlp.hpp", "pg_util.hpp")]
 
 
 def kernel_sha():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ASSOC_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def cpu_model():
@@ -51,16 +56,28 @@ def cpu_model():
     return "unknown"
 
 
-def traffic_entry():
-    """HBM bytes per association launch from the committed counter runs, only
-    while the kernel source is the one they were taken on."""
+def traffic_entry(workload):
+    """HBM bytes per association launch of `workload` from the committed
+    counter runs, only while the kernel source is the one they were taken on."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if t.get("kernel_sha") != kernel_sha():
         return None
-    return t.get("traffic_bytes_per_launch")
+    return t.get("workloads", {}).get(workload, {}).get("traffic_bytes_per_launch")
+
+
+def counter_rate(roof):
+    """Beside the algorithmic rate: the counters' HBM bytes per launch over the
+    same launch time (the association re-reads targets from L2 and the
+    memory-side cache, so its DRAM traffic is below the algorithmic bytes)."""
+    t = roof.get("traffic")
+    if t:
+        rate = t / (roof["avg_launch_us"] * 1e-6) / 1e9
+        roof["traffic_GBps"] = round(rate, 1)
+        roof["traffic_frac"] = round(rate / HBM_PEAK_GBS, 4)
+    return roof
 
 
 def cpu_baseline(g, iters, seconds, P_gpu):
@@ -263,13 +280,14 @@ def main():
         bytes_alg = SRC_BYTES * src + TGT_BYTES * reads0 + FEAT_BYTES * n_feat
         achieved = bytes_alg / avg_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(),
+                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry("paper_window"),
                            "kernel": "assoc_kernel", "avg_launch_us": round(avg_s * 1e6, 3),
                            "launches_timed": args.assoc_reps,
                            "algorithmic_bytes_per_launch": int(bytes_alg),
                            "in_step_avg_launch_us": round(ms_phase[0] / n_launch * 1000.0, 3),
                            "frac_in_step": round(bytes_alg / (ms_phase[0] / n_launch / 1000.0) / 1e9 / HBM_PEAK_GBS,
                                                  4)}
+        counter_rate(out["roofline"])
         out["events_pass"] = {"ms_per_step": round(1000.0 * el_ev / args.steps, 4),
                               "gpu_ms_per_step": {k: round(v / args.steps, 4) for k, v in
                                                   zip(["assoc", "feature", "assemble", "solve", "total"],
@@ -466,6 +484,11 @@ def batch_forms(graphs, iters, steps):
     out["plain_fp32"]["assoc_avg_launch_us"] = round(avg_s * 1e6, 2)
     out["plain_fp32"]["assoc_algorithmic_bytes_per_launch"] = int(bytes_alg)
     out["plain_fp32"]["assoc_algorithmic_GBps"] = round(bytes_alg / avg_s / 1e9, 1)
+    # the counters' HBM bytes: the batch's sources re-read their targets from
+    # L2 and the memory-side cache, so the algorithmic rate can pass the HBM peak
+    traffic = traffic_entry("batch64")
+    out["plain_fp32"]["assoc_hbm_bytes_per_launch"] = traffic
+    out["plain_fp32"]["assoc_hbm_GBps"] = round(traffic / avg_s / 1e9, 1) if traffic else None
     for name, kw in [("bf16x3", dict(precision=_lib.PG_PREC_BF16X3)),
                      ("learned_bf16x3", dict(weighting=_lib.PG_WEIGHT_LEARNED, prune_frac=0.25,
                                              precision=_lib.PG_PREC_BF16X3))]:
@@ -568,8 +591,10 @@ def run_batch(args, graphs):
         bytes_alg = SRC_BYTES * src + TGT_BYTES * reads + FEAT_BYTES * n_feat
         achieved = bytes_alg / avg_s / 1e9
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "assoc_kernel",
+                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry("batch64"),
+                           "kernel": "assoc_kernel",
                            "avg_launch_us": round(avg_s * 1e6, 3), "algorithmic_bytes_per_launch": int(bytes_alg)}
+        counter_rate(out["roofline"])
         out["events_pass"] = {"gpu_ms_per_step": {k: round(v / args.steps, 4) for k, v in
                                                   zip(["assoc", "feature", "assemble", "solve", "total"], ms)}}
     print(json.dumps(out), flush=True)

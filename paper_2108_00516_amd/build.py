@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libposegraph.so")
-SOURCES = ["pg_kernels.hip", "pg_host.hip", "pg_mlp.hip", "pg_frontend.hip"]
+SOURCES = ["pg_assoc.hip", "pg_solve.hip", "pg_host.hip", "pg_mlp.hip", "pg_frontend.hip"]
 ARCH = "gfx950"
 
 
