@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-events", action="store_true", help="time without per-kernel events")
     ap.add_argument("--no-forms", action="store_true", help="skip the learned / BF16x3 forms")
+    ap.add_argument("--forms", default="window,pcg,X,B",
+                    help="forms to run: window (learned / BF16x3 on the window), pcg (matrix-free PCG), "
+                         "X (20-keyframe window), B (64-window batch)")
     ap.add_argument("--assoc-reps", type=int, default=200, help="back-to-back association launches timed")
     ap.add_argument("--workload", choices=["paper", "batch"], default="paper",
                     help="paper: the 10-keyframe 640x480 window (the headline); batch: 64 uneven windows "
@@ -172,7 +175,8 @@ def main():
     from paper_2108_00516_amd import Config, from_synth
 
     graphs = None
-    if args.workload == "batch" or not args.no_forms:
+    forms = set() if args.no_forms else set(f for f in args.forms.split(",") if f)
+    if args.workload == "batch" or "B" in forms:
         # scene generation in forked CPU workers, before this process touches
         # the GPU; the workers finish and exit on their own (close + join)
         if args.gen_workers > 1:
@@ -297,11 +301,14 @@ def main():
         out["cpu_baseline"] = cb
         out["max_pose_diff_vs_oracle"] = {"rad": dr, "m": dt}
     pg.close()
-    if not args.no_forms:
-        out["forms"] = other_forms(g, iters, P_gpu, min(args.steps, 50), args.tile)
-        out["forms"]["pcg_matrix_free"] = matrix_free_form(g, iters, P_gpu, min(args.steps, 20))
-        out["forms"]["window_X"] = window_x_form(iters, min(args.steps, 20))
-        out["forms"]["batch_B"] = batch_forms(batch_graphs, iters, min(args.steps, 10))
+    if forms:
+        out["forms"] = other_forms(g, iters, P_gpu, min(args.steps, 50), args.tile) if "window" in forms else {}
+        if "pcg" in forms:
+            out["forms"]["pcg_matrix_free"] = matrix_free_form(g, iters, P_gpu, min(args.steps, 20))
+        if "X" in forms:
+            out["forms"]["window_X"] = window_x_form(iters, min(args.steps, 20))
+        if "B" in forms:
+            out["forms"]["batch_B"] = batch_forms(batch_graphs, iters, min(args.steps, 10))
     print(json.dumps(out), flush=True)
 
 

@@ -289,6 +289,13 @@ pg_status prepare_graph(pg_graph* g)
             break;
         default: g->solver = ldl_fits ? kSolverLDL : gj_fits ? kSolverGaussJordan : kSolverCholesky; break;
         }
+        // the LDS kernel runs every optimisation's transforms prologue (and
+        // the Cholesky/PCG solve) with this graph's packed layout: creation
+        // checked it for one fixed node, a window with fewer must fit as well
+        const size_t lds = solve_lds_bytes(g->n_free, N);
+        if (lds > (size_t)g->lds_limit)
+            return fail(g, PG_ERR_CAPACITY, "%d free nodes need %zu B of LDS for the solve, the limit is %d B",
+                        g->n_free, lds, g->lds_limit);
     }
     // learned weighting: each frame keeps its n_src - floor(frac * n_src)
     // best-scored source pixels; the counts are known here, the choice is

@@ -335,6 +335,23 @@ def test_abi_errors_on_gpu():
     pg.close()  # destroy is NULL-safe / idempotent in the binding
 
 
+def test_window_without_fixed_node_beyond_lds_is_refused():
+    """32 frames with none fixed: 192 unknowns, whose packed solve layout
+    exceeds the workgroup's LDS; the optimisation is refused with a capacity
+    status before any launch and the poses are left as they were."""
+    from paper_2108_00516_amd import Camera, Config, PoseGraph, PoseGraphError, _lib
+    g = graph("T")
+    say("32 free frames: LDS capacity")
+    pg = PoseGraph(Camera(g.width, g.height, g.fx, g.fy, g.cx, g.cy), Config(max_frames=32))
+    for k in range(32):
+        pg.add_frame(g.depth[k % g.n_frames], g.mask[k % g.n_frames], g.poses_init[k % g.n_frames])
+    with pytest.raises(PoseGraphError) as e:
+        pg.optimize()
+    assert e.value.status == _lib.PG_ERR_CAPACITY
+    assert np.array_equal(pg.poses[:g.n_frames], g.poses_init)
+    pg.close()
+
+
 @pytest.mark.parametrize("use_graph", [0, 1])
 def test_zero_iterations_and_continuation(use_graph):
     """Zero iterations return the start poses (no solve runs, the result block
