@@ -21,6 +21,20 @@
 
 namespace pg {
 
+// Stores through global-address pointers (the graph's pointers are generic in
+// C++): global stores, which LDS waits do not count.
+template <typename T>
+__device__ __forceinline__ void st_global(T* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
+__device__ __forceinline__ void st_global_f4(float* p, float x, float y, float z, float w)
+{
+    pg_f4v v = {x, y, z, w};
+    *(__attribute__((address_space(1))) pg_f4v*)p = v;
+}
+
 // --------------------------------------------------- FP64 normal equations
 
 // 6x6 adjoint of A = [R t] for twists [v; w]: [[R, [t]x R], [0, R]]
@@ -72,7 +86,7 @@ __device__ __forceinline__ double sum_records(const float* __restrict__ src, int
 #pragma unroll
         for (int k = 0; k < kSumBatch; ++k) {
             const int tk = (t + k < t1) ? t + k : t1 - 1;
-            const float x = src[(size_t)tk * kDenseStride];
+            const float x = ld_global(src + (size_t)tk * kDenseStride);
             v[k] = (t + k < t1) ? (double)x : 0.0;
         }
 #pragma unroll
@@ -104,10 +118,11 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
     const GraphDev& gd = gds[nb.x];
     // the reads of phase 1 are in bounds whatever the status holds: it is
     // loaded with them and tested before anything is written
-    const int status = *gd.status;
+    const int status = ld_global(gd.status);
     const int I = nb.y & 0xff, J = (nb.y >> 8) & 0xff;
     const int N = gd.n_frames, n6 = 6 * N;
-    const int fI = gd.free_pos[I], fJ = gd.free_pos[J];   // free-node positions (-1: fixed)
+    // free-node positions (-1: fixed)
+    const int fI = ld_global(gd.free_pos + I), fJ = ld_global(gd.free_pos + J);
     const int nf1 = 6 * gd.n_free + 1;                       // row length of the free-node system
     const bool diag = (I == J);
     const int np = diag ? 2 * (N - 1) : 2;       // pairs summed
@@ -155,7 +170,7 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
             int i, j;
             pair_of(k, i, j);
             const int p = pair_index(i, j, N);
-            const int b0 = gd.pair_base[p], b1 = gd.pair_base[p + 1];
+            const int b0 = ld_global(gd.pair_base + p), b1 = ld_global(gd.pair_base + p + 1);
             if (diag) {
                 S[k][f] = sum_records(gd.partials + f, b0, b1);
             } else {
@@ -168,12 +183,12 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
             const int q = task - n_sum, pk = q / 12;
             int i, j;
             pair_of(kt0 + pk, i, j);
-            AX[pk][q % 12] = gd.xf64[12 * pair_index(i, j, N) + q % 12];
+            AX[pk][q % 12] = ld_global(gd.xf64 + 12 * pair_index(i, j, N) + q % 12);
         } else {
             const int q = task - n_sum - n_ax;
             const int K = diag ? q / 22 : J, e0 = diag ? q % 22 : q;
             double v0 = 0.0, v1 = 0.0;
-            const int s = (K != I) ? gd.set_of[I * N + K] : -1;
+            const int s = (K != I) ? ld_global(gd.set_of + I * N + K) : -1;
             if (s >= 0) {
                 // the entries of both orientations depend only on the set: all
                 // loaded at once from computed (in-bounds) indices, the one of
@@ -187,9 +202,10 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
                     return (e < 36) ? sym12_index(o + e / 6, o + e % 6) : (e < 42) ? 78 + o + (e - 36) : 90 + (e - 42);
                 };
                 const int e1 = diag ? e0 + 22 : e0;
-                const double a0 = F[index(e0, 0)], b0 = F[index(e0, 6)];
-                const double a1 = F[index(e1, 0)], b1 = F[index(e1, 6)];
-                const bool first = gd.fsets[s].x == I;   // loaded after the entries
+                const double a0 = ld_global(F + index(e0, 0)), b0 = ld_global(F + index(e0, 6));
+                const double a1 = ld_global(F + index(e1, 0)), b1 = ld_global(F + index(e1, 6));
+                // loaded after the entries
+                const bool first = ld_global((const int*)(gd.fsets + s)) == I;
                 v0 = first ? a0 : b0;                        // diagonal e0 < 22: an H entry
                 v1 = first ? a1 : ((e1 < 42) ? b1 : 0.0);
             }
@@ -312,13 +328,19 @@ __global__ __launch_bounds__(kAsmThreads) void assemble_kernel(const GraphDev* _
 
 constexpr int kSolveThreads = 512;
 
-// SE(3) exponential of [v; w] (Rodrigues and the left Jacobian V), 4x4 row-major
-__device__ void se3_exp(const double* xi, double* T)
+// Entry (r, c) of Exp(x) T for one node (x = [v; w], T its pose, 4x4
+// row-major): row r of Exp(x) is [I + a K + b K^2 | (I + b K + c K^2) v]
+// (Rodrigues and the left Jacobian, K = [w]x, K^2 = w w^T - |w|^2 I), row 3 is
+// (0, 0, 0, 1); times column c of T.
+__device__ __forceinline__ double se3_exp_entry(const double* __restrict__ xi, const double* __restrict__ T, int r,
+                                                int c)
 {
+    const double t0 = T[c], t1 = T[4 + c], t2 = T[8 + c], t3 = T[12 + c];
+    const double v0 = xi[0], v1 = xi[1], v2 = xi[2];
     const double w0 = xi[3], w1 = xi[4], w2 = xi[5];
     const double th2 = w0 * w0 + w1 * w1 + w2 * w2;
     // a = sin t / t, b = (1 - cos t) / t^2, c = (t - sin t) / t^3
-    double a, b, c;
+    double a, b, cc;
     if (th2 < 0.25) {
         // |t| < 0.5 (every Gauss-Newton step in practice): Taylor series in
         // t^2 through t^16, truncation below 1e-22; no cancellation
@@ -327,30 +349,25 @@ __device__ void se3_exp(const double* xi, double* T)
             (1.0 - x * (1.0 / 110) * (1.0 - x * (1.0 / 156) * (1.0 - x * (1.0 / 210) * (1.0 - x * (1.0 / 272))))))));
         b = 0.5 * (1.0 - x * (1.0 / 12) * (1.0 - x * (1.0 / 30) * (1.0 - x * (1.0 / 56) * (1.0 - x * (1.0 / 90) *
             (1.0 - x * (1.0 / 132) * (1.0 - x * (1.0 / 182) * (1.0 - x * (1.0 / 240) * (1.0 - x * (1.0 / 306)))))))));
-        c = (1.0 / 6) * (1.0 - x * (1.0 / 20) * (1.0 - x * (1.0 / 42) * (1.0 - x * (1.0 / 72) * (1.0 - x * (1.0 / 110) *
-            (1.0 - x * (1.0 / 156) * (1.0 - x * (1.0 / 210) * (1.0 - x * (1.0 / 272) * (1.0 - x * (1.0 / 342)))))))));
+        cc = (1.0 / 6) * (1.0 - x * (1.0 / 20) * (1.0 - x * (1.0 / 42) * (1.0 - x * (1.0 / 72) * (1.0 - x * (1.0 / 110) *
+             (1.0 - x * (1.0 / 156) * (1.0 - x * (1.0 / 210) * (1.0 - x * (1.0 / 272) * (1.0 - x * (1.0 / 342)))))))));
     } else {
         const double th = sqrt(th2), sn = sin(th), cs = cos(th);
         a = sn / th;
         b = (1.0 - cs) / th2;
-        c = (th - sn) / (th2 * th);
+        cc = (th - sn) / (th2 * th);
     }
-    const double K[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
-    double K2[9];
-    for (int r = 0; r < 3; ++r)
-        for (int s = 0; s < 3; ++s)
-            K2[3 * r + s] = K[3 * r] * K[s] + K[3 * r + 1] * K[3 + s] + K[3 * r + 2] * K[6 + s];
-    for (int r = 0; r < 3; ++r) {
-        double t = 0.0;
-        for (int s = 0; s < 3; ++s) {
-            const double I = (r == s) ? 1.0 : 0.0;
-            T[4 * r + s] = I + a * K[3 * r + s] + b * K2[3 * r + s];
-            t += (I + b * K[3 * r + s] + c * K2[3 * r + s]) * xi[s];
-        }
-        T[4 * r + 3] = t;
-    }
-    T[12] = T[13] = T[14] = 0.0;
-    T[15] = 1.0;
+    // row r of K and of K^2 (r < 3; row 3 is selected at the end)
+    const double k0 = (r == 0) ? 0.0 : (r == 1) ? w2 : -w1;
+    const double k1 = (r == 0) ? -w2 : (r == 1) ? 0.0 : w0;
+    const double k2 = (r == 0) ? w1 : (r == 1) ? -w0 : 0.0;
+    const double wr = (r == 0) ? w0 : (r == 1) ? w1 : w2;
+    const double i0 = (r == 0) ? 1.0 : 0.0, i1 = (r == 1) ? 1.0 : 0.0, i2 = (r == 2) ? 1.0 : 0.0;
+    const double q0 = wr * w0 - i0 * th2, q1 = wr * w1 - i1 * th2, q2 = wr * w2 - i2 * th2;
+    const double e0 = i0 + a * k0 + b * q0, e1 = i1 + a * k1 + b * q1, e2 = i2 + a * k2 + b * q2;
+    const double e3 = (i0 + b * k0 + cc * q0) * v0 + (i1 + b * k1 + cc * q1) * v1 + (i2 + b * k2 + cc * q2) * v2;
+    const double out = e0 * t0 + e1 * t1 + e2 * t2 + e3 * t3;
+    return (r == 3) ? t3 : out;
 }
 
 // Block barrier that orders LDS only: waits for the thread's own LDS (and
@@ -364,61 +381,83 @@ __device__ __forceinline__ void lds_barrier()
 }
 
 // A = T_i T_j^-1, B = T_j T_i^-1 per ordered pair (FP64, stored FP32 and
-// FP64), and T^-1 = [R^T | -R^T t] per node (FP64), from the poses in LDS:
-// one thread per row of a node's inverse, then one per row of A or B.  The
-// translation of A is t_i + R_i (-R_j^T t_j), from the nodes' inverse
-// translations of the first pass.  Every thread of the block takes part (one
-// barrier).
-__device__ void compute_transforms(const GraphDev& gd, const double* __restrict__ Ts)
+// FP64), and T^-1 = [R^T | -R^T t] per node (FP64), from the poses in LDS,
+// one thread per row: rows 0 .. 3N-1 are the nodes' inverses, then six per
+// pair (three of A, three of B).  Row r of T_a T_b^-1 is
+// [R_a(r) R_b^T | t_a(r) + R_a(r) (-R_b^T t_b)].  No barrier: every row reads
+// the poses only, so all rows of a thread load together.
+constexpr int kTfPer = 3;   // rows per thread and pass
+
+__device__ __forceinline__ double sel3(int r, double x0, double x1, double x2)
 {
-    __shared__ double su[3 * kMaxFrames];   // -R^T t per node
+    return (r == 0) ? x0 : (r == 1) ? x1 : x2;
+}
+
+__device__ __forceinline__ void compute_transforms(const GraphDev& gd, const double* __restrict__ Ts)
+{
     const int N = gd.n_frames;
-    for (int q = threadIdx.x; q < 3 * N; q += blockDim.x) {
-        const int node = q / 3, r = q - 3 * node;
-        const double* T = Ts + 16 * node;
-        const double u = -(T[r] * T[3] + T[4 + r] * T[7] + T[8 + r] * T[11]);
-        double* dst = gd.tinv64 + 12 * node + 4 * r;
-        dst[0] = T[r];
-        dst[1] = T[4 + r];
-        dst[2] = T[8 + r];
-        dst[3] = u;
-        su[q] = u;
-    }
-    lds_barrier();
+    const int np = N * (N - 1);
+    const int n_inv = 3 * N, total = n_inv + 6 * np;
     // pair p = i (N - 1) + jj: i from a float reciprocal (exact: the
     // fraction (jj + 1/2) / (N - 1) stays at least 1/62 from an integer)
     const float inv = 1.0f / (float)max(N - 1, 1);
-    const int np = N * (N - 1);
-    for (int e = threadIdx.x; e < 6 * np; e += blockDim.x) {
-        const int p = e / 6, w = e - 6 * p;
-        const int i = (int)(((float)p + 0.5f) * inv), jj = p - i * (N - 1), j = (jj < i) ? jj : jj + 1;
-        const bool isA = w < 3;   // rows of A, then of B = T_j T_i^-1
-        const int r = isA ? w : w - 3;
-        const double* Ta = Ts + 16 * (isA ? i : j);
-        const int nb = isA ? j : i;
-        const double* Tb = Ts + 16 * nb;
-        const double a0 = Ta[4 * r], a1 = Ta[4 * r + 1], a2 = Ta[4 * r + 2];
-        double v[4];
+    for (int base = 0; base < total; base += kTfPer * (int)blockDim.x) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            v[c] = a0 * Tb[4 * c] + a1 * Tb[4 * c + 1] + a2 * Tb[4 * c + 2];
-        v[3] = Ta[4 * r + 3] + (a0 * su[3 * nb] + a1 * su[3 * nb + 1] + a2 * su[3 * nb + 2]);
-        float* d32 = gd.xf32 + 24 * p + (isA ? 0 : 12) + 4 * r;
-        *(float4*)d32 = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
-        if (isA) {
-            double* d64 = gd.xf64 + 12 * p + 4 * r;
+        for (int u = 0; u < kTfPer; ++u) {
+            const int e = base + u * (int)blockDim.x + (int)threadIdx.x;
+            if (e >= total)
+                continue;
+            const bool tinv = e < n_inv;
+            const int f = tinv ? 0 : e - n_inv;
+            const int p = f / 6, w = f - 6 * p;
+            const int i = (int)(((float)p + 0.5f) * inv), jj = p - i * (N - 1), j = (jj < i) ? jj : jj + 1;
+            const bool isA = w < 3;   // rows of A, then of B = T_j T_i^-1
+            const int node = e / 3;
+            const int r = tinv ? e - 3 * node : (isA ? w : w - 3);
+            const double* Ta = Ts + 16 * (tinv ? node : (isA ? i : j));
+            const double* Tb = Ts + 16 * (tinv ? node : (isA ? j : i));
+            const double a0 = Ta[4 * r], a1 = Ta[4 * r + 1], a2 = Ta[4 * r + 2], a3 = Ta[4 * r + 3];
+            double bm[12];
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                d64[c] = v[c];
+            for (int k = 0; k < 12; ++k)
+                bm[k] = Tb[k];
+            double su[3];   // -R_b^T t_b
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                su[k] = -(bm[k] * bm[3] + bm[4 + k] * bm[7] + bm[8 + k] * bm[11]);
+            if (tinv) {
+                double* dst = gd.tinv64 + 12 * node + 4 * r;
+                st_global(dst, sel3(r, bm[0], bm[1], bm[2]));
+                st_global(dst + 1, sel3(r, bm[4], bm[5], bm[6]));
+                st_global(dst + 2, sel3(r, bm[8], bm[9], bm[10]));
+                st_global(dst + 3, sel3(r, su[0], su[1], su[2]));
+                continue;
+            }
+            double v[4];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                v[c] = a0 * bm[4 * c] + a1 * bm[4 * c + 1] + a2 * bm[4 * c + 2];
+            v[3] = a3 + (a0 * su[0] + a1 * su[1] + a2 * su[2]);
+            st_global_f4(gd.xf32 + 24 * p + (isA ? 0 : 12) + 4 * r, (float)v[0], (float)v[1], (float)v[2],
+                         (float)v[3]);
+            if (isA) {
+                double* d64 = gd.xf64 + 12 * p + 4 * r;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    st_global(d64 + c, v[c]);
+            }
         }
     }
 }
 
 // T_q <- Exp(x_q) T_q for the free nodes q (x: 6 per free node, Ts: the
 // poses, both in LDS), 16 threads per node, one entry each; then the new
-// poses in LDS and in the graph.  Every thread of the block takes part (two
-// barriers); at least 256 threads.
-__device__ void update_poses(const GraphDev& gd, const double* __restrict__ xs, const int* __restrict__ sfree,
+// poses in LDS and in the graph.  A node's 16 entries are read and written by
+// 16 consecutive threads of one wavefront, whose writes wait for all their
+// reads (each written value depends on the entry's whole column), so only
+// the final barrier is needed.  Every thread of the block takes part; at
+// least 256 threads.
+__device__ __forceinline__ void update_poses(const GraphDev& gd, const double* __restrict__ xs, const int* __restrict__ sfree,
                              double* __restrict__ Ts)
 {
     static_assert(16 * kMaxFrames <= 2 * 256, "pose update: two entries per thread");
@@ -433,24 +472,16 @@ __device__ void update_poses(const GraphDev& gd, const double* __restrict__ xs, 
         if (e < 16 * nf) {
             const int q = e >> 4, r = (e >> 2) & 3, c = e & 3;
             const int node = sfree[q];
-            double E[16];
-            se3_exp(xs + 6 * q, E);
-            const double* T = Ts + 16 * node;
-            const double t0 = T[c], t1 = T[4 + c], t2 = T[8 + c], t3 = T[12 + c];
-            double row[4];   // entry (rr, c) of E T for every row rr (constant register indices)
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
-                row[rr] = E[4 * rr] * t0 + E[4 * rr + 1] * t1 + E[4 * rr + 2] * t2 + E[4 * rr + 3] * t3;
-            tn[u] = (r & 2) ? ((r & 1) ? row[3] : row[2]) : ((r & 1) ? row[1] : row[0]);
+            tn[u] = se3_exp_entry(xs + 6 * q, Ts + 16 * node, r, c);
             at[u] = 16 * node + (e & 15);
         }
     }
-    lds_barrier();
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int u = 0; u < 2; ++u)
         if (at[u] >= 0) {
             Ts[at[u]] = tn[u];
-            gd.poses[at[u]] = tn[u];
+            st_global(gd.poses + at[u], tn[u]);
         }
     lds_barrier();
 }
@@ -1039,9 +1070,10 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd, double* __restrict
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int m = lane >> 4, c = lane & 15;
-    const int it = *gd.iters_done;
-    const int status = *gd.status;
-    const double maxdiag = __longlong_as_double((long long)*gd.maxdiag);   // written by the assembly
+    const int it = ld_global(gd.iters_done);
+    const int status = ld_global(gd.status);
+    // written by the assembly
+    const double maxdiag = __longlong_as_double((long long)ld_global(gd.maxdiag));
     if (wave == 0) {
         // the upper tiles of the padded system, every load issued first from
         // a clamped (always valid) address; padding pivots equal the largest
@@ -1074,7 +1106,7 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd, double* __restrict
                 }
         if (status == 0 && n > 0 && n <= kM - 4) {
             const double tol = 1e-12 * maxdiag;
-            bool singular = !(maxdiag > 0.0);
+            int singular = (maxdiag > 0.0) ? 0 : 1;
             const bool odd = (m & 1) != 0, hi2 = (m & 2) != 0, mid = (m == 1) || (m == 2);
 #pragma unroll
             for (int s = 0; s < kSteps; ++s) {
@@ -1117,8 +1149,12 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd, double* __restrict
                 const double f00 = p00 - fma(e00, w00, e01 * w01);
                 const double f01 = p01 - fma(e00, w10, e01 * w11);
                 const double f11 = p11 - fma(e10, w10, e11 * w11);
-                // the scalar pivots d00, detP / d00, s00, detS / s00 all exceed tol
-                singular |= !((d00 > tol) && (detP > tol * d00) && (s00 > tol) && (detS > tol * s00));
+                // the scalar pivots d00, detP / d00, s00, detS / s00 all exceed
+                // tol; tested here, beside the step's matrix instructions (the
+                // empty asm keeps the test from sinking to the end of the loop,
+                // where the 15 steps' tests would run one after another)
+                singular |= ((d00 > tol) && (detP > tol * d00) && (s00 > tol) && (detS > tol * s00)) ? 0 : 1;
+                asm volatile("" : "+v"(singular));
                 // row m of D^-1 at columns m, m ^ 1, m ^ 2, m ^ 3 (D^-1 symmetric)
                 const double dq0 = hi2 ? (odd ? z11 : z00) : (odd ? f11 : f00);
                 const double dq1 = hi2 ? z01 : f01;
@@ -1199,14 +1235,14 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd, double* __restrict
         double tv[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
-            tv[r] = (u + 192 * r < 16 * N) ? gd.poses[u + 192 * r] : 0.0;
-        const int fv = (u < gd.n_free) ? gd.free_ids[u] : 0;
+            tv[r] = (u + 192 * r < 16 * N) ? ld_global(gd.poses + u + 192 * r) : 0.0;
+        const int fv = (u < gd.n_free) ? ld_global(gd.free_ids + u) : 0;
         if (u < kNodeStats && status == 0) {
             const int src = (u < 2) ? 1 - u : u;
             double s = 0.0;
             for (int k = 0; k < N; ++k)
-                s += gd.node_stats[kNodeStats * k + src];
-            gd.iter_stats[kIterRecord * it + u] = s;
+                s += ld_global(gd.node_stats + kNodeStats * k + src);
+            st_global(gd.iter_stats + kIterRecord * it + u, s);
         }
 #pragma unroll
         for (int r = 0; r < 3; ++r)
@@ -1222,20 +1258,20 @@ __device__ __forceinline__ void ldl_solve(const GraphDev& gd, double* __restrict
     // every thread has used the diagonal maximum by now: cleared for the
     // next iteration's assembly
     if (tid == 0)
-        *gd.maxdiag = 0ull;
+        st_global(gd.maxdiag, 0ull);
     if (n == 0) {
         if (tid == 0)
-            *gd.iters_done = it + 1;
+            st_global(gd.iters_done, it + 1);
         return;
     }
     if (flags) {
         if (tid == 0)
-            *gd.status |= (flags & 1) ? kStatusSingular : kStatusNonFinite;
+            st_global(gd.status, status | ((flags & 1) ? kStatusSingular : kStatusNonFinite));
         return;
     }
     update_poses(gd, xs, sfree, Ts);
     if (tid == 0)
-        *gd.iters_done = it + 1;
+        st_global(gd.iters_done, it + 1);
     compute_transforms(gd, Ts);
 }
 
