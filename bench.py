@@ -341,7 +341,8 @@ def other_forms(g, iters, P_plain, steps, tile):
     for name, kw in [("learned", dict(weighting=_lib.PG_WEIGHT_LEARNED, prune_frac=0.25)),
                      ("bf16x3", dict(precision=_lib.PG_PREC_BF16X3)),
                      ("learned_bf16x3", dict(weighting=_lib.PG_WEIGHT_LEARNED, prune_frac=0.25,
-                                             precision=_lib.PG_PREC_BF16X3))]:
+                                             precision=_lib.PG_PREC_BF16X3)),
+                     ("persistent_association", dict(persistent=1))]:
         pg = from_synth(g, Config(max_frames=g.n_frames, gn_iters=iters, tile_pixels=tile, **kw),
                         device_inputs=True)
         if kw.get("weighting") == _lib.PG_WEIGHT_LEARNED:
@@ -363,6 +364,9 @@ def other_forms(g, iters, P_plain, steps, tile):
                      "source_pixels_per_iteration": int(st["src_pixels"]),
                      "max_pose_diff_vs_plain": {"rad": dr, "m": dt}, "meets_1e-4": bool(dr <= 1e-4 and dt <= 1e-4),
                      "error_vs_ground_truth": gt_err(P)}
+        if name == "persistent_association":
+            res[name]["poses_equal_plain"] = bool(np.array_equal(P, P_plain))
+            res[name]["assoc_us_per_launch"] = round(1000 * pg.time_assoc(200), 3)
         pg.close()
     return res
 
@@ -496,6 +500,22 @@ def batch_forms(graphs, iters, steps):
     traffic = traffic_entry("batch64")
     out["plain_fp32"]["assoc_hbm_bytes_per_launch"] = traffic
     out["plain_fp32"]["assoc_hbm_GBps"] = round(traffic / avg_s / 1e9, 1) if traffic else None
+    # the same batch replayed as one captured hipGraph, and with one tile
+    # (1024 pixels) for every window instead of the tuned per-class tiles
+    from paper_2108_00516_amd import autotune
+    shipped = autotune.load(autotune.TABLE_PATH)
+    out["plain_fp32"]["tiles"] = sorted({f"{g.width}x{g.height}/{g.n_frames}": autotune.lookup(
+        shipped, g.width, g.height, g.n_frames, 1024) for g in graphs}.items())
+    for name, kw in [("graph_replay", dict(use_graph=1)), ("uniform_tile_1024", dict(tile_pixels=1024)),
+                     ("persistent_association", dict(persistent=1))]:
+        pgs = build(**kw)
+        el2, _ = timed(pgs)
+        same = all(np.array_equal(pg.poses, P0) for pg, P0 in zip(pgs, plain))
+        for pg in pgs:
+            pg.close()
+        out[name] = {"graph_gn_iters_per_s": round(iters * len(graphs) * steps / el2, 2),
+                     "ms_per_step": round(1000 * el2 / steps, 4), "speedup_vs_plain": round(el / el2, 3),
+                     "poses_equal_plain": bool(same) if name != "uniform_tile_1024" else None}
     for name, kw in [("bf16x3", dict(precision=_lib.PG_PREC_BF16X3)),
                      ("learned_bf16x3", dict(weighting=_lib.PG_WEIGHT_LEARNED, prune_frac=0.25,
                                              precision=_lib.PG_PREC_BF16X3))]:
@@ -556,13 +576,34 @@ def run_batch(args, graphs):
         return time.perf_counter() - t0, launches, ms, reads, src
 
     if args.autotune:
+        # per window class: its largest window alone with every tile; then the
+        # best single tile for the whole batch (recorded, not used by the library)
         from paper_2108_00516_amd import autotune
+        log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+
+        def make_one(g, tile):
+            return ([from_synth(g, Config(max_frames=g.n_frames, gn_iters=iters, tile_pixels=tile),
+                                device_inputs=True)], [g.poses_init])
 
         def make(tile):
             return ([from_synth(g, Config(max_frames=g.n_frames, gn_iters=iters, tile_pixels=tile),
                                 device_inputs=True) for g in graphs], [g.poses_init for g in graphs])
-        table = autotune.tune({autotune.BATCH_KEY: make}, steps=5,
-                              log=lambda m: print(m, file=sys.stderr, flush=True))
+        # a batch runs at the largest pixels per thread of its graphs, so the
+        # classes are tuned among the tiles that share the best uniform tile's
+        table = autotune.tune({autotune.BATCH_KEY: make}, steps=5, log=log)
+        best = table[autotune.BATCH_KEY]["tile"]
+        same = [t for t in autotune.TILES if autotune.pixels_per_thread(t) == autotune.pixels_per_thread(best)]
+        table.update(autotune.tune_classes(graphs, make_one, tiles=same, steps=10, log=log))
+        # the batch with the class tiles against the uniform tile
+        autotune.apply(table)
+        t_cls = autotune.time_optimize(lambda t: make(0), 0, steps=5)
+        t_uni = autotune.time_optimize(make, best, steps=5)
+        table[autotune.BATCH_KEY]["check_ms"] = {"class_tiles": round(t_cls, 4), "uniform": round(t_uni, 4)}
+        if t_cls > t_uni:
+            # no gain in the batch: every class takes the uniform tile
+            for k in table:
+                if k != autotune.BATCH_KEY:
+                    table[k]["tile"] = best
         autotune.save(table, args.autotune)
         print(json.dumps(table), flush=True)
         return

@@ -94,8 +94,11 @@ typedef struct {
     int precision;              /* PG_PREC_FP32 (default) or PG_PREC_BF16X3                  */
     int use_graph;              /* 1 = replay the iteration loop as a captured hipGraph (0)  */
     int timing;                 /* 1 = HIP events around each kernel, launched directly (0)  */
-    int tile_pixels;            /* source pixels per association work item, 0 = library pick */
+    int tile_pixels;            /* source pixels per association work item (rounded up to a multiple
+                                   of 256, at most 2048); 0 = the tile table's, else 1024 */
     double prune_frac;          /* learned weighting: fraction of source pixels dropped (0.25) */
+    int persistent;             /* 1 = persistent association blocks drain the work table through
+                                   atomic counters (0: one block per work item); same results */
 } pg_config;
 
 /* Per-optimize statistics. */
@@ -215,6 +218,16 @@ pg_status pose_graph_set_mlp(pg_graph *g, const void *fp16_params, size_t n_byte
  * Errors: PG_ERR_INVALID_ARG. */
 pg_status pose_graph_pair_features(pg_graph *g, int i, int j, int iteration, float *features,
                                    float *sigma, int32_t *target);
+
+/* Tuned association tiles (project addition: the tile autotuner's table).
+ * entries: n_entries (0..256) records of 5 ints {width, height, min_frames,
+ * max_frames, tile_pixels} in host memory, copied; tile_pixels a multiple of
+ * 256 in 256..2048.  A graph whose cfg.tile_pixels is 0 takes the tile of the
+ * first record matching its resolution and node count (else 1024) when its
+ * schedule is next built; each graph of a batch keeps its own tile.  Replaces
+ * the previous table (n_entries 0 clears it); process-wide, thread-safe.
+ * Errors: PG_ERR_INVALID_ARG (message in pose_graph_last_error(NULL)). */
+pg_status pg_set_tile_table(const int *entries, int n_entries);
 
 /* Timing of the dense association kernel alone at the current poses (for
  * roofline figures): after one untimed launch, reps (1..10000) launches of

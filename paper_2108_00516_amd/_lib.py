@@ -42,7 +42,7 @@ class pg_config(C.Structure):
                 ("gate_dist_m", C.c_double), ("gate_normal_rad", C.c_double),
                 ("solver", C.c_int), ("pcg_max_iters", C.c_int), ("pcg_rel_tol", C.c_double),
                 ("weighting", C.c_int), ("precision", C.c_int), ("use_graph", C.c_int), ("timing", C.c_int),
-                ("tile_pixels", C.c_int), ("prune_frac", C.c_double)]
+                ("tile_pixels", C.c_int), ("prune_frac", C.c_double), ("persistent", C.c_int)]
 
 
 class pg_stats(C.Structure):
@@ -76,6 +76,7 @@ SIGNATURES = {
     "pose_graph_pair_features": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, _vp]),
     "pose_graph_prune": (C.c_int, [_vp, _vp, _vp]),
     "pose_graph_time_assoc": (C.c_int, [_vp, C.c_int, _dp]),
+    "pg_set_tile_table": (C.c_int, [_vp, C.c_int]),
     "pg_mlp_create": (C.c_int, [C.c_int, _vp, C.POINTER(_vp)]),
     "pg_mlp_destroy": (None, [_vp]),
     "pg_mlp_set_params": (C.c_int, [_vp, _vp]),
@@ -122,4 +123,9 @@ def load(path: str = LIB_PATH):
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    # the tuned association tiles shipped with the package
+    from . import autotune
+    table = autotune.load(autotune.TABLE_PATH)
+    if table:
+        autotune.apply(table, lib)
     return lib

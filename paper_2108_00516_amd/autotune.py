@@ -1,11 +1,14 @@
 """Tile-size autotuner of the association kernel.
 
 The association work item is one ordered keyframe pair times a tile of the
-source frame's valid-pixel list (256 threads x 1, 2, 4 or 8 pixels).  The best
-tile depends on the resolution and the number of keyframes (how many items a
-launch has to fill 256 CUs with).  This module times whole optimisations on
-the GPU for each candidate tile and keeps a JSON table keyed by
-"<width>x<height>/<node bucket>", which Config.tile_pixels can be filled from.
+source frame's valid-pixel list (a multiple of 256 pixels, run by 256 threads
+with 1, 2, 4 or 8 pixels each).  The best tile depends on the resolution and
+the number of keyframes (how many items a launch has to fill 256 CUs with).
+This module times whole optimisations on the GPU for each candidate tile and
+keeps a JSON table keyed by "<width>x<height>/<node bucket>".  The table
+shipped beside this module is handed to the library when it is loaded
+(pg_set_tile_table): a graph whose Config.tile_pixels is 0 takes its class's
+tile, and every graph of a batch keeps its own.
 """
 from __future__ import annotations
 
@@ -14,7 +17,8 @@ import os
 import time
 from typing import Callable, Dict, Iterable, Optional, Sequence
 
-TILES = (256, 512, 1024, 2048)
+TILES = (256, 512, 768, 1024, 1536, 2048)
+TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_tiles.json")
 BATCH_KEY = "batch"   # table key of a whole batched schedule (one tile for every window)
 NODE_BUCKETS = ((2, 7), (8, 11), (12, 15), (16, 32))
 
@@ -84,3 +88,62 @@ def lookup(table: Dict[str, dict], width: int, height: int, n_frames: int, defau
     """Tuned tile for a window (0 = the library's own choice)."""
     e = table.get(bucket_key(width, height, n_frames))
     return int(e["tile"]) if e else default
+
+
+def parse_key(key: str):
+    """(width, height, min_frames, max_frames) of a class key, or None (the
+    batch key and unbounded buckets)."""
+    try:
+        res, bucket = key.split("/")
+        w, h = (int(x) for x in res.split("x"))
+        lo, hi = (int(x) for x in bucket.split("-"))
+    except ValueError:
+        return None
+    return w, h, lo, hi
+
+
+def table_entries(table: Dict[str, dict]):
+    """The library's records {width, height, min_frames, max_frames, tile}
+    of every class entry of a table."""
+    out = []
+    for key in sorted(table):
+        k = parse_key(key)
+        if k is not None:
+            out.append((*k, int(table[key]["tile"])))
+    return out
+
+
+def apply(table: Dict[str, dict], lib=None) -> int:
+    """Hand a table's class entries to the library; returns their count."""
+    import ctypes as C
+
+    from . import _lib
+    lib = lib or _lib.load()
+    ent = table_entries(table)
+    arr = (C.c_int * (5 * max(len(ent), 1)))(*[v for e in ent for v in e])
+    rc = lib.pg_set_tile_table(arr, len(ent))
+    if rc != 0:
+        raise RuntimeError(f"pg_set_tile_table: {lib.pose_graph_last_error(None).decode()}")
+    return len(ent)
+
+
+def pixels_per_thread(tile: int) -> int:
+    """Pixels per thread of the kernel that runs a tile (as the library picks)."""
+    p = -(-tile // 256)
+    for q in (1, 2, 4, 8):
+        if q >= p:
+            return q
+    return 8
+
+
+def tune_classes(graphs: Sequence, make: Callable[[object, int], Sequence], tiles: Iterable[int] = TILES,
+                 steps: int = 10, log: Optional[Callable[[str], None]] = print) -> Dict[str, dict]:
+    """One entry per class of `graphs` (their resolution and node bucket):
+    the class's largest window is optimised alone with every tile
+    (make(window, tile) -> (graphs, start poses)) and the fastest kept."""
+    rep = {}
+    for g in graphs:
+        key = bucket_key(g.width, g.height, g.n_frames)
+        if key not in rep or g.n_frames > rep[key].n_frames:
+            rep[key] = g
+    return tune({key: (lambda t, w=w: make(w, t)) for key, w in sorted(rep.items())}, tiles, steps, log)

@@ -391,23 +391,8 @@ __device__ __forceinline__ int wave_sum32_f32(float (&acc)[32], int lane)
 // 8) walks a contiguous run of the item list, which is ordered source tile
 // first: the items that re-read one source tile share an L2.
 template <int PPT, bool LEARNED>
-__global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __restrict__ gds,
-                                                              const WorkItem* __restrict__ items, int n_items,
-                                                              int per_xcd, int iteration,
-                                                              const int2* __restrict__ fitems, int n_fitems)
+__device__ __forceinline__ void assoc_item(const GraphDev* __restrict__ gds, const WorkItem it, int iteration)
 {
-    // the first blocks (a multiple of 8) take the feature match sets
-    const int nf8 = (n_fitems + 7) & ~7;
-    if ((int)blockIdx.x < nf8) {
-        if ((int)blockIdx.x < n_fitems)
-            feature_set(gds, fitems[blockIdx.x]);
-        return;
-    }
-    const int b = blockIdx.x - nf8;
-    const int L = (b & 7) * per_xcd + (b >> 3);
-    if (L >= n_items)
-        return;
-    const WorkItem it = items[L];
     const int gid = it.gij >> 16, i = it.gij & 0xff, j = (it.gij >> 8) & 0xff;
     const GraphDev& gd = gds[gid];
     // the graph status is loaded with the first reads and tested before the
@@ -535,6 +520,26 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __
     }
 }
 
+template <int PPT, bool LEARNED>
+__global__ __launch_bounds__(kAssocThreads) void assoc_kernel(const GraphDev* __restrict__ gds,
+                                                              const WorkItem* __restrict__ items, int n_items,
+                                                              int per_xcd, int iteration,
+                                                              const int2* __restrict__ fitems, int n_fitems)
+{
+    // the first blocks (a multiple of 8) take the feature match sets
+    const int nf8 = (n_fitems + 7) & ~7;
+    if ((int)blockIdx.x < nf8) {
+        if ((int)blockIdx.x < n_fitems)
+            feature_set(gds, fitems[blockIdx.x]);
+        return;
+    }
+    const int b = blockIdx.x - nf8;
+    const int L = (b & 7) * per_xcd + (b >> 3);
+    if (L >= n_items)
+        return;
+    assoc_item<PPT, LEARNED>(gds, items[L], iteration);
+}
+
 // ------------------------------------------- BF16x3 split-precision MFMA form
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -551,23 +556,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // 8 (l / 16) .. 8 (l / 16) + 7 of a 32-pixel half.  Energy and counts stay on
 // the VALU.  The partial record has the same layout as assoc_kernel's.
 template <int PPT, bool LEARNED>
-__global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const GraphDev* __restrict__ gds,
-                                                                     const WorkItem* __restrict__ items,
-                                                                     int n_items, int per_xcd, int iteration,
-                                                                     const int2* __restrict__ fitems, int n_fitems)
+__device__ __forceinline__ void assoc_bf16x3_item(const GraphDev* __restrict__ gds, const WorkItem it, int iteration)
 {
-    // the first blocks (a multiple of 8) take the feature match sets
-    const int nf8 = (n_fitems + 7) & ~7;
-    if ((int)blockIdx.x < nf8) {
-        if ((int)blockIdx.x < n_fitems)
-            feature_set(gds, fitems[blockIdx.x]);
-        return;
-    }
-    const int b = blockIdx.x - nf8;
-    const int L = (b & 7) * per_xcd + (b >> 3);
-    if (L >= n_items)
-        return;
-    const WorkItem it = items[L];
     const int gid = it.gij >> 16, i = it.gij & 0xff, j = (it.gij >> 8) & 0xff;
     const GraphDev& gd = gds[gid];
     // the graph status is loaded with the first reads and tested before the
@@ -717,6 +707,73 @@ __global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const Graph
         for (int w = 1; w < kAssocThreads / 64; ++w)
             v += red[w][threadIdx.x];
         gd.partials[(size_t)it.slot * kDenseStride + threadIdx.x] = v;
+    }
+}
+
+template <int PPT, bool LEARNED>
+__global__ __launch_bounds__(kAssocThreads) void assoc_bf16x3_kernel(const GraphDev* __restrict__ gds,
+                                                                     const WorkItem* __restrict__ items,
+                                                                     int n_items, int per_xcd, int iteration,
+                                                                     const int2* __restrict__ fitems, int n_fitems)
+{
+    // the first blocks (a multiple of 8) take the feature match sets
+    const int nf8 = (n_fitems + 7) & ~7;
+    if ((int)blockIdx.x < nf8) {
+        if ((int)blockIdx.x < n_fitems)
+            feature_set(gds, fitems[blockIdx.x]);
+        return;
+    }
+    const int b = blockIdx.x - nf8;
+    const int L = (b & 7) * per_xcd + (b >> 3);
+    if (L >= n_items)
+        return;
+    assoc_bf16x3_item<PPT, LEARNED>(gds, items[L], iteration);
+}
+
+// Persistent form: a fixed grid of association blocks (bpx for each of the 8
+// runs of the item list, after the feature blocks) drains the work table.
+// Block b of run x = b mod 8 first takes item b / 8 of its run, then claims
+// the run's later items one at a time from the run's counter (which starts at
+// bpx); each claim is issued when the block starts its current item, so its
+// round trip overlaps the item's work.  Which block runs an item does not
+// change its result (each item writes its own partial record, summed later in
+// a fixed order); the last block to finish clears the counters for the next
+// launch, so a captured graph replays it with no memory set.  ctr: 8 run
+// counters and a count of finished blocks, zero at launch.
+template <int PPT, bool LEARNED, bool BF16>
+__global__ __launch_bounds__(kAssocThreads) void assoc_persistent_kernel(
+    const GraphDev* __restrict__ gds, const WorkItem* __restrict__ items, int n_items, int per_xcd,
+    int iteration, const int2* __restrict__ fitems, int n_fitems, unsigned* __restrict__ ctr, int n_blocks)
+{
+    const int nf8 = (n_fitems + 7) & ~7;
+    if ((int)blockIdx.x < nf8) {
+        if ((int)blockIdx.x < n_fitems)
+            feature_set(gds, fitems[blockIdx.x]);
+        return;
+    }
+    const int b = (int)blockIdx.x - nf8;
+    const int x = b & 7, bpx = n_blocks / 8;
+    __shared__ int s_next;
+    int k = b >> 3;   // index within the run of this block's current item
+    for (;;) {
+        const int L = x * per_xcd + k;
+        if (k >= per_xcd || L >= n_items)
+            break;
+        if (threadIdx.x == 0)
+            s_next = bpx + (int)atomicAdd(ctr + x, 1u);   // the next claim, in flight during the item
+        if constexpr (BF16)
+            assoc_bf16x3_item<PPT, LEARNED>(gds, items[L], iteration);
+        else
+            assoc_item<PPT, LEARNED>(gds, items[L], iteration);
+        __syncthreads();
+        k = s_next;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(ctr + 8, 1u) == (unsigned)(n_blocks - 1))
+            for (int q = 0; q < 9; ++q)
+                atomicExch(ctr + q, 0u);
     }
 }
 
@@ -1391,10 +1448,29 @@ int assoc_ppt_supported(int ppt) { return ppt == 1 || ppt == 2 || ppt == 4 || pp
 
 template <bool LEARNED>
 static void launch_assoc_t(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision,
-                           int iteration, const int2* fitems, int n_fitems, hipStream_t st)
+                           int iteration, const int2* fitems, int n_fitems, unsigned* ctr, int blocks_per_xcd,
+                           hipStream_t st)
 {
     const int per_xcd = (n_items + 7) / 8;
-    const int grid = ((n_fitems + 7) & ~7) + 8 * per_xcd;
+    const int nf8 = (n_fitems + 7) & ~7;
+    if (ctr && n_items > 0) {
+        const int bpx = std::max(1, std::min(blocks_per_xcd, per_xcd));
+        const int grid = nf8 + 8 * bpx;
+#define PG_PERSIST_LAUNCH(P, B)                                                                            \
+    assoc_persistent_kernel<P, LEARNED, B><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd,    \
+                                                                          iteration, fitems, n_fitems, ctr, \
+                                                                          8 * bpx)
+        const bool bf = precision == 1;
+        switch (ppt) {
+        case 1: if (bf) PG_PERSIST_LAUNCH(1, true); else PG_PERSIST_LAUNCH(1, false); break;
+        case 2: if (bf) PG_PERSIST_LAUNCH(2, true); else PG_PERSIST_LAUNCH(2, false); break;
+        case 8: if (bf) PG_PERSIST_LAUNCH(8, true); else PG_PERSIST_LAUNCH(8, false); break;
+        default: if (bf) PG_PERSIST_LAUNCH(4, true); else PG_PERSIST_LAUNCH(4, false); break;
+        }
+#undef PG_PERSIST_LAUNCH
+        return;
+    }
+    const int grid = nf8 + 8 * per_xcd;
 #define PG_ASSOC_LAUNCH(K)                                                                                  \
     switch (ppt) {                                                                                          \
     case 1: K<1, LEARNED><<<grid, kAssocThreads, 0, st>>>(gds, items, n_items, per_xcd, iteration, fitems, n_fitems); break;  \
@@ -1411,14 +1487,45 @@ static void launch_assoc_t(const GraphDev* gds, const WorkItem* items, int n_ite
 }
 
 void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision, bool learned,
-                  int iteration, const int2* fitems, int n_fitems, hipStream_t st)
+                  int iteration, const int2* fitems, int n_fitems, unsigned* ctr, int blocks_per_xcd,
+                  hipStream_t st)
 {
     if (n_items <= 0 && n_fitems <= 0)
         return;
     if (learned)
-        launch_assoc_t<true>(gds, items, n_items, ppt, precision, iteration, fitems, n_fitems, st);
+        launch_assoc_t<true>(gds, items, n_items, ppt, precision, iteration, fitems, n_fitems, ctr,
+                             blocks_per_xcd, st);
     else
-        launch_assoc_t<false>(gds, items, n_items, ppt, precision, iteration, fitems, n_fitems, st);
+        launch_assoc_t<false>(gds, items, n_items, ppt, precision, iteration, fitems, n_fitems, ctr,
+                              blocks_per_xcd, st);
+}
+
+// Resident blocks per XCD of the persistent association kernel for these
+// settings (occupancy x compute units / 8), 0 if unknown.
+int assoc_persistent_blocks(int ppt, int precision, bool learned)
+{
+    const void* k = nullptr;
+    const bool bf = precision == 1;
+#define PG_K(P)                                                                                               \
+    k = learned ? (bf ? (const void*)assoc_persistent_kernel<P, true, true>                                  \
+                      : (const void*)assoc_persistent_kernel<P, true, false>)                                \
+                : (bf ? (const void*)assoc_persistent_kernel<P, false, true>                                 \
+                      : (const void*)assoc_persistent_kernel<P, false, false>)
+    switch (ppt) {
+    case 1: PG_K(1); break;
+    case 2: PG_K(2); break;
+    case 8: PG_K(8); break;
+    default: PG_K(4); break;
+    }
+#undef PG_K
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kAssocThreads, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return per_cu * cus / 8;
 }
 
 void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int iteration, int* target, float* r,

@@ -26,7 +26,9 @@ void launch_match_points(const float* di, const uint8_t* mi, const float* dj, co
                          const float* uvi, const float* uvj, int n, float4* out, hipStream_t st);
 int assoc_ppt_supported(int ppt);
 void launch_assoc(const GraphDev* gds, const WorkItem* items, int n_items, int ppt, int precision, bool learned,
-                  int iteration, const int2* fitems, int n_fitems, hipStream_t st);
+                  int iteration, const int2* fitems, int n_fitems, unsigned* ctr, int blocks_per_xcd,
+                  hipStream_t st);
+int assoc_persistent_blocks(int ppt, int precision, bool learned);
 void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int iteration, int* target, float* r,
                         float* uv, float* feat, float* sigma, hipStream_t st);
 void launch_prune(const GraphDev* gds, const WorkItem* pitems, int n_pitems, const int2* pframes, int n_pframes,
@@ -99,6 +101,9 @@ struct Schedule {
     size_t mf_lds = 0;    // dynamic LDS of the matrix-free solve
     int precision = 0;    // PG_PREC_* of every graph of the schedule
     int gj_slots = 1;   // widest Gauss-Jordan system (columns) of the schedule (1 if none)
+    bool persistent = false;   // persistent association blocks draining the work table
+    int persist_bpx = 0;       //   their count per XCD
+    DevBuf ctr;                //   8 run counters and a finished-block count (zero between launches)
     hipGraphExec_t exec = nullptr;
     std::vector<hipEvent_t> events;   // timing: start, then 5 per iteration
     ~Schedule()
@@ -234,19 +239,43 @@ hipError_t copy_in(void* dst, const void* src, size_t bytes, hipStream_t st)
                           st);
 }
 
+// Tuned association tiles by window class (resolution, node-count range),
+// set with pg_set_tile_table; consulted when a graph's tile_pixels is 0.
+struct TileClass {
+    int width, height, lo, hi, tile;
+};
+std::mutex g_tile_mutex;
+std::vector<TileClass> g_tile_table;
+constexpr int kTileTableMax = 256;
+
+int table_tile(int width, int height, int n_frames)
+{
+    std::lock_guard<std::mutex> lk(g_tile_mutex);
+    for (const TileClass& e : g_tile_table)
+        if (e.width == width && e.height == height && e.lo <= n_frames && n_frames <= e.hi)
+            return e.tile;
+    return 0;
+}
+
+// Source pixels per work item (a multiple of 256, at most kTileMaxPixels) and
+// the pixels per thread of the kernel that runs it (1, 2, 4 or 8: the
+// smallest whose 256-thread block covers the tile).  A batch runs with the
+// largest pixels per thread of its graphs; a shorter item leaves the slots
+// past its end empty, so every graph keeps its own tile.
 int pick_tile(const pg_graph* g, int* ppt)
 {
     int t = g->cfg.tile_pixels;
     if (t <= 0)
+        t = table_tile(g->cam.width, g->cam.height, g->n_frames);
+    if (t <= 0)
         t = 1024;
-    // tile = 256 threads x PPT pixels
+    t = std::min(std::max(t, kAssocThreads), kTileMaxPixels);
+    t = (t + kAssocThreads - 1) / kAssocThreads * kAssocThreads;
     int p = t / kAssocThreads;
-    if (p < 1)
-        p = 1;
-    if (!assoc_ppt_supported(p))
-        p = (p >= 8) ? 8 : (p >= 4) ? 4 : (p >= 2) ? 2 : 1;
+    while (!assoc_ppt_supported(p))
+        ++p;
     *ppt = p;
-    return p * kAssocThreads;
+    return t;
 }
 
 // (Re)build the graph's tables and device state for the current frames/matches.
@@ -522,11 +551,12 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
             s.learned = g->learned;
         } else if (g->learned != s.learned) {
             return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must use one weighting");
-        } else if (p != ppt) {
-            return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must use one tile size");
         } else if (g->cfg.precision != s.precision) {
             return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must use one precision");
+        } else if ((g->cfg.persistent != 0) != (g0->cfg.persistent != 0)) {
+            return fail(g0, PG_ERR_INVALID_ARG, "graphs of a batch must share the persistent setting");
         }
+        ppt = std::max(ppt, p);
         devs.push_back(make_dev(g));
         for (const WorkItem& w : g->items) {
             WorkItem v = w;
@@ -589,6 +619,16 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
     HIP_OR_FAIL(g0, s.pitems.ensure(sizeof(WorkItem) * std::max<size_t>(pitems.size(), 1)));
     HIP_OR_FAIL(g0, s.pframes.ensure(sizeof(int2) * std::max<size_t>(pframes.size(), 1)));
     hipStream_t st = g0->stream;
+    // persistent association: as many blocks as stay resident, counters
+    // zeroed here once (the kernel clears them after every launch)
+    s.persistent = g0->cfg.persistent != 0;
+    if (s.persistent) {
+        s.persist_bpx = assoc_persistent_blocks(ppt, s.precision, s.learned);
+        if (s.persist_bpx <= 0)
+            s.persist_bpx = 32;
+        HIP_OR_FAIL(g0, s.ctr.ensure(sizeof(unsigned) * 9));
+        HIP_OR_FAIL(g0, hipMemsetAsync(s.ctr.p, 0, sizeof(unsigned) * 9, st));
+    }
     HIP_OR_FAIL(g0, hipMemcpyAsync(s.gds.p, devs.data(), sizeof(GraphDev) * devs.size(), hipMemcpyHostToDevice, st));
     if (!items.empty())
         HIP_OR_FAIL(g0, hipMemcpyAsync(s.items.p, items.data(), sizeof(WorkItem) * items.size(),
@@ -635,7 +675,8 @@ hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std
         if (m && (e = hipEventRecord(m[1], st)) != hipSuccess)
             return e;
         launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, it,
-                     s.fitems.as<int2>(), s.n_fitems, st);
+                     s.fitems.as<int2>(), s.n_fitems, s.persistent ? s.ctr.as<unsigned>() : nullptr,
+                     s.persist_bpx, st);
         if (m && (e = hipEventRecord(m[2], st)) != hipSuccess)
             return e;
         if (!s.mf)
@@ -821,6 +862,8 @@ pg_status pose_graph_create(const pg_config* cfg, const pg_camera* cam, void* hi
         return fail(nullptr, PG_ERR_INVALID_ARG, "unknown precision");
     if (cfg->tile_pixels < 0 || cfg->tile_pixels > kTileMaxPixels)
         return fail(nullptr, PG_ERR_INVALID_ARG, "tile_pixels out of range");
+    if (cfg->persistent != 0 && cfg->persistent != 1)
+        return fail(nullptr, PG_ERR_INVALID_ARG, "persistent must be 0 or 1");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
         (void)hipGetLastError();
@@ -1089,7 +1132,7 @@ pg_status pose_graph_linearize(pg_graph* g, double* H, double* grad, pg_stats* s
     launch_solve(gds, 1, s.lds, 1, st);
     launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, st);
     launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, s.fitems.as<int2>(),
-                 s.n_fitems, st);
+                 s.n_fitems, s.persistent ? s.ctr.as<unsigned>() : nullptr, s.persist_bpx, st);
     launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
     HIP_OR_FAIL(g, hipGetLastError());
     const int N = g->n_frames;
@@ -1224,6 +1267,24 @@ pg_status pose_graph_pair_features(pg_graph* g, int i, int j, int iteration, flo
     return PG_OK;
 }
 
+pg_status pg_set_tile_table(const int* entries, int n_entries)
+{
+    if (n_entries < 0 || n_entries > kTileTableMax || (n_entries > 0 && !entries))
+        return fail(nullptr, PG_ERR_INVALID_ARG, "tile table: 0..%d entries of 5 ints", kTileTableMax);
+    std::vector<TileClass> t;
+    for (int k = 0; k < n_entries; ++k) {
+        const int* e = entries + 5 * k;
+        const TileClass c{e[0], e[1], e[2], e[3], e[4]};
+        if (c.width <= 0 || c.height <= 0 || c.lo < 1 || c.hi < c.lo || c.tile < kAssocThreads ||
+            c.tile > kTileMaxPixels || c.tile % kAssocThreads != 0)
+            return fail(nullptr, PG_ERR_INVALID_ARG, "tile table entry %d invalid", k);
+        t.push_back(c);
+    }
+    std::lock_guard<std::mutex> lk(g_tile_mutex);
+    g_tile_table.swap(t);
+    return PG_OK;
+}
+
 pg_status pose_graph_time_assoc(pg_graph* g, int reps, double* ms_per_launch)
 {
     if (!g)
@@ -1238,7 +1299,7 @@ pg_status pose_graph_time_assoc(pg_graph* g, int reps, double* ms_per_launch)
     launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, g->stream);
     // one untimed launch, then reps back-to-back launches between two events
     launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, s.fitems.as<int2>(),
-                 s.n_fitems, g->stream);
+                 s.n_fitems, s.persistent ? s.ctr.as<unsigned>() : nullptr, s.persist_bpx, g->stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OR_FAIL(g, hipEventCreate(&e0));
     hipError_t e = hipEventCreate(&e1);
@@ -1246,7 +1307,7 @@ pg_status pose_graph_time_assoc(pg_graph* g, int reps, double* ms_per_launch)
         e = hipEventRecord(e0, g->stream);
     for (int k = 0; k < reps && e == hipSuccess; ++k) {
         launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, s.fitems.as<int2>(),
-                     s.n_fitems, g->stream);
+                     s.n_fitems, s.persistent ? s.ctr.as<unsigned>() : nullptr, s.persist_bpx, g->stream);
         e = hipGetLastError();
     }
     if (e == hipSuccess)

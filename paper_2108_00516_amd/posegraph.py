@@ -42,6 +42,7 @@ class Config:
     timing: int = 0
     tile_pixels: int = 0
     prune_frac: float = 0.25
+    persistent: int = 0
 
     def to_c(self) -> L.pg_config:
         c = L.pg_config()

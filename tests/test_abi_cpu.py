@@ -126,3 +126,32 @@ def test_match_argument_errors_without_a_device(lib):
     assert lib.pg_match_descriptors(*args(1, 100, 1.0)) == _lib.PG_ERR_INVALID_ARG
     assert lib.pg_match_descriptors(*args(1, 128, -1.0)) == _lib.PG_ERR_INVALID_ARG
     assert lib.pg_frontend_last_error()
+
+
+def test_tile_table_argument_checks(lib):
+    """pg_set_tile_table validates every record (positive resolution, a
+    node range, a tile that is a multiple of 256 in 256..2048) and the count,
+    before anything changes; a valid table and an empty one are accepted."""
+    from paper_2108_00516_amd import _lib, autotune
+
+    def call(rows):
+        arr = (C.c_int * (5 * max(len(rows), 1)))(*[v for r in rows for v in r])
+        return lib.pg_set_tile_table(arr, len(rows))
+    try:
+        assert call([(640, 480, 8, 11, 768), (320, 240, 2, 7, 256)]) == 0
+        for bad in [(0, 480, 8, 11, 768), (640, 480, 0, 11, 768), (640, 480, 9, 8, 768),
+                    (640, 480, 8, 11, 700), (640, 480, 8, 11, 128), (640, 480, 8, 11, 2304)]:
+            assert call([bad]) == _lib.PG_ERR_INVALID_ARG, bad
+            assert b"tile table" in lib.pose_graph_last_error(None)
+        assert lib.pg_set_tile_table(None, 1) == _lib.PG_ERR_INVALID_ARG
+        assert lib.pg_set_tile_table(None, 257) == _lib.PG_ERR_INVALID_ARG
+        assert lib.pg_set_tile_table(None, 0) == 0
+        # the class keys of the autotuner's table map onto the records
+        assert autotune.table_entries({"640x480/8-11": {"tile": 768}, "batch": {"tile": 1024},
+                                       "320x240/other": {"tile": 512}}) == [(640, 480, 8, 11, 768)]
+    finally:
+        table = autotune.load(autotune.TABLE_PATH)
+        if table:
+            autotune.apply(table, lib)
+        else:
+            lib.pg_set_tile_table(None, 0)

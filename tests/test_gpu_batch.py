@@ -238,3 +238,96 @@ def test_batched_forms_equal_single_runs(form):
         assert np.array_equal(pg.poses, single[k]), k
         assert stats[k]["iters_done"] == 7
         pg.close()
+
+
+def test_tile_table_gives_each_graph_its_tile():
+    """A tile table with a different tile per window class: graphs with
+    tile_pixels 0 take their class's tile (the result equals an explicit
+    tile_pixels run bit for bit), and one batch of windows with tiles of 256,
+    512, 768 and 1024 pixels (one launch with the largest pixels per thread,
+    shorter items leaving slots empty) equals their single runs bit for bit."""
+    from paper_2108_00516_amd import _lib, autotune, optimize_batch
+    lib = _lib.load()
+    # four window classes: 160x120 with 3 and with 8 keyframes, 120x90, 80x60
+    graphs = small_uneven()[:3] + [synth.make_graph("T", seed=6, n_frames=8)]
+    tiles = [256, 512, 768, 1024]
+    table = {autotune.bucket_key(g.width, g.height, g.n_frames): {"tile": t} for g, t in zip(graphs, tiles)}
+    assert len(table) == 4
+    say("tile table: " + ", ".join(f"{k} -> {v['tile']}" for k, v in sorted(table.items())))
+    try:
+        autotune.apply(table, lib)
+        single = []
+        for g, t in zip(graphs, tiles):
+            pg = gpu_graph(g)
+            pg.optimize()
+            single.append(pg.poses)
+            pg.close()
+            ref = gpu_graph(g, tile_pixels=t)
+            ref.optimize()
+            assert np.array_equal(ref.poses, single[-1]), t
+            ref.close()
+        pgs = [gpu_graph(g) for g in graphs]
+        rc, stats = optimize_batch(pgs)
+        assert rc == 0
+        for k, pg in enumerate(pgs):
+            assert np.array_equal(pg.poses, single[k]), k
+            assert stats[k]["iters_done"] == 7
+            pg.close()
+        # against the oracle as well: the tile changes only the order of the sums
+        Po, _ = oracle.OracleProblem.from_synth(graphs[2]).optimize(graphs[2].poses_init, 7)
+        dr, dt = max_pose_diff(single[2], Po)
+        assert dr <= POSE_TOL_RAD and dt <= POSE_TOL_M
+    finally:
+        shipped = autotune.load(autotune.TABLE_PATH)
+        if shipped:
+            autotune.apply(shipped, lib)
+        else:
+            lib.pg_set_tile_table(None, 0)
+
+
+def test_persistent_association_equals_one_shot():
+    """The persistent association (a fixed grid draining the work table
+    through per-run atomic counters) gives the one-block-per-item results bit
+    for bit: the 10-keyframe 640x480 window alone, after back-to-back timing
+    launches (the counters clear themselves after every launch), replayed as
+    a captured graph three times, and a batch of uneven windows against their
+    single runs."""
+    from paper_2108_00516_amd import optimize_batch
+    g = synth.make_graph("P")
+    say("persistent association: 10-keyframe window")
+    ref = gpu_graph(g)
+    ref.optimize()
+    P0 = ref.poses
+    ref.close()
+    pg = gpu_graph(g, persistent=1)
+    pg.optimize()
+    assert np.array_equal(pg.poses, P0)
+    ms = pg.time_assoc(20)
+    say(f"  persistent association {1000 * ms:.2f} us per launch")
+    pg.set_poses(g.poses_init)
+    pg.optimize()
+    assert np.array_equal(pg.poses, P0)
+    pg.close()
+    pr = gpu_graph(g, persistent=1, use_graph=1)
+    for rep in range(3):
+        pr.set_poses(g.poses_init)
+        pr.optimize()
+        assert np.array_equal(pr.poses, P0), rep
+    pr.close()
+    graphs = small_uneven()
+    single = []
+    for x in graphs:
+        p1 = gpu_graph(x)
+        p1.optimize()
+        single.append(p1.poses)
+        p1.close()
+    pgs = [gpu_graph(x, persistent=1) for x in graphs]
+    for rep in range(2):
+        for p1, x in zip(pgs, graphs):
+            p1.set_poses(x.poses_init)
+        rc, _ = optimize_batch(pgs)
+        assert rc == 0
+        for k, p1 in enumerate(pgs):
+            assert np.array_equal(p1.poses, single[k]), (rep, k)
+    for p1 in pgs:
+        p1.close()
