@@ -43,12 +43,14 @@ def _pairs(n: int) -> List[Tuple[int, int]]:
 
 
 def collect(windows: Iterable[Tuple[object, np.ndarray]], iters: int = 7, inlier_m: float = 0.003,
-            config: Optional[Config] = None, sample_frac: float = 1.0, seed: int = 0):
+            config: Optional[Config] = None, sample_frac: float = 1.0, seed: int = 0, max_pairs: int = 0):
     """Samples of (features (n, 6), labels (n,)) as float32 device tensors.
 
     windows: (SynthGraph with leaky masks, reference poses (N, 4, 4)).
     Features are taken at the first `iters` iterates of the plain optimiser;
-    sample_frac < 1 keeps a seeded random subset of each pair's samples."""
+    sample_frac < 1 keeps a seeded random subset of each pair's samples;
+    max_pairs > 0 takes a seeded subset of that many ordered pairs of a larger
+    window (the same pairs at every iterate)."""
     import torch
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
@@ -63,16 +65,20 @@ def collect(windows: Iterable[Tuple[object, np.ndarray]], iters: int = 7, inlier
         hw = g.width * g.height
         f = torch.empty((hw, 6), dtype=torch.float32, device="cuda")
         t = torch.empty(hw, dtype=torch.int32, device="cuda")
+        pairs = _pairs(g.n_frames)
+        if 0 < max_pairs < len(pairs):
+            pick = np.random.default_rng([seed, g.n_frames, 17]).choice(len(pairs), max_pairs, replace=False)
+            pairs = [pairs[q] for q in sorted(pick)]
         # reference association per ordered pair
         fg.set_poses(ref)
         good = {}
-        for (i, j) in _pairs(g.n_frames):
+        for (i, j) in pairs:
             fg.pair_features(i, j, 0, out=(f, None, t))
             good[(i, j)] = (t >= 0) & (f[:, 0].abs() * cfg.huber_g_m < inlier_m)
         P = np.array(g.poses_init)
         for k in range(iters):
             fg.set_poses(P)
-            for (i, j) in _pairs(g.n_frames):
+            for (i, j) in pairs:
                 fg.pair_features(i, j, k, out=(f, None, t))
                 sel = t >= 0
                 if sample_frac < 1.0:
@@ -125,12 +131,76 @@ def reference_poses(g_clean, config: Optional[Config] = None) -> np.ndarray:
     return P
 
 
-def _training_window(k: int):
-    """k-th training window: a 4-keyframe 160x120 scene (seed 10000 + k) with
-    its true masks and with masks grown by k mod 6 pixels."""
+def _training_window(k: int, large_every: int = 0):
+    """k-th training window (seed 10000 + k) with its true masks and with
+    masks grown by k mod 6 pixels: the 20-keyframe 640x480 shape ('L') for
+    every large_every-th k (none for 0), else a 4-keyframe 160x120 scene."""
     import synth
     seed = 10_000 + k
-    return synth.make_graph("T", seed=seed), synth.make_graph("T", seed=seed, mask_dilate=k % 6)
+    preset = "L" if large_every > 0 and k % large_every == 0 else "T"
+    return synth.make_graph(preset, seed=seed), synth.make_graph(preset, seed=seed, mask_dilate=k % 6)
+
+
+def _evaluation_window(k: int):
+    """k-th evaluation window (seed 20000 + k, held out from training), masks
+    grown by 4 pixels: the 10-keyframe 640x480 shape for every 5th k, else a
+    4-keyframe 160x120 scene."""
+    import synth
+    return synth.make_graph("P" if k % 5 == 0 else "T", seed=20_000 + k, mask_dilate=4)
+
+
+def pose_error_rad(Ta: np.ndarray, Tb: np.ndarray) -> float:
+    """Rotation angle between two poses' rotations (radians)."""
+    c = (np.trace(Ta[:3, :3] @ Tb[:3, :3].T) - 1.0) / 2.0
+    return float(np.arccos(np.clip(c, -1.0, 1.0)))
+
+
+def evaluate(p16: np.ndarray, n: int = 100, workers: int = 16, prune_frac: float = 0.25, log=print) -> dict:
+    """Plain and learned optimisation of the held-out windows of seeds 20000 ..
+    20000 + n - 1: per window shape, the mean and median over the windows of
+    each form's largest rotation error against the ground truth, of the
+    learned form's largest pose difference to the plain one, and the count of
+    windows where the learned form is closer to the ground truth."""
+    import multiprocessing as mp
+    import os
+
+    import torch
+
+    from . import _lib as L2
+    res = {}
+    with mp.get_context("fork").Pool(max(1, min(workers, os.cpu_count() or 1))) as pool:
+        torch.cuda.set_device(0)
+        for g in pool.imap(_evaluation_window, range(n), chunksize=2):
+            out = {}
+            for kind in ("plain", "learned"):
+                cfg = Config(max_frames=g.n_frames)
+                if kind == "learned":
+                    cfg = Config(max_frames=g.n_frames, weighting=L2.PG_WEIGHT_LEARNED, prune_frac=prune_frac)
+                pg = from_synth(g, cfg, device_inputs=True)
+                if kind == "learned":
+                    pg.set_mlp(p16)
+                pg.optimize(check=False)
+                out[kind] = pg.poses
+                pg.close()
+            e = {k: max(pose_error_rad(out[k][f], g.poses_gt[f]) for f in range(g.n_frames)) for k in out}
+            d = max(pose_error_rad(out["learned"][f], out["plain"][f]) for f in range(g.n_frames))
+            r = res.setdefault(f"{g.n_frames} keyframes {g.width}x{g.height}", {"plain": [], "learned": [], "diff": []})
+            r["plain"].append(e["plain"])
+            r["learned"].append(e["learned"])
+            r["diff"].append(d)
+            if log and sum(len(v["plain"]) for v in res.values()) % 20 == 0:
+                log(f"evaluated {sum(len(v['plain']) for v in res.values())} windows")
+    summary = {}
+    for shape, r in res.items():
+        pl, le, di = (np.array(r[k]) for k in ("plain", "learned", "diff"))
+        summary[shape] = {"windows": int(len(pl)),
+                          "plain_rot_err_rad": {"mean": float(pl.mean()), "median": float(np.median(pl))},
+                          "learned_rot_err_rad": {"mean": float(le.mean()), "median": float(np.median(le))},
+                          "learned_vs_plain_rad": {"mean": float(di.mean()), "max": float(di.max())},
+                          "learned_closer": int((le < pl).sum())}
+        if log:
+            log(f"{shape}: {summary[shape]}")
+    return summary
 
 
 def main(argv=None):
@@ -152,6 +222,10 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--out", required=True, help="output .npy (fp16 parameters)")
+    ap.add_argument("--evaluate", type=int, default=100, help="held-out evaluation windows (0: none)")
+    ap.add_argument("--large-every", type=int, default=0,
+                    help="every n-th training window has the 20-keyframe 640x480 shape (0: none)")
+    ap.add_argument("--log-every", type=int, default=100)
     a = ap.parse_args(argv)
     t0 = time.time()
     xs, ys = [], []
@@ -160,14 +234,17 @@ def main(argv=None):
     with mp.get_context("fork").Pool(max(1, min(a.workers, os.cpu_count() or 1))) as pool:
         torch.cuda.set_device(0)
         done = 0
-        for clean, leaky in pool.imap(_training_window, range(a.graphs), chunksize=8):
+        import functools
+        window = functools.partial(_training_window, large_every=a.large_every)
+        for clean, leaky in pool.imap(window, range(a.graphs), chunksize=8):
             ref = reference_poses(clean)
-            x, y = collect([(leaky, ref)], sample_frac=a.sample_frac, seed=a.seed + done)
+            x, y = collect([(leaky, ref)], sample_frac=a.sample_frac, seed=a.seed + done, max_pairs=40)
             xs.append(x)
             ys.append(y)
             done += 1
-            if done % 500 == 0:
-                print(f"{done} windows, {sum(len(v) for v in ys)} samples, {time.time() - t0:.0f} s", flush=True)
+            if done % a.log_every == 0 or clean.n_frames > 4:
+                print(f"{done} windows ({clean.n_frames} keyframes last), {sum(len(v) for v in ys)} samples, "
+                      f"{time.time() - t0:.0f} s", flush=True)
     x, y = torch.cat(xs), torch.cat(ys)
     t1 = time.time()
     p16, tr = train(x, y, steps=a.steps, lr=a.lr, batch=a.batch, seed=a.seed,
@@ -181,6 +258,16 @@ def main(argv=None):
                collect_s=round(t1 - t0, 1), train_s=round(time.time() - t1, 1),
                windows="4 keyframes 160x120 (seeds 10000..), masks grown by k mod 6 px; labels: gated in "
                        "with |r| < 3 mm at the plain optimiser's poses on the true masks")
+    large = len(range(0, a.graphs, a.large_every)) if a.large_every > 0 else 0
+    shapes = (f"{large} of 20 keyframes 640x480 (every {a.large_every}th, 40 seeded ordered pairs each), the rest "
+              "4 keyframes 160x120" if large else "4 keyframes 160x120")
+    rec["windows"] = (f"seeds 10000..{10_000 + a.graphs - 1}: {shapes}; masks grown by k mod 6 px; labels: gated "
+                      "in with |r| < 3 mm at the plain optimiser's poses on the true masks")
+    rec["large_windows"] = large
+    if a.evaluate > 0:
+        rec["evaluation"] = {"seeds": f"20000..{20_000 + a.evaluate - 1} (every 5th 10 keyframes 640x480, the rest "
+                                      "4 keyframes 160x120; masks grown by 4 px), prune 25 %",
+                             "results": evaluate(p16, a.evaluate, a.workers)}
     with open(os.path.splitext(a.out)[0] + ".json", "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec), flush=True)
