@@ -467,6 +467,79 @@ __device__ __forceinline__ void assoc_item(const GraphDev* __restrict__ gds, con
         t[m] = (y[m] >= 0) ? ld_global(tmap + px_index(y[m], pc.W)) : make_float4(0.f, 0.f, 0.f, 0.f);
         acc[29] += (y[m] >= 0) ? 1.0f : 0.0f;
     }
+    if constexpr (LEARNED) {
+        // the network runs wave-wide on the wave's gated-in pixel-pairs only:
+        // their features are packed in LDS (in pixel order), evaluated 64 at a
+        // time, and each pair's output read back from its slot.  A sample's
+        // output does not depend on the others of its batch, so packing
+        // changes no result.
+        __shared__ float s_feat[kAssocThreads / 64][kMlpIn][64 * PPT];
+        __shared__ float s_sig[kAssocThreads / 64][64 * PPT];
+        float rr[PPT], JJ[PPT][6];
+        int slot[PPT];
+        int nw = 0;   // gated-in pixel-pairs of the wave so far (uniform)
+        const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+            float d2 = 0.f, cg = 0.f, sn = 0.f;
+            rr[m] = 0.f;
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+                JJ[m][a] = 0.f;
+            bool gated = false;
+            if (y[m] >= 0)
+                gated = finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], pc, rr[m], JJ[m], d2,
+                                  cg, sn) >= 0;
+            const unsigned long long bal = __ballot(gated);
+            slot[m] = gated ? nw + __popcll(bal & below) : -1;
+            if (gated) {
+                float f[kMlpIn];
+                learned_features(gd, rr[m], d2, cg, sn, s[m].w, uvs[m], iteration, f);
+#pragma unroll
+                for (int k = 0; k < kMlpIn; ++k)
+                    s_feat[wave][k][slot[m]] = f[k];
+            }
+            nw += __popcll(bal);
+        }
+        // the wave reads back its own LDS writes (in order within a wavefront)
+        asm volatile("" ::: "memory");
+        for (int b0 = 0; b0 < nw; b0 += 64) {
+            const int q = b0 + lane;
+            float f[kMlpIn];
+#pragma unroll
+            for (int k = 0; k < kMlpIn; ++k)
+                f[k] = (q < nw) ? s_feat[wave][k][q] : 0.f;
+            const float sgv = mlp_sigma_wave(M, s_tail, f, lane);
+            if (q < nw)
+                s_sig[wave][q] = sgv;
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+            if (slot[m] < 0)
+                continue;
+            const float sg = s_sig[wave][slot[m]];
+            const float r = rr[m];
+            const float ar = fabsf(r);
+            const float w = ((ar <= huber) ? 1.0f : huber * __builtin_amdgcn_rcpf(ar)) * sg;
+            const float e = ((ar <= huber) ? 0.5f * ar * ar : huber * (ar - 0.5f * huber)) * sg;
+            float wJ[6];
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+                wJ[a] = w * JJ[m][a];
+            int q = 0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+#pragma unroll
+                for (int c = a; c < 6; ++c)
+                    acc[q++] += wJ[a] * JJ[m][c];
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+                acc[21 + a] += wJ[a] * r;
+            acc[27] += e;
+            acc[28] += 1.0f;
+        }
+    } else {
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         float r = 0.f, J[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, d2 = 0.f, cg = 0.f, sn = 0.f;
@@ -474,14 +547,6 @@ __device__ __forceinline__ void assoc_item(const GraphDev* __restrict__ gds, con
         if (y[m] >= 0)
             gated = finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], pc, r, J, d2, cg, sn) >= 0;
         float sg = 1.0f;
-        if (LEARNED) {
-            // the network runs wave-wide: every lane takes part, gated in or not
-            float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            if (gated)
-                learned_features(gd, r, d2, cg, sn, s[m].w, uvs[m], iteration, f);
-            if (__ballot(gated))
-                sg = mlp_sigma_wave(M, s_tail, f, lane);
-        }
         if (!gated)
             continue;
         const float ar = fabsf(r);
@@ -502,6 +567,7 @@ __device__ __forceinline__ void assoc_item(const GraphDev* __restrict__ gds, con
             acc[21 + a] += wJ[a] * r;
         acc[27] += e;
         acc[28] += 1.0f;
+    }
     }
     if (status)   // uniform over the block
         return;
@@ -630,23 +696,71 @@ __device__ __forceinline__ void assoc_bf16x3_item(const GraphDev* __restrict__ g
 
     float energy = 0.f, count = 0.f, reads = 0.f;
     f32x4 C = {0.f, 0.f, 0.f, 0.f};
+    // learned weighting: the network on the wave's gated-in pixel-pairs only,
+    // packed in LDS and evaluated 64 at a time before the contraction (as in
+    // the FP32 association)
+    float rr[PPT], JJ[PPT][6];
+    int slot[PPT];
+    __shared__ float s_feat[kAssocThreads / 64][kMlpIn][64 * PPT];   // learned only
+    if constexpr (LEARNED) {
+        int nw = 0;
+        const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+        for (int m = 0; m < PPT; ++m) {
+            float d2 = 0.f, cg = 0.f, sn = 0.f;
+            rr[m] = 0.f;
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                JJ[m][q] = 0.f;
+            bool gated = false;
+            if (y[m] >= 0) {
+                reads += 1.0f;
+                gated = finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], pc, rr[m], JJ[m], d2,
+                                  cg, sn) >= 0;
+            }
+            const unsigned long long bal = __ballot(gated);
+            slot[m] = gated ? nw + __popcll(bal & below) : -1;
+            if (gated) {
+                float f[kMlpIn];
+                learned_features(gd, rr[m], d2, cg, sn, s[m].w, uvs[m], iteration, f);
+#pragma unroll
+                for (int k = 0; k < kMlpIn; ++k)
+                    s_feat[wave][k][slot[m]] = f[k];
+            }
+            nw += __popcll(bal);
+        }
+        // the wave reads back its own LDS writes (in order within a wavefront);
+        // each output goes to the slot of its features
+        asm volatile("" ::: "memory");
+        for (int b0 = 0; b0 < nw; b0 += 64) {
+            const int q = b0 + lane;
+            float f[kMlpIn];
+#pragma unroll
+            for (int k = 0; k < kMlpIn; ++k)
+                f[k] = (q < nw) ? s_feat[wave][k][q] : 0.f;
+            const float sgv = mlp_sigma_wave(M, s_tail, f, lane);
+            if (q < nw)
+                s_feat[wave][0][q] = sgv;
+        }
+        asm volatile("" ::: "memory");
+    }
 #pragma unroll
     for (int m = 0; m < PPT; ++m) {
         float x[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         float r = 0.f, J[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, d2 = 0.f, cg = 0.f, sn = 0.f;
         bool gated = false;
-        if (y[m] >= 0) {
+        float sg = 1.0f;
+        if constexpr (LEARNED) {
+            gated = slot[m] >= 0;
+            r = rr[m];
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                J[q] = JJ[m][q];
+            if (gated)
+                sg = s_feat[wave][0][slot[m]];
+        } else if (y[m] >= 0) {
             reads += 1.0f;
             gated = finish_px(A, px[m], py[m], s[m].w, s[m].x, s[m].y, s[m].z, y[m], t[m], pc, r, J, d2, cg, sn) >= 0;
-        }
-        float sg = 1.0f;
-        if (LEARNED) {
-            // the network runs wave-wide: every lane takes part, gated in or not
-            float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            if (gated)
-                learned_features(gd, r, d2, cg, sn, s[m].w, uvs[m], iteration, f);
-            if (__ballot(gated))
-                sg = mlp_sigma_wave(M, s_tail, f, lane);
         }
         if (gated) {
             const float ar = fabsf(r);
@@ -876,36 +990,75 @@ __global__ __launch_bounds__(kPruneThreads) void prune_score_kernel(const GraphD
     __syncthreads();
     const float px = s.w * (((float)(uv & 0xffffu) - gd.cx) * gd.ifx);
     const float py = s.w * (((float)(uv >> 16) - gd.cy) * gd.ify);
+    // the network runs wave-wide on the gated-in (pixel, target) samples of a
+    // group of kPruneGroup targets, packed in LDS and evaluated 64 at a time;
+    // each output goes back to its pixel's lane (the maximum is exact, so the
+    // grouping changes no score)
+    constexpr int kPruneGroup = 4;
+    __shared__ float s_feat[kPruneThreads / 64][kMlpIn][64 * kPruneGroup];
+    __shared__ float s_sig[kPruneThreads / 64][64 * kPruneGroup];
+    const int wave = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
     float best = 0.0f;
-    for (int j = 0; j < gd.n_frames; ++j) {
-        if (j == i)
-            continue;
-        const int p = pair_index(i, j, gd.n_frames);
-        float A[12], B[12];
+    for (int j0 = 0; j0 < gd.n_frames; j0 += kPruneGroup) {
+        int slot[kPruneGroup];
+        int nw = 0;   // gated-in samples of the wave in this group (uniform)
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            A[k] = gd.xf32[p * 24 + k];
-            B[k] = gd.xf32[p * 24 + 12 + k];
-        }
-        bool gated = false;
-        float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (live) {
-            float uf, vf;
-            const int y = project_px(B, px, py, s.w, gd, uf, vf);
-            if (y >= 0) {
-                const float4 t = gd.maps[(size_t)j * gd.HW + px_index(y, gd.W)];
-                float r, J[6], d2, c, sn;
-                if (finish_px(A, px, py, s.w, s.x, s.y, s.z, y, t, gd, r, J, d2, c, sn) >= 0) {
-                    gated = true;
-                    learned_features(gd, r, d2, c, sn, s.w, uv, 0, f);
+        for (int g = 0; g < kPruneGroup; ++g) {
+            const int j = j0 + g;
+            slot[g] = -1;
+            if (j >= gd.n_frames || j == i)   // uniform
+                continue;
+            const int p = pair_index(i, j, gd.n_frames);
+            float A[12], B[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                A[k] = gd.xf32[p * 24 + k];
+                B[k] = gd.xf32[p * 24 + 12 + k];
+            }
+            bool gated = false;
+            float f[kMlpIn] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            if (live) {
+                float uf, vf;
+                const int y = project_px(B, px, py, s.w, gd, uf, vf);
+                if (y >= 0) {
+                    const float4 t = gd.maps[(size_t)j * gd.HW + px_index(y, gd.W)];
+                    float r, J[6], d2, c, sn;
+                    if (finish_px(A, px, py, s.w, s.x, s.y, s.z, y, t, gd, r, J, d2, c, sn) >= 0) {
+                        gated = true;
+                        learned_features(gd, r, d2, c, sn, s.w, uv, 0, f);
+                    }
                 }
             }
+            const unsigned long long bal = __ballot(gated);
+            if (gated) {
+                slot[g] = nw + __popcll(bal & below);
+#pragma unroll
+                for (int k = 0; k < kMlpIn; ++k)
+                    s_feat[wave][k][slot[g]] = f[k];
+            }
+            nw += __popcll(bal);
         }
-        if (__ballot(gated)) {
-            const float sg = mlp_sigma_wave(M, s_tail, f, lane);
-            if (gated)
-                best = fmaxf(best, sg);
+        // the wave reads back its own LDS writes (in order within a wavefront)
+        asm volatile("" ::: "memory");
+        for (int b0 = 0; b0 < nw; b0 += 64) {
+            const int q = b0 + lane;
+            float f[kMlpIn];
+#pragma unroll
+            for (int k = 0; k < kMlpIn; ++k)
+                f[k] = (q < nw) ? s_feat[wave][k][q] : 0.f;
+            const float sgv = mlp_sigma_wave(M, s_tail, f, lane);
+            if (q < nw)
+                s_sig[wave][q] = sgv;
         }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int g = 0; g < kPruneGroup; ++g)
+            if (slot[g] >= 0)
+                best = fmaxf(best, s_sig[wave][slot[g]]);
+        // the next group's writes after every lane has read this group's
+        // outputs (in order within a wavefront)
+        asm volatile("" ::: "memory");
     }
     if (live)
         gd.score[e] = __float_as_uint(best);
