@@ -1064,159 +1064,565 @@ __global__ __launch_bounds__(kPruneThreads) void prune_score_kernel(const GraphD
         gd.score[e] = __float_as_uint(best);
 }
 
-// Exclusive prefix of flag over the block (1024 threads = 16 waves) and the
-// block total; wave counts go through LDS.
-__device__ __forceinline__ int block_excl_scan(bool flag, int* wave_cnt, int& total)
+// Inclusive prefix sum over the 64 lanes of a wave by DPP (row shifts within
+// the four 16-lane rows, then the row totals broadcast to the rows above): no
+// LDS traffic.
+__device__ __forceinline__ int wave_incl_scan(int x)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const unsigned long long bal = __ballot(flag);
-    const int pre = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0)
-        wave_cnt[wv] = __popcll(bal);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return x;
+}
+
+__device__ __forceinline__ int wave_sum(int x) { return __builtin_amdgcn_readlane(wave_incl_scan(x), 63); }
+
+// The select kernel's block-wide scans: 16 waves, the wave values through LDS
+// (read back in one unrolled pass) and one barrier; each call site has its
+// own wave_vals buffer, so none is rewritten while a wave may still read it.
+constexpr int kSelectThreads = 1024;
+constexpr int kSelectWaves = kSelectThreads / 64;
+
+// Exclusive prefix over the waves of one value per wave (every lane of a wave
+// passes the same v) and the block total.
+__device__ __forceinline__ int select_wave_excl(int v, int* wave_vals, int& total)
+{
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        wave_vals[wv] = v;
     __syncthreads();
     int off = 0, tot = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-        const int c = wave_cnt[w];
+#pragma unroll
+    for (int w = 0; w < kSelectWaves; ++w) {
+        const int c = wave_vals[w];
         off += (w < wv) ? c : 0;
         tot += c;
     }
-    __syncthreads();
     total = tot;
-    return off + pre;
+    return off;
 }
 
-constexpr int kSelectPer = 8;   // consecutive entries per thread in the compaction
-
-// Per frame, kSelectBlocks blocks of 1024 threads: drop the n_drop source
-// pixels of lowest score, ties by position in the row-major source list, and
-// compact the kept ones in order into the pruned lists.  Every block finds
-// the n_drop-th smallest key itself (the same computation on the same data,
-// so all agree): an MSB-first radix select, four 8-bit passes over LDS
-// histograms kept in 16 copies (lane % 16) so that lanes hitting one bin do
-// not serialise on one address; integer counts, so the result does not
-// depend on the order of the atomics.  Block b then compacts its own segment
-// of the list; its output offset and its rank among the keys equal to the
-// threshold come from counting the keys before the segment.
-constexpr int kSelectThreads = 1024;
-constexpr int kSelectBlocks = 8;
-constexpr int kHistCopies = 16;
-
-__global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const GraphDev* __restrict__ gds,
-                                                                      const int2* __restrict__ frames)
+// Exclusive prefix of one value per thread over the block, and the total.
+__device__ __forceinline__ int select_thread_excl(int v, int* wave_vals, int& total)
 {
-    __shared__ int hist16[256 * kHistCopies];
-    __shared__ int hist[256];
-    __shared__ int wave_cnt[16];
-    __shared__ unsigned int s_prefix;
-    __shared__ int s_rank;
-    const int2 fr = frames[blockIdx.x / kSelectBlocks];
-    const int seg = blockIdx.x % kSelectBlocks;
+    const int incl = wave_incl_scan(v);
+    return select_wave_excl(__builtin_amdgcn_readlane(incl, 63), wave_vals, total) + incl - v;
+}
+
+// Block totals of two per-thread counts a and b, and the exclusive prefix over
+// the waves of one value per wave c (every lane of a wave passes the same c).
+__device__ __forceinline__ void select_counts(int a, int b, int c, int* wave_vals, int& ta, int& tb, int& c_off)
+{
+    const int wv = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((threadIdx.x & 63) == 0) {
+        wave_vals[3 * wv] = a;
+        wave_vals[3 * wv + 1] = b;
+        wave_vals[3 * wv + 2] = c;
+    }
+    __syncthreads();
+    ta = tb = c_off = 0;
+#pragma unroll
+    for (int w = 0; w < kSelectWaves; ++w) {
+        ta += wave_vals[3 * w];
+        tb += wave_vals[3 * w + 1];
+        c_off += (w < wv) ? wave_vals[3 * w + 2] : 0;
+    }
+}
+
+// Histograms of one digit of the keys k < n: LDS atomics of integer counts,
+// so a histogram does not depend on which thread counts a key or in which
+// order.  The whole slices of T keys (one per thread) go through a short
+// sequence of compares into lane masks (inline assembly: the compiler's own
+// form of these branches cost several times the instructions): a key costs a
+// few vector instructions, and an LDS atomic is issued only when a lane of the
+// wave has a key to add; the last, partial slice takes plain code with a
+// bounds test.
+constexpr int kSelectDom = 3;
+constexpr int kSelectDomRounds = 16;
+
+// The counting of select_hist_top with dominant bins bd0..bd2 (ZERO: bd2 is
+// bin 0 and counts only keys equal to zero, their total also added to
+// *zeros).
+template <bool ZERO, typename KeyAt>
+__device__ __forceinline__ void select_top_sweep(KeyAt key_at, int n, int* h, int bd0, int bd1, int bd2, int* zeros)
+{
+    constexpr int T = kSelectThreads, P = 8;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // per-lane counts of the dominant bins
+    int c0 = 0, c1 = 0, c2 = 0;
+    const unsigned int hb = (unsigned int)(uintptr_t)(const __attribute__((address_space(3))) int*)h;
+    // whole slices of T keys: compares into lane masks, counts by
+    // add-with-carry, and the LDS atomic of the other lanes with the
+    // execution mask narrowed to them (skipped when there are none; the mask
+    // is restored before the block ends)
+    auto whole = [&](unsigned int key) {
+        unsigned int bin, addr;
+        unsigned long long m0, m1, m2, co, sv;
+        if constexpr (ZERO) {
+            asm volatile(
+                "v_lshrrev_b32 %[bin], 20, %[key]\n\t"
+                "v_cmp_eq_u32 %[m0], %[b0], %[bin]\n\t"
+                "v_cmp_eq_u32 %[m1], %[b1], %[bin]\n\t"
+                "v_cmp_eq_u32 %[m2], 0, %[key]\n\t"
+                "v_addc_co_u32 %[c0], %[co], 0, %[c0], %[m0]\n\t"
+                "v_addc_co_u32 %[c1], %[co], 0, %[c1], %[m1]\n\t"
+                "v_addc_co_u32 %[c2], %[co], 0, %[c2], %[m2]\n\t"
+                "s_or_b64 %[m0], %[m0], %[m1]\n\t"
+                "s_or_b64 %[m0], %[m0], %[m2]\n\t"
+                "s_mov_b64 %[sv], exec\n\t"
+                "s_andn2_b64 exec, exec, %[m0]\n\t"
+                "s_cbranch_execz .Lsel_topz_skip%=\n\t"
+                "v_lshl_add_u32 %[addr], %[bin], 2, %[hb]\n\t"
+                "ds_add_u32 %[addr], %[one]\n\t"
+                ".Lsel_topz_skip%=:\n\t"
+                "s_mov_b64 exec, %[sv]"
+                : [bin] "=&v"(bin), [addr] "=&v"(addr), [m0] "=&s"(m0), [m1] "=&s"(m1), [m2] "=&s"(m2),
+                  [co] "=&s"(co), [sv] "=&s"(sv), [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2)
+                : [key] "v"(key), [b0] "s"(bd0), [b1] "s"(bd1), [hb] "s"(hb), [one] "v"(1)
+                : "memory", "scc");
+        } else {
+            asm volatile(
+                "v_lshrrev_b32 %[bin], 20, %[key]\n\t"
+                "v_cmp_eq_u32 %[m0], %[b0], %[bin]\n\t"
+                "v_cmp_eq_u32 %[m1], %[b1], %[bin]\n\t"
+                "v_cmp_eq_u32 %[m2], %[b2], %[bin]\n\t"
+                "v_addc_co_u32 %[c0], %[co], 0, %[c0], %[m0]\n\t"
+                "v_addc_co_u32 %[c1], %[co], 0, %[c1], %[m1]\n\t"
+                "v_addc_co_u32 %[c2], %[co], 0, %[c2], %[m2]\n\t"
+                "s_or_b64 %[m0], %[m0], %[m1]\n\t"
+                "s_or_b64 %[m0], %[m0], %[m2]\n\t"
+                "s_mov_b64 %[sv], exec\n\t"
+                "s_andn2_b64 exec, exec, %[m0]\n\t"
+                "s_cbranch_execz .Lsel_top_skip%=\n\t"
+                "v_lshl_add_u32 %[addr], %[bin], 2, %[hb]\n\t"
+                "ds_add_u32 %[addr], %[one]\n\t"
+                ".Lsel_top_skip%=:\n\t"
+                "s_mov_b64 exec, %[sv]"
+                : [bin] "=&v"(bin), [addr] "=&v"(addr), [m0] "=&s"(m0), [m1] "=&s"(m1), [m2] "=&s"(m2),
+                  [co] "=&s"(co), [sv] "=&s"(sv), [c0] "+v"(c0), [c1] "+v"(c1), [c2] "+v"(c2)
+                : [key] "v"(key), [b0] "s"(bd0), [b1] "s"(bd1), [b2] "s"(bd2), [hb] "s"(hb), [one] "v"(1)
+                : "memory", "scc");
+        }
+    };
+    const int full = (n / T) * T;
+    int k0 = 0;
+    for (; k0 + T * P <= full; k0 += T * P) {
+        unsigned int kk[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+            kk[q] = key_at(k0 + q * T + tid);
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+            whole(kk[q]);
+    }
+    if (k0 < full) {   // the other whole slices, loaded together
+        const int ns = (full - k0) / T;
+        unsigned int kk[P - 1];
+#pragma unroll
+        for (int q = 0; q < P - 1; ++q)
+            if (q < ns)
+                kk[q] = key_at(k0 + q * T + tid);
+#pragma unroll
+        for (int q = 0; q < P - 1; ++q)
+            if (q < ns)
+                whole(kk[q]);
+        k0 = full;
+    }
+    if (k0 < n && k0 + tid < n) {   // the last, partial slice
+        const unsigned int key = key_at(k0 + tid);
+        const int bin = (int)(key >> 20);
+        if (bin == bd0)
+            ++c0;
+        else if (bin == bd1)
+            ++c1;
+        else if (ZERO ? key == 0u : bin == bd2)
+            ++c2;
+        else
+            atomicAdd(&h[bin], 1);
+    }
+    c0 = wave_sum(c0);
+    c1 = wave_sum(c1);
+    c2 = wave_sum(c2);
+    if (lane == 0) {
+        if (c0 > 0)
+            atomicAdd(&h[bd0], c0);
+        if (c1 > 0)
+            atomicAdd(&h[bd1], c1);
+        if (c2 > 0) {
+            atomicAdd(&h[bd2], c2);
+            if (ZERO)
+                atomicAdd(zeros, c2);
+        }
+    }
+}
+
+// First digit, bits 20..31 of every key.  Each wave first takes the
+// kSelectDom most frequent bins of 64 keys spread over the list (at most
+// kSelectDomRounds distinct bins looked at) as its dominant bins and counts
+// the keys in those in registers, added with one atomic each at the end (the
+// first digit of the scores falls in a few bins: mostly one, and zero for
+// sources gated in nowhere; lanes of a wave that hit one address would
+// serialise their atomics); every other key is one LDS atomic.  *zeros
+// receives the count of keys equal to zero when bin 0 is a dominant bin (else
+// it is left as it is).
+template <typename KeyAt>
+__device__ __forceinline__ void select_hist_top(KeyAt key_at, int n, int* h, int* zeros)
+{
+    constexpr int T = kSelectThreads, P = 8;
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (n <= 0)
+        return;
+    int bd[kSelectDom], cnt[kSelectDom];
+#pragma unroll
+    for (int e = 0; e < kSelectDom; ++e) {
+        bd[e] = -1;
+        cnt[e] = 0;
+    }
+    {
+        const int b = (int)(key_at((int)(((long long)lane * n) >> 6)) >> 20);
+        unsigned long long left = ~0ull;
+        for (int r = 0; r < kSelectDomRounds && left != 0ull; ++r) {
+            const int cb = __builtin_amdgcn_readlane(b, __ffsll((long long)left) - 1);
+            const unsigned long long same = __ballot(b == cb);
+            left &= ~same;
+            int c = __popcll(same), bb = cb;
+#pragma unroll
+            for (int e = 0; e < kSelectDom; ++e)   // insertion into the descending list
+                if (c > cnt[e]) {
+                    const int tc = cnt[e], tb = bd[e];
+                    cnt[e] = c;
+                    bd[e] = bb;
+                    c = tc;
+                    bb = tb;
+                }
+        }
+    }
+    // bin 0 (zero and subnormal scores) among them: that slot counts only the
+    // exact zeros (the others fall to the atomics), so that a threshold at
+    // zero is recognised without the later digits (a tie of many keys)
+    if (bd[0] == 0) {
+        bd[0] = bd[2];
+        bd[2] = 0;
+    } else if (bd[1] == 0) {
+        bd[1] = bd[2];
+        bd[2] = 0;
+    }
+    if (bd[2] == 0)
+        select_top_sweep<true>(key_at, n, h, bd[0], bd[1], 0, zeros);
+    else
+        select_top_sweep<false>(key_at, n, h, bd[0], bd[1], bd[2], zeros);
+}
+
+// A later digit, (key >> shift) & dmask of the keys with (key & mask) == prefix.
+// AGG (a prefix shared by many equal keys: zero, the score of sources gated in
+// nowhere): the lanes in the bin of the first counted lane add with one
+// atomic of their count, as equal keys would serialise on one address.
+template <bool AGG, typename KeyAt>
+__device__ __forceinline__ void select_hist_low(KeyAt key_at, int n, int shift, unsigned int dmask,
+                                                unsigned int mask, unsigned int prefix, int* h)
+{
+    constexpr int T = kSelectThreads, P = 8;
+    const int tid = threadIdx.x;
+    const unsigned int hb = (unsigned int)(uintptr_t)(const __attribute__((address_space(3))) int*)h;
+    // whole slices of T keys
+    auto whole = [&](unsigned int key) {
+        if constexpr (!AGG) {
+            // the LDS atomic with the execution mask narrowed to the lanes
+            // whose key has the prefix (skipped when there are none; the
+            // mask is restored before the block ends)
+            unsigned int t, addr;
+            unsigned long long m, sv;
+            asm volatile(
+                "v_and_b32 %[t], %[mask], %[key]\n\t"
+                "v_cmp_eq_u32 %[m], %[prefix], %[t]\n\t"
+                "s_mov_b64 %[sv], exec\n\t"
+                "s_and_b64 exec, exec, %[m]\n\t"
+                "s_cbranch_execz .Lsel_low_skip%=\n\t"
+                "v_lshrrev_b32 %[t], %[shift], %[key]\n\t"
+                "v_and_b32 %[t], %[dmask], %[t]\n\t"
+                "v_lshl_add_u32 %[addr], %[t], 2, %[hb]\n\t"
+                "ds_add_u32 %[addr], %[one]\n\t"
+                ".Lsel_low_skip%=:\n\t"
+                "s_mov_b64 exec, %[sv]"
+                : [t] "=&v"(t), [addr] "=&v"(addr), [m] "=&s"(m), [sv] "=&s"(sv)
+                : [key] "v"(key), [mask] "s"(mask), [prefix] "s"(prefix), [shift] "s"(shift),
+                  [dmask] "s"(dmask), [hb] "s"(hb), [one] "v"(1)
+                : "memory", "scc");
+        } else {
+            // of the lanes whose key has the prefix, those in the bin of the
+            // first of them add with one atomic of their count, the others
+            // with one atomic each, the execution mask narrowed to them (all
+            // skipped when no lane has the prefix; the mask is restored
+            // before the block ends)
+            unsigned int t, addr, vc;
+            unsigned long long m, same, one_lane, sv;
+            unsigned int fl, b0, cnt;
+            asm volatile(
+                "v_and_b32 %[t], %[mask], %[key]\n\t"
+                "v_cmp_eq_u32 %[m], %[prefix], %[t]\n\t"
+                "s_cmp_eq_u64 %[m], 0\n\t"
+                "s_cbranch_scc1 .Lsel_low_none%=\n\t"
+                "v_lshrrev_b32 %[t], %[shift], %[key]\n\t"
+                "v_and_b32 %[t], %[dmask], %[t]\n\t"
+                "s_ff1_i32_b64 %[fl], %[m]\n\t"
+                "s_nop 4\n\t"
+                "v_readlane_b32 %[b0], %[t], %[fl]\n\t"
+                "v_cmp_eq_u32 %[same], %[b0], %[t]\n\t"
+                "s_and_b64 %[same], %[same], %[m]\n\t"
+                "s_andn2_b64 %[m], %[m], %[same]\n\t"
+                "s_bcnt1_i32_b64 %[cnt], %[same]\n\t"
+                "s_lshl_b64 %[one], 1, %[fl]\n\t"
+                "s_mov_b64 %[sv], exec\n\t"
+                "s_mov_b64 exec, %[one]\n\t"
+                "v_mov_b32 %[vc], %[cnt]\n\t"
+                "v_lshl_add_u32 %[addr], %[t], 2, %[hb]\n\t"
+                "ds_add_u32 %[addr], %[vc]\n\t"
+                "s_and_b64 exec, %[sv], %[m]\n\t"
+                "s_cbranch_execz .Lsel_low_restore%=\n\t"
+                "v_lshl_add_u32 %[addr], %[t], 2, %[hb]\n\t"
+                "ds_add_u32 %[addr], %[onev]\n\t"
+                ".Lsel_low_restore%=:\n\t"
+                "s_mov_b64 exec, %[sv]\n\t"
+                ".Lsel_low_none%=:"
+                : [t] "=&v"(t), [addr] "=&v"(addr), [vc] "=&v"(vc), [m] "=&s"(m), [same] "=&s"(same),
+                  [one] "=&s"(one_lane), [sv] "=&s"(sv), [fl] "=&s"(fl), [b0] "=&s"(b0), [cnt] "=&s"(cnt)
+                : [key] "v"(key), [mask] "s"(mask), [prefix] "s"(prefix), [shift] "s"(shift),
+                  [dmask] "s"(dmask), [hb] "s"(hb), [onev] "v"(1)
+                : "memory", "scc");
+        }
+    };
+    const int full = (n / T) * T;
+    int k0 = 0;
+    for (; k0 + T * P <= full; k0 += T * P) {
+        unsigned int kk[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+            kk[q] = key_at(k0 + q * T + tid);
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+            whole(kk[q]);
+    }
+    if (k0 < full) {   // the other whole slices, loaded together
+        const int ns = (full - k0) / T;
+        unsigned int kk[P - 1];
+#pragma unroll
+        for (int q = 0; q < P - 1; ++q)
+            if (q < ns)
+                kk[q] = key_at(k0 + q * T + tid);
+#pragma unroll
+        for (int q = 0; q < P - 1; ++q)
+            if (q < ns)
+                whole(kk[q]);
+        k0 = full;
+    }
+    if (k0 < n && k0 + tid < n) {   // the last, partial slice
+        const unsigned int key = key_at(k0 + tid);
+        if ((key & mask) == prefix)
+            atomicAdd(&h[(key >> shift) & dmask], 1);
+    }
+}
+
+// The bin holding the entry of 0-based rank 'rank' in histogram h (PER
+// consecutive bins per thread of the 1024): out = {bin, rank within the bin},
+// visible to the block on return.
+template <int PER>
+__device__ __forceinline__ void select_bin(const int* h, int rank, int* wave_vals, int* out)
+{
+    int c[PER], sum = 0;
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        c[e] = h[PER * threadIdx.x + e];
+        sum += c[e];
+    }
+    int tot;
+    const int excl = select_thread_excl(sum, wave_vals, tot);
+    if (excl <= rank && rank < excl + sum) {
+        int r = rank - excl, bin = -1;
+#pragma unroll
+        for (int e = 0; e < PER; ++e)
+            if (bin < 0) {
+                if (r < c[e])
+                    bin = e;
+                else
+                    r -= c[e];
+            }
+        out[0] = PER * (int)threadIdx.x + bin;
+        out[1] = r;
+    }
+    __syncthreads();
+}
+
+// Per frame, bpf >= kSelectBlocks blocks of 1024 threads: drop the n_drop
+// source pixels of lowest score, ties by position in the row-major source
+// list, and compact the kept ones in order into the pruned lists.  Every block
+// finds the n_drop-th smallest key itself (the same computation on the same
+// data, so all agree): an MSB-first radix select over three digits (bits
+// 20..31, 10..19, 0..9) with LDS histograms of integer counts, so the result
+// does not depend on the order of the atomics.  STAGED (at most kSelectStageKeys sources): the frame's keys are loaded into
+// LDS once, every load in flight together, and the passes read them there;
+// otherwise they are read from global memory.  Block b then compacts its own segment of the list: its output
+// offset and its rank among the keys equal to the threshold come from
+// counting the keys before the segment.  Within the segment each wave takes a
+// contiguous run in slices of 64 consecutive entries (ranks by ballot, wave
+// offsets by a scan over the waves), so the loads of the source records and
+// the stores of the kept ones are coalesced; staged, the run's records are
+// loaded at the start, in flight during the select.
+constexpr int kSelectBlocks = 8;          // blocks per frame, at least
+constexpr int kSelectMaxSlices = 64;      // 64-entry slices of one wave's run (bits of a mask)
+constexpr int kSelectPer = 8;             // keys per thread and step of a histogram pass
+constexpr int kSelectStagePer = 32;       // keys per thread when staged
+constexpr int kSelectStageKeys = kSelectStagePer * kSelectThreads;
+constexpr int kSelectGroup = 4;           // slices whose records are loaded together
+constexpr int kSelectBinsA = 4096;       // digit A: key bits 20..31
+constexpr int kSelectBinsB = 1024;       // digits B, C: bits 10..19 and 0..9
+// staged, a wave's run is at most kSelectGroup slices (one load group)
+static_assert(kSelectStageKeys / kSelectBlocks <= kSelectWaves * 64 * kSelectGroup, "staged runs");
+
+template <bool STAGED>
+__global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const GraphDev* __restrict__ gds,
+                                                                      const int2* __restrict__ frames, int bpf)
+{
+    __shared__ __attribute__((aligned(16))) unsigned int s_key[STAGED ? kSelectStageKeys : 4];
+    // the three digits' histograms (cleared together), one wave-value buffer
+    // per scan and one result per digit, so no buffer is rewritten before
+    // every wave has passed a barrier after its last read
+    __shared__ __attribute__((aligned(16))) int hist[kSelectBinsA + 2 * kSelectBinsB];
+    __shared__ int wave_vals[5][3 * kSelectWaves];
+    __shared__ int s_sel[3][2];
+    __shared__ int s_zeros;   // keys equal to zero, when counted by the first digit
+    const int2 fr = frames[blockIdx.x / bpf];
+    const int seg = blockIdx.x % bpf;
     const GraphDev& gd = gds[fr.x];
     const int i = fr.y;
-    const int V = gd.n_src[i];
-    const int drop = gd.n_drop[i];
+    const int V = ld_global(gd.n_src + i);
+    const int drop = ld_global(gd.n_drop + i);
     const size_t base = (size_t)i * gd.HW;
-    const unsigned int* __restrict__ key = gd.score + base;
-    const int tid = threadIdx.x, lane = tid & 63;
+    const unsigned int* key = gd.score + base;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+
+    // this block's segment [s0, s1) of the list and this wave's run [r0, r1)
+    // of it: n_slices <= kSelectMaxSlices (the launch sizes bpf for that)
+    const int s0 = (int)(((long long)V * seg) / bpf);
+    const int s1 = (int)(((long long)V * (seg + 1)) / bpf);
+    const int run = (s1 - s0 + kSelectWaves * 64 - 1) / (kSelectWaves * 64) * 64;
+    const int r0 = min(s0 + wv * run, s1), r1 = min(r0 + run, s1);
+    const int n_slices = (r1 - r0 + 63) / 64;
+
+    float4 pnz[kSelectGroup];
+    uint32_t puv[kSelectGroup];
+    if constexpr (STAGED) {
+        // the run's source records and every key of the frame, all in flight
+        // together
+#pragma unroll
+        for (int d = 0; d < kSelectGroup; ++d) {
+            const int k = r0 + 64 * d + lane;
+            pnz[d] = make_float4(0.f, 0.f, 0.f, 0.f);
+            puv[d] = 0u;
+            if (k < r1) {
+                pnz[d] = ld_global(gd.src_nz + base + k);
+                puv[d] = ld_global(gd.src_uv + base + k);
+            }
+        }
+        // (the slots past the list, never read, hold all ones).  Rows of a
+        // multiple of 4 pixels: 4 keys per load (16-byte aligned; a group past
+        // the list start stays inside the frame, whose size is a multiple of 4)
+        if ((gd.HW & 3) == 0) {
+            typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+            u4v kv[kSelectStagePer / 4];
+#pragma unroll
+            for (int q = 0; q < kSelectStagePer / 4; ++q) {
+                const int k = 4 * (q * kSelectThreads + tid);
+                kv[q] = (u4v){0u, 0u, 0u, 0u};
+                if (k < V)
+                    kv[q] = *(const __attribute__((address_space(1))) u4v*)(key + k);
+            }
+#pragma unroll
+            for (int q = 0; q < kSelectStagePer / 4; ++q) {
+                const int k = 4 * (q * kSelectThreads + tid);
+                u4v w = kv[q];
+                w.x = (k < V) ? w.x : 0xffffffffu;
+                w.y = (k + 1 < V) ? w.y : 0xffffffffu;
+                w.z = (k + 2 < V) ? w.z : 0xffffffffu;
+                w.w = (k + 3 < V) ? w.w : 0xffffffffu;
+                *(u4v*)(s_key + k) = w;
+            }
+        } else {
+            unsigned int kk[kSelectStagePer];
+#pragma unroll
+            for (int q = 0; q < kSelectStagePer; ++q)
+                kk[q] = (V > 0) ? ld_global(key + min(q * kSelectThreads + tid, V - 1)) : 0u;
+#pragma unroll
+            for (int q = 0; q < kSelectStagePer; ++q)
+                s_key[q * kSelectThreads + tid] = (q * kSelectThreads + tid < V) ? kk[q] : 0xffffffffu;
+        }
+    }
+    if (STAGED && drop <= 0)
+        __syncthreads();   // the staging ends (with drop > 0, at the histogram clear)
+    auto key_at = [&](int k) -> unsigned int {
+        if constexpr (STAGED)
+            return s_key[k];
+        else
+            return ld_global(key + k);
+    };
 
     unsigned int tau = 0;   // key of the last dropped entry in (key, position) order
     int need = 0;           // entries equal to tau that are dropped (lowest positions first)
     if (drop > 0) {
-        unsigned int prefix = 0, mask = 0;
-        int rank = drop - 1;    // 0-based rank of the entry sought
-        for (int shift = 24; shift >= 0; shift -= 8) {
-            for (int q = tid; q < 256 * kHistCopies; q += kSelectThreads)
-                hist16[q] = 0;
+        for (int q = tid; q < kSelectBinsA + 2 * kSelectBinsB; q += kSelectThreads)
+            hist[q] = 0;
+        if (tid == 0)
+            s_zeros = 0;
+        __syncthreads();   // (also ends the staging)
+        // digit A: key bits 20..31
+        select_hist_top(key_at, V, hist, &s_zeros);
+        __syncthreads();
+        select_bin<kSelectBinsA / kSelectThreads>(hist, drop - 1, wave_vals[0], s_sel[0]);
+        if (s_sel[0][0] == 0 && hist[0] == s_zeros) {
+            // the entry sought is a zero and its bin holds zeros only: a tie
+            // of many keys, resolved without the later digits
+            tau = 0u;
+            need = s_sel[0][1] + 1;
+        } else {
+            unsigned int prefix = (unsigned int)s_sel[0][0] << 20;
+            // digit B: bits 10..19 of the keys with that digit A
+            int* const histB = hist + kSelectBinsA;
+            // (ties at zero: the aggregating form)
+            const bool zero = s_sel[0][0] == 0;
+            if (zero)
+                select_hist_low<true>(key_at, V, 10, kSelectBinsB - 1, 0xfff00000u, prefix, histB);
+            else
+                select_hist_low<false>(key_at, V, 10, kSelectBinsB - 1, 0xfff00000u, prefix, histB);
             __syncthreads();
-            // coalesced: entry k0 + q kSelectThreads + tid (a histogram does
-            // not depend on which thread counts an entry)
-            for (int k0 = 0; k0 < V; k0 += kSelectThreads * kSelectPer) {
-                unsigned int kk[kSelectPer];
-#pragma unroll
-                for (int q = 0; q < kSelectPer; ++q)
-                    kk[q] = key[min(k0 + q * kSelectThreads + tid, V - 1)];
-#pragma unroll
-                for (int q = 0; q < kSelectPer; ++q) {
-                    // wave-aggregated when every counted lane of the wave hits
-                    // one bin (the common case in the high passes, where the
-                    // scores share their exponent bits): one atomic with the
-                    // lane count instead of up to 64 on one address
-                    const bool in = k0 + q * kSelectThreads + tid < V && (kk[q] & mask) == prefix;
-                    const unsigned int bin = (kk[q] >> shift) & 255u;
-                    const unsigned long long act = __ballot(in);
-                    if (act == 0ull)
-                        continue;
-                    const int fl = __ffsll((long long)act) - 1;
-                    const unsigned int b0 = (unsigned int)__shfl((int)bin, fl);
-                    const unsigned long long same = __ballot(in && bin == b0);
-                    if (same == act) {
-                        if (lane == fl)
-                            atomicAdd(&hist16[b0 * kHistCopies + (lane & (kHistCopies - 1))], (int)__popcll(act));
-                    } else if (in) {
-                        atomicAdd(&hist16[bin * kHistCopies + (lane & (kHistCopies - 1))], 1);
-                    }
-                }
-            }
+            select_bin<kSelectBinsB / kSelectThreads>(histB, s_sel[0][1], wave_vals[1], s_sel[1]);
+            prefix |= (unsigned int)s_sel[1][0] << 10;
+            // digit C: bits 0..9 of the keys with those digits A and B
+            int* const histC = histB + kSelectBinsB;
+            if (zero)
+                select_hist_low<true>(key_at, V, 0, kSelectBinsB - 1, 0xfffffc00u, prefix, histC);
+            else
+                select_hist_low<false>(key_at, V, 0, kSelectBinsB - 1, 0xfffffc00u, prefix, histC);
             __syncthreads();
-            if (tid < 256) {
-                int h = 0;
-#pragma unroll
-                for (int c = 0; c < kHistCopies; ++c)
-                    h += hist16[tid * kHistCopies + c];
-                hist[tid] = h;
-            }
-            __syncthreads();
-            if (tid < 64) {
-                // lane l holds bins 4l..4l+3; inclusive scan of the lane sums
-                const int h0 = hist[4 * tid], h1 = hist[4 * tid + 1], h2 = hist[4 * tid + 2], h3 = hist[4 * tid + 3];
-                const int sum = h0 + h1 + h2 + h3;
-                int incl = sum;
-                for (int d = 1; d < 64; d <<= 1) {
-                    const int o = __shfl_up(incl, d, 64);
-                    if (tid >= d)
-                        incl += o;
-                }
-                const int excl = incl - sum;
-                const unsigned long long hit = __ballot(incl > rank);
-                const int first = __ffsll((long long)hit) - 1;
-                if (tid == first) {
-                    int r = rank - excl, b = 4 * tid;
-                    if (r >= h0) {
-                        r -= h0;
-                        ++b;
-                        if (r >= h1) {
-                            r -= h1;
-                            ++b;
-                            if (r >= h2) {
-                                r -= h2;
-                                ++b;
-                            }
-                        }
-                    }
-                    s_prefix = prefix | ((unsigned int)b << shift);
-                    s_rank = r;
-                }
-            }
-            __syncthreads();
-            prefix = s_prefix;
-            rank = s_rank;
-            mask |= 255u << shift;
-            __syncthreads();
+            select_bin<kSelectBinsB / kSelectThreads>(histC, s_sel[1][1], wave_vals[2], s_sel[2]);
+            tau = prefix | (unsigned int)s_sel[2][0];
+            need = s_sel[2][1] + 1;
         }
-        tau = prefix;
-        need = rank + 1;
     }
-    // this block's segment [s0, s1) of the list; keys before it give the
-    // output offset and the rank among the keys equal to tau
-    const int s0 = (int)(((long long)V * seg) / kSelectBlocks);
-    const int s1 = (int)(((long long)V * (seg + 1)) / kSelectBlocks);
-    int n_lt = 0, n_eq = 0;
-    if (drop > 0)
-        for (int k0 = 0; k0 < s0; k0 += kSelectThreads * kSelectPer) {   // coalesced, as above
+    // keys before the segment (the output offset and the rank among the keys
+    // equal to tau) and the entries equal to tau in this wave's run, in one
+    // exchange over the waves
+    int n_lt = 0, n_eq = 0, eq_w = 0;
+    if (drop > 0) {
+        for (int k0 = 0; k0 < s0; k0 += kSelectThreads * kSelectPer) {
             unsigned int kk[kSelectPer];
 #pragma unroll
             for (int q = 0; q < kSelectPer; ++q)
-                kk[q] = key[min(k0 + q * kSelectThreads + tid, V - 1)];
+                kk[q] = key_at(min(k0 + q * kSelectThreads + tid, V - 1));
 #pragma unroll
             for (int q = 0; q < kSelectPer; ++q) {
                 const bool in = k0 + q * kSelectThreads + tid < s0;
@@ -1224,51 +1630,62 @@ __global__ __launch_bounds__(kSelectThreads) void prune_select_kernel(const Grap
                 n_eq += (in && kk[q] == tau) ? 1 : 0;
             }
         }
-    int lt_before, eq_seen;
-    (void)block_excl_scan_int(n_lt, wave_cnt, lt_before);
-    (void)block_excl_scan_int(n_eq, wave_cnt, eq_seen);
-    int out = s0 - lt_before - min(need, eq_seen);
-    // ordered compaction of the segment: entry k is kept unless key < tau, or
-    // key == tau and it is among the first 'need' entries equal to tau.
-    // Chunks of kSelectThreads x kSelectPer entries, each thread a run of
-    // kSelectPer; block scans of the per-thread counts keep the order.
-    for (int k0 = s0; k0 < s1; k0 += kSelectThreads * kSelectPer) {
-        const int kb = k0 + tid * kSelectPer;
-        unsigned int kk[kSelectPer];
-        int m_eq = 0;
-#pragma unroll
-        for (int q = 0; q < kSelectPer; ++q) {
-            kk[q] = key[min(kb + q, V - 1)];
-            m_eq += (kb + q < s1 && drop > 0 && kk[q] == tau) ? 1 : 0;
+        for (int c = 0; c < n_slices; ++c) {
+            const int k = r0 + 64 * c + lane;
+            eq_w += __popcll(__ballot(k < r1 && key_at(k) == tau));
         }
-        int eq_tot;
-        int eq_rank = eq_seen + block_excl_scan_int(m_eq, wave_cnt, eq_tot);
-        unsigned int keep = 0;   // bit q: entry kb + q is kept
+    }
+    int lt_before, eq_before, eq_off;
+    select_counts(n_lt, n_eq, eq_w, wave_vals[3], lt_before, eq_before, eq_off);
+    int eq_rank = eq_before + eq_off;
+    // keep decisions of the run in order: entry k is kept unless key < tau,
+    // or key == tau and it is among the first 'need' entries equal to tau
+    unsigned long long keep = 0ull;   // bit c: this lane's entry of slice c is kept
+    int kept_w = 0;
+    for (int c = 0; c < n_slices; ++c) {
+        const int k = r0 + 64 * c + lane;
+        const bool live = k < r1;
+        const unsigned int kv = live ? key_at(k) : 0u;
+        const bool eq = live && drop > 0 && kv == tau;
+        const unsigned long long be = __ballot(eq);
+        const bool kq = live && (drop == 0 || kv > tau || (eq && eq_rank + __popcll(be & below) >= need));
+        eq_rank += __popcll(be);
+        keep |= (kq ? 1ull : 0ull) << c;
+        kept_w += __popcll(__ballot(kq));
+    }
+    int kept_tot;
+    int pos = s0 - lt_before - min(need, eq_before) + select_wave_excl(kept_w, wave_vals[4], kept_tot);
+    // the kept records at their ranks, kSelectGroup slices loaded together
+    for (int c0 = 0; c0 < n_slices; c0 += kSelectGroup) {
+        float4 nz[kSelectGroup];
+        uint32_t uv[kSelectGroup];
 #pragma unroll
-        for (int q = 0; q < kSelectPer; ++q) {
-            const bool live = kb + q < s1;
-            const bool eq = live && drop > 0 && kk[q] == tau;
-            const bool kq = live && (drop == 0 || kk[q] > tau || (eq && eq_rank >= need));
-            eq_rank += eq ? 1 : 0;
-            keep |= (kq ? 1u : 0u) << q;
-        }
-        int keep_tot;
-        const int pos = out + block_excl_scan_int(__popc(keep), wave_cnt, keep_tot);
-        // the source records of the run, loaded together after the scans, and
-        // stored at their ranks among the kept entries of the run
-#pragma unroll
-        for (int q = 0; q < kSelectPer; ++q) {
-            const int kq = min(kb + q, V - 1);
-            const float4 nz = gd.src_nz[base + kq];
-            const uint32_t uv = gd.src_uv[base + kq];
-            if ((keep >> q) & 1u) {
-                const int at = pos + __popc(keep & ((1u << q) - 1u));
-                gd.psrc_nz[base + at] = nz;
-                gd.psrc_uv[base + at] = uv;
+        for (int d = 0; d < kSelectGroup; ++d) {
+            if constexpr (STAGED) {   // a single group, loaded at the start
+                nz[d] = pnz[d];
+                uv[d] = puv[d];
+            } else {
+                const int k = r0 + 64 * (c0 + d) + lane;
+                nz[d] = make_float4(0.f, 0.f, 0.f, 0.f);
+                uv[d] = 0u;
+                if (k < r1) {
+                    nz[d] = ld_global(gd.src_nz + base + k);
+                    uv[d] = ld_global(gd.src_uv + base + k);
+                }
             }
         }
-        out += keep_tot;
-        eq_seen += eq_tot;
+#pragma unroll
+        for (int d = 0; d < kSelectGroup; ++d) {
+            const int c = c0 + d;
+            const bool kq = c < n_slices && ((keep >> c) & 1ull);
+            const unsigned long long bk = __ballot(kq);
+            if (kq) {
+                const int at = pos + __popcll(bk & below);
+                st_global(gd.psrc_nz + base + at, nz[d]);
+                st_global(gd.psrc_uv + base + at, uv[d]);
+            }
+            pos += __popcll(bk);
+        }
     }
 }
 
@@ -1700,12 +2117,19 @@ void launch_mlp_to_float(const __half* p16, float* p32, hipStream_t st)
 }
 
 void launch_prune(const GraphDev* gds, const WorkItem* pitems, int n_pitems, const int2* pframes, int n_pframes,
-                  hipStream_t st)
+                  int max_src, hipStream_t st)
 {
     if (n_pitems > 0)
         prune_score_kernel<<<n_pitems, kPruneThreads, 0, st>>>(gds, pitems);
-    if (n_pframes > 0)
-        prune_select_kernel<<<n_pframes * kSelectBlocks, kSelectThreads, 0, st>>>(gds, pframes);
+    if (n_pframes > 0) {
+        // blocks per frame: at most kSelectMaxSlices slices per wave run
+        const int per_block = kSelectWaves * 64 * kSelectMaxSlices;
+        const int bpf = std::max(kSelectBlocks, (max_src + per_block - 1) / per_block);
+        if (max_src <= kSelectStageKeys)
+            prune_select_kernel<true><<<n_pframes * bpf, kSelectThreads, 0, st>>>(gds, pframes, bpf);
+        else
+            prune_select_kernel<false><<<n_pframes * bpf, kSelectThreads, 0, st>>>(gds, pframes, bpf);
+    }
 }
 
 }  // namespace pg

@@ -32,7 +32,7 @@ int assoc_persistent_blocks(int ppt, int precision, bool learned);
 void launch_assoc_debug(const GraphDev* gds, int HW, int i, int j, int iteration, int* target, float* r,
                         float* uv, float* feat, float* sigma, hipStream_t st);
 void launch_prune(const GraphDev* gds, const WorkItem* pitems, int n_pitems, const int2* pframes, int n_pframes,
-                  hipStream_t st);
+                  int max_src, hipStream_t st);
 void launch_mlp_to_float(const __half* p16, float* p32, hipStream_t st);
 void launch_assemble(const GraphDev* gds, const int2* nbs, int n, hipStream_t st);
 size_t solve_lds_bytes(int n_free, int n_frames);
@@ -92,6 +92,7 @@ struct Schedule {
     std::vector<unsigned long long> versions;
     DevBuf gds, items, fitems, nbs, pitems, pframes;
     int n_items = 0, n_fitems = 0, n_nbs = 0, n_pitems = 0, n_pframes = 0;
+    int max_src = 0;      // largest source list of a pruned frame
     bool learned = false; // learned weighting in every graph of the schedule
     size_t lds = 0;
     int ppt = 4;
@@ -531,6 +532,7 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
     pg_graph* g0 = gs[0];
     s.graphs = gs;
     s.versions.clear();
+    s.max_src = 0;
     std::vector<GraphDev> devs;
     std::vector<WorkItem> items;
     std::vector<int2> fitems, nbs, pframes;
@@ -571,8 +573,10 @@ pg_status build_schedule(const std::vector<pg_graph*>& gs, Schedule& s)
             pitems.push_back(v);
         }
         if (g->pruned)
-            for (int f = 0; f < g->n_frames; ++f)
+            for (int f = 0; f < g->n_frames; ++f) {
                 pframes.push_back(make_int2((int)k, f));
+                s.max_src = std::max(s.max_src, g->n_src[f]);
+            }
         for (int I = 0; I < g->n_frames; ++I)
             for (int J = 0; J <= I; ++J)
                 nbs.push_back(make_int2((int)k, I | (J << 8)));
@@ -665,7 +669,7 @@ hipError_t enqueue_iters(const Schedule& s, int iters, hipStream_t st, const std
     if (ev && (e = hipEventRecord((*ev)[0], st)) != hipSuccess)
         return e;
     launch_solve(gds, ng, s.lds, 1, st);
-    launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, st);
+    launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, s.max_src, st);
     for (int it = 0; it < iters; ++it) {
         const hipEvent_t* m = ev ? ev->data() + 1 + 5 * it : nullptr;
         if (m && (e = hipEventRecord(m[0], st)) != hipSuccess)
@@ -1130,7 +1134,7 @@ pg_status pose_graph_linearize(pg_graph* g, double* H, double* grad, pg_stats* s
     const GraphDev* gds = s.gds.as<GraphDev>();
     hipStream_t st = g->stream;
     launch_solve(gds, 1, s.lds, 1, st);
-    launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, st);
+    launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, s.max_src, st);
     launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, s.fitems.as<int2>(),
                  s.n_fitems, s.persistent ? s.ctr.as<unsigned>() : nullptr, s.persist_bpx, st);
     launch_assemble(gds, s.nbs.as<int2>(), s.n_nbs, st);
@@ -1296,7 +1300,7 @@ pg_status pose_graph_time_assoc(pg_graph* g, int reps, double* ms_per_launch)
         return rc;
     Schedule& s = *g->sched;
     const GraphDev* gds = s.gds.as<GraphDev>();
-    launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, g->stream);
+    launch_prune(gds, s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes, s.max_src, g->stream);
     // one untimed launch, then reps back-to-back launches between two events
     launch_assoc(gds, s.items.as<WorkItem>(), s.n_items, s.ppt, s.precision, s.learned, 0, s.fitems.as<int2>(),
                  s.n_fitems, s.persistent ? s.ctr.as<unsigned>() : nullptr, s.persist_bpx, g->stream);
@@ -1336,7 +1340,7 @@ pg_status pose_graph_prune(pg_graph* g, float* score, uint8_t* keep)
         return rc;
     Schedule& s = *g->sched;
     launch_prune(s.gds.as<GraphDev>(), s.pitems.as<WorkItem>(), s.n_pitems, s.pframes.as<int2>(), s.n_pframes,
-                 g->stream);
+                 s.max_src, g->stream);
     HIP_OR_FAIL(g, hipGetLastError());
     const int N = g->n_frames;
     const size_t HW = g->HW, NHW = (size_t)N * HW;

@@ -21,14 +21,6 @@
 
 namespace pg {
 
-// Stores through global-address pointers (the graph's pointers are generic in
-// C++): global stores, which LDS waits do not count.
-template <typename T>
-__device__ __forceinline__ void st_global(T* p, T v)
-{
-    *(__attribute__((address_space(1))) T*)p = v;
-}
-
 __device__ __forceinline__ void st_global_f4(float* p, float x, float y, float z, float w)
 {
     pg_f4v v = {x, y, z, w};

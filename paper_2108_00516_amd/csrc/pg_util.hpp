@@ -25,4 +25,19 @@ __device__ __forceinline__ float4 ld_global<float4>(const float4* p)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
+// Stores through global-address pointers (pointers held in C++ structures are
+// generic): global stores, which LDS waits do not count.
+template <typename T>
+__device__ __forceinline__ void st_global(T* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+
+template <>
+__device__ __forceinline__ void st_global<float4>(float4* p, float4 v)
+{
+    const pg_f4v w = {v.x, v.y, v.z, v.w};
+    *(__attribute__((address_space(1))) pg_f4v*)p = w;
+}
+
 }  // namespace pg

@@ -254,6 +254,31 @@ def test_prune_scores_and_selection(frac):
     pg.close()
 
 
+@pytest.mark.parametrize("params", ["random", "flat"])
+def test_prune_selection_beyond_staged_keys(params):
+    """Source lists longer than the select holds in LDS (32,768 keys; 640x480
+    with the masks grown by 40 pixels gives about 56k sources a frame) take the
+    select that reads its keys from global memory: its keep mask is the
+    definition's and the oracle's selection from the same scores, also when
+    every gated-in score ties (flat parameters)."""
+    g = synth.make_graph("T", n_frames=3, width=640, height=480, mask_dilate=40)
+    if params == "random":
+        p16 = rand_params(7)
+    else:
+        p16 = np.zeros(1313, np.float16)
+        p16[1312] = 2.0
+    pg = gpu_graph(g, learned_cfg(g, prune_frac=0.25), p16)
+    score, keep = pg.prune()
+    V = (score >= 0).sum(axis=1)
+    say(f"sources per frame {V.tolist()}")
+    assert V.max() > 32768
+    check_selection(score, keep, 0.25)
+    pb = oracle.OracleProblem.from_synth(g, oracle.Params(mlp=p16.astype(np.float64)))
+    ko = pb.prune_select(score.reshape(g.n_frames, g.height, g.width).astype(np.float64), 0.25)
+    assert np.array_equal(ko.reshape(g.n_frames, -1).astype(bool), keep)
+    pg.close()
+
+
 def test_prune_edge_cases():
     from paper_2108_00516_amd import Config, PoseGraphError, from_synth
     g = synth.make_graph("T", n_frames=2)
