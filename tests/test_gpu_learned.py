@@ -279,6 +279,33 @@ def test_prune_selection_beyond_staged_keys(params):
     pg.close()
 
 
+def test_prune_threshold_inside_zero_scores():
+    """A threshold inside the zero scores (sources gated in nowhere), the tie
+    the select resolves from its first digit's count of exact zeros: the keep
+    mask is the definition's (the lowest positions of the zeros dropped) and
+    the oracle's selection from the same scores."""
+    g = synth.make_graph("T", mask_dilate=8)
+    p16 = rand_params(5)
+    pg = gpu_graph(g, learned_cfg(g, prune_frac=0.25), p16)
+    score, _ = pg.prune()
+    pg.close()
+    src = score >= 0
+    V = src.sum(axis=1)
+    zeros = (src & (score == 0)).sum(axis=1)
+    say(f"sources {V.tolist()}, zero scores {zeros.tolist()}")
+    assert zeros.min() >= 8
+    frac = 0.5 * float((zeros / V).min())
+    pg = gpu_graph(g, learned_cfg(g, prune_frac=frac), p16)
+    score, keep = pg.prune()
+    check_selection(score, keep, frac)
+    # every dropped source is a zero score
+    assert np.all(score[src & ~keep] == 0)
+    pb = oracle.OracleProblem.from_synth(g, oracle.Params(mlp=p16.astype(np.float64)))
+    ko = pb.prune_select(score.reshape(g.n_frames, g.height, g.width).astype(np.float64), frac)
+    assert np.array_equal(ko.reshape(g.n_frames, -1).astype(bool), keep)
+    pg.close()
+
+
 def test_prune_edge_cases():
     from paper_2108_00516_amd import Config, PoseGraphError, from_synth
     g = synth.make_graph("T", n_frames=2)
